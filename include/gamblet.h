@@ -1,0 +1,168 @@
+/*
+ * gamblet.h -- C ABI of the MI355X (gfx950) gamblet hierarchy and solve.
+ *
+ * Problem (Section 1, discrete form of Section 5.1): find the Q1 finite
+ * element function u on the unit square meshed by n x n square cells,
+ * n = 2^q, h = 1/n, such that <phi_j, u>_a = int phi_j g for every interior
+ * node j, with u equal to given Dirichlet values on the boundary.  The
+ * coefficient a is one positive value per cell; the source g is one value
+ * per cell.
+ *
+ * Method (Section 4 and Algorithm 2 of Section 5): the fine-to-coarse
+ * hierarchy of localized gamblets is built once per coefficient field
+ * (gbl_build): for k = q..2, the subband operator B^(k) = W^(k) A^(k) W^(k)T
+ * (eq. defining B, Section 4.7), one small SPD patch system per coarse
+ * cell (Definition 5.3) giving the restriction R^(k-1,k) = pibar + D W
+ * (theorem expressing R through pibar and D), and the Galerkin coarse
+ * operator A^(k-1) = R A^(k) R^T (Theorem 4.8).  A solve (gbl_solve)
+ * restricts the right-hand side through the levels (eq. g^(k-1) = R g^(k)),
+ * solves the independent subband systems B^(k) w^(k) = W^(k) g^(k) and the
+ * coarse system A^(1) U^(1) = g^(1) (Section 4.7), and sums the subbands
+ * (Theorem 4.15).  Because the hierarchy is localized, that sum is an
+ * approximate inverse; gbl_solve wraps it in flexible conjugate gradients on
+ * the FP64 fine residual until the requested accuracy is reached (inexact
+ * inner solves are allowed, Theorem 5.6).
+ *
+ * Memory and ownership
+ *  - All array arguments named *_dev are device pointers (HIP global memory)
+ *    on the current device; the caller owns them and keeps them alive until
+ *    the call's stream work has completed.
+ *  - The hierarchy lives in one caller-owned device workspace whose size is
+ *    given by gbl_workspace_bytes; the library never allocates device memory
+ *    itself.  The library owns only the small host-side context returned by
+ *    gbl_build, released by gbl_destroy.
+ *  - Every call enqueues its kernels on the given stream (0 = null stream)
+ *    and, where it must read a device status word, synchronises that stream.
+ *
+ * Layouts (C order, float64 unless stated)
+ *  - cell arrays  [n][n]      : index ex*n + ey, cell [ex h,(ex+1)h) x [ey h,(ey+1)h)
+ *  - nodal arrays [n+1][n+1]  : index i*(n+1) + j, node (i h, j h)
+ *  - batched arrays carry a leading [nrhs] dimension.
+ *
+ * Errors: every function returns an int status; nothing throws across the
+ * ABI.  gbl_last_error() gives a message for the last failing call on a
+ * context (or the last failing context-less call when ctx is NULL).
+ */
+#ifndef GAMBLET_H
+#define GAMBLET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBL_VERSION 10000 /* 1.0.0 */
+
+enum gbl_status {
+  GBL_OK = 0,
+  GBL_EINVAL = -1,   /* bad argument: q out of range, null pointer, a <= 0 or non-finite, nrhs too large */
+  GBL_ENOTSPD = -2,  /* a patch or coarse matrix had a non-positive pivot */
+  GBL_ENOCONV = -3,  /* the solve did not reach rtol within max_outer iterations; u holds the last iterate */
+  GBL_ENOMEM = -4,   /* the workspace is smaller than gbl_workspace_bytes reports */
+  GBL_EHIP = -5      /* a HIP runtime call failed */
+};
+
+enum gbl_precision {
+  GBL_FP64 = 0,   /* hierarchy, patch solves and subband CG in FP64 */
+  GBL_MIXED = 1   /* hierarchy and subband CG in FP32; fine residual, outer iteration and A^(1) in FP64 */
+};
+
+typedef struct gbl_opts {
+  int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3); 1..4 */
+  int precision;      /* enum gbl_precision */
+  double rtol;        /* target relative l2 error of u (estimated by the preconditioned residual) */
+  int max_outer;      /* maximum outer (flexible CG) iterations */
+  int inner_iters;    /* block-Jacobi PCG iterations per subband system per outer iteration */
+  int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */
+} gbl_opts;
+
+typedef struct gbl_solve_info {
+  int outer_iters;        /* outer iterations taken (max over right-hand sides) */
+  int status;             /* same value as the return code */
+  double rel_update;      /* last preconditioned-residual estimate ||z|| / ||u|| (max over rhs) */
+  double rel_residual;    /* ||b - A u|| / ||b|| at exit (max over rhs) */
+} gbl_solve_info;
+
+typedef struct gbl_level_desc {
+  /* Device views into the workspace for level k (for inspection and tests).
+   * Level k has side nk = 2^k: cells for k < q, node slots for k = q (slot
+   * (x, y) is node (x, y); slots with x = 0 or y = 0 hold no unknown).
+   * elem_bytes is 8 (FP64) or 4 (MIXED). */
+  int k;
+  int nk;
+  int s;              /* A^(k) stencil half-width: A[x][y][2s+1][2s+1] */
+  int t;              /* B^(k) parent-stencil half-width: B[px][py][2t+1][2t+1][3][3] (k >= 2) */
+  int rw;             /* R^(k-1,k) block width: R[cx][cy][rw][rw] over level-k slots starting at 2(c-rho_k) (k >= 2) */
+  int rho;            /* effective patch radius at this level */
+  int elem_bytes;
+  const void* A;      /* A^(k) */
+  const void* B;      /* B^(k), NULL for k = 1 */
+  const void* R;      /* R^(k-1,k), NULL for k = 1 */
+} gbl_level_desc;
+
+typedef struct gbl_ctx gbl_ctx;
+
+/* Library version (GBL_VERSION). */
+int gbl_version(void);
+
+/* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 60,
+ * inner_iters 24, max_rhs 1. */
+int gbl_default_opts(gbl_opts* opts);
+
+/* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
+ * these options, including solve buffers for opts->max_rhs right-hand sides.
+ * Pure host computation.  EINVAL on a bad q or options. */
+int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
+
+/* Build the localized hierarchy for the cell coefficient a_dev [n][n] (n = 2^q).
+ * The hierarchy is stored in ws_dev (ws_bytes >= gbl_workspace_bytes); the
+ * caller must keep ws_dev alive and untouched until gbl_destroy.  On success
+ * *out receives a new context.  EINVAL if any a <= 0 or non-finite (checked on
+ * the device), ENOTSPD on a non-positive pivot, ENOMEM if ws_bytes is short.
+ * Synchronises the stream once at the end to read the status word. */
+int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts,
+              void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Solve for nrhs right-hand sides (nrhs <= opts->max_rhs).
+ * g_dev : [nrhs][n][n] cell source.
+ * u_dev : [nrhs][n+1][n+1] nodal; on entry its boundary entries hold the
+ *         Dirichlet data (interior entries are ignored), on exit the interior
+ *         holds the solution.
+ * info  : optional (may be NULL).
+ * ENOCONV if rtol was not reached within max_outer iterations (u holds the
+ * last iterate).  Synchronises the stream. */
+int gbl_solve(gbl_ctx* ctx, int nrhs, const double* g_dev, double* u_dev,
+              gbl_solve_info* info, void* stream);
+
+/* Adjoint gradient of a scalar J(u) (not in the paper; differentiates the
+ * discrete problem of Section 5.1).  With u the solution returned by gbl_solve
+ * for coefficient a and source g, and dJdu_dev [nrhs][n+1][n+1] the gradient
+ * of J with respect to the nodal values (boundary entries ignored), solves
+ * the symmetric adjoint system A lambda = dJ/du with the same hierarchy and
+ * writes
+ *   dJdloga_dev [nrhs][n][n] : -a_e lambda_e^T K_e u_e per cell
+ *   dJdg_dev    [nrhs][n][n] : (h^2/4) sum of lambda over the cell's corners (may be NULL)
+ *   lambda_dev  [nrhs][n+1][n+1] : the adjoint state, zero on the boundary (may be NULL)
+ * where K_e is the unit bilinear element stiffness.  u_dev is read only.
+ * Same status codes as gbl_solve. */
+int gbl_adjoint(gbl_ctx* ctx, int nrhs, const double* u_dev, const double* dJdu_dev,
+                double* dJdloga_dev, double* dJdg_dev, double* lambda_dev,
+                gbl_solve_info* info, void* stream);
+
+/* Describe level k (1 <= k <= q) of a built hierarchy.  EINVAL on a bad k. */
+int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);
+
+/* Release the host context (the workspace stays owned by the caller). */
+int gbl_destroy(gbl_ctx* ctx);
+
+/* Message of the last error on ctx, or of the last context-less failure when
+ * ctx is NULL.  Never NULL. */
+const char* gbl_last_error(const gbl_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAMBLET_H */

@@ -1,0 +1,496 @@
+// Host driver of the gamblet library: the C ABI declared in gamblet.h.
+//
+// gbl_build runs the fine-to-coarse sweep of Algorithm 2 (lines 2, 7, 11,
+// 12, 13 for k = q..2, then the coarse factor of line 16) as kernel launches
+// on the caller's stream.  gbl_solve applies the subband solve of
+// Section 4.7 / Theorem 4.15 (restriction, independent subband systems,
+// coarse system, reconstruction sum) as an approximate inverse inside
+// flexible conjugate gradients on the FP64 fine residual.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/gamblet.h"
+#include "gamblet_internal.hpp"
+#include "solve_internal.hpp"
+
+using namespace gbl;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  int q = 0, n = 0, rho = 0, prec = 0, max_rhs = 1;
+  size_t elem = 8;
+  LevelGeom lv[kMaxLevels];
+  size_t a_off = 0;          // copy of the coefficient (FP64, n^2)
+  size_t hier_off = 0;       // hierarchy arena (T)
+  size_t hier_elems = 0;
+  size_t L1_off = 0;         // 16 doubles
+  size_t status_off = 0;     // 4 ints
+  size_t oscal_off = 0;      // outer scalars
+  size_t dpart_off = 0;      // dot partials
+  size_t dcnt_off = 0;       // dot ticket
+  size_t fine_off[5] = {};   // FP64 slot vectors u, r, z, p, w
+  size_t lam_off = 0;        // FP64 nodal adjoint state
+  size_t g_off[kMaxLevels] = {};     // T slot vectors per level
+  size_t cgv_off[kMaxLevels] = {};   // T CG vectors per level (5 x 3 np^2)
+  size_t cgscal_off = 0;     // doubles
+  size_t cgpart_off[kMaxLevels] = {};
+  size_t cgcnt_off = 0;
+  int cg_blocks = 0;
+  size_t total = 0;
+};
+
+int validate_opts(const gbl_opts* o, std::string& msg) {
+  if (!o) { msg = "opts is NULL"; return GBL_EINVAL; }
+  if (o->rho < 1 || o->rho > kMaxRho) { msg = "rho must be in [1, 4]"; return GBL_EINVAL; }
+  if (o->precision != GBL_FP64 && o->precision != GBL_MIXED) { msg = "unknown precision"; return GBL_EINVAL; }
+  if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) { msg = "rtol must be in (0, 1)"; return GBL_EINVAL; }
+  if (o->max_outer < 1 || o->max_outer > 100000) { msg = "max_outer must be in [1, 100000]"; return GBL_EINVAL; }
+  if (o->inner_iters < 0 || o->inner_iters > 100000) { msg = "inner_iters must be in [0, 100000]"; return GBL_EINVAL; }
+  if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
+  return GBL_OK;
+}
+
+int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
+  if (q < 2 || q > 12) { msg = "q must be in [2, 12]"; return GBL_EINVAL; }
+  int st = validate_opts(o, msg);
+  if (st) return st;
+  L.q = q;
+  L.n = 1 << q;
+  L.rho = o->rho;
+  L.prec = o->precision;
+  L.max_rhs = o->max_rhs;
+  L.elem = (o->precision == GBL_FP64) ? 8 : 4;
+  // stencil widths: A^(q) is the 9-point Q1 stencil; a restriction row of
+  // level k-1 spans 2(2 rho_k + 1) level-k slots, so A^(k-1) = R A R^T
+  // couples coarse slots up to (4 rho_k + 1 + s_k) / 2 apart.
+  for (int k = 1; k <= q; ++k) {
+    L.lv[k].k = k;
+    L.lv[k].nk = 1 << k;
+  }
+  L.lv[q].s = std::min(1, L.lv[q].nk - 1);
+  for (int k = q; k >= 2; --k) {
+    LevelGeom& g = L.lv[k];
+    const int nc = g.nk / 2;
+    g.rho = std::min(o->rho, nc - 1);
+    g.rw = 2 * (2 * g.rho + 1);
+    g.t = std::min((g.s + 1) / 2, nc - 1);
+    L.lv[k - 1].s = std::min((4 * g.rho + 1 + g.s) / 2, nc - 1);
+  }
+  size_t e = 0;
+  for (int k = 1; k <= q; ++k) {
+    LevelGeom& g = L.lv[k];
+    const size_t nk2 = (size_t)g.nk * g.nk;
+    const size_t S = 2 * g.s + 1;
+    g.nA = S * S * nk2;
+    g.offA = e;
+    e += align_up(g.nA, 64);
+    if (k >= 2) {
+      const size_t np2 = nk2 / 4;
+      const size_t TT = 2 * g.t + 1;
+      g.nB = TT * TT * 9 * np2;
+      g.offB = e;
+      e += align_up(g.nB, 64);
+      g.nR = (size_t)g.rw * g.rw * np2;
+      g.offR = e;
+      e += align_up(g.nR, 64);
+      g.nBJ = 9 * np2;
+      g.offBJ = e;
+      e += align_up(g.nBJ, 64);
+    }
+  }
+  L.hier_elems = e;
+  const size_t n2 = (size_t)L.n * L.n;
+  size_t b = 0;
+  L.a_off = b; b = align_up(b + n2 * 8);
+  L.hier_off = b; b = align_up(b + e * L.elem);
+  L.L1_off = b; b = align_up(b + 16 * 8);
+  L.status_off = b; b = align_up(b + 4 * sizeof(int));
+  L.oscal_off = b; b = align_up(b + kNumOuterScalars * 8);
+  L.dpart_off = b; b = align_up(b + 3 * kDotBlocks * 8);
+  L.dcnt_off = b; b = align_up(b + 4 * sizeof(unsigned));
+  for (int i = 0; i < 5; ++i) { L.fine_off[i] = b; b = align_up(b + n2 * 8); }
+  L.lam_off = b; b = align_up(b + (size_t)(L.n + 1) * (L.n + 1) * 8);
+  for (int k = 1; k <= q; ++k) {
+    L.g_off[k] = b;
+    b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * L.elem);
+  }
+  int blocks = 0;
+  for (int k = 2; k <= q; ++k) {
+    const size_t np2 = (size_t)L.lv[k].nk * L.lv[k].nk / 4;
+    L.cgv_off[k] = b;
+    b = align_up(b + 5 * 3 * np2 * L.elem);
+    const int nb = (int)((np2 + 255) / 256);
+    L.cgpart_off[k] = b;
+    b = align_up(b + (size_t)nb * 8);
+    blocks += nb;
+  }
+  L.cg_blocks = blocks;
+  L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
+  L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
+  L.total = b;
+  return GBL_OK;
+}
+
+}  // namespace
+
+struct gbl_ctx {
+  Layout L;
+  gbl_opts opts;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err = "no error";
+  double* host = nullptr;   // pinned host mirror: [0..7] outer scalars, [8] status bits
+  CGArgs<float> cgf;
+  CGArgs<double> cgd;
+
+  template <typename T>
+  T* hier(size_t off) const { return reinterpret_cast<T*>(ws + L.hier_off) + off; }
+  double* fine(int i) const { return reinterpret_cast<double*>(ws + L.fine_off[i]); }
+  int* status() const { return reinterpret_cast<int*>(ws + L.status_off); }
+  double* oscal() const { return reinterpret_cast<double*>(ws + L.oscal_off); }
+  const double* a() const { return reinterpret_cast<const double*>(ws + L.a_off); }
+  double* L1() const { return reinterpret_cast<double*>(ws + L.L1_off); }
+};
+
+namespace {
+
+int fail(gbl_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail((ctx), GBL_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+CGArgs<T> make_cg_args(gbl_ctx* c) {
+  const Layout& L = c->L;
+  CGArgs<T> A{};
+  int blk = 0, l = 0;
+  for (int k = L.q; k >= 2; --k, ++l) {
+    const LevelGeom& g = L.lv[k];
+    const size_t np2 = (size_t)g.nk * g.nk / 4;
+    CGLev<T>& v = A.lv[l];
+    v.B = c->hier<T>(g.offB);
+    v.BJ = c->hier<T>(g.offBJ);
+    v.g = reinterpret_cast<const T*>(c->ws + L.g_off[k]);
+    T* base = reinterpret_cast<T*>(c->ws + L.cgv_off[k]);
+    v.x = base;
+    v.r = base + 3 * np2;
+    v.z = base + 6 * np2;
+    v.p = base + 9 * np2;
+    v.q = base + 12 * np2;
+    v.scal = reinterpret_cast<double*>(c->ws + L.cgscal_off) + l * kNumCGScalars;
+    v.part = reinterpret_cast<double*>(c->ws + L.cgpart_off[k]);
+    v.cnt = reinterpret_cast<unsigned*>(c->ws + L.cgcnt_off) + l;
+    v.np = g.nk / 2;
+    v.t = g.t;
+    v.fine = (k == L.q) ? 1 : 0;
+    v.blk0 = blk;
+    v.nblk = (int)((np2 + 255) / 256);
+    blk += v.nblk;
+  }
+  A.nlev = l;
+  return A;
+}
+
+template <typename T>
+int build_impl(gbl_ctx* c, hipStream_t st) {
+  const Layout& L = c->L;
+  const int q = L.q;
+  launch_assemble_fine<T>(c->a(), c->hier<T>(L.lv[q].offA), L.n, c->status(), st);
+  for (int k = q; k >= 2; --k) {
+    const LevelGeom& g = L.lv[k];
+    const bool fine = (k == q);
+    launch_subband_operator<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offBJ), fine, st);
+    launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR), fine, c->status(),
+                          st);
+    launch_galerkin<T>(g, L.lv[k - 1], c->hier<T>(g.offA), c->hier<T>(g.offR), c->hier<T>(L.lv[k - 1].offA),
+                       st);
+  }
+  launch_coarse_factor<T>(c->hier<T>(L.lv[1].offA), L.lv[1].s, c->L1(), c->status(), st);
+  HIPCHK(c, hipGetLastError());
+  return GBL_OK;
+}
+
+// z = S r: the subband solve of the localized hierarchy applied to the fine
+// residual r (FP64 slot vectors); inner arithmetic in T.
+template <typename T>
+void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, hipStream_t st) {
+  const Layout& L = c->L;
+  const int q = L.q;
+  const size_t n2 = (size_t)L.n * L.n;
+  T* g[kMaxLevels];
+  for (int k = 1; k <= q; ++k) g[k] = reinterpret_cast<T*>(c->ws + L.g_off[k]);
+  launch_convert<T, double>(n2, r, g[q], st);
+  for (int k = q; k >= 2; --k) launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], st);
+  launch_cg_init<T>(cg, L.cg_blocks, st);
+  for (int it = 0; it < c->opts.inner_iters; ++it) launch_cg_iter<T>(cg, L.cg_blocks, st);
+  launch_coarse_solve<T>(c->L1(), g[1], g[1], st);
+  for (int k = 2; k <= q; ++k) {
+    const int l = q - k;
+    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[l].x, g[k], k == q, st);
+  }
+  launch_convert<double, T>(n2, g[q], z, st);
+}
+
+// Flexible CG on the FP64 fine system with the subband solve as
+// preconditioner.  mode 0: source given per cell; mode 1: nodal right-hand side.
+template <typename T>
+int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, double* u_nodal,
+              gbl_solve_info* info, hipStream_t st) {
+  const Layout& L = c->L;
+  const int n = L.n;
+  const int len = n * n;
+  double* u = c->fine(0);
+  double* r = c->fine(1);
+  double* z = c->fine(2);
+  double* p = c->fine(3);
+  double* w = c->fine(4);
+  double* sc = c->oscal();
+  double* part = reinterpret_cast<double*>(c->ws + L.dpart_off);
+  unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
+  launch_residual(c->a(), n, mode, src, u_nodal, nullptr, r, st);
+  launch_fill((size_t)len, 0.0, u, st);
+  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSBB, st);
+  precondition<T>(c, cg, r, z, st);
+  launch_outer_direction(len, sc, z, p, 1, st);
+  int it = 0;
+  int status = GBL_ENOCONV;
+  double est = 1.0;
+  // ||z|| = ||S r|| estimates the error only up to the quality of S; keep a margin
+  const double tol = 0.1 * c->opts.rtol;
+  for (it = 1; it <= c->opts.max_outer; ++it) {
+    launch_apply_fine(c->a(), n, p, w, st);
+    launch_dots(len, 2, p, w, p, r, nullptr, nullptr, part, cnt, sc + kSPW, st);
+    launch_outer_update(len, sc, u, r, p, w, st);
+    precondition<T>(c, cg, r, z, st);
+    launch_dots(len, 3, z, z, u, u, z, w, part, cnt, sc + kSZZ, st);
+    HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double zz = c->host[kSZZ], uu = c->host[kSUU];
+    est = (uu > 0.0) ? std::sqrt(zz / uu) : (zz > 0.0 ? 1.0 : 0.0);
+    if (!std::isfinite(est)) {
+      status = GBL_ENOCONV;
+      break;
+    }
+    if (est <= tol) {
+      status = GBL_OK;
+      break;
+    }
+    launch_outer_direction(len, sc, z, p, 0, st);
+  }
+  if (it > c->opts.max_outer) it = c->opts.max_outer;
+  launch_slots_to_nodal(n, u, u_nodal, st);
+  // final residual of the returned iterate
+  launch_residual(c->a(), n, mode, src, u_nodal, u, r, st);
+  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSRR, st);
+  HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  HIPCHK(c, hipGetLastError());
+  if (info) {
+    info->outer_iters = std::max(info->outer_iters, it);
+    info->rel_update = std::max(info->rel_update, est);
+    const double bb = c->host[kSBB], rr = c->host[kSRR];
+    info->rel_residual = std::max(info->rel_residual, bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr));
+  }
+  return status;
+}
+
+template <typename T>
+const CGArgs<T>& cg_of(const gbl_ctx* c);
+template <>
+const CGArgs<float>& cg_of<float>(const gbl_ctx* c) { return c->cgf; }
+template <>
+const CGArgs<double>& cg_of<double>(const gbl_ctx* c) { return c->cgd; }
+
+template <typename T>
+int solve_many(gbl_ctx* c, int nrhs, int mode, const double* src, size_t src_stride, double* u,
+               gbl_solve_info* info, hipStream_t st) {
+  int worst = GBL_OK;
+  const size_t us = (size_t)(c->L.n + 1) * (c->L.n + 1);
+  for (int r = 0; r < nrhs; ++r) {
+    const int s = fcg_solve<T>(c, cg_of<T>(c), mode, src + r * src_stride, u + r * us, info, st);
+    if (s == GBL_EHIP) return s;
+    if (s != GBL_OK) worst = s;
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbl_version(void) { return GBL_VERSION; }
+
+int gbl_default_opts(gbl_opts* o) {
+  if (!o) return fail(nullptr, GBL_EINVAL, "opts is NULL");
+  o->rho = 3;
+  o->precision = GBL_MIXED;
+  o->rtol = 1e-8;
+  o->max_outer = 60;
+  o->inner_iters = 24;
+  o->max_rhs = 1;
+  return GBL_OK;
+}
+
+int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(nullptr, GBL_EINVAL, "bytes is NULL");
+  Layout L;
+  std::string msg;
+  const int st = make_layout(q, opts, L, msg);
+  if (st) return fail(nullptr, st, msg);
+  *bytes = L.total;
+  return GBL_OK;
+}
+
+int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, void* ws_dev, size_t ws_bytes,
+              void* stream) {
+  if (!out) return fail(nullptr, GBL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!a_dev) return fail(nullptr, GBL_EINVAL, "a_dev is NULL");
+  if (!ws_dev) return fail(nullptr, GBL_EINVAL, "ws_dev is NULL");
+  Layout L;
+  std::string msg;
+  int st = make_layout(q, opts, L, msg);
+  if (st) return fail(nullptr, st, msg);
+  if (ws_bytes < L.total)
+    return fail(nullptr, GBL_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  gbl_ctx* c = new (std::nothrow) gbl_ctx();
+  if (!c) return fail(nullptr, GBL_ENOMEM, "host allocation failed");
+  c->L = L;
+  c->opts = *opts;
+  c->ws = static_cast<char*>(ws_dev);
+  c->ws_bytes = ws_bytes;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(nullptr, GBL_EHIP, "hipHostMalloc failed");
+  }
+  auto bail = [&](int code) {
+    g_last_error = c->err;
+    hipHostFree(c->host);
+    delete c;
+    return code;
+  };
+  const size_t n2 = (size_t)L.n * L.n;
+  if (hipMemcpyAsync(c->ws + L.a_off, a_dev, n2 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    c->err = "copy of the coefficient failed";
+    return bail(GBL_EHIP);
+  }
+  // zero the status word, reduction tickets and the coarse factor
+  {
+    const size_t nz = (L.lam_off - L.L1_off) / 8;
+    launch_fill(nz, 0.0, reinterpret_cast<double*>(c->ws + L.L1_off), s);
+    launch_fill((L.total - L.cgscal_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.cgscal_off), s);
+  }
+  c->cgf = make_cg_args<float>(c);
+  c->cgd = make_cg_args<double>(c);
+  st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
+  if (st) return bail(st);
+  if (hipMemcpyAsync(c->host + 8, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    c->err = "status read failed";
+    return bail(GBL_EHIP);
+  }
+  int bits = 0;
+  std::memcpy(&bits, c->host + 8, sizeof(int));
+  if (bits & kBadCoefficient) {
+    c->err = "coefficient must be positive and finite in every cell";
+    return bail(GBL_EINVAL);
+  }
+  if (bits & kBadPivot) {
+    c->err = "non-positive pivot in a patch or coarse matrix";
+    return bail(GBL_ENOTSPD);
+  }
+  *out = c;
+  return GBL_OK;
+}
+
+int gbl_solve(gbl_ctx* c, int nrhs, const double* g_dev, double* u_dev, gbl_solve_info* info, void* stream) {
+  if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
+  if (!g_dev || !u_dev) return fail(c, GBL_EINVAL, "g_dev and u_dev must not be NULL");
+  if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n2 = (size_t)c->L.n * c->L.n;
+  const int st = (c->L.prec == GBL_FP64) ? solve_many<double>(c, nrhs, 0, g_dev, n2, u_dev, info, s)
+                                         : solve_many<float>(c, nrhs, 0, g_dev, n2, u_dev, info, s);
+  if (info) info->status = st;
+  if (st == GBL_ENOCONV) return fail(c, st, "solve did not reach rtol within max_outer iterations");
+  return st;
+}
+
+int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_dev, double* dJdloga_dev,
+                double* dJdg_dev, double* lambda_dev, gbl_solve_info* info, void* stream) {
+  if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
+  if (!u_dev || !dJdu_dev || !dJdloga_dev) return fail(c, GBL_EINVAL, "u, dJdu and dJdloga must not be NULL");
+  if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = c->L.n;
+  const size_t n2 = (size_t)n * n, us = (size_t)(n + 1) * (n + 1);
+  int worst = GBL_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    double* lam = lambda_dev ? lambda_dev + r * us : reinterpret_cast<double*>(c->ws + c->L.lam_off);
+    launch_fill(us, 0.0, lam, s);
+    const int st = (c->L.prec == GBL_FP64)
+                       ? fcg_solve<double>(c, c->cgd, 1, dJdu_dev + r * us, lam, info, s)
+                       : fcg_solve<float>(c, c->cgf, 1, dJdu_dev + r * us, lam, info, s);
+    if (st == GBL_EHIP) return st;
+    if (st != GBL_OK) worst = st;
+    launch_cell_gradient(c->a(), n, u_dev + r * us, lam, dJdloga_dev + r * n2, dJdg_dev ? dJdg_dev + r * n2 : nullptr,
+                         s);
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (info) info->status = worst;
+  if (worst == GBL_ENOCONV) return fail(c, worst, "adjoint solve did not reach rtol within max_outer iterations");
+  return worst;
+}
+
+int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
+  if (!c || !d) return fail(nullptr, GBL_EINVAL, "ctx and desc must not be NULL");
+  if (k < 1 || k > c->L.q) return fail(const_cast<gbl_ctx*>(c), GBL_EINVAL, "level out of range");
+  const LevelGeom& g = c->L.lv[k];
+  d->k = k;
+  d->nk = g.nk;
+  d->s = g.s;
+  d->t = k >= 2 ? g.t : 0;
+  d->rw = k >= 2 ? g.rw : 0;
+  d->rho = k >= 2 ? g.rho : 0;
+  d->elem_bytes = (int)c->L.elem;
+  const char* base = c->ws + c->L.hier_off;
+  d->A = base + g.offA * c->L.elem;
+  d->B = k >= 2 ? base + g.offB * c->L.elem : nullptr;
+  d->R = k >= 2 ? base + g.offR * c->L.elem : nullptr;
+  return GBL_OK;
+}
+
+int gbl_destroy(gbl_ctx* c) {
+  if (!c) return GBL_OK;
+  if (c->host) hipHostFree(c->host);
+  delete c;
+  return GBL_OK;
+}
+
+const char* gbl_last_error(const gbl_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

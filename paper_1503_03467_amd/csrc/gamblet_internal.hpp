@@ -1,0 +1,71 @@
+// Internal declarations shared by the host driver and the kernel files.
+//
+// Geometry used by every kernel ("slot" layout).  The fine mesh has n = 2^q
+// cells per dimension.  Level k (1 <= k <= q) is a square grid of nk = 2^k
+// slots, index x*nk + y.  For k < q a slot is a dyadic cell of side 2^-k;
+// for k = q slot (x, y) is the mesh node (x, y) and slots with x = 0 or
+// y = 0 carry no unknown (they are boundary nodes).  The parent of slot
+// (x, y) of level k is slot (x/2, y/2) of level k-1, its child position is
+// t = 2 (x mod 2) + (y mod 2) (nested aggregation, Construction 4.2, with the
+// nodal measurements at level q allowed in the discussion of Algorithm 1).
+//
+// Subband unknowns of level k (Lemma 4.9) are stored three per parent,
+// index 3 * parent + t, t = 0..2; for parents of level q-1 that have fewer
+// than four children the missing rows are padded with identity rows (zero
+// right-hand side), which leaves every result unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gamblet.h"
+
+namespace gbl {
+
+constexpr int kMaxLevels = 13;     // q <= 12
+constexpr int kMaxRho = 4;
+
+// Device status bits (or-ed into the workspace status word).
+constexpr int kBadCoefficient = 1;
+constexpr int kBadPivot = 2;
+constexpr int kBadInput = 4;
+
+struct LevelGeom {
+  int k = 0;       // level
+  int nk = 0;      // side (slots)
+  int s = 0;       // A^(k) stencil half-width
+  int t = 0;       // B^(k) parent-stencil half-width (k >= 2)
+  int rho = 0;     // effective patch radius for the patches of level k-1 (k >= 2)
+  int rw = 0;      // R^(k-1,k) block width 2(2 rho + 1) (k >= 2)
+  size_t offA = 0, offB = 0, offR = 0, offBJ = 0;   // element offsets into the hierarchy arena
+  size_t nA = 0, nB = 0, nR = 0, nBJ = 0;            // element counts
+  int nparent() const { return (nk / 2) * (nk / 2); }
+  int nsub() const { return 3 * nparent(); }
+};
+
+// Launchers (defined in kernels_*.hip), templated on the hierarchy scalar T.
+template <typename T>
+void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t st);
+template <typename T>
+void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool fine, hipStream_t st);
+template <typename T>
+void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
+                        hipStream_t st);
+template <typename T>
+void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
+                     hipStream_t st);
+template <typename T>
+void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStream_t st);
+
+// Solve-phase launchers.
+struct CGLevelArgs;
+template <typename T>
+void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st);
+template <typename T>
+void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
+                    hipStream_t st);
+template <typename T>
+void launch_coarse_solve(const double* L1, const T* g1, T* v1, hipStream_t st);
+
+}  // namespace gbl

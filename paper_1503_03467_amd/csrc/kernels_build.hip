@@ -1,0 +1,563 @@
+// Build-phase kernels of the localized gamblet hierarchy (Algorithm 2,
+// lines 2, 7, 11, 12, 13) for gfx950.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.hpp"
+#include "gamblet_internal.hpp"
+
+namespace gbl {
+
+// ---------------------------------------------------------------------------
+// Fine stiffness A^(q) = A (Algorithm 2, line 2; level-q gamblets are the
+// nodal basis functions).  Bilinear element on a square cell with
+// coefficient a_e: diagonal 2/3 a_e, edge neighbours -1/6 a_e, opposite
+// corner -1/3 a_e.  One thread per node slot; the nine couplings are
+// written offset-major, A[ox*3+oy][x*n+y].  Couplings to boundary nodes and
+// the rows of boundary slots are zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_assemble_fine(const double* __restrict__ a, T* __restrict__ A, int n,
+                                int* __restrict__ status) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  const size_t nn = (size_t)n * n;
+  if (x == 0 || y == 0) {
+    for (int e = 0; e < 9; ++e) A[e * nn + id] = T(0);
+    return;
+  }
+  // cells around node (x, y): (x-1,y-1), (x,y-1), (x-1,y), (x,y)
+  const double a00 = a[(x - 1) * n + (y - 1)];
+  const double a10 = a[x * n + (y - 1)];
+  const double a01 = a[(x - 1) * n + y];
+  const double a11 = a[x * n + y];
+  if (!(a00 > 0.0 && a10 > 0.0 && a01 > 0.0 && a11 > 0.0) ||
+      !(a00 < INFINITY && a10 < INFINITY && a01 < INFINITY && a11 < INFINITY)) {
+    atomicOr(status, kBadCoefficient);
+  }
+  double v[3][3];
+  v[1][1] = (2.0 / 3.0) * (a00 + a10 + a01 + a11);
+  v[2][1] = -(a10 + a11) / 6.0;
+  v[0][1] = -(a00 + a01) / 6.0;
+  v[1][2] = -(a01 + a11) / 6.0;
+  v[1][0] = -(a00 + a10) / 6.0;
+  v[2][2] = -a11 / 3.0;
+  v[0][0] = -a00 / 3.0;
+  v[2][0] = -a10 / 3.0;
+  v[0][2] = -a01 / 3.0;
+  for (int ox = 0; ox < 3; ++ox) {
+    for (int oy = 0; oy < 3; ++oy) {
+      const int xx = x + ox - 1, yy = y + oy - 1;
+      const bool inner = xx >= 1 && xx <= n - 1 && yy >= 1 && yy <= n - 1;
+      A[(ox * 3 + oy) * nn + id] = inner ? T(v[ox][oy]) : T(0);
+    }
+  }
+}
+
+template <typename T>
+void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t st) {
+  const int tot = n * n;
+  hipLaunchKernelGGL(k_assemble_fine<T>, dim3((tot + 255) / 256), dim3(256), 0, st, a, A, n, status);
+}
+
+// ---------------------------------------------------------------------------
+// Subband operator B^(k) = W^(k) A^(k) W^(k)T (eq. defining B, Section 4.7;
+// Algorithm 2, line 7) in parent-block stencil form, offset-major:
+// B[(o*9 + 3i + j)][px*np+py] with o = ox*(2t+1)+oy the neighbour parent
+// offset and (i, j) the 3x3 block entry, plus the inverse of every 3x3 diagonal block
+// (block-Jacobi preconditioner of the subband CG).  One thread per
+// (parent, neighbour parent) pair.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T a_entry(const T* __restrict__ A, int nk, int s, int cx, int cy, int dx,
+                                     int dy) {
+  // A^(k)_{(cx,cy),(dx,dy)}; zero outside the grid or the stencil
+  if (cx < 0 || cy < 0 || cx >= nk || cy >= nk) return T(0);
+  if (dx < 0 || dy < 0 || dx >= nk || dy >= nk) return T(0);
+  const int ox = dx - cx + s, oy = dy - cy + s;
+  const int S = 2 * s + 1;
+  if (ox < 0 || oy < 0 || ox >= S || oy >= S) return T(0);
+  return A[(size_t)(ox * S + oy) * nk * nk + cx * nk + cy];
+}
+
+template <typename T>
+__global__ void k_subband_operator(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ BJ,
+                                   int nk, int s, int t, int fine) {
+  const int np = nk / 2;
+  const int TT = 2 * t + 1;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long)np * np * TT * TT) return;
+  const int o = (int)(id % (TT * TT));
+  const int p = (int)(id / (TT * TT));
+  const int px = p / np, py = p % np;
+  const int ox = o / TT, oy = o % TT;
+  const int qx = px + ox - t, qy = py + oy - t;
+  const size_t np2 = (size_t)np * np;
+  T* out = B + (size_t)o * 9 * np2 + p;   // B[(o*9 + e) * np2 + p]
+  if (qx < 0 || qy < 0 || qx >= np || qy >= np) {
+    for (int e = 0; e < 9; ++e) out[e * np2] = T(0);
+    return;
+  }
+  const int tp = parent_type(fine != 0, px, py);
+  const int tq = parent_type(fine != 0, qx, qy);
+  // M[d][d'] = A_{child d of p, child d' of q}
+  double M[4][4];
+  for (int d = 0; d < 4; ++d) {
+    for (int e = 0; e < 4; ++e) {
+      M[d][e] = (double)a_entry(A, nk, s, 2 * px + (d >> 1), 2 * py + (d & 1), 2 * qx + (e >> 1),
+                                2 * qy + (e & 1));
+    }
+  }
+  double Bl[3][3];
+  for (int i = 0; i < 3; ++i) {
+    double tmp[4];
+    for (int e = 0; e < 4; ++e) {
+      double acc = 0.0;
+      for (int d = 0; d < 4; ++d) acc += wcoef(tp, i, d) * M[d][e];
+      tmp[e] = acc;
+    }
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int e = 0; e < 4; ++e) acc += tmp[e] * wcoef(tq, j, e);
+      Bl[i][j] = acc;
+    }
+  }
+  const bool center = (ox == t && oy == t);
+  if (center) {
+    for (int i = 0; i < 3; ++i) {
+      if (is_pad_row(tp, i)) {
+        for (int j = 0; j < 3; ++j) Bl[i][j] = Bl[j][i] = 0.0;
+        Bl[i][i] = 1.0;
+      }
+    }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[(i * 3 + j) * np2] = T(Bl[i][j]);
+  if (center) {
+    // inverse of the symmetric 3x3 diagonal block by cofactors
+    const double a0 = Bl[0][0], a1 = Bl[0][1], a2 = Bl[0][2];
+    const double b1 = Bl[1][1], b2 = Bl[1][2], c2 = Bl[2][2];
+    const double C00 = b1 * c2 - b2 * b2, C01 = -(a1 * c2 - a2 * b2), C02 = a1 * b2 - a2 * b1;
+    const double C11 = a0 * c2 - a2 * a2, C12 = -(a0 * b2 - a1 * a2), C22 = a0 * b1 - a1 * a1;
+    const double det = a0 * C00 + a1 * C01 + a2 * C02;
+    const double id = det != 0.0 ? 1.0 / det : 0.0;
+    T* bj = BJ + p;   // BJ[e * np2 + p]
+    bj[0 * np2] = T(C00 * id); bj[1 * np2] = T(C01 * id); bj[2 * np2] = T(C02 * id);
+    bj[3 * np2] = T(C01 * id); bj[4 * np2] = T(C11 * id); bj[5 * np2] = T(C12 * id);
+    bj[6 * np2] = T(C02 * id); bj[7 * np2] = T(C12 * id); bj[8 * np2] = T(C22 * id);
+  }
+}
+
+template <typename T>
+void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool fine, hipStream_t st) {
+  const int np = L.nk / 2;
+  const int TT = 2 * L.t + 1;
+  const long tot = (long)np * np * TT * TT;
+  hipLaunchKernelGGL(k_subband_operator<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, B,
+                     BJ, L.nk, L.s, L.t, fine ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Patch solves and restriction (Definition 5.3; Algorithm 2, lines 11-12).
+//
+// One workgroup of 256 threads (a 16 x 16 thread grid) per coarse cell i of
+// level k-1.  The patch is the box of coarse cells within rho of i, clipped
+// to the domain; its unknowns are the subband indices of those parents
+// (3 per parent).  The patch matrix B^(i,rho), symmetrically scaled by the
+// inverse square roots of its diagonal, is held in registers in a
+// block-cyclic layout: thread (tr, tc) owns entries (tr + 16 a, tc + 16 b),
+// a >= b.  The right-hand side -(W A pibar^T)_{i^chi, i} is appended as an
+// extra last row, so the right-looking Cholesky factorisation also performs
+// the forward substitution.  Column j is broadcast through LDS (double
+// buffered, one barrier per column); a back substitution follows.  The
+// patch solution y gives the restriction row
+// R_i = pibar_i + sum_{j in i^chi} y_j W_j.
+// ---------------------------------------------------------------------------
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, const T* __restrict__ B,
+                                                     T* __restrict__ R, int nk, int s, int t, int rho,
+                                                     int fine, int* __restrict__ status) {
+  constexpr int P = 16 * MB;
+  constexpr int NE = MB * (MB + 1) / 2;
+  const int nc = nk / 2;
+  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = ci / nc, cy = ci % nc;
+  const int x0 = max(0, cx - rho), x1 = min(nc - 1, cx + rho);
+  const int y0 = max(0, cy - rho), y1 = min(nc - 1, cy + rho);
+  const int wy = y1 - y0 + 1;
+  const int npar = (x1 - x0 + 1) * wy;
+  const int p = 3 * npar;   // unknowns; row p carries the right-hand side
+  const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
+  const int TT = 2 * t + 1;
+  const int S = 2 * s + 1;
+  const int ti = parent_type(fine != 0, cx, cy);
+  const size_t nc2 = (size_t)nc * nc;
+
+  __shared__ T colbuf[2][P];
+  __shared__ T pivv[P];
+  __shared__ T ldiag[P];
+  __shared__ T zb[P];
+  __shared__ T sc[P];
+  __shared__ int flag;
+  if (tid == 0) flag = 0;
+
+  // scaling and right-hand side
+  for (int r = tid; r < P; r += 256) {
+    T scale = T(1), rhs = T(0);
+    if (r < p) {
+      const int lp = r / 3, tt = r - 3 * lp;
+      const int px = x0 + lp / wy, py = y0 + lp % wy;
+      const T d = B[((size_t)(t * TT + t) * 9 + tt * 4) * nc2 + px * nc + py];
+      if (d > T(0)) {
+        scale = T(1) / my_sqrt<T>(d);
+      } else {
+        atomicOr(status, kBadPivot);
+      }
+      const int tp = parent_type(fine != 0, px, py);
+      // b_(p,tt) = - sum_d W_tt(p)[d] sum_e pibar_i[e] A_{2p+d, 2i+e}
+      if (abs(px - cx) <= t && abs(py - cy) <= t && !is_pad_row(tp, tt)) {
+        double acc = 0.0;
+        for (int d = 0; d < 4; ++d) {
+          const double wd = wcoef(tp, tt, d);
+          if (wd == 0.0) continue;
+          const int fx = 2 * px + (d >> 1), fy = 2 * py + (d & 1);
+          double inner = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double pe = pibar(ti, e);
+            if (pe == 0.0) continue;
+            const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
+            const int ox = gx - fx + s, oy = gy - fy + s;
+            if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
+            inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
+          }
+          acc += wd * inner;
+        }
+        rhs = T(-acc);
+      }
+    }
+    sc[r] = scale;
+    zb[r] = rhs * scale;
+  }
+  __syncthreads();
+
+  // load the scaled patch matrix (lower triangle) and the right-hand-side row
+  T a[NE];
+#pragma unroll
+  for (int ai = 0; ai < MB; ++ai) {
+#pragma unroll
+    for (int bi = 0; bi <= ai; ++bi) {
+      const int r = tr + 16 * ai, c = tc + 16 * bi;
+      T v;
+      if (r < p && c < p) {
+        if (r >= c) {
+          const int lr = r / 3, trr = r - 3 * lr;
+          const int lc = c / 3, tcc = c - 3 * lc;
+          const int rx = x0 + lr / wy, ry = y0 + lr % wy;
+          const int qx = x0 + lc / wy, qy = y0 + lc % wy;
+          const int ox = qx - rx + t, oy = qy - ry + t;
+          T bv = T(0);
+          if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
+            bv = B[((size_t)(ox * TT + oy) * 9 + trr * 3 + tcc) * nc2 + rx * nc + ry];
+          v = bv * sc[r] * sc[c];
+        } else {
+          v = T(0);
+        }
+      } else if (r == p && c < p) {
+        v = zb[c];
+      } else {
+        v = (r == c) ? T(1) : T(0);
+      }
+      a[ai * (ai + 1) / 2 + bi] = v;
+    }
+  }
+
+  // first column broadcast
+  if (tc == 0) {
+#pragma unroll
+    for (int ai = 0; ai < MB; ++ai) {
+      const int r = tr + 16 * ai;
+      const T v = a[ai * (ai + 1) / 2];
+      colbuf[0][r] = (r > 0 && r <= p) ? v : T(0);
+      if (r == 0) pivv[0] = v;
+    }
+  }
+  __syncthreads();
+
+  for (int j = 0; j < p; ++j) {
+    const T* cur = colbuf[j & 1];
+    T* nxt = colbuf[(j + 1) & 1];
+    T pv = pivv[j];
+    if (!(pv > T(0))) {
+      if (tid == 0) flag = 1;
+      pv = T(1);
+    }
+    const T sq = my_sqrt<T>(pv);
+    const T inv = T(1) / pv;
+    const T rs = T(1) / sq;
+    T cr[MB], cc[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      cr[m] = cur[tr + 16 * m];
+      cc[m] = cur[tc + 16 * m] * inv;
+    }
+    // scale the owned part of column j into L
+    const int bj = j >> 4;
+    if (tc == (j & 15)) {
+#pragma unroll
+      for (int bi = 0; bi < MB; ++bi) {
+        if (bi == bj) {
+#pragma unroll
+          for (int ai = bi; ai < MB; ++ai) {
+            const int r = tr + 16 * ai;
+            T& e = a[ai * (ai + 1) / 2 + bi];
+            if (r > j) e = e * rs;
+            else if (r == j) { e = sq; ldiag[j] = sq; }
+          }
+        }
+      }
+    }
+    // trailing update a_rc -= c_r c_c / pivot (entries of retired columns see c = 0)
+#pragma unroll
+    for (int bi = 0; bi < MB; ++bi) {
+      if (16 * bi + 15 > j) {
+#pragma unroll
+        for (int ai = bi; ai < MB; ++ai) a[ai * (ai + 1) / 2 + bi] -= cr[ai] * cc[bi];
+      }
+    }
+    // publish column j+1
+    const int jn = j + 1;
+    if (jn < p && tc == (jn & 15)) {
+      const int bn = jn >> 4;
+#pragma unroll
+      for (int bi = 0; bi < MB; ++bi) {
+        if (bi == bn) {
+#pragma unroll
+          for (int ai = bi; ai < MB; ++ai) {
+            const int r = tr + 16 * ai;
+            const T v = a[ai * (ai + 1) / 2 + bi];
+            nxt[r] = (r > jn && r <= p) ? v : T(0);
+            if (r == jn) pivv[jn] = v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // forward-substitution result z = L^{-1} b sits in row p
+  if (tr == (p & 15)) {
+    const int ap = p >> 4;
+#pragma unroll
+    for (int ai = 0; ai < MB; ++ai) {
+      if (ai == ap) {
+#pragma unroll
+        for (int bi = 0; bi <= ai; ++bi) {
+          const int c = tc + 16 * bi;
+          if (c < p) zb[c] = a[ai * (ai + 1) / 2 + bi];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // back substitution L^T x = z, row j of L owned by threads with tr = j mod 16
+  for (int j = p - 1; j >= 0; --j) {
+    if (tr == (j & 15)) {
+      const int aj = j >> 4;
+      const T xj = zb[j] / ldiag[j];
+#pragma unroll
+      for (int ai = 0; ai < MB; ++ai) {
+        if (ai == aj) {
+#pragma unroll
+          for (int bi = 0; bi <= ai; ++bi) {
+            const int c = tc + 16 * bi;
+            if (c < j) zb[c] -= a[ai * (ai + 1) / 2 + bi] * xj;
+          }
+        }
+      }
+      if (tc == (j & 15)) pivv[j] = xj;   // x_j (pivot values are no longer needed)
+    }
+    __syncthreads();
+  }
+  // unscale: y_r = sc_r x_r
+  for (int r = tid; r < p; r += 256) zb[r] = pivv[r] * sc[r];
+  if (tid == 0 && flag) atomicOr(status, kBadPivot);
+  __syncthreads();
+
+  // R_i[bx][by] over level-k slots c = 2(cx - rho) + bx
+  const int rw = 2 * (2 * rho + 1);
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
+  T* Ri = R + ci;   // R[e * nc2 + ci]
+  for (int e = tid; e < rw * rw; e += 256) {
+    const int bx = e / rw, by = e % rw;
+    const int fx = ox0 + bx, fy = oy0 + by;
+    double v = 0.0;
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      const int px = fx >> 1, py = fy >> 1;
+      const int d = 2 * (fx & 1) + (fy & 1);
+      const int tp = parent_type(fine != 0, px, py);
+      if (px == cx && py == cy) v = pibar(tp, d);
+      const int lp = (px - x0) * wy + (py - y0);
+      for (int tt = 0; tt < 3; ++tt) v += (double)zb[3 * lp + tt] * wcoef(tp, tt, d);
+    }
+    Ri[(size_t)e * nc2] = T(v);
+  }
+}
+
+template <typename T>
+void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
+                        hipStream_t st) {
+  const int nc = L.nk / 2;
+  const int wmax = (2 * L.rho + 1) < nc ? (2 * L.rho + 1) : nc;
+  const int need = 3 * wmax * wmax + 1;
+  const dim3 grid(nc * nc), block(256);
+  const int f = fine ? 1 : 0;
+  if (need <= 32) {
+    hipLaunchKernelGGL((k_patch_solve<T, 2>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+  } else if (need <= 80) {
+    hipLaunchKernelGGL((k_patch_solve<T, 5>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+  } else if (need <= 160) {
+    hipLaunchKernelGGL((k_patch_solve<T, 10>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+  } else {
+    hipLaunchKernelGGL((k_patch_solve<T, 16>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarsening A^(k-1) = R^(k-1,k) A^(k) R^(k,k-1) (Theorem 4.8;
+// Algorithm 2, line 13 -- the step the paper names as its complexity
+// bottleneck).  One workgroup per coarse row i: first z = R_i A^(k) on the
+// window of level-k slots the row can reach (staged in LDS; A is symmetric
+// so z_c' is row c' of A against R_i), then every entry
+// A^(k-1)_{i,i'} = z . R_{i'} of the coarse stencil.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_galerkin(const T* __restrict__ A, const T* __restrict__ R,
+                                                  T* __restrict__ Ac, int nk, int s, int rho, int sc) {
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int nc = nk / 2;
+  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = ci / nc, cy = ci % nc;
+  const int rw = 2 * (2 * rho + 1);
+  const int S = 2 * s + 1;
+  const int zw = rw + 2 * s;
+  T* Rl = smem;              // rw * rw
+  T* z = smem + rw * rw;     // zw * zw
+  const int orgx = 2 * (cx - rho), orgy = 2 * (cy - rho);
+  const size_t nc2 = (size_t)nc * nc;
+  const size_t nk2 = (size_t)nk * nk;
+  for (int e = threadIdx.x; e < rw * rw; e += blockDim.x) Rl[e] = R[e * nc2 + ci];
+  __syncthreads();
+  for (int e = threadIdx.x; e < zw * zw; e += blockDim.x) {
+    const int zx = e / zw, zy = e % zw;
+    const int fx = orgx - s + zx, fy = orgy - s + zy;
+    T acc = T(0);
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      const int dx = fx - orgx, dy = fy - orgy;   // position in R coordinates
+      const int oxl = max(0, s - dx), oxh = min(S - 1, s - dx + rw - 1);
+      const int oyl = max(0, s - dy), oyh = min(S - 1, s - dy + rw - 1);
+      const T* Arow = A + (size_t)(fx * nk + fy);
+      for (int ox = oxl; ox <= oxh; ++ox) {
+        const T* Ar = Arow + (size_t)ox * S * nk2;
+        const T* Rr = Rl + (dx + ox - s) * rw + (dy - s);
+        for (int oy = oyl; oy <= oyh; ++oy) acc += Ar[oy * nk2] * Rr[oy];
+      }
+    }
+    z[e] = acc;
+  }
+  __syncthreads();
+  const int Sc = 2 * sc + 1;
+  T* out = Ac + ci;   // Ac[e * nc2 + ci]
+  for (int e = threadIdx.x; e < Sc * Sc; e += blockDim.x) {
+    const int ox = e / Sc, oy = e % Sc;
+    const int jx = cx + ox - sc, jy = cy + oy - sc;
+    T acc = T(0);
+    if (jx >= 0 && jy >= 0 && jx < nc && jy < nc) {
+      const T* Rj = R + (jx * nc + jy);
+      const int ojx = 2 * (jx - rho), ojy = 2 * (jy - rho);
+      // z index of R_j entry (bx, by): (ojx + bx) - (orgx - s)
+      const int shx = ojx - orgx + s, shy = ojy - orgy + s;
+      const int bxl = max(0, -shx), bxh = min(rw - 1, zw - 1 - shx);
+      const int byl = max(0, -shy), byh = min(rw - 1, zw - 1 - shy);
+      for (int bx = bxl; bx <= bxh; ++bx) {
+        const T* Rr = Rj + (size_t)bx * rw * nc2;
+        const T* zr = z + (shx + bx) * zw + shy;
+        for (int by = byl; by <= byh; ++by) acc += Rr[by * nc2] * zr[by];
+      }
+    }
+    out[(size_t)e * nc2] = acc;
+  }
+}
+
+template <typename T>
+void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
+                     hipStream_t st) {
+  const int nc = L.nk / 2;
+  const int zw = L.rw + 2 * L.s;
+  const size_t shm = (size_t)(L.rw * L.rw + zw * zw) * sizeof(T);
+  hipLaunchKernelGGL(k_galerkin<T>, dim3(nc * nc), dim3(256), shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: Cholesky factor of the 4 x 4 matrix A^(1) in FP64
+// (Algorithm 2, line 16).  A single thread; L1 holds the dense factor.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_coarse_factor(const T* __restrict__ A1, int s1, double* __restrict__ L1,
+                                int* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int S = 2 * s1 + 1;
+  double M[4][4];
+  for (int i = 0; i < 4; ++i) {
+    const int ix = i / 2, iy = i % 2;
+    for (int j = 0; j < 4; ++j) {
+      const int jx = j / 2, jy = j % 2;
+      const int ox = jx - ix + s1, oy = jy - iy + s1;
+      double v = 0.0;
+      if (ox >= 0 && oy >= 0 && ox < S && oy < S) v = (double)A1[(ox * S + oy) * 4 + i];
+      M[i][j] = v;
+    }
+  }
+  // symmetrise (the FP32 hierarchy may carry rounding asymmetry)
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < i; ++j) M[i][j] = M[j][i] = 0.5 * (M[i][j] + M[j][i]);
+  for (int j = 0; j < 4; ++j) {
+    double d = M[j][j];
+    for (int k = 0; k < j; ++k) d -= M[j][k] * M[j][k];
+    if (!(d > 0.0)) {
+      atomicOr(status, kBadPivot);
+      d = 1.0;
+    }
+    const double l = sqrt(d);
+    M[j][j] = l;
+    for (int i = j + 1; i < 4; ++i) {
+      double v = M[i][j];
+      for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
+      M[i][j] = v / l;
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) L1[i * 4 + j] = j <= i ? M[i][j] : 0.0;
+}
+
+template <typename T>
+void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_factor<T>, dim3(1), dim3(64), 0, st, A1, s1, L1, status);
+}
+
+#define GBL_INST(T)                                                                                   \
+  template void launch_assemble_fine<T>(const double*, T*, int, int*, hipStream_t);                  \
+  template void launch_subband_operator<T>(const LevelGeom&, const T*, T*, T*, bool, hipStream_t);   \
+  template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, bool, int*,          \
+                                      hipStream_t);                                                  \
+  template void launch_galerkin<T>(const LevelGeom&, const LevelGeom&, const T*, const T*, T*,      \
+                                   hipStream_t);                                                     \
+  template void launch_coarse_factor<T>(const T*, int, double*, int*, hipStream_t);
+GBL_INST(float)
+GBL_INST(double)
+#undef GBL_INST
+
+}  // namespace gbl

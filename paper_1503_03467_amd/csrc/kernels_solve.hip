@@ -1,0 +1,576 @@
+// Solve-phase kernels for gfx950: fine residual (FP64, matrix-free from the
+// cell coefficient), restriction g^(k-1) = R g^(k), the subband systems
+// B^(k) w^(k) = W^(k) g^(k) for all levels at once (block-Jacobi
+// preconditioned CG, one launch per CG phase covering every level), the
+// coarse solve, prolongation and the reconstruction sum, outer flexible-CG
+// vector operations, and the adjoint gradient.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "gamblet_internal.hpp"
+#include "solve_internal.hpp"
+
+namespace gbl {
+
+// ---------------------------------------------------------------------------
+// Reductions: block sum, then the last block to finish (atomic ticket) adds
+// the per-block partials in a fixed order -- deterministic, no waiting.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  // sh: NV * 8 doubles (one per wave of a 256-thread block... up to 16 waves)
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[k * 16 + wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double x = 0.0;
+      for (int w = 0; w < nw; ++w) x += sh[k * 16 + w];
+      v[k] = x;
+    }
+  }
+}
+
+// Returns true in thread 0 of the last block; partial sums of all blocks are
+// then visible and summed into out[0..NV).
+template <int NV>
+__device__ __forceinline__ void finish_reduction(const double (&v)[NV], double* part, int nblk, int blk,
+                                                 unsigned* cnt, double* out, bool* is_last) {
+  *is_last = false;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[k * nblk + blk] = v[k];
+    __threadfence();
+    const unsigned ticket = atomicAdd(cnt, 1u);
+    if (ticket == (unsigned)(nblk - 1)) {
+      __threadfence();
+      const volatile double* vp = part;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        double x = 0.0;
+        for (int b = 0; b < nblk; ++b) x += vp[k * nblk + b];
+        out[k] = x;
+      }
+      *cnt = 0u;
+      *is_last = true;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fine operator, matrix-free from the cell coefficient (FP64).  For node
+// (x, y) the cells around it are (x-1,y-1), (x,y-1), (x-1,y), (x,y).
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ double apply_fine(const double* __restrict__ a, int n, int x, int y, F U) {
+  const double a00 = a[(x - 1) * n + (y - 1)];
+  const double a10 = a[x * n + (y - 1)];
+  const double a01 = a[(x - 1) * n + y];
+  const double a11 = a[x * n + y];
+  double s = (2.0 / 3.0) * (a00 + a10 + a01 + a11) * U(x, y);
+  s -= (a10 + a11) * (1.0 / 6.0) * U(x + 1, y);
+  s -= (a00 + a01) * (1.0 / 6.0) * U(x - 1, y);
+  s -= (a01 + a11) * (1.0 / 6.0) * U(x, y + 1);
+  s -= (a00 + a10) * (1.0 / 6.0) * U(x, y - 1);
+  s -= a11 * (1.0 / 3.0) * U(x + 1, y + 1);
+  s -= a00 * (1.0 / 3.0) * U(x - 1, y - 1);
+  s -= a10 * (1.0 / 3.0) * U(x + 1, y - 1);
+  s -= a01 * (1.0 / 3.0) * U(x - 1, y + 1);
+  return s;
+}
+
+// r = b - A u over interior node slots.  b comes from the cell source
+// (mode 0: b_i = (h^2/4) sum of g over the four cells at node i) or from a
+// nodal array (mode 1).  u is nodal with boundary values; its interior
+// values are read from u_slot when given (else taken as zero).
+__global__ void k_residual(const double* __restrict__ a, int n, int mode, const double* __restrict__ src,
+                           const double* __restrict__ u_nodal, const double* __restrict__ u_slot,
+                           double* __restrict__ r) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  if (x == 0 || y == 0) {
+    r[id] = 0.0;
+    return;
+  }
+  const int s1 = n + 1;
+  double b;
+  if (mode == 0) {
+    const double h = 1.0 / n;
+    b = 0.25 * h * h *
+        (src[(x - 1) * n + (y - 1)] + src[x * n + (y - 1)] + src[(x - 1) * n + y] + src[x * n + y]);
+  } else {
+    b = src[x * s1 + y];
+  }
+  auto U = [&](int i, int j) -> double {
+    if (i == 0 || j == 0 || i == n || j == n) return u_nodal[i * s1 + j];
+    return u_slot ? u_slot[i * n + j] : 0.0;
+  };
+  r[id] = b - apply_fine(a, n, x, y, U);
+}
+
+// w = A p for an interior slot vector p (zero Dirichlet data).
+__global__ void k_apply_fine(const double* __restrict__ a, int n, const double* __restrict__ p,
+                             double* __restrict__ w) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  if (x == 0 || y == 0) {
+    w[id] = 0.0;
+    return;
+  }
+  auto U = [&](int i, int j) -> double {
+    if (i == 0 || j == 0 || i == n || j == n) return 0.0;
+    return p[i * n + j];
+  };
+  w[id] = apply_fine(a, n, x, y, U);
+}
+
+// Up to three dot products of FP64 slot vectors at once -> out[0..nv).
+__global__ __launch_bounds__(256) void k_dots(int len, int nv, const double* __restrict__ x0,
+                                              const double* __restrict__ y0, const double* __restrict__ x1,
+                                              const double* __restrict__ y1, const double* __restrict__ x2,
+                                              const double* __restrict__ y2, double* part, unsigned* cnt,
+                                              double* out) {
+  __shared__ double sh[3 * 16];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+    v[0] += x0[i] * y0[i];
+    if (nv > 1) v[1] += x1[i] * y1[i];
+    if (nv > 2) v[2] += x2[i] * y2[i];
+  }
+  block_sum<3>(v, sh);
+  bool last;
+  double res[3];
+  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last);
+  if (last) {
+    for (int k = 0; k < nv; ++k) out[k] = res[k];
+  }
+}
+
+// Outer flexible CG steps (scalars live on the device).
+//   alpha = (p, r) / (p, w);  u += alpha p;  r -= alpha w
+__global__ void k_outer_update(int len, const double* __restrict__ sc, double* __restrict__ u,
+                               double* __restrict__ r, const double* __restrict__ p,
+                               const double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double pw = sc[kSPW], pr = sc[kSPR];
+  const double alpha = (pw > 0.0) ? pr / pw : 0.0;
+  u[i] += alpha * p[i];
+  r[i] -= alpha * w[i];
+}
+
+//   beta = -(z, w) / (p, w);  p = z + beta p   (A-orthogonalise against the last direction)
+__global__ void k_outer_direction(int len, const double* __restrict__ sc, const double* __restrict__ z,
+                                  double* __restrict__ p, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double beta = 0.0;
+  if (!first) {
+    const double pw = sc[kSPW];
+    beta = (pw > 0.0) ? -sc[kSZW] / pw : 0.0;
+    p[i] = z[i] + beta * p[i];
+  } else {
+    p[i] = z[i];
+  }
+}
+
+// slot vector -> nodal interior (boundary entries untouched)
+__global__ void k_slots_to_nodal(int n, const double* __restrict__ s, double* __restrict__ u) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  if (x == 0 || y == 0) return;
+  u[x * (n + 1) + y] = s[id];
+}
+
+__global__ void k_fill(size_t len, double v, double* __restrict__ x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) x[i] = v;
+}
+
+template <typename T>
+__global__ void k_fill_t(size_t len, T* __restrict__ x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) x[i] = T(0);
+}
+
+template <typename TD, typename TS>
+__global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__ d) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) d[i] = TD(s[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Restriction g^(k-1)_i = sum_c R_{i,c} g^(k)_c (eq. g^(k) = R g^(k+1),
+// Section 4.7; Algorithm 2, line 15).  One thread per coarse slot; R is
+// entry-major (R[e][cell]) so consecutive threads read consecutive words.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ R, const T* __restrict__ gf, T* __restrict__ gc, int nk,
+                           int rho) {
+  const int nc = nk / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc * nc) return;
+  const int cx = i / nc, cy = i % nc;
+  const int rw = 2 * (2 * rho + 1);
+  const int ox = 2 * (cx - rho), oy = 2 * (cy - rho);
+  const size_t nc2 = (size_t)nc * nc;
+  const int bxl = max(0, -ox), bxh = min(rw - 1, nk - 1 - ox);
+  const int byl = max(0, -oy), byh = min(rw - 1, nk - 1 - oy);
+  T acc = T(0);
+  for (int bx = bxl; bx <= bxh; ++bx) {
+    const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
+    const T* gr = gf + (size_t)(ox + bx) * nk + oy;
+    for (int by = byl; by <= byh; ++by) acc += Rr[(size_t)by * nc2] * gr[by];
+  }
+  gc[i] = acc;
+}
+
+template <typename T>
+void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st) {
+  const int nc = L.nk / 2;
+  hipLaunchKernelGGL(k_restrict<T>, dim3((nc * nc + 255) / 256), dim3(256), 0, st, R, gf, gc, L.nk, L.rho);
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation and subband sum: v^(k) = R^(k,k-1) v^(k-1) + W^(k)T w^(k)
+// (Theorem 4.15; the subband gamblets are never formed, discussion of
+// Algorithm 1 in Section 5.2).  One thread per level-k slot, gathering the
+// restriction rows of the (2 rho + 1)^2 coarse slots whose patch covers it.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, const T* __restrict__ w,
+                          T* __restrict__ vf, int nk, int rho, int fine) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nk * nk) return;
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int fx = id / nk, fy = id % nk;
+  const int px = fx >> 1, py = fy >> 1;
+  const int d = 2 * (fx & 1) + (fy & 1);
+  const int rw = 2 * (2 * rho + 1);
+  T acc = T(0);
+  const int ixl = max(0, px - rho), ixh = min(nc - 1, px + rho);
+  const int iyl = max(0, py - rho), iyh = min(nc - 1, py + rho);
+  for (int ix = ixl; ix <= ixh; ++ix) {
+    const int bx = fx - 2 * (ix - rho);
+    for (int iy = iyl; iy <= iyh; ++iy) {
+      const int by = fy - 2 * (iy - rho);
+      const int i = ix * nc + iy;
+      acc += R[(size_t)(bx * rw + by) * nc2 + i] * vc[i];
+    }
+  }
+  const int tp = parent_type(fine != 0, px, py);
+  const int p = px * nc + py;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) acc += T(wcoef(tp, t, d)) * w[t * nc2 + p];
+  vf[id] = acc;
+}
+
+template <typename T>
+void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
+                    hipStream_t st) {
+  const int tot = L.nk * L.nk;
+  hipLaunchKernelGGL(k_prolong<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, w, vf, L.nk, L.rho,
+                     fine ? 1 : 0);
+}
+
+// Coarsest system A^(1) U^(1) = g^(1) (Algorithm 2, line 16) with the FP64
+// Cholesky factor computed at build time.
+template <typename T>
+__global__ void k_coarse_solve(const double* __restrict__ L1, const T* __restrict__ g1, T* __restrict__ v1) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double y[4];
+  for (int i = 0; i < 4; ++i) {
+    double v = (double)g1[i];
+    for (int k = 0; k < i; ++k) v -= L1[i * 4 + k] * y[k];
+    y[i] = v / L1[i * 4 + i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 4; ++k) v -= L1[k * 4 + i] * y[k];
+    y[i] = v / L1[i * 4 + i];
+  }
+  for (int i = 0; i < 4; ++i) v1[i] = T(y[i]);
+}
+
+template <typename T>
+void launch_coarse_solve(const double* L1, const T* g1, T* v1, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(64), 0, st, L1, g1, v1);
+}
+
+// ---------------------------------------------------------------------------
+// Subband systems B^(k) w^(k) = W^(k) g^(k) (eq. for w^(k), Section 4.7;
+// Algorithm 2, line 8), all levels in one grid.  Conjugate gradients
+// (Section 4.9) with a block-Jacobi preconditioner (inverse 3x3 parent
+// blocks).  Subband vectors are stored t-major: v[t * np^2 + parent].
+// The direction update is folded into the operator application using
+// B p_new = B z + beta B p_old, so each iteration takes two launches.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int find_level(const CGArgs<T>& A, int b) {
+  int l = 0;
+  while (l + 1 < A.nlev && b >= A.lv[l + 1].blk0) ++l;
+  return l;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
+  __shared__ double sh[16];
+  const int l = find_level(args, blockIdx.x);
+  const CGLev<T>& L = args.lv[l];
+  const int blk = blockIdx.x - L.blk0;
+  const int p = blk * 256 + threadIdx.x;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int nk = 2 * np;
+  double v[1] = {0.0};
+  if (p < np * np) {
+    const int px = p / np, py = p % np;
+    const int tp = parent_type(L.fine != 0, px, py);
+    T gch[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) gch[d] = L.g[(2 * px + (d >> 1)) * nk + 2 * py + (d & 1)];
+    T r[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      T acc = T(0);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) acc += T(wcoef(tp, t, d)) * gch[d];
+      r[t] = acc;
+    }
+    T z[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc += L.BJ[(i * 3 + j) * np2 + p] * r[j];
+      z[i] = acc;
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      L.x[t * np2 + p] = T(0);
+      L.r[t * np2 + p] = r[t];
+      L.z[t * np2 + p] = z[t];
+      L.p[t * np2 + p] = T(0);
+      L.q[t * np2 + p] = T(0);
+      v[0] += (double)(r[t] * z[t]);
+    }
+  }
+  block_sum<1>(v, sh);
+  bool last;
+  double res[1];
+  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  if (last) {
+    L.scal[kCRZ] = res[0];
+    L.scal[kCBETA] = 0.0;
+    L.scal[kCALPHA] = 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_spmv(CGArgs<T> args) {
+  __shared__ double sh[16];
+  const int l = find_level(args, blockIdx.x);
+  const CGLev<T>& L = args.lv[l];
+  const int blk = blockIdx.x - L.blk0;
+  const int p = blk * 256 + threadIdx.x;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int t = L.t, TT = 2 * L.t + 1;
+  double v[1] = {0.0};
+  if (p < np * np) {
+    const int px = p / np, py = p % np;
+    const T beta = T(L.scal[kCBETA]);
+    T y[3] = {T(0), T(0), T(0)};
+    const int oxl = max(0, t - px), oxh = min(TT - 1, np - 1 - px + t);
+    const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
+    for (int ox = oxl; ox <= oxh; ++ox) {
+      for (int oy = oyl; oy <= oyh; ++oy) {
+        const int qn = (px + ox - t) * np + (py + oy - t);
+        const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
+        const T* Bb = L.B + (size_t)(ox * TT + oy) * 9 * np2 + p;
+        y[0] += Bb[0] * z0 + Bb[np2] * z1 + Bb[2 * np2] * z2;
+        y[1] += Bb[3 * np2] * z0 + Bb[4 * np2] * z1 + Bb[5 * np2] * z2;
+        y[2] += Bb[6 * np2] * z0 + Bb[7 * np2] * z1 + Bb[8 * np2] * z2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T qv = y[i] + beta * L.q[i * np2 + p];
+      const T pv = L.z[i * np2 + p] + beta * L.p[i * np2 + p];
+      L.q[i * np2 + p] = qv;
+      L.p[i * np2 + p] = pv;
+      v[0] += (double)(pv * qv);
+    }
+  }
+  block_sum<1>(v, sh);
+  bool last;
+  double res[1];
+  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  if (last) {
+    const double pq = res[0];
+    L.scal[kCPQ] = pq;
+    L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args) {
+  __shared__ double sh[16];
+  const int l = find_level(args, blockIdx.x);
+  const CGLev<T>& L = args.lv[l];
+  const int blk = blockIdx.x - L.blk0;
+  const int p = blk * 256 + threadIdx.x;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  double v[1] = {0.0};
+  if (p < np * np) {
+    const T alpha = T(L.scal[kCALPHA]);
+    T r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      L.x[i * np2 + p] += alpha * L.p[i * np2 + p];
+      r[i] = L.r[i * np2 + p] - alpha * L.q[i * np2 + p];
+      L.r[i * np2 + p] = r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc += L.BJ[(i * 3 + j) * np2 + p] * r[j];
+      L.z[i * np2 + p] = acc;
+      v[0] += (double)(acc * r[i]);
+    }
+  }
+  block_sum<1>(v, sh);
+  bool last;
+  double res[1];
+  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  if (last) {
+    const double rz_new = res[0];
+    const double rz = L.scal[kCRZ];
+    L.scal[kCBETA] = (rz > 0.0) ? rz_new / rz : 0.0;
+    L.scal[kCRZ] = rz_new;
+  }
+}
+
+template <typename T>
+void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks), dim3(256), 0, st, a);
+}
+template <typename T>
+void launch_cg_iter(const CGArgs<T>& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gradient per cell (not in the paper): dJ/dlog a_e = -a_e lam_e^T K u_e
+// and dJ/dg_e = (h^2/4) sum of lam at the cell's corners, with the unit
+// bilinear element stiffness K (local order (0,0),(1,0),(0,1),(1,1)).
+// ---------------------------------------------------------------------------
+__global__ void k_cell_gradient(const double* __restrict__ a, int n, const double* __restrict__ u,
+                                const double* __restrict__ lam, double* __restrict__ dloga,
+                                double* __restrict__ dg) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int ex = id / n, ey = id % n;
+  const int s1 = n + 1;
+  const int nd[4] = {ex * s1 + ey, (ex + 1) * s1 + ey, ex * s1 + ey + 1, (ex + 1) * s1 + ey + 1};
+  double ue[4], le[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ue[i] = u[nd[i]];
+    le[i] = lam[nd[i]];
+  }
+  const double K[4][4] = {{4.0, -1.0, -1.0, -2.0}, {-1.0, 4.0, -2.0, -1.0}, {-1.0, -2.0, 4.0, -1.0},
+                          {-2.0, -1.0, -1.0, 4.0}};
+  double e = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double ku = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ku += K[i][j] * ue[j];
+    e += le[i] * ku;
+  }
+  dloga[id] = -a[id] * e * (1.0 / 6.0);
+  if (dg) {
+    const double h = 1.0 / n;
+    dg[id] = 0.25 * h * h * (le[0] + le[1] + le[2] + le[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launch helpers for the non-templated kernels.
+// ---------------------------------------------------------------------------
+void launch_residual(const double* a, int n, int mode, const double* src, const double* u_nodal,
+                     const double* u_slot, double* r, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, mode, src, u_nodal, u_slot,
+                     r);
+}
+void launch_apply_fine(const double* a, int n, const double* p, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_apply_fine, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, p, w);
+}
+void launch_dots(int len, int nv, const double* x0, const double* y0, const double* x1, const double* y1,
+                 const double* x2, const double* y2, double* part, unsigned* cnt, double* out,
+                 hipStream_t st) {
+  int nb = (len + 255) / 256;
+  if (nb > kDotBlocks) nb = kDotBlocks;
+  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(256), 0, st, len, nv, x0, y0, x1, y1, x2, y2, part, cnt, out);
+}
+void launch_outer_update(int len, const double* sc, double* u, double* r, const double* p, const double* w,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_outer_update, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, u, r, p, w);
+}
+void launch_outer_direction(int len, const double* sc, const double* z, double* p, int first,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_outer_direction, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, z, p, first);
+}
+void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st) {
+  hipLaunchKernelGGL(k_slots_to_nodal, dim3((n * n + 255) / 256), dim3(256), 0, st, n, s, u);
+}
+void launch_fill(size_t len, double v, double* x, hipStream_t st) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, v, x);
+}
+template <typename T>
+void launch_zero(size_t len, T* x, hipStream_t st) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_fill_t<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, x);
+}
+template <typename TD, typename TS>
+void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st) {
+  if (len == 0) return;
+  hipLaunchKernelGGL((k_convert<TD, TS>), dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, s, d);
+}
+void launch_cell_gradient(const double* a, int n, const double* u, const double* lam, double* dloga,
+                          double* dg, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_gradient, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, u, lam, dloga, dg);
+}
+
+#define GBL_INST(T)                                                                                      \
+  template void launch_restrict<T>(const LevelGeom&, const T*, const T*, T*, hipStream_t);              \
+  template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t); \
+  template void launch_coarse_solve<T>(const double*, const T*, T*, hipStream_t);                       \
+  template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t);                                  \
+  template void launch_cg_iter<T>(const CGArgs<T>&, int, hipStream_t);                                  \
+  template void launch_zero<T>(size_t, T*, hipStream_t);
+GBL_INST(float)
+GBL_INST(double)
+#undef GBL_INST
+template void launch_convert<float, double>(size_t, const double*, float*, hipStream_t);
+template void launch_convert<double, float>(size_t, const float*, double*, hipStream_t);
+template void launch_convert<double, double>(size_t, const double*, double*, hipStream_t);
+
+}  // namespace gbl

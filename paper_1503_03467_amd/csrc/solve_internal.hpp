@@ -1,0 +1,79 @@
+// Solve-phase structures shared by the host driver and kernels_solve.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+#include "gamblet_internal.hpp"
+
+namespace gbl {
+
+// Outer (FP64) scalar slots.
+constexpr int kSPW = 0;   // (p, A p)
+constexpr int kSPR = 1;   // (p, r)
+constexpr int kSZZ = 2;   // (z, z)
+constexpr int kSUU = 3;   // (u, u)
+constexpr int kSZW = 4;   // (z, A p)
+constexpr int kSRR = 5;   // (r, r)
+constexpr int kSBB = 6;   // (b, b)
+constexpr int kNumOuterScalars = 8;
+constexpr int kDotBlocks = 512;
+
+// Per-level CG scalar slots.
+constexpr int kCRZ = 0;
+constexpr int kCPQ = 1;
+constexpr int kCALPHA = 2;
+constexpr int kCBETA = 3;
+constexpr int kNumCGScalars = 4;
+
+template <typename T>
+struct CGLev {
+  const T* B;      // B^(k), offset-major
+  const T* BJ;     // inverse 3x3 diagonal blocks
+  const T* g;      // level-k right-hand side g^(k) (slots)
+  T* x;            // w^(k)
+  T* r;
+  T* z;
+  T* p;
+  T* q;            // B p
+  double* scal;    // kNumCGScalars
+  double* part;    // one partial sum per block
+  unsigned* cnt;   // reduction ticket
+  int np;          // parents per dimension (n_{k-1})
+  int t;           // parent-stencil half-width
+  int fine;        // k == q
+  int blk0;        // first block of this level in the grid
+  int nblk;        // blocks of this level
+};
+
+template <typename T>
+struct CGArgs {
+  CGLev<T> lv[kMaxLevels];
+  int nlev;
+};
+
+template <typename T>
+void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st);
+template <typename T>
+void launch_cg_iter(const CGArgs<T>& a, int nblocks, hipStream_t st);
+template <typename T>
+void launch_zero(size_t len, T* x, hipStream_t st);
+template <typename TD, typename TS>
+void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st);
+
+void launch_residual(const double* a, int n, int mode, const double* src, const double* u_nodal,
+                     const double* u_slot, double* r, hipStream_t st);
+void launch_apply_fine(const double* a, int n, const double* p, double* w, hipStream_t st);
+void launch_dots(int len, int nv, const double* x0, const double* y0, const double* x1, const double* y1,
+                 const double* x2, const double* y2, double* part, unsigned* cnt, double* out,
+                 hipStream_t st);
+void launch_outer_update(int len, const double* sc, double* u, double* r, const double* p, const double* w,
+                         hipStream_t st);
+void launch_outer_direction(int len, const double* sc, const double* z, double* p, int first,
+                            hipStream_t st);
+void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st);
+void launch_fill(size_t len, double v, double* x, hipStream_t st);
+void launch_cell_gradient(const double* a, int n, const double* u, const double* lam, double* dloga,
+                          double* dg, hipStream_t st);
+
+}  // namespace gbl

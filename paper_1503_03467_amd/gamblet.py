@@ -1,0 +1,237 @@
+"""Thin ctypes binding of ``libgamblet.so`` (the C ABI of ``include/gamblet.h``).
+
+Argument marshalling only: device memory and streams come from PyTorch, every
+step of the hierarchy build and of the solve runs in the library's HIP
+kernels.  There is no CPU fallback; a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgamblet.so")
+
+GBL_OK, GBL_EINVAL, GBL_ENOTSPD, GBL_ENOCONV, GBL_ENOMEM, GBL_EHIP = 0, -1, -2, -3, -4, -5
+GBL_FP64, GBL_MIXED = 0, 1
+_STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "ENOMEM", -5: "EHIP"}
+
+
+class GblOpts(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+
+
+class GblSolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_update", ctypes.c_double), ("rel_residual", ctypes.c_double)]
+
+
+class GblLevelDesc(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("nk", ctypes.c_int), ("s", ctypes.c_int), ("t", ctypes.c_int),
+                ("rw", ctypes.c_int), ("rho", ctypes.c_int), ("elem_bytes", ctypes.c_int),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("R", ctypes.c_void_p)]
+
+
+class GambletError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1503_03467_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.gbl_version.restype = i
+        L.gbl_default_opts.argtypes = [ctypes.POINTER(GblOpts)]
+        L.gbl_workspace_bytes.argtypes = [i, ctypes.POINTER(GblOpts), ctypes.POINTER(ctypes.c_size_t)]
+        L.gbl_build.argtypes = [ctypes.POINTER(vp), i, vp, ctypes.POINTER(GblOpts), vp, ctypes.c_size_t, vp]
+        L.gbl_solve.argtypes = [vp, i, vp, vp, ctypes.POINTER(GblSolveInfo), vp]
+        L.gbl_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(GblSolveInfo), vp]
+        L.gbl_level_layout.argtypes = [vp, i, ctypes.POINTER(GblLevelDesc)]
+        L.gbl_destroy.argtypes = [vp]
+        L.gbl_last_error.argtypes = [vp]
+        L.gbl_last_error.restype = ctypes.c_char_p
+        for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
+                     "gbl_level_layout", "gbl_destroy"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _check(code: int, ctx=None):
+    if code != GBL_OK:
+        msg = lib().gbl_last_error(ctx).decode()
+        raise GambletError(code, msg)
+
+
+def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 60,
+              inner_iters: int = 24, max_rhs: int = 1) -> GblOpts:
+    o = GblOpts()
+    _check(lib().gbl_default_opts(ctypes.byref(o)))
+    o.rho = int(rho)
+    o.precision = GBL_FP64 if precision in ("fp64", "f64", "double") else GBL_MIXED
+    o.rtol = float(rtol)
+    o.max_outer = int(max_outer)
+    o.inner_iters = int(inner_iters)
+    o.max_rhs = int(max_rhs)
+    return o
+
+
+def workspace_bytes(q: int, opts: GblOpts) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().gbl_workspace_bytes(int(q), ctypes.byref(opts), ctypes.byref(b)))
+    return int(b.value)
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require(t: torch.Tensor, shape, name):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass
+class SolveInfo:
+    outer_iters: int
+    status: int
+    rel_update: float
+    rel_residual: float
+
+
+class Hierarchy:
+    """Localized gamblet hierarchy of one coefficient field, built on the GPU."""
+
+    def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
+                 max_outer: int = 60, inner_iters: int = 24, max_rhs: int = 1):
+        n = a.shape[0]
+        q = n.bit_length() - 1
+        if n != (1 << q) or q < 2:
+            raise ValueError("a must be [2^q][2^q] with q >= 2")
+        _require(a, (n, n), "a")
+        self.q, self.n, self.device = q, n, a.device
+        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs)
+        self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
+        self.ctx = ctypes.c_void_p()
+        with torch.cuda.device(a.device):
+            _check(lib().gbl_build(ctypes.byref(self.ctx), q, ctypes.c_void_p(a.data_ptr()),
+                                   ctypes.byref(self.opts), ctypes.c_void_p(self.ws.data_ptr()),
+                                   ctypes.c_size_t(self.ws.numel()), _stream_ptr(a.device)))
+        self.last_info: SolveInfo | None = None
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().gbl_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, g: torch.Tensor, u_boundary: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+        """Solve for cell sources ``g`` ([n][n] or [nrhs][n][n]); returns nodal u ([.., n+1, n+1])."""
+        single = g.dim() == 2
+        gg = g.unsqueeze(0) if single else g
+        nrhs = gg.shape[0]
+        _require(gg, (nrhs, self.n, self.n), "g")
+        m = self.n + 1
+        if u_boundary is None:
+            u = torch.zeros((nrhs, m, m), dtype=torch.float64, device=self.device)
+        else:
+            u = u_boundary.reshape(-1, m, m).expand(nrhs, m, m).clone().contiguous()
+        info = GblSolveInfo()
+        with torch.cuda.device(self.device):
+            code = lib().gbl_solve(self.ctx, nrhs, ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                   ctypes.byref(info), _stream_ptr(self.device))
+        self.last_info = SolveInfo(info.outer_iters, info.status, info.rel_update, info.rel_residual)
+        if check or code not in (GBL_OK, GBL_ENOCONV):
+            _check(code, self.ctx)
+        return u[0] if single else u
+
+    def adjoint(self, u: torch.Tensor, dJdu: torch.Tensor, check: bool = True):
+        """Return (dJ/dlog a, dJ/dg, lambda) for the solution u and nodal gradient dJ/du."""
+        single = u.dim() == 2
+        uu = u.unsqueeze(0) if single else u
+        dd = dJdu.unsqueeze(0) if single else dJdu
+        nrhs = uu.shape[0]
+        m = self.n + 1
+        _require(uu, (nrhs, m, m), "u")
+        _require(dd, (nrhs, m, m), "dJdu")
+        dloga = torch.empty((nrhs, self.n, self.n), dtype=torch.float64, device=self.device)
+        dg = torch.empty_like(dloga)
+        lam = torch.empty((nrhs, m, m), dtype=torch.float64, device=self.device)
+        info = GblSolveInfo()
+        with torch.cuda.device(self.device):
+            code = lib().gbl_adjoint(self.ctx, nrhs, ctypes.c_void_p(uu.data_ptr()), ctypes.c_void_p(dd.data_ptr()),
+                                     ctypes.c_void_p(dloga.data_ptr()), ctypes.c_void_p(dg.data_ptr()),
+                                     ctypes.c_void_p(lam.data_ptr()), ctypes.byref(info), _stream_ptr(self.device))
+        self.last_info = SolveInfo(info.outer_iters, info.status, info.rel_update, info.rel_residual)
+        if check or code not in (GBL_OK, GBL_ENOCONV):
+            _check(code, self.ctx)
+        if single:
+            return dloga[0], dg[0], lam[0]
+        return dloga, dg, lam
+
+    def level(self, k: int) -> dict:
+        """Device views of A^(k), B^(k), R^(k-1,k) (offset-major layouts of ``gamblet.h``)."""
+        d = GblLevelDesc()
+        _check(lib().gbl_level_layout(self.ctx, int(k), ctypes.byref(d)), self.ctx)
+        dt = torch.float64 if d.elem_bytes == 8 else torch.float32
+        base = self.ws.data_ptr()
+
+        def view(ptr, count):
+            off = ptr - base
+            return self.ws[off: off + count * d.elem_bytes].view(dt)
+
+        nk = d.nk
+        S = 2 * d.s + 1
+        out = {"k": d.k, "nk": nk, "s": d.s, "t": d.t, "rw": d.rw, "rho": d.rho,
+               "A": view(d.A, S * S * nk * nk).view(S, S, nk, nk)}
+        if k >= 2:
+            np_ = nk // 2
+            T = 2 * d.t + 1
+            out["B"] = view(d.B, T * T * 9 * np_ * np_).view(T, T, 3, 3, np_, np_)
+            out["R"] = view(d.R, d.rw * d.rw * np_ * np_).view(d.rw, d.rw, np_, np_)
+        return out
+
+
+class GambletSolve(torch.autograd.Function):
+    """u = solve(exp(log_a), g) with a hand-written adjoint.
+
+    Forward builds the hierarchy for ``a = exp(log_a)`` and solves; backward
+    reuses the same hierarchy for the symmetric adjoint system and returns
+    dJ/dlog a and dJ/dg per cell.
+    """
+
+    @staticmethod
+    def forward(ctx, log_a, g, rho=3, precision="mixed", rtol=1e-8):
+        a = torch.exp(log_a.detach()).contiguous()
+        H = Hierarchy(a, rho=rho, precision=precision, rtol=rtol, max_rhs=g.shape[0] if g.dim() == 3 else 1)
+        u = H.solve(g.detach().contiguous())
+        ctx.H = H
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        (u,) = ctx.saved_tensors
+        dloga, dg, _ = ctx.H.adjoint(u, grad_u.contiguous())
+        ctx.H.close()
+        return dloga, dg, None, None, None

@@ -1,0 +1,83 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/gamblet.h, and validates arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "gamblet.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gbl_\w+)\s*\(", src, flags=re.M)))
+
+
+def _lib():
+    import paper_1503_03467_amd as P
+    return P, P.lib()
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 8
+    _, L = _lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_version_and_defaults():
+    P, L = _lib()
+    assert L.gbl_version() == 10000
+    o = P.make_opts()
+    assert o.rho == 3 and o.precision == 1 and o.rtol == 1e-8
+
+
+@pytest.mark.parametrize("q", [1, 13, -2])
+def test_bad_q_rejected(q):
+    P, _ = _lib()
+    with pytest.raises(P.GambletError) as e:
+        P.workspace_bytes(q, P.make_opts())
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("field,value", [("rho", 0), ("rho", 5), ("precision", 7), ("rtol", 0.0),
+                                         ("rtol", 2.0), ("max_outer", 0), ("max_rhs", 0)])
+def test_bad_options_rejected(field, value):
+    P, _ = _lib()
+    o = P.make_opts()
+    setattr(o, field, value)
+    with pytest.raises(P.GambletError):
+        P.workspace_bytes(6, o)
+
+
+def test_workspace_grows_with_q_and_precision():
+    P, _ = _lib()
+    sizes = [P.workspace_bytes(q, P.make_opts(precision="mixed")) for q in range(2, 11)]
+    assert all(b > a for a, b in zip(sizes, sizes[1:]))
+    assert P.workspace_bytes(9, P.make_opts(precision="fp64")) > P.workspace_bytes(9, P.make_opts())
+
+
+def test_null_arguments_rejected():
+    P, L = _lib()
+    o = P.make_opts()
+    ctx = ctypes.c_void_p()
+    assert L.gbl_build(ctypes.byref(ctx), 6, None, ctypes.byref(o), ctypes.c_void_p(16), 1 << 30, None) == -1
+    assert b"a_dev" in L.gbl_last_error(None)
+    assert L.gbl_build(ctypes.byref(ctx), 6, ctypes.c_void_p(16), ctypes.byref(o), None, 1 << 30, None) == -1
+    assert L.gbl_build(None, 6, ctypes.c_void_p(16), ctypes.byref(o), ctypes.c_void_p(16), 1 << 30, None) == -1
+    assert L.gbl_solve(None, 1, None, None, None, None) == -1
+    assert L.gbl_destroy(None) == 0
+
+
+def test_short_workspace_rejected_before_any_device_work():
+    P, L = _lib()
+    o = P.make_opts()
+    need = P.workspace_bytes(6, o)
+    ctx = ctypes.c_void_p()
+    rc = L.gbl_build(ctypes.byref(ctx), 6, ctypes.c_void_p(16), ctypes.byref(o), ctypes.c_void_p(16),
+                     need - 1, None)
+    assert rc == -4
+    assert b"workspace" in L.gbl_last_error(None)

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP hierarchy and solve against the FP64 CPU oracle.
+
+Every test calls the library through its C ABI (ctypes binding) on seeded
+inputs from ``synthetic`` and compares element by element with ``oracle``.
+Tolerances: FP64 path 1e-10 relative (hierarchy Frobenius per level, solution
+l2), mixed path 1e-8 relative after refinement, gradients 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import fem
+from oracle import gamblets as G
+from tests.gpu_layout import (block_stencil_to_matrix, restriction_to_matrix, stencil_to_matrix)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_1503_03467_amd as P
+    return P
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _relerr(x, y):
+    return float(np.linalg.norm(np.ravel(x) - np.ravel(y)) / max(np.linalg.norm(np.ravel(y)), 1e-300))
+
+
+def _print_case(**kw):
+    print("CASE", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("q,rho,sigma", [(4, 1, 1.0), (5, 2, 2.0), (6, 3, 2.0), (5, 4, 1.0), (3, 3, 1.0)])
+def test_hierarchy_levels_match_oracle_fp64(q, rho, sigma):
+    _print_case(test="hierarchy", q=q, rho=rho, sigma=sigma)
+    pr = S.rough_problem(q, sigma, 21)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    ref = G.localized_hierarchy(fe.A, tree, rho)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision="fp64")
+    torch.cuda.synchronize()
+    for k in range(q, 0, -1):
+        lv = H.level(k)
+        A_gpu = stencil_to_matrix(lv["A"].cpu().numpy(), q, k, tree.size(k))
+        A_ref = ref.levels[k].A
+        err = abs(A_gpu - A_ref).max() / abs(A_ref).max()
+        assert err < 1e-10, (k, "A", err)
+        if k >= 2:
+            B_gpu = block_stencil_to_matrix(lv["B"].cpu().numpy(), tree, k)
+            B_ref = ref.levels[k].B
+            err = abs(B_gpu - B_ref).max() / abs(B_ref).max()
+            assert err < 1e-10, (k, "B", err)
+            R_gpu = restriction_to_matrix(lv["R"].cpu().numpy(), lv["rho"], q, k, tree.size(k))
+            R_ref = ref.levels[k].R
+            err = abs(R_gpu - R_ref).max() / abs(R_ref).max()
+            assert err < 1e-10, (k, "R", err)
+    H.close()
+
+
+@pytest.mark.parametrize("q,rho,sigma,prec,tol", [
+    (6, 3, 1.0, "fp64", 1e-10), (6, 3, 2.0, "fp64", 1e-10), (6, 3, 2.0, "mixed", 1e-8),
+    (7, 2, 2.0, "mixed", 1e-8), (5, 1, 1.0, "fp64", 1e-10), (2, 3, 1.0, "fp64", 1e-10),
+])
+def test_solve_matches_direct(q, rho, sigma, prec, tol):
+    _print_case(test="solve", q=q, rho=rho, sigma=sigma, prec=prec)
+    pr = S.rough_problem(q, sigma, 22, nrhs=2)
+    u_ref = fem.solve(pr.a, pr.g)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec, rtol=tol, max_rhs=2)
+    u = H.solve(_dev(pr.g)).cpu().numpy()
+    info = H.last_info
+    for r in range(2):
+        err = _relerr(u[r][1:-1, 1:-1], u_ref[r][1:-1, 1:-1])
+        assert err < tol, (r, err, info)
+    H.close()
+
+
+def test_dirichlet_lifting():
+    _print_case(test="dirichlet")
+    q = 5
+    n = 1 << q
+    pr = S.rough_problem(q, 1.0, 23)
+    xs = np.arange(n + 1) / n
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    ub = np.sin(3 * X) + Y * Y
+    u_ref = fem.solve(pr.a, pr.g[0], ub)
+    H = _P().Hierarchy(_dev(pr.a), rho=2, precision="fp64", rtol=1e-11)
+    u = H.solve(_dev(pr.g[0]), u_boundary=_dev(ub)).cpu().numpy()
+    assert _relerr(u, u_ref) < 1e-10
+    np.testing.assert_array_equal(u[0, :], ub[0, :])
+    np.testing.assert_array_equal(u[:, -1], ub[:, -1])
+    H.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-7), ("mixed", 1e-5)])
+def test_adjoint_gradient_matches_oracle(prec, tol):
+    _print_case(test="adjoint", prec=prec)
+    pr = S.adjoint_problem(q=6, tag=31)
+    u_obs = fem.solve(pr.extra["a_obs"], pr.g[0])
+    _, J, ga_ref, gg_ref = fem.adjoint(pr.a, pr.g[0], u_obs[1:-1, 1:-1].ravel())
+    H = _P().Hierarchy(_dev(pr.a), rho=3, precision=prec, rtol=1e-10 if prec == "fp64" else 1e-8)
+    u = H.solve(_dev(pr.g[0]))
+    dJdu = (u - _dev(u_obs)).contiguous()
+    ga, gg, lam = H.adjoint(u, dJdu)
+    assert _relerr(ga.cpu().numpy(), ga_ref) < tol
+    assert _relerr(gg.cpu().numpy(), gg_ref) < tol
+    H.close()
+
+
+def test_autograd_function():
+    _print_case(test="autograd")
+    P = _P()
+    pr = S.adjoint_problem(q=5, tag=32)
+    u_obs = fem.solve(pr.extra["a_obs"], pr.g[0])
+    log_a = _dev(np.log(pr.a)).requires_grad_(True)
+    g = _dev(pr.g[0]).requires_grad_(True)
+    u = P.GambletSolve.apply(log_a, g, 3, "fp64", 1e-11)
+    J = 0.5 * ((u - _dev(u_obs)) ** 2).sum()
+    J.backward()
+    _, J_ref, ga_ref, gg_ref = fem.adjoint(pr.a, pr.g[0], u_obs[1:-1, 1:-1].ravel())
+    assert abs(J.item() - J_ref) <= 1e-9 * abs(J_ref)
+    assert _relerr(log_a.grad.cpu().numpy(), ga_ref) < 1e-7
+    assert _relerr(g.grad.cpu().numpy(), gg_ref) < 1e-7
+
+
+def test_bad_coefficient_is_rejected():
+    _print_case(test="bad_a")
+    P = _P()
+    a = np.ones((16, 16))
+    a[3, 4] = -1.0
+    with pytest.raises(P.GambletError) as e:
+        P.Hierarchy(_dev(a), rho=2)
+    assert e.value.code == -1
+    a[3, 4] = np.nan
+    with pytest.raises(P.GambletError):
+        P.Hierarchy(_dev(a), rho=2)
+
+
+def test_no_convergence_is_reported():
+    _print_case(test="noconv")
+    P = _P()
+    pr = S.rough_problem(5, 2.0, 24)
+    H = P.Hierarchy(_dev(pr.a), rho=1, precision="mixed", rtol=1e-14, max_outer=1, inner_iters=1)
+    u = H.solve(_dev(pr.g[0]), check=False)
+    assert H.last_info.status == -3
+    assert torch.isfinite(u).all()
+    H.close()
