@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Throughput of the gamblet hierarchy build + solve on one MI355X.
+
+One step = one pass of the whole hot path on the 512 x 512-cell rough
+problem (q = 9, 261,121 interior DOF, lognormal product coefficient with
+sigma = 2, N(0,1) cell source, patch radius 3): build the localized
+hierarchy from the coefficient (assembly, subband operators, patch solves,
+restrictions, Galerkin coarsening) and solve to a relative error of 1e-8
+(flexible CG on the FP64 fine residual, subband solves in FP32).  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64 or unpacked FP32 FMA)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--inner-iters", type=int, default=24)
+    ap.add_argument("--inner-iters-coarse", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
+    return ap.parse_args()
+
+
+def level_geometry(H):
+    return {k: H.level(k) for k in range(1, H.q + 1)}
+
+
+def kernel_work(name, geo, q, elem):
+    """Algorithmic bytes (HBM-bound classes) or flops (arithmetic-bound) summed over one
+    build (build kernels) or one launch (solve kernels).  Returns (kind, amount)."""
+    if name == "patch_solve":
+        fl = 0.0
+        for k in range(2, q + 1):
+            g = geo[k]
+            nc = g["nk"] // 2
+            rho = g["rho"]
+            import numpy as np
+            w = np.minimum(np.arange(nc) + rho, nc - 1) - np.maximum(np.arange(nc) - rho, 0) + 1
+            p = 3.0 * np.outer(w, w)
+            fl += float((p ** 3 / 3.0 + 2.0 * p ** 2).sum())
+        return "flops", fl
+    if name == "galerkin":
+        fl = 0.0
+        for k in range(2, q + 1):
+            g, c = geo[k], geo[k - 1]
+            nc = g["nk"] // 2
+            Sk = 2 * g["s"] + 1
+            Sc = 2 * c["s"] + 1
+            fl += 2.0 * nc * nc * g["rw"] ** 2 * (Sk * Sk + Sc * Sc)
+        return "flops", fl
+    if name in ("cg_spmv", "cg_update", "cg_init"):
+        by = 0.0
+        for k in range(2, q + 1):
+            g = geo[k]
+            np2 = (g["nk"] // 2) ** 2
+            T = 2 * g["t"] + 1
+            if name == "cg_spmv":
+                # B blocks, z once, q and p read + written
+                by += elem * np2 * (9 * T * T + 3 + 12)
+            elif name == "cg_update":
+                # x rw, p, r rw, q, BJ, z written
+                by += elem * np2 * (6 + 3 + 6 + 3 + 9 + 3)
+            else:
+                by += elem * np2 * (4 + 9 + 15)
+        return "bytes", by
+    if name in ("restrict", "prolong"):
+        by = 0.0
+        for k in range(2, q + 1):
+            g = geo[k]
+            nc2 = (g["nk"] // 2) ** 2
+            nk2 = g["nk"] ** 2
+            by += elem * (g["rw"] ** 2 * nc2 + nk2 + nc2 + (3 * nc2 if name == "prolong" else 0))
+        return "bytes", by
+    if name == "fine_apply":
+        n2 = geo[q]["nk"] ** 2
+        return "bytes", 8.0 * 3 * n2
+    if name == "subband_operator":
+        by = 0.0
+        for k in range(2, q + 1):
+            g = geo[k]
+            S = 2 * g["s"] + 1
+            T = 2 * g["t"] + 1
+            by += elem * (S * S * g["nk"] ** 2 + (9 * T * T + 9) * (g["nk"] // 2) ** 2)
+        return "bytes", by
+    return "bytes", 0.0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1503_03467_amd as P
+    import synthetic as S
+
+    dev = torch.device("cuda:0")
+    pr = S.q9_rough_problem()
+    q, dof = pr.q, pr.dof
+    a = torch.as_tensor(pr.a, device=dev)
+    g = torch.as_tensor(pr.g[0], device=dev)
+    torch.cuda.synchronize()
+
+    def step(prec):
+        H = P.Hierarchy(a, rho=pr.rho, precision=prec, rtol=args.rtol, inner_iters=args.inner_iters,
+                        inner_iters_coarse=args.inner_iters_coarse)
+        u = H.solve(g, check=False)
+        info = H.last_info
+        return H, u, info
+
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    # warm-up with every kernel class timed, to find the dominant one
+    P.profile_reset()
+    P.profile_enable("all")
+    for _ in range(max(1, args.warmup)):
+        H, u, info = step(args.precision)
+        geo = level_geometry(H)
+        H.close()
+    torch.cuda.synchronize()
+    prof_all = P.profile_read()
+    P.profile_enable(None)
+    P.profile_reset()
+    dominant = max(prof_all, key=lambda k: prof_all[k][0])
+
+    # timed region: only the dominant class is bracketed by events
+    P.profile_enable([dominant])
+    print(f"# timed {args.steps} steps (events on {dominant})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        H, u, info = step(args.precision)
+        infos.append(info)
+        H.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.profile_enable(None)
+    dom_ms, dom_launches = P.profile_read()[dominant]
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = dof / (ms_per_step * 1e-3)
+
+    elem = 4 if args.precision == "mixed" else 8
+    kind, work = kernel_work(dominant, geo, q, elem)
+    build_kernel = dominant in ("patch_solve", "galerkin", "subband_operator", "assemble")
+    launches_per_unit = (q - 1) if build_kernel else 1
+    per_launch_work = work / launches_per_unit
+    avg_launch_ms = dom_ms / max(dom_launches, 1)
+    if kind == "flops":
+        achieved = per_launch_work / (avg_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / VALU_FMA_PEAK_TFLOPS, "traffic": None}
+    else:
+        achieved = per_launch_work / (avg_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": dominant, "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_launches / args.steps,
+                 "algorithmic_per_launch": per_launch_work})
+
+    # accuracy of the timed configuration against the CPU oracle's direct solve
+    extras = {}
+    print("# oracle reference solve", file=sys.stderr, flush=True)
+    from oracle import fem
+    t2 = time.perf_counter()
+    fe = fem.assemble(pr.a)
+    b = fem.load_cellwise(pr.g[0], fe.h)
+    u_ref = fem.DirectSolver(fe.A).solve(b)
+    t_oracle = time.perf_counter() - t2
+    u_int = u.cpu().numpy()[1:-1, 1:-1].ravel()
+    rel_err = float(np.linalg.norm(u_int - u_ref) / np.linalg.norm(u_ref))
+    extras["rel_err_vs_oracle"] = rel_err
+    extras["outer_iters"] = max(i.outer_iters for i in infos)
+    extras["profile_warmup_ms_per_step"] = {k: v[0] / max(1, args.warmup) for k, v in prof_all.items() if v[1]}
+
+    if not args.no_extras:
+        # plain FP64 GPU path at the same accuracy
+        print("# fp64 path", file=sys.stderr, flush=True)
+        H, u64, _ = step("fp64")
+        H.close()
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        n64 = 2
+        for _ in range(n64):
+            H, u64, info64 = step("fp64")
+            H.close()
+        torch.cuda.synchronize()
+        extras["fp64_ms_per_step"] = (time.perf_counter() - tt) * 1e3 / n64
+        extras["fp64_rel_err_vs_oracle"] = float(
+            np.linalg.norm(u64.cpu().numpy()[1:-1, 1:-1].ravel() - u_ref) / np.linalg.norm(u_ref))
+        extras["mixed_speedup_vs_fp64"] = extras["fp64_ms_per_step"] / ms_per_step
+        # adjoint gradient of J = 1/2 |u - u_obs|^2 through the same hierarchy
+        print("# adjoint", file=sys.stderr, flush=True)
+        a_obs = torch.as_tensor(S.product_field(pr.n) * S.lognormal_factor(pr.n, 1.0, S.rng(pr.tag, 0, S.KIND_OBS)),
+                                device=dev)
+        Hobs = P.Hierarchy(a_obs, rho=pr.rho, precision="mixed", rtol=args.rtol)
+        u_obs = Hobs.solve(g)
+        Hobs.close()
+        H, u, _ = step(args.precision)
+        dJdu = (u - u_obs).contiguous()
+        H.adjoint(u, dJdu, check=False)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        nadj = 3
+        for _ in range(nadj):
+            H.adjoint(u, dJdu, check=False)
+        torch.cuda.synchronize()
+        extras["adjoint_grad_ms"] = (time.perf_counter() - tt) * 1e3 / nadj
+        H.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle direct solve)", file=sys.stderr, flush=True)
+        reps, spent, t_sum = 0, 0.0, 0.0
+        while spent < 10.0 and reps < 8:
+            tt = time.perf_counter()
+            fe = fem.assemble(pr.a)
+            b = fem.load_cellwise(pr.g[0], fe.h)
+            fem.DirectSolver(fe.A).solve(b)
+            d = time.perf_counter() - tt
+            t_sum += d
+            spent += d
+            reps += 1
+        cpu = {"value": dof / (t_sum / reps), "unit": "DOF/s", "cores": 1, "kind": "oracle",
+               "sample": f"full 512x512-cell problem, {reps} repetitions: Q1 assembly + SuperLU factor/solve + "
+                         f"2 FP64 refinement steps (single-threaded); host has {len(os.sched_getaffinity(0))} cores"}
+
+    out = {
+        "metric": "DOF/s gamblet build+solve at 1e-8 rel err; adjoint grad time; % HBM roof",
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "q9 rough lognormal (sigma=2) product coefficient, 512x512 cells, 261121 DOF, "
+                               "N(0,1) cell source, patch radius 3, build+solve to 1e-8",
+                   "q": q, "dof": dof, "rho": pr.rho, "sigma": 2.0, "precision": args.precision,
+                   "rtol": args.rtol, "inner_iters": args.inner_iters,
+                   "inner_iters_coarse": args.inner_iters_coarse},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        **extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,8 +74,9 @@ typedef struct gbl_opts {
   int precision;      /* enum gbl_precision */
   double rtol;        /* target relative l2 error of u (estimated by the preconditioned residual) */
   int max_outer;      /* maximum outer (flexible CG) iterations */
-  int inner_iters;    /* block-Jacobi PCG iterations per subband system per outer iteration */
+  int inner_iters;    /* block-Jacobi PCG iterations on the finest subband system per outer iteration */
   int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */
+  int inner_iters_coarse; /* block-Jacobi PCG iterations on each coarser subband system (k < q) */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -89,12 +90,15 @@ typedef struct gbl_level_desc {
   /* Device views into the workspace for level k (for inspection and tests).
    * Level k has side nk = 2^k: cells for k < q, node slots for k = q (slot
    * (x, y) is node (x, y); slots with x = 0 or y = 0 hold no unknown).
-   * elem_bytes is 8 (FP64) or 4 (MIXED). */
+   * Arrays are offset-major (the grid position is the fastest index) so that
+   * neighbouring threads read neighbouring words.  elem_bytes is 8 (FP64) or
+   * 4 (MIXED). */
   int k;
   int nk;
-  int s;              /* A^(k) stencil half-width: A[x][y][2s+1][2s+1] */
-  int t;              /* B^(k) parent-stencil half-width: B[px][py][2t+1][2t+1][3][3] (k >= 2) */
-  int rw;             /* R^(k-1,k) block width: R[cx][cy][rw][rw] over level-k slots starting at 2(c-rho_k) (k >= 2) */
+  int s;              /* A^(k) stencil half-width; A[ox][oy][x][y] = A_{(x,y),(x+ox-s,y+oy-s)} */
+  int t;              /* B^(k) parent-stencil half-width (k >= 2); B[ox][oy][i][j][px][py] couples subband
+                         row (parent (px,py), i) to (parent (px+ox-t, py+oy-t), j) */
+  int rw;             /* R^(k-1,k) block width (k >= 2); R[bx][by][cx][cy] = R_{(cx,cy),(2(cx-rho)+bx, 2(cy-rho)+by)} */
   int rho;            /* effective patch radius at this level */
   int elem_bytes;
   const void* A;      /* A^(k) */
@@ -108,7 +112,7 @@ typedef struct gbl_ctx gbl_ctx;
 int gbl_version(void);
 
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 60,
- * inner_iters 24, max_rhs 1. */
+ * inner_iters 24, max_rhs 1, inner_iters_coarse 6. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
@@ -153,6 +157,32 @@ int gbl_adjoint(gbl_ctx* ctx, int nrhs, const double* u_dev, const double* dJdu_
 
 /* Describe level k (1 <= k <= q) of a built hierarchy.  EINVAL on a bad k. */
 int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);
+
+/* Kernel classes for the optional timing of gbl_profile_*. */
+enum gbl_prof_kernel {
+  GBL_PROF_ASSEMBLE = 0,          /* fine stiffness A^(q) */
+  GBL_PROF_SUBBAND_OPERATOR = 1,  /* B^(k) = W A^(k) W^T and block-Jacobi factors */
+  GBL_PROF_PATCH_SOLVE = 2,       /* patch Cholesky solves and R^(k-1,k) */
+  GBL_PROF_GALERKIN = 3,          /* A^(k-1) = R A^(k) R^T */
+  GBL_PROF_RESTRICT = 4,          /* g^(k-1) = R g^(k) */
+  GBL_PROF_CG_INIT = 5,           /* subband CG start, all levels */
+  GBL_PROF_CG_SPMV = 6,           /* subband CG operator application, all levels */
+  GBL_PROF_CG_UPDATE = 7,         /* subband CG vector update, all levels */
+  GBL_PROF_PROLONG = 8,           /* v^(k) = R^T v^(k-1) + W^T w^(k) */
+  GBL_PROF_FINE_APPLY = 9,        /* FP64 fine operator in the outer iteration */
+  GBL_PROF_GRADIENT = 10,         /* adjoint cell gradient */
+  GBL_PROF_NUM_KERNELS = 11
+};
+
+/* Process-wide kernel timing: every launch of a class whose bit (1 << class)
+ * is set in mask is bracketed by HIP events recorded on its stream (mask 0
+ * switches timing off; it is off by default).  gbl_profile_read waits for
+ * the recorded events and returns the summed elapsed time (ms) and the number
+ * of timed launches since the last reset.  Not for concurrent use from
+ * several host threads. */
+int gbl_profile_enable(unsigned mask);
+int gbl_profile_reset(void);
+int gbl_profile_read(int kernel, double* total_ms, long* launches);
 
 /* Release the host context (the workspace stays owned by the caller). */
 int gbl_destroy(gbl_ctx* ctx);

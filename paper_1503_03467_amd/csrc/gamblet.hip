@@ -12,8 +12,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/gamblet.h"
 #include "gamblet_internal.hpp"
@@ -25,6 +28,61 @@ namespace {
 
 thread_local std::string g_last_error = "no error";
 
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// around every launch of a kernel class (process-wide, off by default).
+struct Profiler {
+  unsigned mask = 0;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[GBL_PROF_NUM_KERNELS];
+  double total_ms[GBL_PROF_NUM_KERNELS] = {};
+  long launches[GBL_PROF_NUM_KERNELS] = {};
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void drain() {
+    for (int k = 0; k < GBL_PROF_NUM_KERNELS; ++k) {
+      for (auto& pr : pending[k]) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+          total_ms[k] += ms;
+          launches[k] += 1;
+        }
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[k].clear();
+    }
+  }
+};
+Profiler g_prof;
+std::mutex g_prof_mu;
+
+struct ProfScope {
+  int k;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int kernel, hipStream_t s) : k(kernel), st(s) {
+    if (!((g_prof.mask >> k) & 1u)) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    a = g_prof.get();
+    b = g_prof.get();
+    if (a) hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.pending[k].emplace_back(a, b);
+  }
+};
+
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 struct Layout {
@@ -34,6 +92,7 @@ struct Layout {
   size_t a_off = 0;          // copy of the coefficient (FP64, n^2)
   size_t hier_off = 0;       // hierarchy arena (T)
   size_t hier_elems = 0;
+  size_t acell_off = 0;      // element offset of the coefficient in the hierarchy arena (T)
   size_t L1_off = 0;         // 16 doubles
   size_t status_off = 0;     // 4 ints
   size_t oscal_off = 0;      // outer scalars
@@ -46,7 +105,6 @@ struct Layout {
   size_t cgscal_off = 0;     // doubles
   size_t cgpart_off[kMaxLevels] = {};
   size_t cgcnt_off = 0;
-  int cg_blocks = 0;
   size_t total = 0;
 };
 
@@ -57,6 +115,10 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) { msg = "rtol must be in (0, 1)"; return GBL_EINVAL; }
   if (o->max_outer < 1 || o->max_outer > 100000) { msg = "max_outer must be in [1, 100000]"; return GBL_EINVAL; }
   if (o->inner_iters < 0 || o->inner_iters > 100000) { msg = "inner_iters must be in [0, 100000]"; return GBL_EINVAL; }
+  if (o->inner_iters_coarse < 0 || o->inner_iters_coarse > 100000) {
+    msg = "inner_iters_coarse must be in [0, 100000]";
+    return GBL_EINVAL;
+  }
   if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
   return GBL_OK;
 }
@@ -109,6 +171,8 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
       e += align_up(g.nBJ, 64);
     }
   }
+  L.acell_off = e;
+  e += align_up((size_t)L.n * L.n, 64);
   L.hier_elems = e;
   const size_t n2 = (size_t)L.n * L.n;
   size_t b = 0;
@@ -125,17 +189,15 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     L.g_off[k] = b;
     b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * L.elem);
   }
-  int blocks = 0;
   for (int k = 2; k <= q; ++k) {
     const size_t np2 = (size_t)L.lv[k].nk * L.lv[k].nk / 4;
     L.cgv_off[k] = b;
     b = align_up(b + 5 * 3 * np2 * L.elem);
-    const int nb = (int)((np2 + 255) / 256);
+    const int pp = 256 / (2 * L.lv[k].t + 1);
+    const size_t nb = std::max((np2 + 255) / 256, (np2 + pp - 1) / pp);
     L.cgpart_off[k] = b;
-    b = align_up(b + (size_t)nb * 8);
-    blocks += nb;
+    b = align_up(b + nb * 8);
   }
-  L.cg_blocks = blocks;
   L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
   L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
   L.total = b;
@@ -180,7 +242,7 @@ template <typename T>
 CGArgs<T> make_cg_args(gbl_ctx* c) {
   const Layout& L = c->L;
   CGArgs<T> A{};
-  int blk = 0, l = 0;
+  int blk = 0, blks = 0, l = 0;
   for (int k = L.q; k >= 2; --k, ++l) {
     const LevelGeom& g = L.lv[k];
     const size_t np2 = (size_t)g.nk * g.nk / 4;
@@ -200,9 +262,20 @@ CGArgs<T> make_cg_args(gbl_ctx* c) {
     v.np = g.nk / 2;
     v.t = g.t;
     v.fine = (k == L.q) ? 1 : 0;
+    v.acell = (k == L.q) ? c->hier<T>(L.acell_off) : nullptr;
+    v.iters = (k == L.q) ? c->opts.inner_iters : c->opts.inner_iters_coarse;
     v.blk0 = blk;
     v.nblk = (int)((np2 + 255) / 256);
     blk += v.nblk;
+    const int pp = 256 / (2 * g.t + 1);
+    v.blk0s = blks;
+    if (k == L.q) {
+      const int tp = std::min(16, g.nk / 2);
+      v.nblks = (g.nk / 2 / tp) * (g.nk / 2 / tp);
+    } else {
+      v.nblks = (int)((np2 + pp - 1) / pp);
+    }
+    blks += v.nblks;
   }
   A.nlev = l;
   return A;
@@ -212,15 +285,28 @@ template <typename T>
 int build_impl(gbl_ctx* c, hipStream_t st) {
   const Layout& L = c->L;
   const int q = L.q;
-  launch_assemble_fine<T>(c->a(), c->hier<T>(L.lv[q].offA), L.n, c->status(), st);
+  {
+    ProfScope ps(GBL_PROF_ASSEMBLE, st);
+    launch_assemble_fine<T>(c->a(), c->hier<T>(L.lv[q].offA), L.n, c->status(), st);
+    launch_convert<T, double>((size_t)L.n * L.n, c->a(), c->hier<T>(L.acell_off), st);
+  }
   for (int k = q; k >= 2; --k) {
     const LevelGeom& g = L.lv[k];
     const bool fine = (k == q);
-    launch_subband_operator<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offBJ), fine, st);
-    launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR), fine, c->status(),
-                          st);
-    launch_galerkin<T>(g, L.lv[k - 1], c->hier<T>(g.offA), c->hier<T>(g.offR), c->hier<T>(L.lv[k - 1].offA),
-                       st);
+    {
+      ProfScope ps(GBL_PROF_SUBBAND_OPERATOR, st);
+      launch_subband_operator<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offBJ), fine, st);
+    }
+    {
+      ProfScope ps(GBL_PROF_PATCH_SOLVE, st);
+      launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR), fine, c->status(),
+                            st);
+    }
+    {
+      ProfScope ps(GBL_PROF_GALERKIN, st);
+      launch_galerkin<T>(g, L.lv[k - 1], c->hier<T>(g.offA), c->hier<T>(g.offR),
+                         c->hier<T>(L.lv[k - 1].offA), st);
+    }
   }
   launch_coarse_factor<T>(c->hier<T>(L.lv[1].offA), L.lv[1].s, c->L1(), c->status(), st);
   HIPCHK(c, hipGetLastError());
@@ -237,12 +323,35 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   T* g[kMaxLevels];
   for (int k = 1; k <= q; ++k) g[k] = reinterpret_cast<T*>(c->ws + L.g_off[k]);
   launch_convert<T, double>(n2, r, g[q], st);
-  for (int k = q; k >= 2; --k) launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], st);
-  launch_cg_init<T>(cg, L.cg_blocks, st);
-  for (int it = 0; it < c->opts.inner_iters; ++it) launch_cg_iter<T>(cg, L.cg_blocks, st);
+  for (int k = q; k >= 2; --k) {
+    ProfScope ps(GBL_PROF_RESTRICT, st);
+    launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], st);
+  }
+  {
+    const CGLev<T>& last = cg.lv[cg.nlev - 1];
+    ProfScope ps(GBL_PROF_CG_INIT, st);
+    launch_cg_init<T>(cg, last.blk0 + last.nblk, st);
+  }
+  // levels are ordered finest first; launch only up to the last level whose
+  // iteration budget is not yet spent (levels in between exit on their own)
+  const int itmax = std::max(c->opts.inner_iters, c->opts.inner_iters_coarse);
+  for (int it = 0; it < itmax; ++it) {
+    int lastl = -1;
+    for (int l = 0; l < cg.nlev; ++l)
+      if (it < cg.lv[l].iters) lastl = l;
+    if (lastl < 0) break;
+    const CGLev<T>& lv = cg.lv[lastl];
+    {
+      ProfScope ps(GBL_PROF_CG_SPMV, st);
+      launch_cg_spmv<T>(cg, lv.blk0s + lv.nblks, it, st);
+    }
+    ProfScope ps(GBL_PROF_CG_UPDATE, st);
+    launch_cg_update<T>(cg, lv.blk0 + lv.nblk, it, st);
+  }
   launch_coarse_solve<T>(c->L1(), g[1], g[1], st);
   for (int k = 2; k <= q; ++k) {
     const int l = q - k;
+    ProfScope ps(GBL_PROF_PROLONG, st);
     launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[l].x, g[k], k == q, st);
   }
   launch_convert<double, T>(n2, g[q], z, st);
@@ -275,7 +384,10 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   // ||z|| = ||S r|| estimates the error only up to the quality of S; keep a margin
   const double tol = 0.1 * c->opts.rtol;
   for (it = 1; it <= c->opts.max_outer; ++it) {
-    launch_apply_fine(c->a(), n, p, w, st);
+    {
+      ProfScope ps(GBL_PROF_FINE_APPLY, st);
+      launch_apply_fine(c->a(), n, p, w, st);
+    }
     launch_dots(len, 2, p, w, p, r, nullptr, nullptr, part, cnt, sc + kSPW, st);
     launch_outer_update(len, sc, u, r, p, w, st);
     precondition<T>(c, cg, r, z, st);
@@ -345,6 +457,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->max_outer = 60;
   o->inner_iters = 24;
   o->max_rhs = 1;
+  o->inner_iters_coarse = 6;
   return GBL_OK;
 }
 
@@ -453,6 +566,7 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
                        : fcg_solve<float>(c, c->cgf, 1, dJdu_dev + r * us, lam, info, s);
     if (st == GBL_EHIP) return st;
     if (st != GBL_OK) worst = st;
+    ProfScope ps(GBL_PROF_GRADIENT, s);
     launch_cell_gradient(c->a(), n, u_dev + r * us, lam, dJdloga_dev + r * n2, dJdg_dev ? dJdg_dev + r * n2 : nullptr,
                          s);
   }
@@ -478,6 +592,32 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
   d->A = base + g.offA * c->L.elem;
   d->B = k >= 2 ? base + g.offB * c->L.elem : nullptr;
   d->R = k >= 2 ? base + g.offR * c->L.elem : nullptr;
+  return GBL_OK;
+}
+
+int gbl_profile_enable(unsigned mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.mask = mask;
+  return GBL_OK;
+}
+
+int gbl_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.drain();
+  for (int k = 0; k < GBL_PROF_NUM_KERNELS; ++k) {
+    g_prof.total_ms[k] = 0.0;
+    g_prof.launches[k] = 0;
+  }
+  return GBL_OK;
+}
+
+int gbl_profile_read(int kernel, double* total_ms, long* launches) {
+  if (kernel < 0 || kernel >= GBL_PROF_NUM_KERNELS || !total_ms || !launches)
+    return fail(nullptr, GBL_EINVAL, "bad profile query");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.drain();
+  *total_ms = g_prof.total_ms[kernel];
+  *launches = g_prof.launches[kernel];
   return GBL_OK;
 }
 

@@ -407,9 +407,16 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
 }
 
 template <typename T>
+void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st);
+
+template <typename T>
 void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
                         hipStream_t st) {
   const int nc = L.nk / 2;
+  if (fine && L.t == 1 && nc > 2 * L.rho + 1) {
+    launch_patch_solve_band<T>(L, A, B, R, status, st);
+    return;
+  }
   const int wmax = (2 * L.rho + 1) < nc ? (2 * L.rho + 1) : nc;
   const int need = 3 * wmax * wmax + 1;
   const dim3 grid(nc * nc), block(256);
@@ -423,6 +430,185 @@ void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool f
   } else {
     hipLaunchKernelGGL((k_patch_solve<T, 16>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Patch solves at the finest transition (k = q), band form.
+//
+// B^(q) couples only neighbouring parents (its parent stencil is 3 x 3), so
+// with the patch unknowns ordered parent row by parent row the patch matrix
+// is banded with half-bandwidth bw = 3 (wy + 1) + 2.  One wavefront (one
+// workgroup of 64 threads) factors one patch: the band lives in LDS as
+// ab[r][d] = B_{r, r-d}; each step scales the pivot column and updates the
+// trailing bw x bw triangle, the lanes sharing its entries; the forward
+// substitution rides along and a column-oriented back substitution follows.
+// Same scaling, right-hand side and restriction row as the dense kernel.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A, const T* __restrict__ B,
+                                                         T* __restrict__ R, int nk, int s, int rho,
+                                                         int* __restrict__ status) {
+  extern __shared__ unsigned char smem_raw[];
+  const int nc = nk / 2;
+  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = ci / nc, cy = ci % nc;
+  const int x0 = max(0, cx - rho), x1 = min(nc - 1, cx + rho);
+  const int y0 = max(0, cy - rho), y1 = min(nc - 1, cy + rho);
+  const int wy = y1 - y0 + 1;
+  const int npar = (x1 - x0 + 1) * wy;
+  const int p = 3 * npar;
+  const int bw = 3 * (wy + 1) + 2;
+  const int bw1 = bw + 1;
+  const int pmax = 3 * (2 * rho + 1) * (2 * rho + 1);
+  const int bwmax = 3 * (2 * rho + 2) + 2;
+  T* ab = reinterpret_cast<T*>(smem_raw);          // pmax * (bwmax + 1)
+  T* bb = ab + (size_t)pmax * (bwmax + 1);         // pmax: right-hand side / z / x
+  T* sc = bb + pmax;                               // pmax: scaling
+  T* lcol = sc + pmax;                             // bwmax + 1
+  const int lane = threadIdx.x;
+  const int TT = 3;   // parent stencil width at the finest level (t = 1)
+  const int S = 2 * s + 1;
+  const size_t nc2 = (size_t)nc * nc;
+  const int ti = parent_type(true, cx, cy);
+  int bad = 0;
+
+  // scaling and right-hand side
+  for (int r = lane; r < p; r += 64) {
+    const int lp = r / 3, tt = r - 3 * lp;
+    const int px = x0 + lp / wy, py = y0 + lp % wy;
+    const T d = B[((size_t)(1 * TT + 1) * 9 + tt * 4) * nc2 + px * nc + py];
+    T scale = T(1);
+    if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
+    else bad = 1;
+    const int tp = parent_type(true, px, py);
+    double acc = 0.0;
+    if (abs(px - cx) <= 1 && abs(py - cy) <= 1 && !is_pad_row(tp, tt)) {
+      for (int dd = 0; dd < 4; ++dd) {
+        const double wd = wcoef(tp, tt, dd);
+        if (wd == 0.0) continue;
+        const int fx = 2 * px + (dd >> 1), fy = 2 * py + (dd & 1);
+        double inner = 0.0;
+        for (int e = 0; e < 4; ++e) {
+          const double pe = pibar(ti, e);
+          if (pe == 0.0) continue;
+          const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
+          const int ox = gx - fx + s, oy = gy - fy + s;
+          if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
+          inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
+        }
+        acc += wd * inner;
+      }
+    }
+    sc[r] = scale;
+    bb[r] = T(-acc) * scale;
+  }
+  __syncthreads();
+  // band of the scaled patch matrix: ab[r][d] = B_{r, r-d}, 0 <= d <= bw
+  for (int e = lane; e < p * bw1; e += 64) {
+    const int r = e / bw1, d = e - r * bw1;
+    const int c = r - d;
+    T v = T(0);
+    if (c >= 0) {
+      const int lr = r / 3, trr = r - 3 * lr;
+      const int lc = c / 3, tcc = c - 3 * lc;
+      const int rx = x0 + lr / wy, ry = y0 + lr % wy;
+      const int qx = x0 + lc / wy, qy = y0 + lc % wy;
+      const int ox = qx - rx + 1, oy = qy - ry + 1;
+      if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
+        v = B[((size_t)(ox * TT + oy) * 9 + trr * 3 + tcc) * nc2 + rx * nc + ry] * sc[r] * sc[c];
+    }
+    ab[e] = v;
+  }
+  // this lane's fixed share of the trailing triangle: entries (dr, dc),
+  // 1 <= dc <= dr <= bw, enumerated column by column
+  constexpr int kMaxTri = 9;   // ceil(bw (bw + 1) / 2 / 64) for bw <= 32 (rho <= 4)
+  const int ntri = bw * (bw + 1) / 2;
+  int tri_dr[kMaxTri], tri_dc[kMaxTri];
+  {
+    int dc = 1, rem = lane, len = bw;
+#pragma unroll
+    for (int m = 0; m < kMaxTri; ++m) {
+      while (dc <= bw && rem >= len) {
+        rem -= len;
+        ++dc;
+        --len;
+      }
+      const bool ok = (lane + 64 * m) < ntri;
+      tri_dr[m] = ok ? dc + rem : bw + 1 + 1024;   // out of range -> skipped below
+      tri_dc[m] = ok ? dc : 1;
+      rem += 64;
+    }
+  }
+  __syncthreads();
+
+  for (int j = 0; j < p; ++j) {
+    T pv = ab[j * bw1];
+    if (!(pv > T(0))) {
+      bad = 1;
+      pv = T(1);
+    }
+    const T dj = my_sqrt<T>(pv);
+    const T inv = T(1) / dj;
+    const int e = lane + 1;
+    if (e <= bw && j + e < p) {
+      T* pe = ab + (size_t)(j + e) * bw1 + e;
+      const T l = *pe * inv;
+      *pe = l;
+      lcol[e] = l;
+    }
+    const T zj = bb[j] * inv;
+    __syncthreads();
+    if (lane == 0) {
+      ab[j * bw1] = dj;
+      bb[j] = zj;
+    }
+    if (e <= bw && j + e < p) bb[j + e] -= lcol[e] * zj;
+#pragma unroll
+    for (int m = 0; m < kMaxTri; ++m) {
+      const int dr = tri_dr[m], dc = tri_dc[m];
+      if (j + dr < p) ab[(size_t)(j + dr) * bw1 + (dr - dc)] -= lcol[dr] * lcol[dc];
+    }
+    __syncthreads();
+  }
+  // back substitution L^T x = z, row j of L is ab[j][*]
+  for (int j = p - 1; j >= 0; --j) {
+    const T xj = bb[j] / ab[j * bw1];
+    const int d = lane + 1;
+    if (d <= bw && j - d >= 0) bb[j - d] -= ab[(size_t)j * bw1 + d] * xj;
+    __syncthreads();
+    if (lane == 0) bb[j] = xj;
+    __syncthreads();
+  }
+  for (int r = lane; r < p; r += 64) bb[r] *= sc[r];
+  if (bad) atomicOr(status, kBadPivot);
+  __syncthreads();
+
+  const int rw = 2 * (2 * rho + 1);
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
+  T* Ri = R + ci;
+  for (int e = lane; e < rw * rw; e += 64) {
+    const int bx = e / rw, by = e % rw;
+    const int fx = ox0 + bx, fy = oy0 + by;
+    double v = 0.0;
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      const int px = fx >> 1, py = fy >> 1;
+      const int d = 2 * (fx & 1) + (fy & 1);
+      const int tp = parent_type(true, px, py);
+      if (px == cx && py == cy) v = pibar(tp, d);
+      const int lp = (px - x0) * wy + (py - y0);
+      for (int tt = 0; tt < 3; ++tt) v += (double)bb[3 * lp + tt] * wcoef(tp, tt, d);
+    }
+    Ri[(size_t)e * nc2] = T(v);
+  }
+}
+
+template <typename T>
+void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st) {
+  const int nc = L.nk / 2;
+  const int pmax = 3 * (2 * L.rho + 1) * (2 * L.rho + 1);
+  const int bwmax = 3 * (2 * L.rho + 2) + 2;
+  const size_t shm = ((size_t)pmax * (bwmax + 1) + 2 * (size_t)pmax + (bwmax + 1)) * sizeof(T);
+  hipLaunchKernelGGL(k_patch_solve_band<T>, dim3(nc * nc), dim3(64), shm, st, A, B, R, L.nk, L.s, L.rho, status);
 }
 
 // ---------------------------------------------------------------------------

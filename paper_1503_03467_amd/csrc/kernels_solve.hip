@@ -37,28 +37,40 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
       v[k] = x;
     }
   }
+  __syncthreads();
 }
 
-// Returns true in thread 0 of the last block; partial sums of all blocks are
-// then visible and summed into out[0..NV).
+// Publish this block's partial sums; the last block to arrive (atomic
+// ticket) then reduces all partials with every one of its threads, in a
+// fixed order, and thread 0 receives the totals in out[] with *is_last set.
+// Must be called by all threads of the block (it contains barriers).
 template <int NV>
 __device__ __forceinline__ void finish_reduction(const double (&v)[NV], double* part, int nblk, int blk,
-                                                 unsigned* cnt, double* out, bool* is_last) {
+                                                 unsigned* cnt, double* out, bool* is_last, double* sh) {
+  __shared__ int last_flag;
   *is_last = false;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) part[k * nblk + blk] = v[k];
     __threadfence();
     const unsigned ticket = atomicAdd(cnt, 1u);
-    if (ticket == (unsigned)(nblk - 1)) {
-      __threadfence();
-      const volatile double* vp = part;
+    last_flag = (ticket == (unsigned)(nblk - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (last_flag) {
+    __threadfence();
+    const volatile double* vp = part;
+    double acc[NV];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        double x = 0.0;
-        for (int b = 0; b < nblk; ++b) x += vp[k * nblk + b];
-        out[k] = x;
-      }
+    for (int k = 0; k < NV; ++k) {
+      double x = 0.0;
+      for (int b = threadIdx.x; b < nblk; b += blockDim.x) x += vp[k * nblk + b];
+      acc[k] = x;
+    }
+    block_sum<NV>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) out[k] = acc[k];
       *cnt = 0u;
       *is_last = true;
     }
@@ -150,7 +162,7 @@ __global__ __launch_bounds__(256) void k_dots(int len, int nv, const double* __r
   block_sum<3>(v, sh);
   bool last;
   double res[3];
-  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last);
+  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last, sh);
   if (last) {
     for (int k = 0; k < nv; ++k) out[k] = res[k];
   }
@@ -216,30 +228,47 @@ __global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__
 // entry-major (R[e][cell]) so consecutive threads read consecutive words.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_restrict(const T* __restrict__ R, const T* __restrict__ gf, T* __restrict__ gc, int nk,
-                           int rho) {
+__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ R, const T* __restrict__ gf,
+                                                  T* __restrict__ gc, int nk, int rho) {
+  // PP = 256 / rw coarse slots per workgroup; thread (bx, cl) sums row bx of
+  // the restriction block, the rows are added in LDS.
+  __shared__ T red[256];
   const int nc = nk / 2;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc * nc) return;
-  const int cx = i / nc, cy = i % nc;
   const int rw = 2 * (2 * rho + 1);
-  const int ox = 2 * (cx - rho), oy = 2 * (cy - rho);
+  const int PP = 256 / rw;
+  const int tid = threadIdx.x;
+  const int bx = tid / PP, cl = tid - bx * PP;
+  const int i = blockIdx.x * PP + cl;
   const size_t nc2 = (size_t)nc * nc;
-  const int bxl = max(0, -ox), bxh = min(rw - 1, nk - 1 - ox);
-  const int byl = max(0, -oy), byh = min(rw - 1, nk - 1 - oy);
   T acc = T(0);
-  for (int bx = bxl; bx <= bxh; ++bx) {
-    const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
-    const T* gr = gf + (size_t)(ox + bx) * nk + oy;
-    for (int by = byl; by <= byh; ++by) acc += Rr[(size_t)by * nc2] * gr[by];
+  if (bx < rw && i < nc * nc) {
+    const int cx = i / nc, cy = i - (i / nc) * nc;
+    const int ox = 2 * (cx - rho), oy = 2 * (cy - rho);
+    const int fx = ox + bx;
+    if (fx >= 0 && fx < nk) {
+      const int byl = max(0, -oy), byh = min(rw - 1, nk - 1 - oy);
+      const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
+      const T* gr = gf + (size_t)fx * nk + oy;
+      for (int by = byl; by <= byh; ++by) acc += Rr[(size_t)by * nc2] * gr[by];
+    }
   }
-  gc[i] = acc;
+  if (bx < rw) red[bx * PP + cl] = acc;
+  __syncthreads();
+  if (tid < PP) {
+    const int ii = blockIdx.x * PP + tid;
+    if (ii < nc * nc) {
+      T sum = T(0);
+      for (int b = 0; b < rw; ++b) sum += red[b * PP + tid];
+      gc[ii] = sum;
+    }
+  }
 }
 
 template <typename T>
 void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st) {
   const int nc = L.nk / 2;
-  hipLaunchKernelGGL(k_restrict<T>, dim3((nc * nc + 255) / 256), dim3(256), 0, st, R, gf, gc, L.nk, L.rho);
+  const int PP = 256 / L.rw;
+  hipLaunchKernelGGL(k_restrict<T>, dim3((nc * nc + PP - 1) / PP), dim3(256), 0, st, R, gf, gc, L.nk, L.rho);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,6 +354,13 @@ __device__ __forceinline__ int find_level(const CGArgs<T>& A, int b) {
 }
 
 template <typename T>
+__device__ __forceinline__ int find_level_s(const CGArgs<T>& A, int b) {
+  int l = 0;
+  while (l + 1 < A.nlev && b >= A.lv[l + 1].blk0s) ++l;
+  return l;
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
   __shared__ double sh[16];
   const int l = find_level(args, blockIdx.x);
@@ -370,7 +406,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
   block_sum<1>(v, sh);
   bool last;
   double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last, sh);
   if (last) {
     L.scal[kCRZ] = res[0];
     L.scal[kCBETA] = 0.0;
@@ -378,46 +414,173 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
   }
 }
 
+// Finest level, matrix-free: B^(q) z = W (A (W^T z)) with A applied from the
+// cell coefficient.  A workgroup owns a TP x TP tile of parents (one thread
+// each); the nodal values W^T z of the tile plus a one-parent halo and the
+// coefficients of the cells they touch are staged in LDS.  Padding subband
+// rows act as identity rows, as in the assembled B^(q).
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_spmv(CGArgs<T> args) {
-  __shared__ double sh[16];
-  const int l = find_level(args, blockIdx.x);
-  const CGLev<T>& L = args.lv[l];
-  const int blk = blockIdx.x - L.blk0;
-  const int p = blk * 256 + threadIdx.x;
+__device__ __forceinline__ void fine_operator(const CGLev<T>& L, int blk, T* lds, T (&y)[3], int& pout) {
+  const int np = L.np;
+  const int nk = 2 * np;
+  const size_t np2 = (size_t)np * np;
+  const int TP = np < 16 ? np : 16;
+  const int ntx = np / TP;
+  const int tx = blk / ntx, ty = blk - (blk / ntx) * ntx;
+  const int px0 = tx * TP, py0 = ty * TP;
+  const int VW = 2 * TP + 4;       // nodes 2(px0-1) .. 2(px0+TP)+1
+  const int AW = 2 * TP + 1;       // cells 2px0-1 .. 2(px0+TP)-1
+  T* vl = lds;
+  T* al = lds + VW * VW;
+  const int tid = threadIdx.x;
+  const int HW = TP + 2;
+  for (int e = tid; e < HW * HW; e += blockDim.x) {
+    const int hx = e / HW, hy = e - (e / HW) * HW;
+    const int px = px0 - 1 + hx, py = py0 - 1 + hy;
+    T z0 = T(0), z1 = T(0), z2 = T(0);
+    int tp = 0;
+    const bool in = px >= 0 && py >= 0 && px < np && py < np;
+    if (in) {
+      const int q = px * np + py;
+      z0 = L.z[q];
+      z1 = L.z[np2 + q];
+      z2 = L.z[2 * np2 + q];
+      tp = parent_type(true, px, py);
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      T v = T(0);
+      if (in) v = T(wcoef(tp, 0, d)) * z0 + T(wcoef(tp, 1, d)) * z1 + T(wcoef(tp, 2, d)) * z2;
+      vl[(2 * hx + (d >> 1)) * VW + 2 * hy + (d & 1)] = v;
+    }
+  }
+  for (int e = tid; e < AW * AW; e += blockDim.x) {
+    const int cxl = e / AW, cyl = e - (e / AW) * AW;
+    const int cx = 2 * px0 - 1 + cxl, cy = 2 * py0 - 1 + cyl;
+    al[e] = (cx >= 0 && cy >= 0 && cx < nk && cy < nk) ? L.acell[(size_t)cx * nk + cy] : T(0);
+  }
+  __syncthreads();
+  pout = -1;
+  if (tid < TP * TP) {
+    const int px = px0 + tid / TP, py = py0 + tid % TP;
+    const int tp = parent_type(true, px, py);
+    T Av[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int x = 2 * px + (d >> 1), yy = 2 * py + (d & 1);
+      if (x == 0 || yy == 0) {
+        Av[d] = T(0);
+        continue;
+      }
+      const int vx = x - 2 * (px0 - 1), vy = yy - 2 * (py0 - 1);
+      const int ax = x - (2 * px0 - 1), ay = yy - (2 * py0 - 1);
+      const T a00 = al[(ax - 1) * AW + (ay - 1)], a10 = al[ax * AW + (ay - 1)];
+      const T a01 = al[(ax - 1) * AW + ay], a11 = al[ax * AW + ay];
+      const T* v = vl + vx * VW + vy;
+      T acc = T(2.0 / 3.0) * (a00 + a10 + a01 + a11) * v[0];
+      acc -= (a10 + a11) * T(1.0 / 6.0) * v[VW];
+      acc -= (a00 + a01) * T(1.0 / 6.0) * v[-VW];
+      acc -= (a01 + a11) * T(1.0 / 6.0) * v[1];
+      acc -= (a00 + a10) * T(1.0 / 6.0) * v[-1];
+      acc -= a11 * T(1.0 / 3.0) * v[VW + 1];
+      acc -= a00 * T(1.0 / 3.0) * v[-VW - 1];
+      acc -= a10 * T(1.0 / 3.0) * v[VW - 1];
+      acc -= a01 * T(1.0 / 3.0) * v[-VW + 1];
+      Av[d] = acc;
+    }
+    const int pp = px * np + py;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (is_pad_row(tp, t)) {
+        y[t] = L.z[t * np2 + pp];
+      } else {
+        y[t] = T(wcoef(tp, t, 0)) * Av[0] + T(wcoef(tp, t, 1)) * Av[1] + T(wcoef(tp, t, 2)) * Av[2] +
+               T(wcoef(tp, t, 3)) * Av[3];
+      }
+    }
+    pout = pp;
+  }
+}
+
+// Coarser levels, stored block stencil: one workgroup covers PP = 256/(2t+1)
+// consecutive parents; thread (ox, pl) accumulates the neighbour row ox of
+// parent pl and the partial products are summed over ox in LDS.
+template <typename T>
+__device__ __forceinline__ void stencil_operator(const CGLev<T>& L, int blk, T* red, T (&y)[3], int& pout) {
   const int np = L.np;
   const size_t np2 = (size_t)np * np;
   const int t = L.t, TT = 2 * L.t + 1;
-  double v[1] = {0.0};
-  if (p < np * np) {
-    const int px = p / np, py = p % np;
-    const T beta = T(L.scal[kCBETA]);
-    T y[3] = {T(0), T(0), T(0)};
-    const int oxl = max(0, t - px), oxh = min(TT - 1, np - 1 - px + t);
-    const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
-    for (int ox = oxl; ox <= oxh; ++ox) {
+  const int PP = 256 / TT;
+  const int tid = threadIdx.x;
+  const int ox = tid / PP, pl = tid - ox * PP;
+  const int p = blk * PP + pl;
+  T acc[3] = {T(0), T(0), T(0)};
+  if (ox < TT && p < np * np) {
+    const int px = p / np, py = p - px * np;
+    const int qx = px + ox - t;
+    if (qx >= 0 && qx < np) {
+      const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
       for (int oy = oyl; oy <= oyh; ++oy) {
-        const int qn = (px + ox - t) * np + (py + oy - t);
+        const int qn = qx * np + (py + oy - t);
         const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
         const T* Bb = L.B + (size_t)(ox * TT + oy) * 9 * np2 + p;
-        y[0] += Bb[0] * z0 + Bb[np2] * z1 + Bb[2 * np2] * z2;
-        y[1] += Bb[3 * np2] * z0 + Bb[4 * np2] * z1 + Bb[5 * np2] * z2;
-        y[2] += Bb[6 * np2] * z0 + Bb[7 * np2] * z1 + Bb[8 * np2] * z2;
+        acc[0] += Bb[0] * z0 + Bb[np2] * z1 + Bb[2 * np2] * z2;
+        acc[1] += Bb[3 * np2] * z0 + Bb[4 * np2] * z1 + Bb[5 * np2] * z2;
+        acc[2] += Bb[6 * np2] * z0 + Bb[7 * np2] * z1 + Bb[8 * np2] * z2;
       }
     }
+  }
+  if (ox < TT) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[(i * TT + ox) * PP + pl] = acc[i];
+  }
+  __syncthreads();
+  pout = -1;
+  if (tid < PP) {
+    const int pp = blk * PP + tid;
+    if (pp < np * np) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T s = T(0);
+        for (int o = 0; o < TT; ++o) s += red[(i * TT + o) * PP + tid];
+        y[i] = s;
+      }
+      pout = pp;
+    }
+  }
+}
+
+// q = B z + beta q, p = z + beta p and the partial sums of (p, q); the last
+// block of each level forms alpha = (r, z) / (p, q).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_spmv(CGArgs<T> args, int it) {
+  __shared__ double sh[16];
+  __shared__ T lds[36 * 36 + 33 * 33];   // covers the fine tile (TP = 16) and the 3 x 256 partials
+  const int l = find_level_s(args, blockIdx.x);
+  const CGLev<T>& L = args.lv[l];
+  if (it >= L.iters) return;
+  const int blk = blockIdx.x - L.blk0s;
+  const size_t np2 = (size_t)L.np * L.np;
+  T y[3] = {T(0), T(0), T(0)};
+  int pp = -1;
+  if (L.acell) fine_operator<T>(L, blk, lds, y, pp);
+  else stencil_operator<T>(L, blk, lds, y, pp);
+  double v[1] = {0.0};
+  if (pp >= 0) {
+    const T beta = T(L.scal[kCBETA]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const T qv = y[i] + beta * L.q[i * np2 + p];
-      const T pv = L.z[i * np2 + p] + beta * L.p[i * np2 + p];
-      L.q[i * np2 + p] = qv;
-      L.p[i * np2 + p] = pv;
+      const T qv = y[i] + beta * L.q[i * np2 + pp];
+      const T pv = L.z[i * np2 + pp] + beta * L.p[i * np2 + pp];
+      L.q[i * np2 + pp] = qv;
+      L.p[i * np2 + pp] = pv;
       v[0] += (double)(pv * qv);
     }
   }
   block_sum<1>(v, sh);
   bool last;
   double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  finish_reduction<1>(v, L.part, L.nblks, blk, L.cnt, res, &last, sh);
   if (last) {
     const double pq = res[0];
     L.scal[kCPQ] = pq;
@@ -426,10 +589,11 @@ __global__ __launch_bounds__(256) void k_cg_spmv(CGArgs<T> args) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args) {
+__global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it) {
   __shared__ double sh[16];
   const int l = find_level(args, blockIdx.x);
   const CGLev<T>& L = args.lv[l];
+  if (it >= L.iters) return;
   const int blk = blockIdx.x - L.blk0;
   const int p = blk * 256 + threadIdx.x;
   const int np = L.np;
@@ -456,7 +620,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args) {
   block_sum<1>(v, sh);
   bool last;
   double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last);
+  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last, sh);
   if (last) {
     const double rz_new = res[0];
     const double rz = L.scal[kCRZ];
@@ -470,9 +634,12 @@ void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks), dim3(256), 0, st, a);
 }
 template <typename T>
-void launch_cg_iter(const CGArgs<T>& a, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a);
+void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(256), 0, st, a, it);
+}
+template <typename T>
+void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +731,8 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t); \
   template void launch_coarse_solve<T>(const double*, const T*, T*, hipStream_t);                       \
   template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t);                                  \
-  template void launch_cg_iter<T>(const CGArgs<T>&, int, hipStream_t);                                  \
+  template void launch_cg_spmv<T>(const CGArgs<T>&, int, int, hipStream_t);                             \
+  template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t);                           \
   template void launch_zero<T>(size_t, T*, hipStream_t);
 GBL_INST(float)
 GBL_INST(double)

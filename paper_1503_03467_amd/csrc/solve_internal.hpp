@@ -31,6 +31,7 @@ struct CGLev {
   const T* B;      // B^(k), offset-major
   const T* BJ;     // inverse 3x3 diagonal blocks
   const T* g;      // level-k right-hand side g^(k) (slots)
+  const T* acell;  // finest level only: cell coefficient (matrix-free operator), else null
   T* x;            // w^(k)
   T* r;
   T* z;
@@ -42,8 +43,11 @@ struct CGLev {
   int np;          // parents per dimension (n_{k-1})
   int t;           // parent-stencil half-width
   int fine;        // k == q
-  int blk0;        // first block of this level in the grid
-  int nblk;        // blocks of this level
+  int iters;       // CG iteration budget of this level
+  int blk0;        // first block of this level in the update/init grid (256 parents per block)
+  int nblk;        // update/init blocks of this level
+  int blk0s;       // first block of this level in the operator grid (256/(2t+1) parents per block)
+  int nblks;       // operator blocks of this level
 };
 
 template <typename T>
@@ -55,7 +59,9 @@ struct CGArgs {
 template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st);
 template <typename T>
-void launch_cg_iter(const CGArgs<T>& a, int nblocks, hipStream_t st);
+void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st);
+template <typename T>
+void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st);
 template <typename T>
 void launch_zero(size_t len, T* x, hipStream_t st);
 template <typename TD, typename TS>

@@ -22,7 +22,8 @@ _STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "ENOME
 
 class GblOpts(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("inner_iters_coarse", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -63,8 +64,12 @@ def lib() -> ctypes.CDLL:
         L.gbl_destroy.argtypes = [vp]
         L.gbl_last_error.argtypes = [vp]
         L.gbl_last_error.restype = ctypes.c_char_p
+        L.gbl_profile_enable.argtypes = [ctypes.c_uint]
+        L.gbl_profile_reset.argtypes = []
+        L.gbl_profile_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
-                     "gbl_level_layout", "gbl_destroy"):
+                     "gbl_level_layout", "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset",
+                     "gbl_profile_read"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -77,14 +82,17 @@ def _check(code: int, ctx=None):
 
 
 def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 60,
-              inner_iters: int = 24, max_rhs: int = 1) -> GblOpts:
+              inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     o.rho = int(rho)
     o.precision = GBL_FP64 if precision in ("fp64", "f64", "double") else GBL_MIXED
     o.rtol = float(rtol)
     o.max_outer = int(max_outer)
-    o.inner_iters = int(inner_iters)
+    if inner_iters is not None:
+        o.inner_iters = int(inner_iters)
+    if inner_iters_coarse is not None:
+        o.inner_iters_coarse = int(inner_iters_coarse)
     o.max_rhs = int(max_rhs)
     return o
 
@@ -118,14 +126,15 @@ class Hierarchy:
     """Localized gamblet hierarchy of one coefficient field, built on the GPU."""
 
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
-                 max_outer: int = 60, inner_iters: int = 24, max_rhs: int = 1):
+                 max_outer: int = 60, inner_iters: int | None = None, max_rhs: int = 1,
+                 inner_iters_coarse: int | None = None):
         n = a.shape[0]
         q = n.bit_length() - 1
         if n != (1 << q) or q < 2:
             raise ValueError("a must be [2^q][2^q] with q >= 2")
         _require(a, (n, n), "a")
         self.q, self.n, self.device = q, n, a.device
-        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs)
+        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -210,6 +219,37 @@ class Hierarchy:
             out["B"] = view(d.B, T * T * 9 * np_ * np_).view(T, T, 3, 3, np_, np_)
             out["R"] = view(d.R, d.rw * d.rw * np_ * np_).view(d.rw, d.rw, np_, np_)
         return out
+
+
+PROF_KERNELS = ["assemble", "subband_operator", "patch_solve", "galerkin", "restrict", "cg_init", "cg_spmv",
+                "cg_update", "prolong", "fine_apply", "gradient"]
+
+
+def profile_enable(kernels="all"):
+    """Time launches of the named kernel classes with HIP events (``"all"``, a list, or None to stop)."""
+    if kernels is None:
+        mask = 0
+    elif kernels == "all":
+        mask = (1 << len(PROF_KERNELS)) - 1
+    else:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << PROF_KERNELS.index(k)
+    _check(lib().gbl_profile_enable(mask))
+
+
+def profile_reset():
+    _check(lib().gbl_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel: (total_ms, launches)} accumulated since the last reset."""
+    out = {}
+    for i, name in enumerate(PROF_KERNELS):
+        ms, n = ctypes.c_double(), ctypes.c_long()
+        _check(lib().gbl_profile_read(i, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out
 
 
 class GambletSolve(torch.autograd.Function):
