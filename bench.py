@@ -34,8 +34,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--inner-iters", type=int, default=24)
-    ap.add_argument("--inner-iters-coarse", type=int, default=6)
+    ap.add_argument("--inner-iters", type=int, default=8)
+    ap.add_argument("--inner-iters-coarse", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
     return ap.parse_args()
@@ -68,9 +68,14 @@ def kernel_work(name, geo, q, elem):
             Sc = 2 * c["s"] + 1
             fl += 2.0 * nc * nc * g["rw"] ** 2 * (Sk * Sk + Sc * Sc)
         return "flops", fl
+    if name == "fine_cg":
+        # per parent: r, w, s, u, p, x, block-Jacobi 3x3 and 4 cell coefficients read;
+        # u, p, x, r, s, w written (one fused iteration of the finest subband CG)
+        np2 = (geo[q]["nk"] // 2) ** 2
+        return "bytes", elem * np2 * (9 + 9 + 9 + 4 + 18)
     if name in ("cg_spmv", "cg_update", "cg_init"):
         by = 0.0
-        for k in range(2, q + 1):
+        for k in range(2, q):
             g = geo[k]
             np2 = (g["nk"] // 2) ** 2
             T = 2 * g["t"] + 1

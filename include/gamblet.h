@@ -72,7 +72,8 @@ enum gbl_precision {
 typedef struct gbl_opts {
   int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3); 1..4 */
   int precision;      /* enum gbl_precision */
-  double rtol;        /* target relative l2 error of u (estimated by the preconditioned residual) */
+  double rtol;        /* target relative l2 error of u; the solve stops when the larger of ||S r|| and the
+                         last correction, over the last two iterations, is below rtol / 3 of ||u|| */
   int max_outer;      /* maximum outer (flexible CG) iterations */
   int inner_iters;    /* block-Jacobi PCG iterations on the finest subband system per outer iteration */
   int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */
@@ -82,7 +83,7 @@ typedef struct gbl_opts {
 typedef struct gbl_solve_info {
   int outer_iters;        /* outer iterations taken (max over right-hand sides) */
   int status;             /* same value as the return code */
-  double rel_update;      /* last preconditioned-residual estimate ||z|| / ||u|| (max over rhs) */
+  double rel_update;      /* last error estimate (see rtol), relative to ||u|| (max over rhs) */
   double rel_residual;    /* ||b - A u|| / ||b|| at exit (max over rhs) */
 } gbl_solve_info;
 
@@ -96,8 +97,9 @@ typedef struct gbl_level_desc {
   int k;
   int nk;
   int s;              /* A^(k) stencil half-width; A[ox][oy][x][y] = A_{(x,y),(x+ox-s,y+oy-s)} */
-  int t;              /* B^(k) parent-stencil half-width (k >= 2); B[ox][oy][i][j][px][py] couples subband
-                         row (parent (px,py), i) to (parent (px+ox-t, py+oy-t), j) */
+  int t;              /* B^(k) parent-stencil half-width (k >= 2).  Entry (ox, oy, i, j) of parent
+                         p = px*(nk/2)+py couples subband row (p, i) to (parent (px+ox-t, py+oy-t), j);
+                         stored block-interleaved: B[p/64][ox][oy][i][j][p%64] (groups of 64 parents) */
   int rw;             /* R^(k-1,k) block width (k >= 2); R[bx][by][cx][cy] = R_{(cx,cy),(2(cx-rho)+bx, 2(cy-rho)+by)} */
   int rho;            /* effective patch radius at this level */
   int elem_bytes;
@@ -111,8 +113,8 @@ typedef struct gbl_ctx gbl_ctx;
 /* Library version (GBL_VERSION). */
 int gbl_version(void);
 
-/* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 60,
- * inner_iters 24, max_rhs 1, inner_iters_coarse 6. */
+/* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
+ * inner_iters 8, max_rhs 1, inner_iters_coarse 3. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
@@ -165,13 +167,14 @@ enum gbl_prof_kernel {
   GBL_PROF_PATCH_SOLVE = 2,       /* patch Cholesky solves and R^(k-1,k) */
   GBL_PROF_GALERKIN = 3,          /* A^(k-1) = R A^(k) R^T */
   GBL_PROF_RESTRICT = 4,          /* g^(k-1) = R g^(k) */
-  GBL_PROF_CG_INIT = 5,           /* subband CG start, all levels */
-  GBL_PROF_CG_SPMV = 6,           /* subband CG operator application, all levels */
-  GBL_PROF_CG_UPDATE = 7,         /* subband CG vector update, all levels */
+  GBL_PROF_CG_INIT = 5,           /* subband CG start, coarser levels */
+  GBL_PROF_CG_SPMV = 6,           /* subband CG operator application, coarser levels */
+  GBL_PROF_CG_UPDATE = 7,         /* subband CG vector update, coarser levels */
   GBL_PROF_PROLONG = 8,           /* v^(k) = R^T v^(k-1) + W^T w^(k) */
   GBL_PROF_FINE_APPLY = 9,        /* FP64 fine operator in the outer iteration */
   GBL_PROF_GRADIENT = 10,         /* adjoint cell gradient */
-  GBL_PROF_NUM_KERNELS = 11
+  GBL_PROF_FINE_CG = 11,          /* finest-level subband CG iteration (fused) */
+  GBL_PROF_NUM_KERNELS = 12
 };
 
 /* Process-wide kernel timing: every launch of a class whose bit (1 << class)

@@ -21,11 +21,6 @@ __device__ __forceinline__ int parent_type(bool fine, int px, int py) {
 // Helmert rows for m = 4: (1,-1,0,0)/sqrt2, (1,1,-2,0)/sqrt6, (1,1,1,-3)/sqrt12;
 // for m = 2 over the two present children: (1,-1)/sqrt2.  Rows of parents with
 // fewer children are zero (padding rows).
-struct WTable {
-  double w[4][3][4];
-  double pb[4][4];
-};
-
 __device__ __forceinline__ double wcoef(int type, int t, int d) {
   constexpr double r2 = 0.70710678118654752440;
   constexpr double r6 = 0.40824829046386301637;
@@ -63,6 +58,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   if (bid >= full) return bid;
   const int per = full / nx;
   return (bid % nx) * per + bid / nx;
+}
+
+// Block-interleaved index of the subband operator B^(k): the (2t+1)^2 x 9
+// entries of every group of 64 consecutive parents are contiguous, lanes
+// (parents) fastest: B[p / 64][o][e][p % 64], o = ox (2t+1) + oy, e = 3i + j.
+__device__ __forceinline__ size_t b_index(int o, int e, int p, int TT) {
+  return ((size_t)(p >> 6) * (size_t)(TT * TT * 9) + (size_t)(o * 9 + e)) * 64 + (p & 63);
 }
 
 template <typename T>

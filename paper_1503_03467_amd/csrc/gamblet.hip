@@ -105,6 +105,9 @@ struct Layout {
   size_t cgscal_off = 0;     // doubles
   size_t cgpart_off[kMaxLevels] = {};
   size_t cgcnt_off = 0;
+  size_t fcg_off = 0;        // finest-level CG vectors (9 x 3 np^2, T)
+  size_t fcgpart_off = 0;    // tile partials (2 per tile)
+  size_t fcgscal_off = 0;    // kNumFineScalars doubles + ticket
   size_t total = 0;
 };
 
@@ -114,7 +117,7 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   if (o->precision != GBL_FP64 && o->precision != GBL_MIXED) { msg = "unknown precision"; return GBL_EINVAL; }
   if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) { msg = "rtol must be in (0, 1)"; return GBL_EINVAL; }
   if (o->max_outer < 1 || o->max_outer > 100000) { msg = "max_outer must be in [1, 100000]"; return GBL_EINVAL; }
-  if (o->inner_iters < 0 || o->inner_iters > 100000) { msg = "inner_iters must be in [0, 100000]"; return GBL_EINVAL; }
+  if (o->inner_iters < 1 || o->inner_iters > 100000) { msg = "inner_iters must be in [1, 100000]"; return GBL_EINVAL; }
   if (o->inner_iters_coarse < 0 || o->inner_iters_coarse > 100000) {
     msg = "inner_iters_coarse must be in [0, 100000]";
     return GBL_EINVAL;
@@ -160,7 +163,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     if (k >= 2) {
       const size_t np2 = nk2 / 4;
       const size_t TT = 2 * g.t + 1;
-      g.nB = TT * TT * 9 * np2;
+      g.nB = TT * TT * 9 * ((np2 + 63) / 64 * 64);   // block-interleaved, 64 parents per group
       g.offB = e;
       e += align_up(g.nB, 64);
       g.nR = (size_t)g.rw * g.rw * np2;
@@ -189,17 +192,24 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     L.g_off[k] = b;
     b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * L.elem);
   }
+  {
+    const size_t np2 = (size_t)L.lv[q].nk * L.lv[q].nk / 4;
+    L.fcg_off = b;
+    b = align_up(b + 9 * 3 * np2 * L.elem);
+    L.fcgpart_off = b;
+    b = align_up(b + 2 * std::max<size_t>(1, np2 / 256 + 1) * 8);
+  }
   for (int k = 2; k <= q; ++k) {
     const size_t np2 = (size_t)L.lv[k].nk * L.lv[k].nk / 4;
     L.cgv_off[k] = b;
     b = align_up(b + 5 * 3 * np2 * L.elem);
-    const int pp = 256 / (2 * L.lv[k].t + 1);
-    const size_t nb = std::max((np2 + 255) / 256, (np2 + pp - 1) / pp);
+    const size_t nb = std::max((np2 + 255) / 256, (np2 + 63) / 64);
     L.cgpart_off[k] = b;
     b = align_up(b + nb * 8);
   }
   L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
   L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
+  L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
   L.total = b;
   return GBL_OK;
 }
@@ -212,9 +222,13 @@ struct gbl_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err = "no error";
-  double* host = nullptr;   // pinned host mirror: [0..7] outer scalars, [8] status bits
-  CGArgs<float> cgf;
+  double* host = nullptr;   // pinned host mirror: outer scalars, then the status word
+  CGArgs<float> cgf;     // coarser subband levels (k < q)
   CGArgs<double> cgd;
+  FineCG<float> fcgf;    // finest subband level
+  FineCG<double> fcgd;
+  hipStream_t side = nullptr;           // second stream: coarser subband CG runs beside the finest
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   template <typename T>
   T* hier(size_t off) const { return reinterpret_cast<T*>(ws + L.hier_off) + off; }
@@ -238,12 +252,23 @@ int fail(gbl_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail((ctx), GBL_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+void release(gbl_ctx* c) {
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->host) hipHostFree(c->host);
+  delete c;
+}
+
 template <typename T>
 CGArgs<T> make_cg_args(gbl_ctx* c) {
   const Layout& L = c->L;
   CGArgs<T> A{};
   int blk = 0, blks = 0, l = 0;
-  for (int k = L.q; k >= 2; --k, ++l) {
+  for (int k = L.q - 1; k >= 2; --k, ++l) {
     const LevelGeom& g = L.lv[k];
     const size_t np2 = (size_t)g.nk * g.nk / 4;
     CGLev<T>& v = A.lv[l];
@@ -262,23 +287,44 @@ CGArgs<T> make_cg_args(gbl_ctx* c) {
     v.np = g.nk / 2;
     v.t = g.t;
     v.fine = (k == L.q) ? 1 : 0;
-    v.acell = (k == L.q) ? c->hier<T>(L.acell_off) : nullptr;
     v.iters = (k == L.q) ? c->opts.inner_iters : c->opts.inner_iters_coarse;
     v.blk0 = blk;
     v.nblk = (int)((np2 + 255) / 256);
     blk += v.nblk;
-    const int pp = 256 / (2 * g.t + 1);
     v.blk0s = blks;
-    if (k == L.q) {
-      const int tp = std::min(16, g.nk / 2);
-      v.nblks = (g.nk / 2 / tp) * (g.nk / 2 / tp);
-    } else {
-      v.nblks = (int)((np2 + pp - 1) / pp);
-    }
+    v.nblks = (int)((np2 + 63) / 64);
     blks += v.nblks;
   }
   A.nlev = l;
   return A;
+}
+
+template <typename T>
+FineCG<T> make_fine_cg(gbl_ctx* c) {
+  const Layout& L = c->L;
+  const LevelGeom& g = L.lv[L.q];
+  const size_t np2 = (size_t)g.nk * g.nk / 4;
+  FineCG<T> F{};
+  F.g = reinterpret_cast<const T*>(c->ws + L.g_off[L.q]);
+  F.acell = c->hier<T>(L.acell_off);
+  F.BJ = c->hier<T>(g.offBJ);
+  T* base = reinterpret_cast<T*>(c->ws + L.fcg_off);
+  F.x = base;
+  F.u = base + 3 * np2;
+  F.p = base + 6 * np2;
+  F.r[0] = base + 9 * np2;
+  F.r[1] = base + 12 * np2;
+  F.w[0] = base + 15 * np2;
+  F.w[1] = base + 18 * np2;
+  F.s[0] = base + 21 * np2;
+  F.s[1] = base + 24 * np2;
+  F.scal = reinterpret_cast<double*>(c->ws + L.fcgscal_off);
+  F.cnt = reinterpret_cast<unsigned*>(F.scal + kNumFineScalars);
+  F.part = reinterpret_cast<double*>(c->ws + L.fcgpart_off);
+  F.np = g.nk / 2;
+  const int tp = std::min(16, F.np);
+  F.nblk = (F.np / tp) * (F.np / tp);
+  return F;
 }
 
 template <typename T>
@@ -314,47 +360,96 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
 }
 
 // z = S r: the subband solve of the localized hierarchy applied to the fine
-// residual r (FP64 slot vectors); inner arithmetic in T.
+// residual r (FP64 slot vectors); inner arithmetic in T.  The finest subband
+// system runs on the caller's stream while the coarser ones run beside it on
+// a second stream (the subband systems are independent, Section 4.7).
 template <typename T>
-void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, hipStream_t st) {
+const FineCG<T>& fcg_of(const gbl_ctx* c);
+
+// r_converted: g^(q) already holds T(r).  When dots is set, the finest
+// prolongation also forms (z, z), (u, u), (z, w) into dots[0..3).
+template <typename T>
+void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, hipStream_t st,
+                  bool r_converted = false, const double* uo = nullptr, const double* wo = nullptr,
+                  double* dots = nullptr) {
   const Layout& L = c->L;
   const int q = L.q;
   const size_t n2 = (size_t)L.n * L.n;
   T* g[kMaxLevels];
   for (int k = 1; k <= q; ++k) g[k] = reinterpret_cast<T*>(c->ws + L.g_off[k]);
-  launch_convert<T, double>(n2, r, g[q], st);
-  for (int k = q; k >= 2; --k) {
+  const FineCG<T>& F = fcg_of<T>(c);
+  // levels 2..kc (at most 16 x 16 slots, never the finest) run in one workgroup
+  const int kc = std::min(q - 1, 4);
+  ChainArgs<T> chain{};
+  chain.n = std::max(0, kc - 1);
+  chain.g1 = g[1];
+  for (int k = 2; k <= kc; ++k) {
+    ChainLevel<T>& cl = chain.lv[k - 2];
+    cl.R = c->hier<T>(L.lv[k].offR);
+    cl.gf = g[k];
+    cl.gc = g[k - 1];
+    cl.w = cg.lv[q - 1 - k].x;
+    cl.nk = L.lv[k].nk;
+    cl.rho = L.lv[k].rho;
+    cl.fine = 0;
+  }
+  if (!r_converted) launch_convert<T, double>(n2, r, g[q], st);
+  for (int k = q; k > kc; --k) {
     ProfScope ps(GBL_PROF_RESTRICT, st);
     launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], st);
   }
   {
-    const CGLev<T>& last = cg.lv[cg.nlev - 1];
-    ProfScope ps(GBL_PROF_CG_INIT, st);
-    launch_cg_init<T>(cg, last.blk0 + last.nblk, st);
+    ProfScope ps(GBL_PROF_RESTRICT, st);
+    launch_restrict_chain<T>(chain, st);
   }
-  // levels are ordered finest first; launch only up to the last level whose
-  // iteration budget is not yet spent (levels in between exit on their own)
-  const int itmax = std::max(c->opts.inner_iters, c->opts.inner_iters_coarse);
-  for (int it = 0; it < itmax; ++it) {
-    int lastl = -1;
-    for (int l = 0; l < cg.nlev; ++l)
-      if (it < cg.lv[l].iters) lastl = l;
-    if (lastl < 0) break;
-    const CGLev<T>& lv = cg.lv[lastl];
+  const bool coarse = cg.nlev > 0 && c->opts.inner_iters_coarse > 0;
+  hipStream_t cs = c->side ? c->side : st;
+  if (coarse && c->side) {
+    hipEventRecord(c->ev_fork, st);
+    hipStreamWaitEvent(cs, c->ev_fork, 0);
+  }
+  // finest level (its last step x += alpha p is applied inside the prolongation)
+  for (int it = 0; it < c->opts.inner_iters; ++it) {
+    ProfScope ps(GBL_PROF_FINE_CG, st);
+    launch_fine_cg<T>(F, it, st);
+  }
+  // coarser levels, beside it on the second stream
+  if (coarse) {
     {
-      ProfScope ps(GBL_PROF_CG_SPMV, st);
-      launch_cg_spmv<T>(cg, lv.blk0s + lv.nblks, it, st);
+      const CGLev<T>& last = cg.lv[cg.nlev - 1];
+      ProfScope ps(GBL_PROF_CG_INIT, cs);
+      launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
     }
-    ProfScope ps(GBL_PROF_CG_UPDATE, st);
-    launch_cg_update<T>(cg, lv.blk0 + lv.nblk, it, st);
+    for (int it = 0; it < c->opts.inner_iters_coarse; ++it) {
+      const CGLev<T>& lv = cg.lv[cg.nlev - 1];
+      {
+        ProfScope ps(GBL_PROF_CG_SPMV, cs);
+        launch_cg_spmv<T>(cg, lv.blk0s + lv.nblks, it, cs);
+      }
+      ProfScope ps(GBL_PROF_CG_UPDATE, cs);
+      launch_cg_update<T>(cg, lv.blk0 + lv.nblk, it, cs);
+    }
+    if (c->side) {
+      hipEventRecord(c->ev_join, cs);
+      hipStreamWaitEvent(st, c->ev_join, 0);
+    }
+  } else {
+    for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, st);
   }
-  launch_coarse_solve<T>(c->L1(), g[1], g[1], st);
-  for (int k = 2; k <= q; ++k) {
-    const int l = q - k;
+  {
     ProfScope ps(GBL_PROF_PROLONG, st);
-    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[l].x, g[k], k == q, st);
+    launch_prolong_chain<T>(chain, c->L1(), st);
   }
-  launch_convert<double, T>(n2, g[q], z, st);
+  for (int k = kc + 1; k < q; ++k) {
+    ProfScope ps(GBL_PROF_PROLONG, st);
+    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, st);
+  }
+  ProfScope ps(GBL_PROF_PROLONG, st);
+  double* part = reinterpret_cast<double*>(c->ws + L.dpart_off);
+  unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
+  // without a destination the sums still run (same kernel) into spare scalar slots
+  launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z, part,
+                              cnt, dots ? dots : c->oscal() + kSSpare, st);
 }
 
 // Flexible CG on the FP64 fine system with the subband solve as
@@ -380,26 +475,33 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   launch_outer_direction(len, sc, z, p, 1, st);
   int it = 0;
   int status = GBL_ENOCONV;
-  double est = 1.0;
-  // ||z|| = ||S r|| estimates the error only up to the quality of S; keep a margin
-  const double tol = 0.1 * c->opts.rtol;
+  double est = 1.0, prev = INFINITY;
+  // Error estimate: z = S r approximates the error and alpha p is the last
+  // correction; either alone can under-read the error when the inner solves
+  // are loose, so the larger of the two over the last two iterations is
+  // tested against rtol / 3.
+  const double tol = c->opts.rtol / 3.0;
   for (it = 1; it <= c->opts.max_outer; ++it) {
     {
       ProfScope ps(GBL_PROF_FINE_APPLY, st);
-      launch_apply_fine(c->a(), n, p, w, st);
+      launch_apply_fine_dots(c->a(), n, p, r, w, part, cnt, sc + kSPW, st);
     }
-    launch_dots(len, 2, p, w, p, r, nullptr, nullptr, part, cnt, sc + kSPW, st);
-    launch_outer_update(len, sc, u, r, p, w, st);
-    precondition<T>(c, cg, r, z, st);
-    launch_dots(len, 3, z, z, u, u, z, w, part, cnt, sc + kSZZ, st);
+    launch_outer_update_convert<T>(len, sc, u, r, p, w, reinterpret_cast<T*>(c->ws + L.g_off[L.q]), st);
+    precondition<T>(c, cg, r, z, st, true, u, w, sc + kSZZ);
     HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     const double zz = c->host[kSZZ], uu = c->host[kSUU];
-    est = (uu > 0.0) ? std::sqrt(zz / uu) : (zz > 0.0 ? 1.0 : 0.0);
-    if (!std::isfinite(est)) {
+    const double pw = c->host[kSPW], pr = c->host[kSPR], pp = c->host[kSPP];
+    const double alpha = pw > 0.0 ? pr / pw : 0.0;
+    const double cur = (uu > 0.0) ? std::max(std::sqrt(zz / uu), std::fabs(alpha) * std::sqrt(pp / uu))
+                                  : ((zz > 0.0 || pp > 0.0) ? 1.0 : 0.0);
+    if (!std::isfinite(cur)) {
+      est = cur;
       status = GBL_ENOCONV;
       break;
     }
+    est = std::max(cur, prev);
+    prev = cur;
     if (est <= tol) {
       status = GBL_OK;
       break;
@@ -429,6 +531,12 @@ template <>
 const CGArgs<float>& cg_of<float>(const gbl_ctx* c) { return c->cgf; }
 template <>
 const CGArgs<double>& cg_of<double>(const gbl_ctx* c) { return c->cgd; }
+template <typename T>
+const FineCG<T>& fcg_of(const gbl_ctx* c);
+template <>
+const FineCG<float>& fcg_of<float>(const gbl_ctx* c) { return c->fcgf; }
+template <>
+const FineCG<double>& fcg_of<double>(const gbl_ctx* c) { return c->fcgd; }
 
 template <typename T>
 int solve_many(gbl_ctx* c, int nrhs, int mode, const double* src, size_t src_stride, double* u,
@@ -454,10 +562,10 @@ int gbl_default_opts(gbl_opts* o) {
   o->rho = 3;
   o->precision = GBL_MIXED;
   o->rtol = 1e-8;
-  o->max_outer = 60;
-  o->inner_iters = 24;
+  o->max_outer = 100;
+  o->inner_iters = 8;
   o->max_rhs = 1;
-  o->inner_iters_coarse = 6;
+  o->inner_iters_coarse = 3;
   return GBL_OK;
 }
 
@@ -490,14 +598,14 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->ws = static_cast<char*>(ws_dev);
   c->ws_bytes = ws_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4) * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, GBL_EHIP, "hipHostMalloc failed");
   }
   auto bail = [&](int code) {
     g_last_error = c->err;
-    hipHostFree(c->host);
-    delete c;
+    release(c);
     return code;
   };
   const size_t n2 = (size_t)L.n * L.n;
@@ -513,15 +621,23 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   }
   c->cgf = make_cg_args<float>(c);
   c->cgd = make_cg_args<double>(c);
+  c->fcgf = make_fine_cg<float>(c);
+  c->fcgd = make_fine_cg<double>(c);
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    c->err = "stream or event creation failed";
+    return bail(GBL_EHIP);
+  }
   st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
   if (st) return bail(st);
-  if (hipMemcpyAsync(c->host + 8, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(c->host + kNumOuterScalars, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "status read failed";
     return bail(GBL_EHIP);
   }
   int bits = 0;
-  std::memcpy(&bits, c->host + 8, sizeof(int));
+  std::memcpy(&bits, c->host + kNumOuterScalars, sizeof(int));
   if (bits & kBadCoefficient) {
     c->err = "coefficient must be positive and finite in every cell";
     return bail(GBL_EINVAL);
@@ -623,8 +739,7 @@ int gbl_profile_read(int kernel, double* total_ms, long* launches) {
 
 int gbl_destroy(gbl_ctx* c) {
   if (!c) return GBL_OK;
-  if (c->host) hipHostFree(c->host);
-  delete c;
+  release(c);
   return GBL_OK;
 }
 

@@ -64,9 +64,9 @@ void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t
 
 // ---------------------------------------------------------------------------
 // Subband operator B^(k) = W^(k) A^(k) W^(k)T (eq. defining B, Section 4.7;
-// Algorithm 2, line 7) in parent-block stencil form, offset-major:
-// B[(o*9 + 3i + j)][px*np+py] with o = ox*(2t+1)+oy the neighbour parent
-// offset and (i, j) the 3x3 block entry, plus the inverse of every 3x3 diagonal block
+// Algorithm 2, line 7) in parent-block stencil form (entry (o, 3i + j) of
+// parent p couples subband row (p, i) to (p + o - t, j); block-interleaved
+// layout, see b_index), plus the inverse of every 3x3 diagonal block
 // (block-Jacobi preconditioner of the subband CG).  One thread per
 // (parent, neighbour parent) pair.
 // ---------------------------------------------------------------------------
@@ -95,9 +95,9 @@ __global__ void k_subband_operator(const T* __restrict__ A, T* __restrict__ B, T
   const int ox = o / TT, oy = o % TT;
   const int qx = px + ox - t, qy = py + oy - t;
   const size_t np2 = (size_t)np * np;
-  T* out = B + (size_t)o * 9 * np2 + p;   // B[(o*9 + e) * np2 + p]
+  T* out = B + b_index(o, 0, p, TT);   // entry e at out[64 e]
   if (qx < 0 || qy < 0 || qx >= np || qy >= np) {
-    for (int e = 0; e < 9; ++e) out[e * np2] = T(0);
+    for (int e = 0; e < 9; ++e) out[64 * e] = T(0);
     return;
   }
   const int tp = parent_type(fine != 0, px, py);
@@ -134,7 +134,7 @@ __global__ void k_subband_operator(const T* __restrict__ A, T* __restrict__ B, T
     }
   }
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) out[(i * 3 + j) * np2] = T(Bl[i][j]);
+    for (int j = 0; j < 3; ++j) out[64 * (i * 3 + j)] = T(Bl[i][j]);
   if (center) {
     // inverse of the symmetric 3x3 diagonal block by cofactors
     const double a0 = Bl[0][0], a1 = Bl[0][1], a2 = Bl[0][2];
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
     if (r < p) {
       const int lp = r / 3, tt = r - 3 * lp;
       const int px = x0 + lp / wy, py = y0 + lp % wy;
-      const T d = B[((size_t)(t * TT + t) * 9 + tt * 4) * nc2 + px * nc + py];
+      const T d = B[b_index(t * TT + t, tt * 4, px * nc + py, TT)];
       if (d > T(0)) {
         scale = T(1) / my_sqrt<T>(d);
       } else {
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
           const int ox = qx - rx + t, oy = qy - ry + t;
           T bv = T(0);
           if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
-            bv = B[((size_t)(ox * TT + oy) * 9 + trr * 3 + tcc) * nc2 + rx * nc + ry];
+            bv = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)];
           v = bv * sc[r] * sc[c];
         } else {
           v = T(0);
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
   for (int r = lane; r < p; r += 64) {
     const int lp = r / 3, tt = r - 3 * lp;
     const int px = x0 + lp / wy, py = y0 + lp % wy;
-    const T d = B[((size_t)(1 * TT + 1) * 9 + tt * 4) * nc2 + px * nc + py];
+    const T d = B[b_index(1 * TT + 1, tt * 4, px * nc + py, TT)];
     T scale = T(1);
     if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
     else bad = 1;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
       const int qx = x0 + lc / wy, qy = y0 + lc % wy;
       const int ox = qx - rx + 1, oy = qy - ry + 1;
       if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
-        v = B[((size_t)(ox * TT + oy) * 9 + trr * 3 + tcc) * nc2 + rx * nc + ry] * sc[r] * sc[c];
+        v = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)] * sc[r] * sc[c];
     }
     ab[e] = v;
   }

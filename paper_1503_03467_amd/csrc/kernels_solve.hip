@@ -196,6 +196,55 @@ __global__ void k_outer_direction(int len, const double* __restrict__ sc, const 
   }
 }
 
+// w = A p fused with the sums (p, w), (p, r), (p, p) -> out[0..3).
+__global__ __launch_bounds__(256) void k_apply_fine_dots(const double* __restrict__ a, int n,
+                                                         const double* __restrict__ p, const double* __restrict__ r,
+                                                         double* __restrict__ w, double* part, unsigned* cnt,
+                                                         double* out) {
+  __shared__ double sh[3 * 16];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < n * n; id += gridDim.x * blockDim.x) {
+    const int x = id / n, y = id % n;
+    double wv = 0.0;
+    if (x != 0 && y != 0) {
+      auto U = [&](int i, int j) -> double {
+        if (i == 0 || j == 0 || i == n || j == n) return 0.0;
+        return p[i * n + j];
+      };
+      wv = apply_fine(a, n, x, y, U);
+    }
+    w[id] = wv;
+    const double pv = p[id];
+    v[0] += pv * wv;
+    v[1] += pv * r[id];
+    v[2] += pv * pv;
+  }
+  block_sum<3>(v, sh);
+  bool last;
+  double res[3];
+  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last, sh);
+  if (last) {
+    out[0] = res[0];
+    out[1] = res[1];
+    out[2] = res[2];
+  }
+}
+
+// alpha = (p, r) / (p, w); u += alpha p; r -= alpha w; g = T(r) (input of the subband solve)
+template <typename T>
+__global__ void k_outer_update_convert(int len, const double* __restrict__ sc, double* __restrict__ u,
+                                       double* __restrict__ r, const double* __restrict__ p,
+                                       const double* __restrict__ w, T* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double pw = sc[kSPW], pr = sc[kSPR];
+  const double alpha = (pw > 0.0) ? pr / pw : 0.0;
+  u[i] += alpha * p[i];
+  const double rn = r[i] - alpha * w[i];
+  r[i] = rn;
+  g[i] = T(rn);
+}
+
 // slot vector -> nodal interior (boundary entries untouched)
 __global__ void k_slots_to_nodal(int n, const double* __restrict__ s, double* __restrict__ u) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,15 +327,11 @@ void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStre
 // restriction rows of the (2 rho + 1)^2 coarse slots whose patch covers it.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, const T* __restrict__ w,
-                          T* __restrict__ vf, int nk, int rho, int fine) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nk * nk) return;
+__device__ __forceinline__ T prolong_at(const T* __restrict__ R, const T* __restrict__ vc, int nk, int rho,
+                                        int fx, int fy) {
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
-  const int fx = id / nk, fy = id % nk;
   const int px = fx >> 1, py = fy >> 1;
-  const int d = 2 * (fx & 1) + (fy & 1);
   const int rw = 2 * (2 * rho + 1);
   T acc = T(0);
   const int ixl = max(0, px - rho), ixh = min(nc - 1, px + rho);
@@ -299,11 +344,38 @@ __global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, con
       acc += R[(size_t)(bx * rw + by) * nc2 + i] * vc[i];
     }
   }
+  return acc;
+}
+
+// w^(k) for the subband sum: the CG iterate, or for the finest level the
+// iterate plus its pending last step x + alpha (u + beta p) when scal is set.
+template <typename T>
+__global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, const T* __restrict__ w,
+                          T* __restrict__ vf, int nk, int rho, int fine, const T* __restrict__ u,
+                          const T* __restrict__ pdir, const double* __restrict__ scal, double* __restrict__ zout) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nk * nk) return;
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int fx = id / nk, fy = id % nk;
+  T acc = prolong_at<T>(R, vc, nk, rho, fx, fy);
+  const int px = fx >> 1, py = fy >> 1;
+  const int d = 2 * (fx & 1) + (fy & 1);
   const int tp = parent_type(fine != 0, px, py);
   const int p = px * nc + py;
+  T alpha = T(0), beta = T(0);
+  if (scal) {
+    alpha = T(scal[kFAlpha]);
+    beta = T(scal[kFBeta]);
+  }
 #pragma unroll
-  for (int t = 0; t < 3; ++t) acc += T(wcoef(tp, t, d)) * w[t * nc2 + p];
-  vf[id] = acc;
+  for (int t = 0; t < 3; ++t) {
+    T wt = w[t * nc2 + p];
+    if (scal) wt += alpha * (u[t * nc2 + p] + beta * pdir[t * nc2 + p]);
+    acc += T(wcoef(tp, t, d)) * wt;
+  }
+  if (zout) zout[id] = (double)acc;
+  else vf[id] = acc;
 }
 
 template <typename T>
@@ -311,7 +383,156 @@ void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* 
                     hipStream_t st) {
   const int tot = L.nk * L.nk;
   hipLaunchKernelGGL(k_prolong<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, w, vf, L.nk, L.rho,
-                     fine ? 1 : 0);
+                     fine ? 1 : 0, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, (double*)nullptr);
+}
+
+// Finest level: z = R^T v^(q-1) + W^T (x + alpha (u + beta p)) in FP64,
+// fused with the sums (z, z), (u_out, u_out), (z, w_out) of the outer iteration.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__ R, const T* __restrict__ vc,
+                                                           FineCG<T> F, int nk, int rho, double* __restrict__ z,
+                                                           const double* __restrict__ uo,
+                                                           const double* __restrict__ wo, double* part, unsigned* cnt,
+                                                           double* out) {
+  __shared__ double sh[3 * 16];
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const T alpha = T(F.scal[kFAlpha]), beta = T(F.scal[kFBeta]);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < nk * nk; id += gridDim.x * blockDim.x) {
+    const int fx = id / nk, fy = id % nk;
+    T acc = prolong_at<T>(R, vc, nk, rho, fx, fy);
+    const int px = fx >> 1, py = fy >> 1;
+    const int d = 2 * (fx & 1) + (fy & 1);
+    const int tp = parent_type(true, px, py);
+    const int pp = px * nc + py;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const T wt = F.x[t * nc2 + pp] + alpha * (F.u[t * nc2 + pp] + beta * F.p[t * nc2 + pp]);
+      acc += T(wcoef(tp, t, d)) * wt;
+    }
+    const double zv = (double)acc;
+    z[id] = zv;
+    const double uv = uo[id];
+    v[0] += zv * zv;
+    v[1] += uv * uv;
+    v[2] += zv * wo[id];
+  }
+  block_sum<3>(v, sh);
+  bool last;
+  double res[3];
+  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last, sh);
+  if (last) {
+    out[0] = res[0];
+    out[1] = res[1];
+    out[2] = res[2];
+  }
+}
+
+template <typename T>
+void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
+                              const double* uo, const double* wo, double* part, unsigned* cnt, double* out,
+                              hipStream_t st) {
+  const int tot = L.nk * L.nk;
+  int nb = (tot + 255) / 256;
+  if (nb > kDotBlocks) nb = kDotBlocks;
+  hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3(nb), dim3(256), 0, st, R, vc, F, L.nk, L.rho, z, uo, wo, part, cnt,
+                     out);
+}
+
+template <typename T>
+void launch_outer_update_convert(int len, const double* sc, double* u, double* r, const double* p, const double* w,
+                                 T* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_outer_update_convert<T>, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, u, r, p, w, g);
+}
+
+void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
+                            unsigned* cnt, double* out, hipStream_t st) {
+  int nb = (n * n + 255) / 256;
+  if (nb > kDotBlocks) nb = kDotBlocks;
+  hipLaunchKernelGGL(k_apply_fine_dots, dim3(nb), dim3(256), 0, st, a, n, p, r, w, part, cnt, out);
+}
+
+// Small levels in one workgroup.  Restriction g^(k-1) = R g^(k) for k = khi..2;
+// then the coarse solve and the prolongations v^(k) for k = 2..khi, with a
+// workgroup barrier between levels.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c) {
+  __shared__ T red[64 * 18];
+  for (int j = c.n - 1; j >= 0; --j) {
+    const ChainLevel<T>& L = c.lv[j];
+    const int nc = L.nk / 2;
+    const size_t nc2 = (size_t)nc * nc;
+    const int rw = 2 * (2 * L.rho + 1);
+    // work item (cell i, row bx): partial sum over the row, then rows are added
+    for (int e = threadIdx.x; e < nc * nc * rw; e += blockDim.x) {
+      const int i = e / rw, bx = e - (e / rw) * rw;
+      const int cx = i / nc, cy = i % nc;
+      const int ox = 2 * (cx - L.rho), oy = 2 * (cy - L.rho);
+      const int fx = ox + bx;
+      T acc = T(0);
+      if (fx >= 0 && fx < L.nk) {
+        const int byl = max(0, -oy), byh = min(rw - 1, L.nk - 1 - oy);
+        for (int by = byl; by <= byh; ++by)
+          acc += L.R[(size_t)(bx * rw + by) * nc2 + i] * L.gf[(size_t)fx * L.nk + oy + by];
+      }
+      red[e] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
+      T acc = T(0);
+      for (int bx = 0; bx < rw; ++bx) acc += red[i * rw + bx];
+      L.gc[i] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_prolong_chain(ChainArgs<T> c, const double* __restrict__ L1) {
+  if (threadIdx.x == 0) {
+    // coarsest system with the FP64 Cholesky factor of A^(1)
+    double y[4];
+    for (int i = 0; i < 4; ++i) {
+      double v = (double)c.g1[i];
+      for (int k = 0; k < i; ++k) v -= L1[i * 4 + k] * y[k];
+      y[i] = v / L1[i * 4 + i];
+    }
+    for (int i = 3; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < 4; ++k) v -= L1[k * 4 + i] * y[k];
+      y[i] = v / L1[i * 4 + i];
+    }
+    for (int i = 0; i < 4; ++i) c.g1[i] = T(y[i]);
+  }
+  __syncthreads();
+  for (int j = 0; j < c.n; ++j) {
+    const ChainLevel<T>& L = c.lv[j];
+    const int nc = L.nk / 2;
+    const size_t nc2 = (size_t)nc * nc;
+    for (int id = threadIdx.x; id < L.nk * L.nk; id += blockDim.x) {
+      const int fx = id / L.nk, fy = id % L.nk;
+      T acc = prolong_at<T>(L.R, L.gc, L.nk, L.rho, fx, fy);
+      const int px = fx >> 1, py = fy >> 1;
+      const int d = 2 * (fx & 1) + (fy & 1);
+      const int tp = parent_type(L.fine != 0, px, py);
+      const int p = px * nc + py;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc += T(wcoef(tp, t, d)) * L.w[t * nc2 + p];
+      L.gf[id] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st) {
+  if (c.n == 0) return;
+  hipLaunchKernelGGL(k_restrict_chain<T>, dim3(1), dim3(1024), 0, st, c);
+}
+template <typename T>
+void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1), dim3(1024), 0, st, c, L1);
 }
 
 // Coarsest system A^(1) U^(1) = g^(1) (Algorithm 2, line 16) with the FP64
@@ -414,166 +635,61 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
   }
 }
 
-// Finest level, matrix-free: B^(q) z = W (A (W^T z)) with A applied from the
-// cell coefficient.  A workgroup owns a TP x TP tile of parents (one thread
-// each); the nodal values W^T z of the tile plus a one-parent halo and the
-// coefficients of the cells they touch are staged in LDS.  Padding subband
-// rows act as identity rows, as in the assembled B^(q).
-template <typename T>
-__device__ __forceinline__ void fine_operator(const CGLev<T>& L, int blk, T* lds, T (&y)[3], int& pout) {
-  const int np = L.np;
-  const int nk = 2 * np;
-  const size_t np2 = (size_t)np * np;
-  const int TP = np < 16 ? np : 16;
-  const int ntx = np / TP;
-  const int tx = blk / ntx, ty = blk - (blk / ntx) * ntx;
-  const int px0 = tx * TP, py0 = ty * TP;
-  const int VW = 2 * TP + 4;       // nodes 2(px0-1) .. 2(px0+TP)+1
-  const int AW = 2 * TP + 1;       // cells 2px0-1 .. 2(px0+TP)-1
-  T* vl = lds;
-  T* al = lds + VW * VW;
-  const int tid = threadIdx.x;
-  const int HW = TP + 2;
-  for (int e = tid; e < HW * HW; e += blockDim.x) {
-    const int hx = e / HW, hy = e - (e / HW) * HW;
-    const int px = px0 - 1 + hx, py = py0 - 1 + hy;
-    T z0 = T(0), z1 = T(0), z2 = T(0);
-    int tp = 0;
-    const bool in = px >= 0 && py >= 0 && px < np && py < np;
-    if (in) {
-      const int q = px * np + py;
-      z0 = L.z[q];
-      z1 = L.z[np2 + q];
-      z2 = L.z[2 * np2 + q];
-      tp = parent_type(true, px, py);
-    }
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      T v = T(0);
-      if (in) v = T(wcoef(tp, 0, d)) * z0 + T(wcoef(tp, 1, d)) * z1 + T(wcoef(tp, 2, d)) * z2;
-      vl[(2 * hx + (d >> 1)) * VW + 2 * hy + (d & 1)] = v;
-    }
-  }
-  for (int e = tid; e < AW * AW; e += blockDim.x) {
-    const int cxl = e / AW, cyl = e - (e / AW) * AW;
-    const int cx = 2 * px0 - 1 + cxl, cy = 2 * py0 - 1 + cyl;
-    al[e] = (cx >= 0 && cy >= 0 && cx < nk && cy < nk) ? L.acell[(size_t)cx * nk + cy] : T(0);
-  }
-  __syncthreads();
-  pout = -1;
-  if (tid < TP * TP) {
-    const int px = px0 + tid / TP, py = py0 + tid % TP;
-    const int tp = parent_type(true, px, py);
-    T Av[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int x = 2 * px + (d >> 1), yy = 2 * py + (d & 1);
-      if (x == 0 || yy == 0) {
-        Av[d] = T(0);
-        continue;
-      }
-      const int vx = x - 2 * (px0 - 1), vy = yy - 2 * (py0 - 1);
-      const int ax = x - (2 * px0 - 1), ay = yy - (2 * py0 - 1);
-      const T a00 = al[(ax - 1) * AW + (ay - 1)], a10 = al[ax * AW + (ay - 1)];
-      const T a01 = al[(ax - 1) * AW + ay], a11 = al[ax * AW + ay];
-      const T* v = vl + vx * VW + vy;
-      T acc = T(2.0 / 3.0) * (a00 + a10 + a01 + a11) * v[0];
-      acc -= (a10 + a11) * T(1.0 / 6.0) * v[VW];
-      acc -= (a00 + a01) * T(1.0 / 6.0) * v[-VW];
-      acc -= (a01 + a11) * T(1.0 / 6.0) * v[1];
-      acc -= (a00 + a10) * T(1.0 / 6.0) * v[-1];
-      acc -= a11 * T(1.0 / 3.0) * v[VW + 1];
-      acc -= a00 * T(1.0 / 3.0) * v[-VW - 1];
-      acc -= a10 * T(1.0 / 3.0) * v[VW - 1];
-      acc -= a01 * T(1.0 / 3.0) * v[-VW + 1];
-      Av[d] = acc;
-    }
-    const int pp = px * np + py;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      if (is_pad_row(tp, t)) {
-        y[t] = L.z[t * np2 + pp];
-      } else {
-        y[t] = T(wcoef(tp, t, 0)) * Av[0] + T(wcoef(tp, t, 1)) * Av[1] + T(wcoef(tp, t, 2)) * Av[2] +
-               T(wcoef(tp, t, 3)) * Av[3];
-      }
-    }
-    pout = pp;
-  }
-}
-
-// Coarser levels, stored block stencil: one workgroup covers PP = 256/(2t+1)
-// consecutive parents; thread (ox, pl) accumulates the neighbour row ox of
-// parent pl and the partial products are summed over ox in LDS.
-template <typename T>
-__device__ __forceinline__ void stencil_operator(const CGLev<T>& L, int blk, T* red, T (&y)[3], int& pout) {
-  const int np = L.np;
-  const size_t np2 = (size_t)np * np;
-  const int t = L.t, TT = 2 * L.t + 1;
-  const int PP = 256 / TT;
-  const int tid = threadIdx.x;
-  const int ox = tid / PP, pl = tid - ox * PP;
-  const int p = blk * PP + pl;
-  T acc[3] = {T(0), T(0), T(0)};
-  if (ox < TT && p < np * np) {
-    const int px = p / np, py = p - px * np;
-    const int qx = px + ox - t;
-    if (qx >= 0 && qx < np) {
-      const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
-      for (int oy = oyl; oy <= oyh; ++oy) {
-        const int qn = qx * np + (py + oy - t);
-        const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
-        const T* Bb = L.B + (size_t)(ox * TT + oy) * 9 * np2 + p;
-        acc[0] += Bb[0] * z0 + Bb[np2] * z1 + Bb[2 * np2] * z2;
-        acc[1] += Bb[3 * np2] * z0 + Bb[4 * np2] * z1 + Bb[5 * np2] * z2;
-        acc[2] += Bb[6 * np2] * z0 + Bb[7 * np2] * z1 + Bb[8 * np2] * z2;
-      }
-    }
-  }
-  if (ox < TT) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) red[(i * TT + ox) * PP + pl] = acc[i];
-  }
-  __syncthreads();
-  pout = -1;
-  if (tid < PP) {
-    const int pp = blk * PP + tid;
-    if (pp < np * np) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        T s = T(0);
-        for (int o = 0; o < TT; ++o) s += red[(i * TT + o) * PP + tid];
-        y[i] = s;
-      }
-      pout = pp;
-    }
-  }
-}
-
+// Coarser levels, stored block stencil.  A workgroup covers 64 consecutive
+// parents (the lanes of every wavefront) and has one wavefront per neighbour
+// row ox of the parent stencil, so each load instruction of a wavefront
+// reads 64 consecutive words; the rows are summed in LDS.
 // q = B z + beta q, p = z + beta p and the partial sums of (p, q); the last
 // block of each level forms alpha = (r, z) / (p, q).
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_spmv(CGArgs<T> args, int it) {
+__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it) {
   __shared__ double sh[16];
-  __shared__ T lds[36 * 36 + 33 * 33];   // covers the fine tile (TP = 16) and the 3 x 256 partials
+  __shared__ T red[3 * 16 * 64];
   const int l = find_level_s(args, blockIdx.x);
   const CGLev<T>& L = args.lv[l];
   if (it >= L.iters) return;
   const int blk = blockIdx.x - L.blk0s;
-  const size_t np2 = (size_t)L.np * L.np;
-  T y[3] = {T(0), T(0), T(0)};
-  int pp = -1;
-  if (L.acell) fine_operator<T>(L, blk, lds, y, pp);
-  else stencil_operator<T>(L, blk, lds, y, pp);
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int t = L.t, TT = 2 * L.t + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int p = blk * 64 + lane;
+  T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+  if (p < np * np) {
+    const int px = p / np, py = p - (p / np) * np;
+    const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
+    for (int ox = wv; ox < TT; ox += nw) {
+      const int qx = px + ox - t;
+      if (qx < 0 || qx >= np) continue;
+      const T* Bo = L.B + b_index(ox * TT, 0, p, TT);
+      const int qb = qx * np + py - t;
+#pragma unroll 4
+      for (int oy = oyl; oy <= oyh; ++oy) {
+        const int qn = qb + oy;
+        const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
+        const T* Bb = Bo + oy * 9 * 64;
+        acc0 += Bb[0] * z0 + Bb[64] * z1 + Bb[128] * z2;
+        acc1 += Bb[192] * z0 + Bb[256] * z1 + Bb[320] * z2;
+        acc2 += Bb[384] * z0 + Bb[448] * z1 + Bb[512] * z2;
+      }
+    }
+  }
+  red[(0 * 16 + wv) * 64 + lane] = acc0;
+  red[(1 * 16 + wv) * 64 + lane] = acc1;
+  red[(2 * 16 + wv) * 64 + lane] = acc2;
+  __syncthreads();
   double v[1] = {0.0};
-  if (pp >= 0) {
+  if (threadIdx.x < 64 && p < np * np) {
     const T beta = T(L.scal[kCBETA]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const T qv = y[i] + beta * L.q[i * np2 + pp];
-      const T pv = L.z[i * np2 + pp] + beta * L.p[i * np2 + pp];
-      L.q[i * np2 + pp] = qv;
-      L.p[i * np2 + pp] = pv;
+      T sum = T(0);
+      for (int w = 0; w < nw; ++w) sum += red[(i * 16 + w) * 64 + lane];
+      const T qv = sum + beta * L.q[i * np2 + p];
+      const T pv = L.z[i * np2 + p] + beta * L.p[i * np2 + p];
+      L.q[i * np2 + p] = qv;
+      L.p[i * np2 + p] = pv;
       v[0] += (double)(pv * qv);
     }
   }
@@ -635,11 +751,205 @@ void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st) {
 }
 template <typename T>
 void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(256), 0, st, a, it);
+  int tmax = 1;
+  for (int l = 0; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
+  const int nw = tmax < 16 ? tmax : 16;
+  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(64 * nw), 0, st, a, it);
 }
 template <typename T>
 void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a, it);
+}
+
+// ---------------------------------------------------------------------------
+// Finest subband system B^(q) w = W g^(q), preconditioned CG in the
+// Chronopoulos-Gear arrangement: iteration i forms, per parent,
+//   p_{i-1} = u_{i-1} + b p_{i-2},  s_{i-1} = w_{i-1} + b s_{i-2},
+//   x_i = x_{i-1} + a p_{i-1},      r_i = r_{i-1} - a s_{i-1},
+//   u_i = M r_i,  w_i = B u_i,  and the sums (r_i, u_i), (w_i, u_i),
+// from which the last block forms the next a, b.  B u needs u on a
+// one-parent halo of the tile; the halo values are recomputed from the old
+// r, w, s (double buffered), so a single launch covers one iteration.
+// it == 0 starts from x = 0, r = W g.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F, int it) {
+  __shared__ double sh[32];
+  __shared__ T lds[3 * 18 * 18 + 36 * 36 + 33 * 33 + 3 * 16 * 16];
+  const int np = F.np;
+  const int nk = 2 * np;
+  const size_t np2 = (size_t)np * np;
+  const int TP = np < 16 ? np : 16;
+  const int ntx = np / TP;
+  const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tx = blk / ntx, ty = blk - (blk / ntx) * ntx;
+  const int px0 = tx * TP, py0 = ty * TP;
+  const int HW = TP + 2;
+  const int VW = 2 * TP + 4;
+  const int AW = 2 * TP + 1;
+  T* ul = lds;                 // u at tile + halo parents, [t][hx][hy]
+  T* vl = ul + 3 * HW * HW;    // nodal W^T u
+  T* al = vl + VW * VW;        // cell coefficients
+  T* rl = al + AW * AW;        // r_i of the tile's own parents, [t][lx][ly]
+  const int tid = threadIdx.x;
+  // cell coefficients do not depend on the iteration: stage them first
+  for (int e = tid; e < AW * AW; e += blockDim.x) {
+    const int cxl = e / AW, cyl = e - (e / AW) * AW;
+    const int cx = 2 * px0 - 1 + cxl, cy = 2 * py0 - 1 + cyl;
+    al[e] = (cx >= 0 && cy >= 0 && cx < nk && cy < nk) ? F.acell[(size_t)cx * nk + cy] : T(0);
+  }
+  const int rd = (it + 1) & 1, wr = it & 1;   // buffers read / written by this iteration
+  const T alpha = it ? T(F.scal[kFAlpha]) : T(0);
+  const T beta = it ? T(F.scal[kFBeta]) : T(0);
+
+  for (int e = tid; e < HW * HW; e += blockDim.x) {
+    const int hx = e / HW, hy = e - (e / HW) * HW;
+    const int px = px0 - 1 + hx, py = py0 - 1 + hy;
+    T u3[3] = {T(0), T(0), T(0)};
+    if (px >= 0 && py >= 0 && px < np && py < np) {
+      const int q = px * np + py;
+      const int tp = parent_type(true, px, py);
+      T r3[3], s3[3];
+      if (it == 0) {
+        T gc[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) gc[d] = F.g[(2 * px + (d >> 1)) * nk + 2 * py + (d & 1)];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          r3[t] = T(wcoef(tp, t, 0)) * gc[0] + T(wcoef(tp, t, 1)) * gc[1] + T(wcoef(tp, t, 2)) * gc[2] +
+                  T(wcoef(tp, t, 3)) * gc[3];
+          s3[t] = T(0);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          s3[t] = F.w[rd][t * np2 + q] + beta * F.s[rd][t * np2 + q];
+          r3[t] = F.r[rd][t * np2 + q] - alpha * s3[t];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        u3[i] = F.BJ[(i * 3 + 0) * np2 + q] * r3[0] + F.BJ[(i * 3 + 1) * np2 + q] * r3[1] +
+                F.BJ[(i * 3 + 2) * np2 + q] * r3[2];
+      if (hx >= 1 && hx <= TP && hy >= 1 && hy <= TP) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const size_t o = t * np2 + q;
+          if (it == 0) {
+            F.x[o] = T(0);
+            F.p[o] = T(0);
+          } else {
+            const T pn = F.u[o] + beta * F.p[o];
+            F.p[o] = pn;
+            F.x[o] += alpha * pn;
+          }
+          F.u[o] = u3[t];
+          F.r[wr][o] = r3[t];
+          F.s[wr][o] = s3[t];
+          rl[(t * TP + hx - 1) * TP + hy - 1] = r3[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) ul[(t * HW + hx) * HW + hy] = u3[t];
+  }
+  __syncthreads();
+  for (int e = tid; e < HW * HW; e += blockDim.x) {
+    const int hx = e / HW, hy = e - (e / HW) * HW;
+    const int px = px0 - 1 + hx, py = py0 - 1 + hy;
+    const bool in = px >= 0 && py >= 0 && px < np && py < np;
+    const int tp = in ? parent_type(true, px, py) : 3;
+    const T u0 = ul[(0 * HW + hx) * HW + hy], u1 = ul[(1 * HW + hx) * HW + hy], u2 = ul[(2 * HW + hx) * HW + hy];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      T v = T(0);
+      if (in) v = T(wcoef(tp, 0, d)) * u0 + T(wcoef(tp, 1, d)) * u1 + T(wcoef(tp, 2, d)) * u2;
+      vl[(2 * hx + (d >> 1)) * VW + 2 * hy + (d & 1)] = v;
+    }
+  }
+  __syncthreads();
+  double v[2] = {0.0, 0.0};
+  if (tid < TP * TP) {
+    const int lx = tid / TP, ly = tid - (tid / TP) * TP;
+    const int px = px0 + lx, py = py0 + ly;
+    const int tp = parent_type(true, px, py);
+    T Av[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int x = 2 * px + (d >> 1), yy = 2 * py + (d & 1);
+      if (x == 0 || yy == 0) {
+        Av[d] = T(0);
+        continue;
+      }
+      const int vx = x - 2 * (px0 - 1), vy = yy - 2 * (py0 - 1);
+      const int ax = x - (2 * px0 - 1), ay = yy - (2 * py0 - 1);
+      const T a00 = al[(ax - 1) * AW + (ay - 1)], a10 = al[ax * AW + (ay - 1)];
+      const T a01 = al[(ax - 1) * AW + ay], a11 = al[ax * AW + ay];
+      const T* vp = vl + vx * VW + vy;
+      T acc = T(2.0 / 3.0) * (a00 + a10 + a01 + a11) * vp[0];
+      acc -= (a10 + a11) * T(1.0 / 6.0) * vp[VW];
+      acc -= (a00 + a01) * T(1.0 / 6.0) * vp[-VW];
+      acc -= (a01 + a11) * T(1.0 / 6.0) * vp[1];
+      acc -= (a00 + a10) * T(1.0 / 6.0) * vp[-1];
+      acc -= a11 * T(1.0 / 3.0) * vp[VW + 1];
+      acc -= a00 * T(1.0 / 3.0) * vp[-VW - 1];
+      acc -= a10 * T(1.0 / 3.0) * vp[VW - 1];
+      acc -= a01 * T(1.0 / 3.0) * vp[-VW + 1];
+      Av[d] = acc;
+    }
+    const int q = px * np + py;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const T ut = ul[(t * HW + lx + 1) * HW + ly + 1];
+      T wt;
+      if (is_pad_row(tp, t)) {
+        wt = ut;
+      } else {
+        wt = T(wcoef(tp, t, 0)) * Av[0] + T(wcoef(tp, t, 1)) * Av[1] + T(wcoef(tp, t, 2)) * Av[2] +
+             T(wcoef(tp, t, 3)) * Av[3];
+      }
+      F.w[wr][t * np2 + q] = wt;
+      v[0] += (double)(rl[(t * TP + lx) * TP + ly] * ut);
+      v[1] += (double)(wt * ut);
+    }
+  }
+  block_sum<2>(v, sh);
+  bool last;
+  double res[2];
+  finish_reduction<2>(v, F.part, F.nblk, blk, F.cnt, res, &last, sh);
+  if (last) {
+    const double gam = res[0], del = res[1];
+    double b = 0.0, eta = del;
+    if (it > 0) {
+      const double gprev = F.scal[kFGamma], aprev = F.scal[kFAlpha];
+      b = (gprev > 0.0) ? gam / gprev : 0.0;
+      eta = (aprev != 0.0) ? del - b * gam / aprev : del;
+    }
+    F.scal[kFGamma] = gam;
+    F.scal[kFBeta] = b;
+    F.scal[kFAlpha] = (eta > 0.0) ? gam / eta : 0.0;
+  }
+}
+
+// Last update x += a p after the final iteration (no operator application).
+template <typename T>
+__global__ void k_fine_cg_finish(FineCG<T> F, int it) {
+  const size_t np2 = (size_t)F.np * F.np;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * np2) return;
+  const T alpha = T(F.scal[kFAlpha]), beta = T(F.scal[kFBeta]);
+  const T pn = F.u[i] + beta * F.p[i];
+  F.x[i] += alpha * pn;
+}
+
+template <typename T>
+void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st) {
+  if (it >= 0) {
+    hipLaunchKernelGGL(k_fine_cg<T>, dim3(f.nblk), dim3(256), 0, st, f, it);
+  } else {
+    const size_t n = 3 * (size_t)f.np * f.np;
+    hipLaunchKernelGGL(k_fine_cg_finish<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, it);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -733,7 +1043,15 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t);                                  \
   template void launch_cg_spmv<T>(const CGArgs<T>&, int, int, hipStream_t);                             \
   template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t);                           \
-  template void launch_zero<T>(size_t, T*, hipStream_t);
+  template void launch_zero<T>(size_t, T*, hipStream_t);                                                \
+  template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t);                                 \
+  template void launch_prolong_fine_dots<T>(const LevelGeom&, const T*, const T*, const FineCG<T>&,      \
+                                            double*, const double*, const double*, double*, unsigned*,  \
+                                            double*, hipStream_t);                                      \
+  template void launch_outer_update_convert<T>(int, const double*, double*, double*, const double*,     \
+                                               const double*, T*, hipStream_t);                         \
+  template void launch_restrict_chain<T>(const ChainArgs<T>&, hipStream_t);                             \
+  template void launch_prolong_chain<T>(const ChainArgs<T>&, const double*, hipStream_t);
 GBL_INST(float)
 GBL_INST(double)
 #undef GBL_INST

@@ -11,13 +11,15 @@ namespace gbl {
 // Outer (FP64) scalar slots.
 constexpr int kSPW = 0;   // (p, A p)
 constexpr int kSPR = 1;   // (p, r)
-constexpr int kSZZ = 2;   // (z, z)
-constexpr int kSUU = 3;   // (u, u)
-constexpr int kSZW = 4;   // (z, A p)
-constexpr int kSRR = 5;   // (r, r)
-constexpr int kSBB = 6;   // (b, b)
-constexpr int kNumOuterScalars = 8;
-constexpr int kDotBlocks = 512;
+constexpr int kSPP = 2;   // (p, p)
+constexpr int kSZZ = 3;   // (z, z)
+constexpr int kSUU = 4;   // (u, u)
+constexpr int kSZW = 5;   // (z, A p)
+constexpr int kSRR = 6;   // (r, r)
+constexpr int kSBB = 7;   // (b, b)
+constexpr int kSSpare = 8;   // three unused slots
+constexpr int kNumOuterScalars = 12;
+constexpr int kDotBlocks = 1024;
 
 // Per-level CG scalar slots.
 constexpr int kCRZ = 0;
@@ -31,7 +33,6 @@ struct CGLev {
   const T* B;      // B^(k), offset-major
   const T* BJ;     // inverse 3x3 diagonal blocks
   const T* g;      // level-k right-hand side g^(k) (slots)
-  const T* acell;  // finest level only: cell coefficient (matrix-free operator), else null
   T* x;            // w^(k)
   T* r;
   T* z;
@@ -46,7 +47,7 @@ struct CGLev {
   int iters;       // CG iteration budget of this level
   int blk0;        // first block of this level in the update/init grid (256 parents per block)
   int nblk;        // update/init blocks of this level
-  int blk0s;       // first block of this level in the operator grid (256/(2t+1) parents per block)
+  int blk0s;       // first block of this level in the operator grid (64 parents per block)
   int nblks;       // operator blocks of this level
 };
 
@@ -55,6 +56,70 @@ struct CGArgs {
   CGLev<T> lv[kMaxLevels];
   int nlev;
 };
+
+// Finest subband level, conjugate gradients in the Chronopoulos-Gear form
+// (one reduction and one launch per iteration).  r, w (= B u) and s (= B p)
+// are double buffered because tiles read their neighbours' old values.
+constexpr int kFGamma = 0;   // (r_i, u_i)
+constexpr int kFAlpha = 1;
+constexpr int kFBeta = 2;
+constexpr int kNumFineScalars = 4;
+
+template <typename T>
+struct FineCG {
+  const T* g;        // level-q right-hand side (slots)
+  const T* acell;    // cell coefficient
+  const T* BJ;       // inverse 3x3 parent blocks
+  T* x;
+  T* u;
+  T* p;
+  T* r[2];
+  T* w[2];
+  T* s[2];
+  double* scal;
+  double* part;
+  unsigned* cnt;
+  int np;
+  int nblk;          // tiles
+};
+
+template <typename T>
+void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
+template <typename T>
+void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
+                              const double* uo, const double* wo, double* part, unsigned* cnt, double* out,
+                              hipStream_t st);
+template <typename T>
+void launch_outer_update_convert(int len, const double* sc, double* u, double* r, const double* p, const double* w,
+                                 T* g, hipStream_t st);
+void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
+                            unsigned* cnt, double* out, hipStream_t st);
+
+// Small levels handled inside one workgroup (restriction and prolongation
+// chains).  Entry j is level k = kmin + j: R = R^(k-1,k), gf = level-k
+// vector, gc = level-(k-1) vector, w = subband solution of level k.
+template <typename T>
+struct ChainLevel {
+  const T* R;
+  T* gf;
+  T* gc;
+  const T* w;
+  int nk;
+  int rho;
+  int fine;
+};
+
+template <typename T>
+struct ChainArgs {
+  ChainLevel<T> lv[kMaxLevels];
+  int n;   // levels 2 .. 2+n-1, ordered by increasing level for prolongation
+  T* g1;   // level-1 vector (coarse solve in place)
+};
+
+template <typename T>
+void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st);
+template <typename T>
+void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st);
 
 template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st);

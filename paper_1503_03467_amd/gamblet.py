@@ -81,7 +81,7 @@ def _check(code: int, ctx=None):
         raise GambletError(code, msg)
 
 
-def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 60,
+def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 100,
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
@@ -126,7 +126,7 @@ class Hierarchy:
     """Localized gamblet hierarchy of one coefficient field, built on the GPU."""
 
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
-                 max_outer: int = 60, inner_iters: int | None = None, max_rhs: int = 1,
+                 max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                  inner_iters_coarse: int | None = None):
         n = a.shape[0]
         q = n.bit_length() - 1
@@ -199,7 +199,8 @@ class Hierarchy:
         return dloga, dg, lam
 
     def level(self, k: int) -> dict:
-        """Device views of A^(k), B^(k), R^(k-1,k) (offset-major layouts of ``gamblet.h``)."""
+        """A^(k) [S,S,nk,nk] and R^(k-1,k) [rw,rw,nc,nc] as device views, B^(k) as a
+        [T,T,3,3,np,np] copy (the library stores it block-interleaved, see ``gamblet.h``)."""
         d = GblLevelDesc()
         _check(lib().gbl_level_layout(self.ctx, int(k), ctypes.byref(d)), self.ctx)
         dt = torch.float64 if d.elem_bytes == 8 else torch.float32
@@ -216,13 +217,16 @@ class Hierarchy:
         if k >= 2:
             np_ = nk // 2
             T = 2 * d.t + 1
-            out["B"] = view(d.B, T * T * 9 * np_ * np_).view(T, T, 3, 3, np_, np_)
+            ng = (np_ * np_ + 63) // 64
+            Bg = view(d.B, ng * T * T * 9 * 64).view(ng, T, T, 3, 3, 64)
+            out["B"] = Bg.permute(1, 2, 3, 4, 0, 5).reshape(T, T, 3, 3, ng * 64)[..., :np_ * np_].reshape(
+                T, T, 3, 3, np_, np_)
             out["R"] = view(d.R, d.rw * d.rw * np_ * np_).view(d.rw, d.rw, np_, np_)
         return out
 
 
 PROF_KERNELS = ["assemble", "subband_operator", "patch_solve", "galerkin", "restrict", "cg_init", "cg_spmv",
-                "cg_update", "prolong", "fine_apply", "gradient"]
+                "cg_update", "prolong", "fine_apply", "gradient", "fine_cg"]
 
 
 def profile_enable(kernels="all"):
