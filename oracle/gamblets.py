@@ -192,7 +192,7 @@ def exact_hierarchy(A: sp.spmatrix, tree: Tree, construction: int = 2) -> Hierar
 
 
 # ----------------------------------------------------------------------------
-# Localized gamblet transform (Algorithm 2, lines 7-15, Definition 5.3).
+# Localized gamblet transform (Algorithm 2, Definition 5.3).
 # ----------------------------------------------------------------------------
 
 def patch_index_set(tree: Tree, k: int, i: int, rho: int, jpar: np.ndarray) -> np.ndarray:
@@ -204,7 +204,7 @@ def patch_index_set(tree: Tree, k: int, i: int, rho: int, jpar: np.ndarray) -> n
 
 def localized_hierarchy(A: sp.spmatrix, tree: Tree, rho: int, construction: int = 2,
                         keep_D: bool = False) -> Hierarchy:
-    """Localized nested computation (Algorithm 2, lines 7, 11, 12, 13).
+    """Localized nested computation (Algorithm 2: subband operator, patch systems, R, Galerkin).
 
     For every coarse index i of level k-1 the patch system
     B^(i,rho) y = -(W A^(k) pibar^T)_{i^chi, i} of Definition 5.3 is solved by a

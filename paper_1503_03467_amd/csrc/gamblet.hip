@@ -1,7 +1,8 @@
 // Host driver of the gamblet library: the C ABI declared in gamblet.h.
 //
-// gbl_build runs the fine-to-coarse sweep of Algorithm 2 (lines 2, 7, 11,
-// 12, 13 for k = q..2, then the coarse factor of line 16) as kernel launches
+// gbl_build runs the fine-to-coarse sweep of Algorithm 2 (fine stiffness,
+// then for k = q..2 the subband operator, the patch systems, the restriction
+// and the Galerkin product, then the coarse factor) as kernel launches
 // on the caller's stream.  gbl_solve applies the subband solve of
 // Section 4.7 / Theorem 4.15 (restriction, independent subband systems,
 // coarse system, reconstruction sum) as an approximate inverse inside
@@ -11,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -85,6 +87,8 @@ struct ProfScope {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+constexpr int kMaxChunk = 8;   // outer iterations launched between two looks at the estimates
+
 struct Layout {
   int q = 0, n = 0, rho = 0, prec = 0, max_rhs = 1;
   size_t elem = 8;
@@ -97,6 +101,8 @@ struct Layout {
   size_t status_off = 0;     // 4 ints
   size_t oscal_off = 0;      // outer scalars
   size_t dpart_off = 0;      // dot partials
+  size_t opart_off = 0;      // per-block partials of the outer-iteration kernels (2 x 3 x nblk)
+  int onblk = 0;             // blocks of the fine-level slot kernels
   size_t dcnt_off = 0;       // dot ticket
   size_t fine_off[5] = {};   // FP64 slot vectors u, r, z, p, w
   size_t lam_off = 0;        // FP64 nodal adjoint state
@@ -108,6 +114,7 @@ struct Layout {
   size_t fcg_off = 0;        // finest-level CG vectors (9 x 3 np^2, T)
   size_t fcgpart_off = 0;    // tile partials (2 per tile)
   size_t fcgscal_off = 0;    // kNumFineScalars doubles + ticket
+  size_t elog_off = 0;       // per-iteration error estimates of the outer iteration (max_outer + 2 doubles)
   size_t total = 0;
 };
 
@@ -186,6 +193,8 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.oscal_off = b; b = align_up(b + kNumOuterScalars * 8);
   L.dpart_off = b; b = align_up(b + 3 * kDotBlocks * 8);
   L.dcnt_off = b; b = align_up(b + 4 * sizeof(unsigned));
+  L.onblk = (int)((n2 + 255) / 256);
+  L.opart_off = b; b = align_up(b + 6 * (size_t)L.onblk * 8);
   for (int i = 0; i < 5; ++i) { L.fine_off[i] = b; b = align_up(b + n2 * 8); }
   L.lam_off = b; b = align_up(b + (size_t)(L.n + 1) * (L.n + 1) * 8);
   for (int k = 1; k <= q; ++k) {
@@ -210,6 +219,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
   L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
   L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
+  L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
   L.total = b;
   return GBL_OK;
 }
@@ -229,6 +239,11 @@ struct gbl_ctx {
   FineCG<double> fcgd;
   hipStream_t side = nullptr;           // second stream: coarser subband CG runs beside the finest
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // One outer iteration recorded as a graph (captured on its own stream, so
+  // that the caller may pass the null stream) and replayed per iteration.
+  hipStream_t cap = nullptr;
+  hipGraphExec_t iter_graph = nullptr;
+  bool graph_off = false;               // capture failed once: launch kernel by kernel
 
   template <typename T>
   T* hier(size_t off) const { return reinterpret_cast<T*>(ws + L.hier_off) + off; }
@@ -257,6 +272,8 @@ void release(gbl_ctx* c) {
     hipStreamSynchronize(c->side);
     hipStreamDestroy(c->side);
   }
+  if (c->iter_graph) hipGraphExecDestroy(c->iter_graph);
+  if (c->cap) hipStreamDestroy(c->cap);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->host) hipHostFree(c->host);
@@ -408,12 +425,8 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     hipEventRecord(c->ev_fork, st);
     hipStreamWaitEvent(cs, c->ev_fork, 0);
   }
-  // finest level (its last step x += alpha p is applied inside the prolongation)
-  for (int it = 0; it < c->opts.inner_iters; ++it) {
-    ProfScope ps(GBL_PROF_FINE_CG, st);
-    launch_fine_cg<T>(F, it, st);
-  }
-  // coarser levels, beside it on the second stream
+  // coarser levels on the second stream, enqueued first so that they start
+  // together with the finest level
   if (coarse) {
     {
       const CGLev<T>& last = cg.lv[cg.nlev - 1];
@@ -429,13 +442,16 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
       ProfScope ps(GBL_PROF_CG_UPDATE, cs);
       launch_cg_update<T>(cg, lv.blk0 + lv.nblk, it, cs);
     }
-    if (c->side) {
-      hipEventRecord(c->ev_join, cs);
-      hipStreamWaitEvent(st, c->ev_join, 0);
-    }
+    if (c->side) hipEventRecord(c->ev_join, cs);
   } else {
     for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, st);
   }
+  // finest level (its last step x += alpha p is applied inside the prolongation)
+  for (int it = 0; it < c->opts.inner_iters; ++it) {
+    ProfScope ps(GBL_PROF_FINE_CG, st);
+    launch_fine_cg<T>(F, it, st);
+  }
+  if (coarse && c->side) hipStreamWaitEvent(st, c->ev_join, 0);
   {
     ProfScope ps(GBL_PROF_PROLONG, st);
     launch_prolong_chain<T>(chain, c->L1(), st);
@@ -447,9 +463,94 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   ProfScope ps(GBL_PROF_PROLONG, st);
   double* part = reinterpret_cast<double*>(c->ws + L.dpart_off);
   unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
-  // without a destination the sums still run (same kernel) into spare scalar slots
-  launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z, part,
-                              cnt, dots ? dots : c->oscal() + kSSpare, st);
+  // the partial sums (z, z), (u, u), (z, w) go to the second half of the outer partials
+  double* opart = reinterpret_cast<double*>(c->ws + L.opart_off) + 3 * (size_t)L.onblk;
+  launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z, opart,
+                              st);
+  (void)part;
+  (void)cnt;
+}
+
+// One outer iteration of flexible CG on the FP64 fine system, with the subband
+// solve as preconditioner: w = A p, u += alpha p, r -= alpha w, z = S r, and
+// the new direction p = z + beta p, whose kernel also logs the iteration's
+// error estimate on the device.
+template <typename T>
+void outer_iteration(gbl_ctx* c, const CGArgs<T>& cg, hipStream_t st) {
+  const Layout& L = c->L;
+  const int n = L.n;
+  const int len = n * n;
+  double* u = c->fine(0);
+  double* r = c->fine(1);
+  double* z = c->fine(2);
+  double* p = c->fine(3);
+  double* w = c->fine(4);
+  double* sc = c->oscal();
+  double* partA = reinterpret_cast<double*>(c->ws + L.opart_off);
+  double* partB = partA + 3 * (size_t)L.onblk;
+  double* elog = reinterpret_cast<double*>(c->ws + L.elog_off);
+  T* gq = reinterpret_cast<T*>(c->ws + L.g_off[L.q]);
+  {
+    ProfScope ps(GBL_PROF_FINE_APPLY, st);
+    launch_apply_fine_dots(c->a(), n, p, r, w, partA, st);
+  }
+  launch_outer_update_convert<T>(len, partA, L.onblk, sc, u, r, p, w, gq, st);
+  precondition<T>(c, cg, r, z, st, true, u, w, sc);
+  launch_outer_direction(len, sc, partB, L.onblk, z, p, elog, 0, st);
+}
+
+// Kernel classes launched inside the outer iteration: while any of them is
+// being timed, iterations are launched kernel by kernel.
+constexpr unsigned kIterationClasses =
+    (1u << GBL_PROF_RESTRICT) | (1u << GBL_PROF_CG_INIT) | (1u << GBL_PROF_CG_SPMV) | (1u << GBL_PROF_CG_UPDATE) |
+    (1u << GBL_PROF_PROLONG) | (1u << GBL_PROF_FINE_APPLY) | (1u << GBL_PROF_FINE_CG);
+
+// Enqueue m outer iterations on st: replays of the recorded iteration graph
+// (recorded on first use), or kernel-by-kernel launches.
+bool iteration_graph_enabled() {
+  const char* e = getenv("GBL_ITER_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+template <typename T>
+int run_iterations(gbl_ctx* c, const CGArgs<T>& cg, int m, hipStream_t st) {
+  if (!(g_prof.mask & kIterationClasses) && !c->graph_off && iteration_graph_enabled()) {
+    if (!c->iter_graph) {
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        outer_iteration<T>(c, cg, c->cap);
+        ok = hipStreamEndCapture(c->cap, &g) == hipSuccess && g != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&c->iter_graph, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) hipGraphDestroy(g);
+      if (!ok) {
+        c->iter_graph = nullptr;
+        c->graph_off = true;
+        (void)hipGetLastError();
+      }
+    }
+    if (c->iter_graph) {
+      for (int j = 0; j < m; ++j) HIPCHK(c, hipGraphLaunch(c->iter_graph, st));
+      return GBL_OK;
+    }
+  }
+  for (int j = 0; j < m; ++j) outer_iteration<T>(c, cg, st);
+  return GBL_OK;
+}
+
+// Iterations to launch before the next look at the error estimates: the
+// estimates so far are extrapolated geometrically to the iteration that
+// reaches the tolerance, so that few iterations run past it.
+int next_chunk(const std::vector<double>& h, double tol) {
+  const size_t k = h.size();
+  if (k < 3) return 2;
+  const double a = h[k - 1], b = h[k - 3];
+  const double cur = std::max(h[k - 1], h[k - 2]);
+  if (!(a > 0.0) || !(b > 0.0) || !(a < b) || !(cur > tol)) return 1;
+  const double rate = std::sqrt(a / b);
+  const double rem = std::log(tol / cur) / std::log(rate);
+  return (int)std::min((double)kMaxChunk, std::max(1.0, std::floor(rem)));
 }
 
 // Flexible CG on the FP64 fine system with the subband solve as
@@ -468,47 +569,53 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   double* sc = c->oscal();
   double* part = reinterpret_cast<double*>(c->ws + L.dpart_off);
   unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
+  double* partB = reinterpret_cast<double*>(c->ws + L.opart_off) + 3 * (size_t)L.onblk;
+  const double* elog = reinterpret_cast<const double*>(c->ws + L.elog_off);
   launch_residual(c->a(), n, mode, src, u_nodal, nullptr, r, st);
   launch_fill((size_t)len, 0.0, u, st);
+  launch_fill(1, 0.0, sc + kSIter, st);
   launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSBB, st);
-  precondition<T>(c, cg, r, z, st);
-  launch_outer_direction(len, sc, z, p, 1, st);
-  int it = 0;
+  precondition<T>(c, cg, r, z, st, false, u, w, sc);
+  launch_outer_direction(len, sc, partB, L.onblk, z, p, nullptr, 1, st);
+  // Error estimate of iteration i (logged by the direction kernel): z = S r
+  // approximates the error and alpha p is the last correction; either alone
+  // can under-read the error when the inner solves are loose, so the larger
+  // of the two over the last two iterations is tested against rtol / 3.
+  // Iterations that run past the first passing one only lower the A-norm
+  // error further.
+  const double tol = c->opts.rtol / 3.0;
+  double* hl = c->host + kNumOuterScalars + 4;   // host copy of a chunk of estimates
+  std::vector<double> hist;
   int status = GBL_ENOCONV;
   double est = 1.0, prev = INFINITY;
-  // Error estimate: z = S r approximates the error and alpha p is the last
-  // correction; either alone can under-read the error when the inner solves
-  // are loose, so the larger of the two over the last two iterations is
-  // tested against rtol / 3.
-  const double tol = c->opts.rtol / 3.0;
-  for (it = 1; it <= c->opts.max_outer; ++it) {
-    {
-      ProfScope ps(GBL_PROF_FINE_APPLY, st);
-      launch_apply_fine_dots(c->a(), n, p, r, w, part, cnt, sc + kSPW, st);
-    }
-    launch_outer_update_convert<T>(len, sc, u, r, p, w, reinterpret_cast<T*>(c->ws + L.g_off[L.q]), st);
-    precondition<T>(c, cg, r, z, st, true, u, w, sc + kSZZ);
-    HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
+  int done = 0;
+  while (done < c->opts.max_outer) {
+    const int m = std::min(next_chunk(hist, tol), c->opts.max_outer - done);
+    const int rs = run_iterations<T>(c, cg, m, st);
+    if (rs) return rs;
+    HIPCHK(c, hipMemcpyAsync(hl, elog + done, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    const double zz = c->host[kSZZ], uu = c->host[kSUU];
-    const double pw = c->host[kSPW], pr = c->host[kSPR], pp = c->host[kSPP];
-    const double alpha = pw > 0.0 ? pr / pw : 0.0;
-    const double cur = (uu > 0.0) ? std::max(std::sqrt(zz / uu), std::fabs(alpha) * std::sqrt(pp / uu))
-                                  : ((zz > 0.0 || pp > 0.0) ? 1.0 : 0.0);
-    if (!std::isfinite(cur)) {
-      est = cur;
-      status = GBL_ENOCONV;
-      break;
+    done += m;
+    bool stop = false;
+    for (int j = 0; j < m && !stop; ++j) {
+      const double cur = hl[j];
+      hist.push_back(cur);
+      if (!std::isfinite(cur)) {
+        est = cur;
+        status = GBL_ENOCONV;
+        stop = true;
+      } else {
+        est = std::max(cur, prev);
+        prev = cur;
+        if (est <= tol) {
+          status = GBL_OK;
+          stop = true;
+        }
+      }
     }
-    est = std::max(cur, prev);
-    prev = cur;
-    if (est <= tol) {
-      status = GBL_OK;
-      break;
-    }
-    launch_outer_direction(len, sc, z, p, 0, st);
+    if (stop) break;
   }
-  if (it > c->opts.max_outer) it = c->opts.max_outer;
+  const int it = done;
   launch_slots_to_nodal(n, u, u_nodal, st);
   // final residual of the returned iterate
   launch_residual(c->a(), n, mode, src, u_nodal, u, r, st);
@@ -598,7 +705,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->ws = static_cast<char*>(ws_dev);
   c->ws_bytes = ws_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4) * sizeof(double),
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4 + kMaxChunk) * sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, GBL_EHIP, "hipHostMalloc failed");
@@ -624,6 +731,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->fcgf = make_fine_cg<float>(c);
   c->fcgd = make_fine_cg<double>(c);
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
     c->err = "stream or event creation failed";

@@ -1,8 +1,9 @@
 // Build-phase kernels of the localized gamblet hierarchy (Algorithm 2,
-// lines 2, 7, 11, 12, 13) for gfx950.
+// fine-to-coarse sweep) for gfx950.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include "device_common.hpp"
 #include "gamblet_internal.hpp"
@@ -10,7 +11,7 @@
 namespace gbl {
 
 // ---------------------------------------------------------------------------
-// Fine stiffness A^(q) = A (Algorithm 2, line 2; level-q gamblets are the
+// Fine stiffness A^(q) = A (first step of Algorithm 2; level-q gamblets are the
 // nodal basis functions).  Bilinear element on a square cell with
 // coefficient a_e: diagonal 2/3 a_e, edge neighbours -1/6 a_e, opposite
 // corner -1/3 a_e.  One thread per node slot; the nine couplings are
@@ -64,7 +65,7 @@ void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t
 
 // ---------------------------------------------------------------------------
 // Subband operator B^(k) = W^(k) A^(k) W^(k)T (eq. defining B, Section 4.7;
-// Algorithm 2, line 7) in parent-block stencil form (entry (o, 3i + j) of
+// Algorithm 2) in parent-block stencil form (entry (o, 3i + j) of
 // parent p couples subband row (p, i) to (p + o - t, j); block-interleaved
 // layout, see b_index), plus the inverse of every 3x3 diagonal block
 // (block-Jacobi preconditioner of the subband CG).  One thread per
@@ -160,7 +161,7 @@ void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool f
 }
 
 // ---------------------------------------------------------------------------
-// Patch solves and restriction (Definition 5.3; Algorithm 2, lines 11-12).
+// Patch solves and restriction (Definition 5.3; Algorithm 2).
 //
 // One workgroup of 256 threads (a 16 x 16 thread grid) per coarse cell i of
 // level k-1.  The patch is the box of coarse cells within rho of i, clipped
@@ -408,6 +409,22 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
 
 template <typename T>
 void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st);
+template <typename T, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(const T* __restrict__ A, const T* __restrict__ B,
+                                                         T* __restrict__ R, int nk, int s, int t, int rho,
+                                                         int fine, int* __restrict__ status);
+
+// Dense patch kernel choice: the matrix-core kernel for FP32 patches, the
+// register-tiled kernel for FP64 ones (whose accumulator tiles would leave one
+// workgroup per compute unit).  GBL_PATCH_MFMA=1 or 0 forces one kernel for
+// both; the parity tests run both.
+template <typename T>
+static bool patch_mfma_enabled() {
+  const char* e = getenv("GBL_PATCH_MFMA");
+  if (e && e[0] == '1') return true;
+  if (e && e[0] == '0') return false;
+  return sizeof(T) == 4;
+}
 
 template <typename T>
 void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
@@ -421,6 +438,10 @@ void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool f
   const int need = 3 * wmax * wmax + 1;
   const dim3 grid(nc * nc), block(256);
   const int f = fine ? 1 : 0;
+  if (patch_mfma_enabled<T>() && need <= 160) {
+    hipLaunchKernelGGL((k_patch_chol_mfma<T, 10>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+    return;
+  }
   if (need <= 32) {
     hipLaunchKernelGGL((k_patch_solve<T, 2>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
   } else if (need <= 80) {
@@ -429,6 +450,341 @@ void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool f
     hipLaunchKernelGGL((k_patch_solve<T, 10>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
   } else {
     hipLaunchKernelGGL((k_patch_solve<T, 16>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Patch solves on matrix cores (levels k < q): blocked right-looking Cholesky
+// with 16 x 16 tiles.  The scaled patch matrix, with the right-hand side as
+// row p, is held as MFMA accumulator tiles (I, J), J <= I, dealt round-robin
+// to the four wavefronts (tile number I (I + 1) / 2 + J = 4 m + wave).  For
+// each panel P:
+//   1. the panel tiles (I, P) go to LDS;
+//   2. lanes 0..15 of wavefront 0 hold the rows of the diagonal tile in
+//      registers and factor it, L_PP, exchanging column values with lane
+//      reads (no LDS round trips);
+//   3. one thread per panel row solves l L_PP^T = a (rows of L_IP, I > P),
+//      and sixteen more threads solve it for the unit rows, giving the rows
+//      of L_PP^{-T} used by the back substitution;
+//   4. A_IJ -= L_IP L_JP^T for P < J <= I on the matrix cores.
+// Row p of the factor is z = L^{-1} b; a blocked back substitution with the
+// stored L_PP^{-T} gives x = L^{-T} z.  Scaling, right-hand side and the
+// restriction row are those of the register-tiled kernel.
+// ---------------------------------------------------------------------------
+typedef float gbl_v4f __attribute__((ext_vector_type(4)));
+typedef double gbl_v4d __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef gbl_v4f acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l is tile row row(l, r), column l % 16
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+  static __device__ __forceinline__ float lane_value(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+  }
+};
+template <>
+struct Mfma<double> {
+  typedef gbl_v4d acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+  static __device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  }
+};
+
+// tile coordinates of tile number tix = I (I + 1) / 2 + J
+__device__ __forceinline__ void tile_of(int tix, int& I, int& J) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= tix) ++i;
+  I = i;
+  J = tix - i * (i + 1) / 2;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(const T* __restrict__ A, const T* __restrict__ B,
+                                                         T* __restrict__ R, int nk, int s, int t, int rho,
+                                                         int fine, int* __restrict__ status) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  constexpr int SLOTS = (NTILE + 3) / 4;
+  constexpr int P16 = 16 * NT;
+  __shared__ T panel[NT][16][17];   // column-P tiles; rows of L_IP after the solve
+  __shared__ T lpp[16][16];         // factored diagonal tile
+  __shared__ T dinv[16];
+  __shared__ T linvt[NT][16][16];   // rows of L_PP^{-T}
+  __shared__ T sc[P16];
+  __shared__ T rhs[P16];            // scaled right-hand side, later z, then x
+  __shared__ T part[NT][16];
+  __shared__ int bad;
+
+  const int nc = nk / 2;
+  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = ci / nc, cy = ci % nc;
+  const int x0 = max(0, cx - rho), x1 = min(nc - 1, cx + rho);
+  const int y0 = max(0, cy - rho), y1 = min(nc - 1, cy + rho);
+  const int wy = y1 - y0 + 1;
+  const int npar = (x1 - x0 + 1) * wy;
+  const int p = 3 * npar;
+  const int nta = (p + 1 + 15) / 16;    // tiles holding rows 0..p
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l = tid & 63, lc = l & 15;
+  const int TT = 2 * t + 1;
+  const int S = 2 * s + 1;
+  const int ti = parent_type(fine != 0, cx, cy);
+  if (tid == 0) bad = 0;
+
+  // scaling and right-hand side
+  for (int r = tid; r < P16; r += 256) {
+    T scale = T(1), rv = T(0);
+    if (r < p) {
+      const int lp = r / 3, tt = r - 3 * lp;
+      const int px = x0 + lp / wy, py = y0 + lp % wy;
+      const T d = B[b_index(t * TT + t, tt * 4, px * nc + py, TT)];
+      if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
+      else atomicOr(status, kBadPivot);
+      const int tp = parent_type(fine != 0, px, py);
+      if (abs(px - cx) <= t && abs(py - cy) <= t && !is_pad_row(tp, tt)) {
+        double acc = 0.0;
+        for (int dd = 0; dd < 4; ++dd) {
+          const double wd = wcoef(tp, tt, dd);
+          if (wd == 0.0) continue;
+          const int fx = 2 * px + (dd >> 1), fy = 2 * py + (dd & 1);
+          double inner = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double pe = pibar(ti, e);
+            if (pe == 0.0) continue;
+            const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
+            const int ox = gx - fx + s, oy = gy - fy + s;
+            if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
+            inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
+          }
+          acc += wd * inner;
+        }
+        rv = T(-acc);
+      }
+    }
+    sc[r] = scale;
+    rhs[r] = rv * scale;
+  }
+  __syncthreads();
+
+  // this wavefront's tiles, loaded from B^(k)
+  acc_t acc[SLOTS];
+#pragma unroll
+  for (int m = 0; m < SLOTS; ++m) {
+    int I, J;
+    tile_of(4 * m + w, I, J);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[m][r] = T(0);
+    if (4 * m + w < NTILE && I < nta) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + Mfma<T>::row(l, r), j = 16 * J + lc;
+        T v;
+        if (i < p && j < p) {
+          if (i >= j) {
+            const int lr = i / 3, trr = i - 3 * lr;
+            const int lq = j / 3, tcc = j - 3 * lq;
+            const int rx = x0 + lr / wy, ry = y0 + lr % wy;
+            const int qx = x0 + lq / wy, qy = y0 + lq % wy;
+            const int ox = qx - rx + t, oy = qy - ry + t;
+            T bv = T(0);
+            if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
+              bv = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)];
+            v = bv * sc[i] * sc[j];
+          } else {
+            v = T(0);
+          }
+        } else if (i == p && j < p) {
+          v = rhs[j];
+        } else {
+          v = (i == j) ? T(1) : T(0);
+        }
+        acc[m][r] = v;
+      }
+    }
+  }
+
+  for (int P = 0; P < nta; ++P) {
+    // 1. panel tiles (I, P), I >= P, to LDS
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+      int I, J;
+      tile_of(4 * m + w, I, J);
+      if (4 * m + w < NTILE && J == P && I < nta) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) panel[I][Mfma<T>::row(l, r)][lc] = acc[m][r];
+      }
+    }
+    __syncthreads();
+    // 2. diagonal tile in the registers of lanes 0..15 of wavefront 0 (lane i
+    //    holds row i; entries right of the diagonal are never read).  Rows
+    //    from p on are not part of the SPD system: their pivots are taken as 1.
+    if (w == 0) {
+      T a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = panel[P][lc][c];
+      int badl = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        T dk = Mfma<T>::lane_value(a[k], k);
+        if (16 * P + k >= p) {
+          dk = T(1);
+        } else if (!(dk > T(0))) {
+          badl = 1;
+          dk = T(1);
+        }
+        const T sk = my_sqrt<T>(dk);
+        const T rk = T(1) / sk;
+        a[k] = (lc > k) ? a[k] * rk : ((lc == k) ? sk : a[k]);
+#pragma unroll
+        for (int c = k + 1; c < 16; ++c) a[c] -= a[k] * Mfma<T>::lane_value(a[k], c);
+      }
+      if (l < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) lpp[lc][c] = (c <= lc) ? a[c] : T(0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c == lc) dinv[lc] = T(1) / a[c];
+      }
+      if (l == 0 && badl) bad = 1;
+    }
+    __syncthreads();
+    // 3. rows of L_IP (I > P) and of L_PP^{-T}: l[c] = (a[c] - sum_{m<c} l[m] L_PP[c][m]) / L_PP[c][c]
+    const int nrow = 16 * (nta - P);
+    if (tid < nrow) {
+      // threads 0..15 take the unit rows (their tile index is P itself, so the
+      // row read is in bounds and then replaced); no divergent branch here
+      const bool unit = tid < 16;
+      const int I = P + (tid >> 4), i = tid & 15;
+      T x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const T v = panel[I][i][c];
+        x[c] = unit ? ((c == i) ? T(1) : T(0)) : v;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        T v = x[c];
+#pragma unroll
+        for (int m2 = 0; m2 < c; ++m2) v -= x[m2] * lpp[c][m2];
+        x[c] = v * dinv[c];
+      }
+      T* dst = unit ? &linvt[P][i][0] : &panel[I][i][0];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dst[c] = x[c];
+    }
+    __syncthreads();
+    // 4. keep L_IP (I >= P) in the accumulators; A_IJ -= L_IP L_JP^T for J > P
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+      int I, J;
+      tile_of(4 * m + w, I, J);
+      if (4 * m + w < NTILE && I < nta) {
+        if (J == P) {
+          if (I == P) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[m][r] = lpp[Mfma<T>::row(l, r)][lc];
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[m][r] = panel[I][Mfma<T>::row(l, r)][lc];
+          }
+        } else if (J > P) {
+#pragma unroll
+          for (int k4 = 0; k4 < 4; ++k4) {
+            const T av = -panel[I][lc][4 * k4 + (l >> 4)];
+            const T bv = panel[J][lc][4 * k4 + (l >> 4)];
+            acc[m] = Mfma<T>::mma(av, bv, acc[m]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // z = row p of L
+#pragma unroll
+  for (int m = 0; m < SLOTS; ++m) {
+    int I, J;
+    tile_of(4 * m + w, I, J);
+    if (4 * m + w < NTILE && I == p / 16) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + Mfma<T>::row(l, r), j = 16 * J + lc;
+        if (i == p && j < p) rhs[j] = acc[m][r];
+      }
+    }
+  }
+  __syncthreads();
+  // back substitution L^T x = z, one column block at a time from the last
+  const int ntz = (p + 15) / 16;
+  for (int P = ntz - 1; P >= 0; --P) {
+    // partial products L_IP^T x_I of the tiles below the diagonal
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+      int I, J;
+      tile_of(4 * m + w, I, J);
+      if (4 * m + w < NTILE && J == P && I > P && I < ntz) {
+        T v = T(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + Mfma<T>::row(l, r);
+          v += acc[m][r] * ((i < p) ? rhs[i] : T(0));
+        }
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (l < 16) part[I][lc] = v;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      T y = T(0);
+      const int j = 16 * P + lc;
+      if (j < p) {
+        y = rhs[j];
+        for (int I = P + 1; I < ntz; ++I) y -= part[I][lc];
+      }
+      // x_P = L_PP^{-T} y: x_c = sum_i linvt[c][i] y_i
+      T xv = T(0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv += linvt[P][lc][i] * __shfl(y, i, 64);
+      if (l < 16 && j < p) rhs[j] = xv;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && bad) atomicOr(status, kBadPivot);
+  // y = sc x, then the restriction row R_i = pibar_i + sum y_j W_j
+  for (int r = tid; r < p; r += 256) rhs[r] *= sc[r];
+  __syncthreads();
+  const int rw = 2 * (2 * rho + 1);
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
+  const size_t nc2 = (size_t)nc * nc;
+  T* Ri = R + ci;
+  for (int e = tid; e < rw * rw; e += 256) {
+    const int bx = e / rw, by = e % rw;
+    const int fx = ox0 + bx, fy = oy0 + by;
+    double v = 0.0;
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      const int px = fx >> 1, py = fy >> 1;
+      const int d = 2 * (fx & 1) + (fy & 1);
+      const int tp = parent_type(fine != 0, px, py);
+      if (px == cx && py == cy) v = pibar(tp, d);
+      const int lp = (px - x0) * wy + (py - y0);
+      for (int tt = 0; tt < 3; ++tt) v += (double)rhs[3 * lp + tt] * wcoef(tp, tt, d);
+    }
+    Ri[(size_t)e * nc2] = T(v);
   }
 }
 
@@ -613,7 +969,7 @@ void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, i
 
 // ---------------------------------------------------------------------------
 // Galerkin coarsening A^(k-1) = R^(k-1,k) A^(k) R^(k,k-1) (Theorem 4.8;
-// Algorithm 2, line 13 -- the step the paper names as its complexity
+// Algorithm 2 -- the step the paper names as its complexity
 // bottleneck).  One workgroup per coarse row i: first z = R_i A^(k) on the
 // window of level-k slots the row can reach (staged in LDS; A is symmetric
 // so z_c' is row c' of A against R_i), then every entry
@@ -689,7 +1045,7 @@ void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T
 
 // ---------------------------------------------------------------------------
 // Coarsest level: Cholesky factor of the 4 x 4 matrix A^(1) in FP64
-// (Algorithm 2, line 16).  A single thread; L1 holds the dense factor.
+// (coarse system of Algorithm 2).  A single thread; L1 holds the dense factor.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_coarse_factor(const T* __restrict__ A1, int s1, double* __restrict__ L1,

@@ -77,6 +77,30 @@ __device__ __forceinline__ void finish_reduction(const double (&v)[NV], double* 
   }
 }
 
+// Partial sums only (no ticket): thread 0 stores this block's sums; a later
+// kernel or the host adds them in block order.
+template <int NV>
+__device__ __forceinline__ void write_partials(const double (&v)[NV], double* part, int nblk, int blk) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[k * nblk + blk] = v[k];
+  }
+}
+
+// Every block adds the nblk partials of sum k (fixed order per thread, then
+// a fixed-order block reduction); the total is broadcast through LDS.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int k, double* sh) {
+  __shared__ double bcast;
+  double acc[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc[0] += part[k * nblk + b];
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) bcast = acc[0];
+  __syncthreads();
+  const double r = bcast;
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Fine operator, matrix-free from the cell coefficient (FP64).  For node
 // (x, y) the cells around it are (x-1,y-1), (x,y-1), (x-1,y), (x,y).
@@ -182,28 +206,53 @@ __global__ void k_outer_update(int len, const double* __restrict__ sc, double* _
 }
 
 //   beta = -(z, w) / (p, w);  p = z + beta p   (A-orthogonalise against the last direction)
-__global__ void k_outer_direction(int len, const double* __restrict__ sc, const double* __restrict__ z,
-                                  double* __restrict__ p, int first) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// (z, w) is re-added from the partials of the finest prolongation kernel.
+// When elog is set, block 0 also forms the error estimate of the iteration
+// that has just finished, max(||z|| / ||u||, |alpha| ||p|| / ||u||) with
+// z = S r the preconditioned residual and alpha p the last correction, and
+// appends it to elog at the position counted by sc[kSIter] (a NaN in either
+// term is kept).
+__global__ __launch_bounds__(256) void k_outer_direction(int len, double* __restrict__ sc,
+                                                         const double* __restrict__ partz, int nblkz,
+                                                         const double* __restrict__ z, double* __restrict__ p,
+                                                         double* __restrict__ elog, int first) {
+  __shared__ double sh[16];
   double beta = 0.0;
   if (!first) {
+    const double zw = sum_partials(partz, nblkz, 2, sh);
     const double pw = sc[kSPW];
-    beta = (pw > 0.0) ? -sc[kSZW] / pw : 0.0;
-    p[i] = z[i] + beta * p[i];
-  } else {
-    p[i] = z[i];
+    beta = (pw > 0.0) ? -zw / pw : 0.0;
+    if (blockIdx.x == 0 && elog != nullptr) {
+      const double zz = sum_partials(partz, nblkz, 0, sh);
+      const double uu = sum_partials(partz, nblkz, 1, sh);
+      if (threadIdx.x == 0) {
+        const double pr = sc[kSPR], pp = sc[kSPP];
+        const double alpha = (pw > 0.0) ? pr / pw : 0.0;
+        double cur;
+        if (uu > 0.0) {
+          const double e1 = sqrt(zz / uu), e2 = fabs(alpha) * sqrt(pp / uu);
+          cur = (e1 > e2 || e1 != e1) ? e1 : e2;
+        } else {
+          cur = (zz > 0.0 || pp > 0.0) ? 1.0 : 0.0;
+        }
+        const int i = (int)sc[kSIter];
+        elog[i] = cur;
+        sc[kSIter] = (double)(i + 1);
+      }
+    }
   }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
 }
 
-// w = A p fused with the sums (p, w), (p, r), (p, p) -> out[0..3).
+// w = A p fused with the per-block partial sums of (p, w), (p, r), (p, p).
 __global__ __launch_bounds__(256) void k_apply_fine_dots(const double* __restrict__ a, int n,
                                                          const double* __restrict__ p, const double* __restrict__ r,
-                                                         double* __restrict__ w, double* part, unsigned* cnt,
-                                                         double* out) {
+                                                         double* __restrict__ w, double* part) {
   __shared__ double sh[3 * 16];
   double v[3] = {0.0, 0.0, 0.0};
-  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < n * n; id += gridDim.x * blockDim.x) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n * n) {
     const int x = id / n, y = id % n;
     double wv = 0.0;
     if (x != 0 && y != 0) {
@@ -215,34 +264,40 @@ __global__ __launch_bounds__(256) void k_apply_fine_dots(const double* __restric
     }
     w[id] = wv;
     const double pv = p[id];
-    v[0] += pv * wv;
-    v[1] += pv * r[id];
-    v[2] += pv * pv;
+    v[0] = pv * wv;
+    v[1] = pv * r[id];
+    v[2] = pv * pv;
   }
   block_sum<3>(v, sh);
-  bool last;
-  double res[3];
-  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last, sh);
-  if (last) {
-    out[0] = res[0];
-    out[1] = res[1];
-    out[2] = res[2];
-  }
+  write_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
 
-// alpha = (p, r) / (p, w); u += alpha p; r -= alpha w; g = T(r) (input of the subband solve)
+// alpha = (p, r) / (p, w) from the partials of the operator kernel;
+// u += alpha p; r -= alpha w; g = T(r) (input of the subband solve).  Block 0
+// also stores (p, w), (p, r), (p, p) for the host and the next kernels.
 template <typename T>
-__global__ void k_outer_update_convert(int len, const double* __restrict__ sc, double* __restrict__ u,
-                                       double* __restrict__ r, const double* __restrict__ p,
-                                       const double* __restrict__ w, T* __restrict__ g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
-  const double pw = sc[kSPW], pr = sc[kSPR];
+__global__ __launch_bounds__(256) void k_outer_update_convert(int len, const double* __restrict__ part, int nblk,
+                                                              double* __restrict__ sc, double* __restrict__ u,
+                                                              double* __restrict__ r, const double* __restrict__ p,
+                                                              const double* __restrict__ w, T* __restrict__ g) {
+  __shared__ double sh[16];
+  const double pw = sum_partials(part, nblk, 0, sh);
+  const double pr = sum_partials(part, nblk, 1, sh);
+  if (blockIdx.x == 0) {
+    const double pp = sum_partials(part, nblk, 2, sh);
+    if (threadIdx.x == 0) {
+      sc[kSPW] = pw;
+      sc[kSPR] = pr;
+      sc[kSPP] = pp;
+    }
+  }
   const double alpha = (pw > 0.0) ? pr / pw : 0.0;
-  u[i] += alpha * p[i];
-  const double rn = r[i] - alpha * w[i];
-  r[i] = rn;
-  g[i] = T(rn);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+    u[i] += alpha * p[i];
+    const double rn = r[i] - alpha * w[i];
+    r[i] = rn;
+    g[i] = T(rn);
+  }
 }
 
 // slot vector -> nodal interior (boundary entries untouched)
@@ -273,9 +328,31 @@ __global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__
 
 // ---------------------------------------------------------------------------
 // Restriction g^(k-1)_i = sum_c R_{i,c} g^(k)_c (eq. g^(k) = R g^(k+1),
-// Section 4.7; Algorithm 2, line 15).  One thread per coarse slot; R is
+// Section 4.7; the right-hand side step of Algorithm 2).  One thread per coarse slot; R is
 // entry-major (R[e][cell]) so consecutive threads read consecutive words.
 // ---------------------------------------------------------------------------
+template <typename T, int RHO>
+__device__ __forceinline__ T restrict_row(const T* __restrict__ R, const T* __restrict__ gf, int nk, int i, int bx) {
+  constexpr int rw = 2 * (2 * RHO + 1);
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int cx = i / nc, cy = i - (i / nc) * nc;
+  const int fx = 2 * (cx - RHO) + bx;
+  if (fx < 0 || fx >= nk) return T(0);
+  const int oy = 2 * (cy - RHO);
+  const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
+  const T* gr = gf + (size_t)fx * nk;
+  T acc = T(0);
+#pragma unroll
+  for (int by = 0; by < rw; ++by) {
+    const int fy = oy + by;
+    const int fyc = min(max(fy, 0), nk - 1);
+    const T v = Rr[(size_t)by * nc2] * gr[fyc];
+    acc += (fy >= 0 && fy < nk) ? v : T(0);
+  }
+  return acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ R, const T* __restrict__ gf,
                                                   T* __restrict__ gc, int nk, int rho) {
@@ -288,17 +365,13 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ R, const
   const int tid = threadIdx.x;
   const int bx = tid / PP, cl = tid - bx * PP;
   const int i = blockIdx.x * PP + cl;
-  const size_t nc2 = (size_t)nc * nc;
   T acc = T(0);
   if (bx < rw && i < nc * nc) {
-    const int cx = i / nc, cy = i - (i / nc) * nc;
-    const int ox = 2 * (cx - rho), oy = 2 * (cy - rho);
-    const int fx = ox + bx;
-    if (fx >= 0 && fx < nk) {
-      const int byl = max(0, -oy), byh = min(rw - 1, nk - 1 - oy);
-      const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
-      const T* gr = gf + (size_t)fx * nk + oy;
-      for (int by = byl; by <= byh; ++by) acc += Rr[(size_t)by * nc2] * gr[by];
+    switch (rho) {
+      case 1: acc = restrict_row<T, 1>(R, gf, nk, i, bx); break;
+      case 2: acc = restrict_row<T, 2>(R, gf, nk, i, bx); break;
+      case 3: acc = restrict_row<T, 3>(R, gf, nk, i, bx); break;
+      default: acc = restrict_row<T, 4>(R, gf, nk, i, bx); break;
     }
   }
   if (bx < rw) red[bx * PP + cl] = acc;
@@ -326,25 +399,46 @@ void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStre
 // Algorithm 1 in Section 5.2).  One thread per level-k slot, gathering the
 // restriction rows of the (2 rho + 1)^2 coarse slots whose patch covers it.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ R, const T* __restrict__ vc, int nk, int rho,
-                                        int fx, int fy) {
+// (R^T v)_c for level-k slot c = (fx, fy): the (2 rho + 1)^2 coarse rows whose
+// restriction block covers c.  RHO is a compile-time radius so the gather
+// is unrolled; rows outside the level are clamped and masked out.
+template <typename T, int RHO>
+__device__ __forceinline__ T prolong_at_r(const T* __restrict__ R, const T* __restrict__ vc, int nk, int fx, int fy) {
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
   const int px = fx >> 1, py = fy >> 1;
-  const int rw = 2 * (2 * rho + 1);
+  constexpr int rw = 2 * (2 * RHO + 1);
   T acc = T(0);
-  const int ixl = max(0, px - rho), ixh = min(nc - 1, px + rho);
-  const int iyl = max(0, py - rho), iyh = min(nc - 1, py + rho);
-  for (int ix = ixl; ix <= ixh; ++ix) {
-    const int bx = fx - 2 * (ix - rho);
-    for (int iy = iyl; iy <= iyh; ++iy) {
-      const int by = fy - 2 * (iy - rho);
-      const int i = ix * nc + iy;
-      acc += R[(size_t)(bx * rw + by) * nc2 + i] * vc[i];
+#pragma unroll
+  for (int dx = -RHO; dx <= RHO; ++dx) {
+    const int ix = px + dx;
+    const bool okx = ix >= 0 && ix < nc;
+    const int ixc = min(max(ix, 0), nc - 1);
+    const int bx = fx - 2 * (ixc - RHO);
+#pragma unroll
+    for (int dy = -RHO; dy <= RHO; ++dy) {
+      const int iy = py + dy;
+      const bool ok = okx && iy >= 0 && iy < nc;
+      const int iyc = min(max(iy, 0), nc - 1);
+      const int by = fy - 2 * (iyc - RHO);
+      const int bxc = min(max(bx, 0), rw - 1), byc = min(max(by, 0), rw - 1);
+      const int i = ixc * nc + iyc;
+      const T v = R[(size_t)(bxc * rw + byc) * nc2 + i] * vc[i];
+      acc += ok ? v : T(0);
     }
   }
   return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ R, const T* __restrict__ vc, int nk, int rho,
+                                        int fx, int fy) {
+  switch (rho) {
+    case 1: return prolong_at_r<T, 1>(R, vc, nk, fx, fy);
+    case 2: return prolong_at_r<T, 2>(R, vc, nk, fx, fy);
+    case 3: return prolong_at_r<T, 3>(R, vc, nk, fx, fy);
+    default: return prolong_at_r<T, 4>(R, vc, nk, fx, fy);
+  }
 }
 
 // w^(k) for the subband sum: the CG iterate, or for the finest level the
@@ -392,14 +486,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__ R, const T* __restrict__ vc,
                                                            FineCG<T> F, int nk, int rho, double* __restrict__ z,
                                                            const double* __restrict__ uo,
-                                                           const double* __restrict__ wo, double* part, unsigned* cnt,
-                                                           double* out) {
+                                                           const double* __restrict__ wo, double* part) {
   __shared__ double sh[3 * 16];
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
   const T alpha = T(F.scal[kFAlpha]), beta = T(F.scal[kFBeta]);
   double v[3] = {0.0, 0.0, 0.0};
-  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < nk * nk; id += gridDim.x * blockDim.x) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < nk * nk) {
     const int fx = id / nk, fy = id % nk;
     T acc = prolong_at<T>(R, vc, nk, rho, fx, fy);
     const int px = fx >> 1, py = fy >> 1;
@@ -414,43 +508,33 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__
     const double zv = (double)acc;
     z[id] = zv;
     const double uv = uo[id];
-    v[0] += zv * zv;
-    v[1] += uv * uv;
-    v[2] += zv * wo[id];
+    v[0] = zv * zv;
+    v[1] = uv * uv;
+    v[2] = zv * wo[id];
   }
   block_sum<3>(v, sh);
-  bool last;
-  double res[3];
-  finish_reduction<3>(v, part, gridDim.x, blockIdx.x, cnt, res, &last, sh);
-  if (last) {
-    out[0] = res[0];
-    out[1] = res[1];
-    out[2] = res[2];
-  }
+  write_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
 
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, unsigned* cnt, double* out,
-                              hipStream_t st) {
+                              const double* uo, const double* wo, double* part, hipStream_t st) {
   const int tot = L.nk * L.nk;
-  int nb = (tot + 255) / 256;
-  if (nb > kDotBlocks) nb = kDotBlocks;
-  hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3(nb), dim3(256), 0, st, R, vc, F, L.nk, L.rho, z, uo, wo, part, cnt,
-                     out);
+  hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, F, L.nk, L.rho, z, uo,
+                     wo, part);
 }
 
 template <typename T>
-void launch_outer_update_convert(int len, const double* sc, double* u, double* r, const double* p, const double* w,
-                                 T* g, hipStream_t st) {
-  hipLaunchKernelGGL(k_outer_update_convert<T>, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, u, r, p, w, g);
+void launch_outer_update_convert(int len, const double* part, int nblk, double* sc, double* u, double* r,
+                                 const double* p, const double* w, T* g, hipStream_t st) {
+  int nb = (len + 255) / 256;
+  if (nb > kUpdateBlocks) nb = kUpdateBlocks;
+  hipLaunchKernelGGL(k_outer_update_convert<T>, dim3(nb), dim3(256), 0, st, len, part, nblk, sc, u, r, p, w, g);
 }
 
 void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
-                            unsigned* cnt, double* out, hipStream_t st) {
-  int nb = (n * n + 255) / 256;
-  if (nb > kDotBlocks) nb = kDotBlocks;
-  hipLaunchKernelGGL(k_apply_fine_dots, dim3(nb), dim3(256), 0, st, a, n, p, r, w, part, cnt, out);
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_apply_fine_dots, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, p, r, w, part);
 }
 
 // Small levels in one workgroup.  Restriction g^(k-1) = R g^(k) for k = khi..2;
@@ -535,7 +619,7 @@ void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t s
   hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1), dim3(1024), 0, st, c, L1);
 }
 
-// Coarsest system A^(1) U^(1) = g^(1) (Algorithm 2, line 16) with the FP64
+// Coarsest system A^(1) U^(1) = g^(1) (last solve of Algorithm 2) with the FP64
 // Cholesky factor computed at build time.
 template <typename T>
 __global__ void k_coarse_solve(const double* __restrict__ L1, const T* __restrict__ g1, T* __restrict__ v1) {
@@ -561,7 +645,7 @@ void launch_coarse_solve(const double* L1, const T* g1, T* v1, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Subband systems B^(k) w^(k) = W^(k) g^(k) (eq. for w^(k), Section 4.7;
-// Algorithm 2, line 8), all levels in one grid.  Conjugate gradients
+// subband solve of Algorithm 2), all levels in one grid.  Conjugate gradients
 // (Section 4.9) with a block-Jacobi preconditioner (inverse 3x3 parent
 // blocks).  Subband vectors are stored t-major: v[t * np^2 + parent].
 // The direction update is folded into the operator application using
@@ -641,38 +725,62 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
 // reads 64 consecutive words; the rows are summed in LDS.
 // q = B z + beta q, p = z + beta p and the partial sums of (p, q); the last
 // block of each level forms alpha = (r, z) / (p, q).
-template <typename T>
-__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it) {
-  __shared__ double sh[16];
-  __shared__ T red[3 * 16 * 64];
-  const int l = find_level_s(args, blockIdx.x);
-  const CGLev<T>& L = args.lv[l];
-  if (it >= L.iters) return;
-  const int blk = blockIdx.x - L.blk0s;
+// Neighbour rows ox = wv, wv + nw, ... of one parent for a compile-time
+// stencil width TT (the oy loop is unrolled so that a row's loads are all
+// in flight together).
+template <typename T, int TT>
+__device__ __forceinline__ void coarse_rows(const CGLev<T>& L, int p, int wv, int nw, T& acc0, T& acc1, T& acc2) {
+  constexpr int t = TT / 2;
   const int np = L.np;
   const size_t np2 = (size_t)np * np;
-  const int t = L.t, TT = 2 * L.t + 1;
+  const int px = p / np, py = p - (p / np) * np;
+  for (int ox = wv; ox < TT; ox += nw) {
+    const int qx = px + ox - t;
+    if (qx < 0 || qx >= np) continue;
+    const T* Bo = L.B + b_index(ox * TT, 0, p, TT);
+    const int qb = qx * np + py - t;
+    // B is stored as zero for neighbours outside the level, so the z index is
+    // only clamped and every load of the row is unconditional
+#pragma unroll
+    for (int oy = 0; oy < TT; ++oy) {
+      const int qy = min(max(py + oy - t, 0), np - 1);
+      const int qn = qb + t + (qy - py);
+      const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
+      const T* Bb = Bo + oy * 9 * 64;
+      acc0 += Bb[0] * z0 + Bb[64] * z1 + Bb[128] * z2;
+      acc1 += Bb[192] * z0 + Bb[256] * z1 + Bb[320] * z2;
+      acc2 += Bb[384] * z0 + Bb[448] * z1 + Bb[512] * z2;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int blk_begin) {
+  __shared__ double sh[16];
+  __shared__ T red[3 * 16 * 64];
+  const int gb = blk_begin + (int)blockIdx.x;
+  const int l = find_level_s(args, gb);
+  const CGLev<T>& L = args.lv[l];
+  if (it >= L.iters) return;
+  const int blk = gb - L.blk0s;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int TT = 2 * L.t + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int p = blk * 64 + lane;
   T acc0 = T(0), acc1 = T(0), acc2 = T(0);
   if (p < np * np) {
-    const int px = p / np, py = p - (p / np) * np;
-    const int oyl = max(0, t - py), oyh = min(TT - 1, np - 1 - py + t);
-    for (int ox = wv; ox < TT; ox += nw) {
-      const int qx = px + ox - t;
-      if (qx < 0 || qx >= np) continue;
-      const T* Bo = L.B + b_index(ox * TT, 0, p, TT);
-      const int qb = qx * np + py - t;
-#pragma unroll 4
-      for (int oy = oyl; oy <= oyh; ++oy) {
-        const int qn = qb + oy;
-        const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
-        const T* Bb = Bo + oy * 9 * 64;
-        acc0 += Bb[0] * z0 + Bb[64] * z1 + Bb[128] * z2;
-        acc1 += Bb[192] * z0 + Bb[256] * z1 + Bb[320] * z2;
-        acc2 += Bb[384] * z0 + Bb[448] * z1 + Bb[512] * z2;
-      }
+    switch (TT) {
+      case 1: coarse_rows<T, 1>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 3: coarse_rows<T, 3>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 5: coarse_rows<T, 5>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 7: coarse_rows<T, 7>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 9: coarse_rows<T, 9>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 11: coarse_rows<T, 11>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 13: coarse_rows<T, 13>(L, p, wv, nw, acc0, acc1, acc2); break;
+      case 15: coarse_rows<T, 15>(L, p, wv, nw, acc0, acc1, acc2); break;
+      default: coarse_rows<T, 17>(L, p, wv, nw, acc0, acc1, acc2); break;
     }
   }
   red[(0 * 16 + wv) * 64 + lane] = acc0;
@@ -749,12 +857,18 @@ template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks), dim3(256), 0, st, a);
 }
+// The largest coarse level (first in the list) gets its own launch with
+// one wavefront per stencil row; the smaller levels share a second launch.
 template <typename T>
 void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
-  int tmax = 1;
-  for (int l = 0; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
-  const int nw = tmax < 16 ? tmax : 16;
-  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks), dim3(64 * nw), 0, st, a, it);
+  const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
+  const int t0 = 2 * a.lv[0].t + 1;
+  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, it, 0);
+  if (nblocks > n0) {
+    int tmax = 1;
+    for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
+    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks - n0), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, it, n0);
+  }
 }
 template <typename T>
 void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
@@ -1010,9 +1124,11 @@ void launch_outer_update(int len, const double* sc, double* u, double* r, const 
                          hipStream_t st) {
   hipLaunchKernelGGL(k_outer_update, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, u, r, p, w);
 }
-void launch_outer_direction(int len, const double* sc, const double* z, double* p, int first,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_outer_direction, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, z, p, first);
+void launch_outer_direction(int len, double* sc, const double* partz, int nblkz, const double* z, double* p,
+                            double* elog, int first, hipStream_t st) {
+  int nb = (len + 255) / 256;
+  if (nb > kUpdateBlocks) nb = kUpdateBlocks;
+  hipLaunchKernelGGL(k_outer_direction, dim3(nb), dim3(256), 0, st, len, sc, partz, nblkz, z, p, elog, first);
 }
 void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st) {
   hipLaunchKernelGGL(k_slots_to_nodal, dim3((n * n + 255) / 256), dim3(256), 0, st, n, s, u);
@@ -1046,10 +1162,9 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   template void launch_zero<T>(size_t, T*, hipStream_t);                                                \
   template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t);                                 \
   template void launch_prolong_fine_dots<T>(const LevelGeom&, const T*, const T*, const FineCG<T>&,      \
-                                            double*, const double*, const double*, double*, unsigned*,  \
-                                            double*, hipStream_t);                                      \
-  template void launch_outer_update_convert<T>(int, const double*, double*, double*, const double*,     \
-                                               const double*, T*, hipStream_t);                         \
+                                            double*, const double*, const double*, double*, hipStream_t); \
+  template void launch_outer_update_convert<T>(int, const double*, int, double*, double*, double*,      \
+                                               const double*, const double*, T*, hipStream_t);          \
   template void launch_restrict_chain<T>(const ChainArgs<T>&, hipStream_t);                             \
   template void launch_prolong_chain<T>(const ChainArgs<T>&, const double*, hipStream_t);
 GBL_INST(float)

@@ -17,9 +17,11 @@ constexpr int kSUU = 4;   // (u, u)
 constexpr int kSZW = 5;   // (z, A p)
 constexpr int kSRR = 6;   // (r, r)
 constexpr int kSBB = 7;   // (b, b)
-constexpr int kSSpare = 8;   // three unused slots
+constexpr int kSIter = 8;    // outer iterations whose error estimate has been logged
+constexpr int kSSpare = 9;   // unused slots
 constexpr int kNumOuterScalars = 12;
 constexpr int kDotBlocks = 1024;
+constexpr int kUpdateBlocks = 256;   // blocks of the kernels that re-add block partials
 
 // Per-level CG scalar slots.
 constexpr int kCRZ = 0;
@@ -87,13 +89,12 @@ template <typename T>
 void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, unsigned* cnt, double* out,
-                              hipStream_t st);
+                              const double* uo, const double* wo, double* part, hipStream_t st);
 template <typename T>
-void launch_outer_update_convert(int len, const double* sc, double* u, double* r, const double* p, const double* w,
-                                 T* g, hipStream_t st);
+void launch_outer_update_convert(int len, const double* part, int nblk, double* sc, double* u, double* r,
+                                 const double* p, const double* w, T* g, hipStream_t st);
 void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
-                            unsigned* cnt, double* out, hipStream_t st);
+                            hipStream_t st);
 
 // Small levels handled inside one workgroup (restriction and prolongation
 // chains).  Entry j is level k = kmin + j: R = R^(k-1,k), gf = level-k
@@ -140,8 +141,8 @@ void launch_dots(int len, int nv, const double* x0, const double* y0, const doub
                  hipStream_t st);
 void launch_outer_update(int len, const double* sc, double* u, double* r, const double* p, const double* w,
                          hipStream_t st);
-void launch_outer_direction(int len, const double* sc, const double* z, double* p, int first,
-                            hipStream_t st);
+void launch_outer_direction(int len, double* sc, const double* partz, int nblkz, const double* z, double* p,
+                            double* elog, int first, hipStream_t st);
 void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st);
 void launch_fill(size_t len, double v, double* x, hipStream_t st);
 void launch_cell_gradient(const double* a, int n, const double* u, const double* lam, double* dloga,

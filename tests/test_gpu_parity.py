@@ -61,6 +61,38 @@ def test_hierarchy_levels_match_oracle_fp64(q, rho, sigma):
     H.close()
 
 
+@pytest.mark.parametrize("kernel", ["mfma", "registers"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_dense_patch_kernels_match_oracle(monkeypatch, kernel, prec, tol):
+    """Both dense patch kernels of the coarser levels (matrix-core blocked
+    Cholesky, register-tiled Cholesky) against the oracle's R and A^(k-1);
+    rho = 3 at q = 6 gives patches of up to 147 unknowns (10 tiles of 16).
+    FP32 bound: unit roundoff 6e-8 times scaled patch condition numbers up to
+    about 1e3, compounded over the FP32 Galerkin products of the finer levels."""
+    monkeypatch.setenv("GBL_PATCH_MFMA", "1" if kernel == "mfma" else "0")
+    q, rho = 6, 3
+    _print_case(test="dense_patch", kernel=kernel, prec=prec, q=q, rho=rho)
+    pr = S.rough_problem(q, 2.0, 23)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    ref = G.localized_hierarchy(fe.A, tree, rho)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec)
+    torch.cuda.synchronize()
+    for k in range(q - 1, 1, -1):
+        lv = H.level(k)
+        R_gpu = restriction_to_matrix(lv["R"].cpu().double().numpy(), lv["rho"], q, k, tree.size(k))
+        R_ref = ref.levels[k].R
+        err = abs(R_gpu - R_ref).max() / abs(R_ref).max()
+        print(f"level {k} R err {err:.3e}", flush=True)
+        assert err < tol, (k, "R", err)
+        lc = H.level(k - 1)
+        A_gpu = stencil_to_matrix(lc["A"].cpu().double().numpy(), q, k - 1, tree.size(k - 1))
+        A_ref = ref.levels[k - 1].A
+        err = abs(A_gpu - A_ref).max() / abs(A_ref).max()
+        assert err < tol, (k - 1, "A", err)
+    H.close()
+
+
 @pytest.mark.parametrize("q,rho,sigma,prec,tol", [
     (6, 3, 1.0, "fp64", 1e-10), (6, 3, 2.0, "fp64", 1e-10), (6, 3, 2.0, "mixed", 1e-8),
     (7, 2, 2.0, "mixed", 1e-8), (5, 1, 1.0, "fp64", 1e-10), (2, 3, 1.0, "fp64", 1e-10),
@@ -147,4 +179,30 @@ def test_no_convergence_is_reported():
     u = H.solve(_dev(pr.g[0]), check=False)
     assert H.last_info.status == -3
     assert torch.isfinite(u).all()
+    H.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_iteration_graph_matches_direct_launches(monkeypatch, prec):
+    """The outer iteration replayed as a recorded graph gives the same iterates
+    as kernel-by-kernel launches: three right-hand sides, solved twice with
+    each path, eager work (a fresh solve and a host copy) between replays."""
+    q, rho = 6, 3
+    _print_case(test="iteration_graph", prec=prec, q=q, rho=rho)
+    pr = S.rough_problem(q, 2.0, 24, nrhs=3)
+    u_ref = fem.solve(pr.a, pr.g)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec, rtol=1e-8, max_rhs=3)
+    out = {}
+    for mode in ["1", "0", "1"]:
+        monkeypatch.setenv("GBL_ITER_GRAPH", mode)
+        u = H.solve(_dev(pr.g)).cpu().numpy()
+        iters = H.last_info.outer_iters
+        if mode in out:
+            assert np.array_equal(u, out[mode][0]), "graph replays differ between calls"
+        out[mode] = (u, iters)
+    assert out["1"][1] == out["0"][1]
+    assert np.array_equal(out["1"][0], out["0"][0])
+    for r in range(3):
+        err = _relerr(out["1"][0][r][1:-1, 1:-1], u_ref[r][1:-1, 1:-1])
+        assert err < 1e-8, (r, err)
     H.close()
