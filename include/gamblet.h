@@ -58,8 +58,9 @@ extern "C" {
 enum gbl_status {
   GBL_OK = 0,
   GBL_EINVAL = -1,   /* bad argument: q out of range, null pointer, a <= 0 or non-finite, nrhs too large */
-  GBL_ENOTSPD = -2,  /* a patch or coarse matrix had a non-positive pivot */
-  GBL_ENOCONV = -3,  /* the solve did not reach rtol within max_outer iterations; u holds the last iterate */
+  GBL_ENOTSPD = -2,  /* FP64: a patch or coarse matrix had a non-positive pivot (MIXED: see gbl_build_flags) */
+  GBL_ENOCONV = -3,  /* the solve did not reach rtol within max_outer iterations, or diverged (then
+                        gbl_solve_info reports NaN); u holds the last iterate */
   GBL_ENOMEM = -4,   /* the workspace is smaller than gbl_workspace_bytes reports */
   GBL_EHIP = -5      /* a HIP runtime call failed */
 };
@@ -156,6 +157,17 @@ int gbl_solve(gbl_ctx* ctx, int nrhs, const double* g_dev, double* u_dev,
 int gbl_adjoint(gbl_ctx* ctx, int nrhs, const double* u_dev, const double* dJdu_dev,
                 double* dJdloga_dev, double* dJdg_dev, double* lambda_dev,
                 gbl_solve_info* info, void* stream);
+
+/* Build flags (bit set).  GBL_FLAG_PIVOTS_REGULARIZED: in MIXED precision,
+ * one or more pivots of a patch factorisation (scaled to a unit diagonal) or
+ * of the coarse A^(1) factor fell below 1e-6 in FP32 -- a patch straddling a
+ * coefficient jump beyond single-precision resolution -- and were raised to
+ * that floor.  The hierarchy is still symmetric positive definite (any patch
+ * solution D gives a full-rank R = pibar + D W, Section 4.7), so solves stay
+ * correct, but may need more outer iterations; GBL_FP64 avoids it.  In FP64
+ * a non-positive pivot is the ENOTSPD error instead. */
+#define GBL_FLAG_PIVOTS_REGULARIZED 1u
+int gbl_build_flags(const gbl_ctx* ctx, unsigned* flags);
 
 /* Describe level k (1 <= k <= q) of a built hierarchy.  EINVAL on a bad k. */
 int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);

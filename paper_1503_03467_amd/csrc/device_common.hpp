@@ -67,6 +67,31 @@ __device__ __forceinline__ size_t b_index(int o, int e, int p, int TT) {
   return ((size_t)(p >> 6) * (size_t)(TT * TT * 9) + (size_t)(o * 9 + e)) * 64 + (p & 63);
 }
 
+// Pivot of a patch factorisation whose matrix is scaled to a unit diagonal.
+// In FP64 a pivot that is not positive is an error (bad is set).  In FP32 a
+// pivot below kPivotFloor is the rounding of a Schur complement that lies
+// under single-precision resolution (a patch straddling a coefficient jump of
+// many orders of magnitude): it is raised to the floor and reg is set.  The
+// patch solve is then perturbed, but every D gives a full-rank
+// R = pibar + D W, so the hierarchy stays symmetric positive definite and the
+// FP64 outer iteration absorbs the perturbation.
+constexpr float kPivotFloor = 1e-6f;
+template <typename T>
+__device__ __forceinline__ T patch_pivot(T pv, int& bad, int& reg) {
+  if (sizeof(T) == 4) {
+    if (!(pv > T(kPivotFloor))) {
+      reg = 1;
+      return T(kPivotFloor);
+    }
+    return pv;
+  }
+  if (!(pv > T(0))) {
+    bad = 1;
+    return T(1);
+  }
+  return pv;
+}
+
 template <typename T>
 __device__ __forceinline__ T my_sqrt(T x);
 template <>

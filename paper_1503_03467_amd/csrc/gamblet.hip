@@ -244,6 +244,8 @@ struct gbl_ctx {
   hipStream_t cap = nullptr;
   hipGraphExec_t iter_graph = nullptr;
   bool graph_off = false;               // capture failed once: launch kernel by kernel
+  unsigned build_flags = 0;             // GBL_FLAG_* of the build
+  bool diverged = false;                // the last solve produced a non-finite estimate or residual
 
   template <typename T>
   T* hier(size_t off) const { return reinterpret_cast<T*>(ws + L.hier_off) + off; }
@@ -623,12 +625,16 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   HIPCHK(c, hipGetLastError());
+  const double bb = c->host[kSBB], rr = c->host[kSRR];
+  const double rel_res = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
   if (info) {
+    // maxima over right-hand sides that keep a NaN visible
+    auto worst = [](double a, double b) { return (std::isnan(a) || std::isnan(b)) ? NAN : std::max(a, b); };
     info->outer_iters = std::max(info->outer_iters, it);
-    info->rel_update = std::max(info->rel_update, est);
-    const double bb = c->host[kSBB], rr = c->host[kSRR];
-    info->rel_residual = std::max(info->rel_residual, bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr));
+    info->rel_update = worst(info->rel_update, est);
+    info->rel_residual = worst(info->rel_residual, rel_res);
   }
+  if (!std::isfinite(est) || !std::isfinite(rel_res)) c->diverged = true;
   return status;
 }
 
@@ -750,6 +756,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
     c->err = "coefficient must be positive and finite in every cell";
     return bail(GBL_EINVAL);
   }
+  if (bits & kRegularizedPivot) c->build_flags |= GBL_FLAG_PIVOTS_REGULARIZED;
   if (bits & kBadPivot) {
     c->err = "non-positive pivot in a patch or coarse matrix";
     return bail(GBL_ENOTSPD);
@@ -763,12 +770,15 @@ int gbl_solve(gbl_ctx* c, int nrhs, const double* g_dev, double* u_dev, gbl_solv
   if (!g_dev || !u_dev) return fail(c, GBL_EINVAL, "g_dev and u_dev must not be NULL");
   if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
   if (info) std::memset(info, 0, sizeof(*info));
+  c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t n2 = (size_t)c->L.n * c->L.n;
   const int st = (c->L.prec == GBL_FP64) ? solve_many<double>(c, nrhs, 0, g_dev, n2, u_dev, info, s)
                                          : solve_many<float>(c, nrhs, 0, g_dev, n2, u_dev, info, s);
   if (info) info->status = st;
-  if (st == GBL_ENOCONV) return fail(c, st, "solve did not reach rtol within max_outer iterations");
+  if (st == GBL_ENOCONV)
+    return fail(c, st, c->diverged ? "solve diverged (non-finite error estimate or residual)"
+                                   : "solve did not reach rtol within max_outer iterations");
   return st;
 }
 
@@ -778,6 +788,7 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
   if (!u_dev || !dJdu_dev || !dJdloga_dev) return fail(c, GBL_EINVAL, "u, dJdu and dJdloga must not be NULL");
   if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
   if (info) std::memset(info, 0, sizeof(*info));
+  c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = c->L.n;
   const size_t n2 = (size_t)n * n, us = (size_t)(n + 1) * (n + 1);
@@ -797,8 +808,16 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   if (info) info->status = worst;
-  if (worst == GBL_ENOCONV) return fail(c, worst, "adjoint solve did not reach rtol within max_outer iterations");
+  if (worst == GBL_ENOCONV)
+    return fail(c, worst, c->diverged ? "adjoint solve diverged (non-finite error estimate or residual)"
+                                      : "adjoint solve did not reach rtol within max_outer iterations");
   return worst;
+}
+
+int gbl_build_flags(const gbl_ctx* c, unsigned* flags) {
+  if (!c || !flags) return fail(nullptr, GBL_EINVAL, "ctx or flags is NULL");
+  *flags = c->build_flags;
+  return GBL_OK;
 }
 
 int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {

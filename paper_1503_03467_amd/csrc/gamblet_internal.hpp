@@ -30,6 +30,7 @@ constexpr int kMaxRho = 4;
 constexpr int kBadCoefficient = 1;
 constexpr int kBadPivot = 2;
 constexpr int kBadInput = 4;
+constexpr int kRegularizedPivot = 8;   // FP32 patch or coarse pivots raised to the floor (not an error)
 
 struct LevelGeom {
   int k = 0;       // level

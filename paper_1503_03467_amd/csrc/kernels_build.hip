@@ -290,11 +290,9 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
   for (int j = 0; j < p; ++j) {
     const T* cur = colbuf[j & 1];
     T* nxt = colbuf[(j + 1) & 1];
-    T pv = pivv[j];
-    if (!(pv > T(0))) {
-      if (tid == 0) flag = 1;
-      pv = T(1);
-    }
+    int pbad = 0, preg = 0;
+    const T pv = patch_pivot<T>(pivv[j], pbad, preg);
+    if (tid == 0 && (pbad | preg)) flag |= pbad | (preg << 1);
     const T sq = my_sqrt<T>(pv);
     const T inv = T(1) / pv;
     const T rs = T(1) / sq;
@@ -384,7 +382,8 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
   }
   // unscale: y_r = sc_r x_r
   for (int r = tid; r < p; r += 256) zb[r] = pivv[r] * sc[r];
-  if (tid == 0 && flag) atomicOr(status, kBadPivot);
+  if (tid == 0 && (flag & 1)) atomicOr(status, kBadPivot);
+  if (tid == 0 && (flag & 2)) atomicOr(status, kRegularizedPivot);
   __syncthreads();
 
   // R_i[bx][by] over level-k slots c = 2(cx - rho) + bx
@@ -636,15 +635,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       T a[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[c] = panel[P][lc][c];
-      int badl = 0;
+      int badl = 0, regl = 0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         T dk = Mfma<T>::lane_value(a[k], k);
         if (16 * P + k >= p) {
           dk = T(1);
-        } else if (!(dk > T(0))) {
-          badl = 1;
-          dk = T(1);
+        } else {
+          dk = patch_pivot<T>(dk, badl, regl);
         }
         const T sk = my_sqrt<T>(dk);
         const T rk = T(1) / sk;
@@ -659,7 +657,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int c = 0; c < 16; ++c)
           if (c == lc) dinv[lc] = T(1) / a[c];
       }
-      if (l == 0 && badl) bad = 1;
+      if (l == 0 && (badl | regl)) bad |= badl | (regl << 1);
     }
     __syncthreads();
     // 3. rows of L_IP (I > P) and of L_PP^{-T}: l[c] = (a[c] - sum_{m<c} l[m] L_PP[c][m]) / L_PP[c][c]
@@ -764,7 +762,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     __syncthreads();
   }
-  if (tid == 0 && bad) atomicOr(status, kBadPivot);
+  if (tid == 0 && (bad & 1)) atomicOr(status, kBadPivot);
+  if (tid == 0 && (bad & 2)) atomicOr(status, kRegularizedPivot);
   // y = sc x, then the restriction row R_i = pibar_i + sum y_j W_j
   for (int r = tid; r < p; r += 256) rhs[r] *= sc[r];
   __syncthreads();
@@ -826,7 +825,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
   const int S = 2 * s + 1;
   const size_t nc2 = (size_t)nc * nc;
   const int ti = parent_type(true, cx, cy);
-  int bad = 0;
+  int bad = 0, reg = 0;
 
   // scaling and right-hand side
   for (int r = lane; r < p; r += 64) {
@@ -898,11 +897,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
   __syncthreads();
 
   for (int j = 0; j < p; ++j) {
-    T pv = ab[j * bw1];
-    if (!(pv > T(0))) {
-      bad = 1;
-      pv = T(1);
-    }
+    const T pv = patch_pivot<T>(ab[j * bw1], bad, reg);
     const T dj = my_sqrt<T>(pv);
     const T inv = T(1) / dj;
     const int e = lane + 1;
@@ -937,6 +932,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
   }
   for (int r = lane; r < p; r += 64) bb[r] *= sc[r];
   if (bad) atomicOr(status, kBadPivot);
+  if (reg && lane == 0) atomicOr(status, kRegularizedPivot);
   __syncthreads();
 
   const int rw = 2 * (2 * rho + 1);
@@ -1067,9 +1063,13 @@ __global__ void k_coarse_factor(const T* __restrict__ A1, int s1, double* __rest
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < i; ++j) M[i][j] = M[j][i] = 0.5 * (M[i][j] + M[j][i]);
   for (int j = 0; j < 4; ++j) {
-    double d = M[j][j];
+    const double d0 = M[j][j];
+    double d = d0;
     for (int k = 0; k < j; ++k) d -= M[j][k] * M[j][k];
-    if (!(d > 0.0)) {
+    if (sizeof(T) == 4 && d0 > 0.0 && !(d > (double)kPivotFloor * d0)) {
+      atomicOr(status, kRegularizedPivot);   // FP32 Galerkin rounding, as in patch_pivot
+      d = (double)kPivotFloor * d0;
+    } else if (!(d > 0.0)) {
       atomicOr(status, kBadPivot);
       d = 1.0;
     }

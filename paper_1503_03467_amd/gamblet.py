@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
         L.gbl_solve.argtypes = [vp, i, vp, vp, ctypes.POINTER(GblSolveInfo), vp]
         L.gbl_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(GblSolveInfo), vp]
         L.gbl_level_layout.argtypes = [vp, i, ctypes.POINTER(GblLevelDesc)]
+        L.gbl_build_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
         L.gbl_destroy.argtypes = [vp]
         L.gbl_last_error.argtypes = [vp]
         L.gbl_last_error.restype = ctypes.c_char_p
@@ -68,8 +69,8 @@ def lib() -> ctypes.CDLL:
         L.gbl_profile_reset.argtypes = []
         L.gbl_profile_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
-                     "gbl_level_layout", "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset",
-                     "gbl_profile_read"):
+                     "gbl_level_layout", "gbl_build_flags", "gbl_destroy", "gbl_profile_enable",
+                     "gbl_profile_reset", "gbl_profile_read"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -197,6 +198,13 @@ class Hierarchy:
         if single:
             return dloga[0], dg[0], lam[0]
         return dloga, dg, lam
+
+    @property
+    def build_flags(self) -> int:
+        """GBL_FLAG_* bits of the build (1: FP32 pivots raised to the floor)."""
+        f = ctypes.c_uint(0)
+        _check(lib().gbl_build_flags(self.ctx, ctypes.byref(f)), self.ctx)
+        return int(f.value)
 
     def level(self, k: int) -> dict:
         """A^(k) [S,S,nk,nk] and R^(k-1,k) [rw,rw,nc,nc] as device views, B^(k) as a

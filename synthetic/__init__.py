@@ -165,11 +165,11 @@ def adjoint_problem(q: int = 10, tag: int = TAG_ADJOINT_Q10) -> Problem:
     return pr
 
 
-def inclusion_problem(q: int = 11, nrhs: int = 16, tag: int = TAG_Q11_INCL) -> Problem:
-    """Product field with high-contrast circular inclusions (a = 1e6 inside)."""
+def inclusion_problem(q: int = 11, nrhs: int = 16, tag: int = TAG_Q11_INCL, a_incl: float = 1.0e6) -> Problem:
+    """Product field with high-contrast circular inclusions (a = a_incl inside, 1e6 by default)."""
     n = 1 << q
     a = product_field(n)
     mask = inclusion_mask(n, rng(tag, 0, KIND_INCL))
-    a[mask] = 1.0e6
+    a[mask] = a_incl
     g = np.stack([rng(tag, 0, KIND_G, r).standard_normal((n, n)) for r in range(nrhs)])
     return Problem(q=q, a=a, g=g, rho=4, tag=tag)

@@ -70,6 +70,8 @@ def test_null_arguments_rejected():
     assert L.gbl_build(None, 6, ctypes.c_void_p(16), ctypes.byref(o), ctypes.c_void_p(16), 1 << 30, None) == -1
     assert L.gbl_solve(None, 1, None, None, None, None) == -1
     assert L.gbl_destroy(None) == 0
+    flags = ctypes.c_uint(7)
+    assert L.gbl_build_flags(None, ctypes.byref(flags)) == -1
 
 
 def test_short_workspace_rejected_before_any_device_work():

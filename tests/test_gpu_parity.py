@@ -206,3 +206,77 @@ def test_iteration_graph_matches_direct_launches(monkeypatch, prec):
         err = _relerr(out["1"][0][r][1:-1, 1:-1], u_ref[r][1:-1, 1:-1])
         assert err < 1e-8, (r, err)
     H.close()
+
+
+@pytest.mark.timeout(300)
+def test_full_size_q9_matches_direct():
+    """The benchmark workload itself (512 x 512 cells, sigma = 2, rho = 3):
+    mixed path at 1e-8 and FP64 path at 1e-10 against the direct solve."""
+    _print_case(test="full_q9")
+    pr = S.q9_rough_problem()
+    u_ref = fem.solve(pr.a, pr.g)[0][1:-1, 1:-1]
+    print("oracle done", flush=True)
+    for prec, tol in [("mixed", 1e-8), ("fp64", 1e-10)]:
+        H = _P().Hierarchy(_dev(pr.a), rho=3, precision=prec, rtol=tol)
+        u = H.solve(_dev(pr.g[0])).cpu().numpy()
+        err = _relerr(u[1:-1, 1:-1], u_ref)
+        print(prec, "err", err, H.last_info, flush=True)
+        assert err < tol, (prec, err)
+        H.close()
+
+
+@pytest.mark.timeout(400)
+def test_adjoint_q10_matches_oracle_and_fd():
+    """Adjoint workload (1024 x 1024 cells, J = |u - u_obs|^2 / 2, mixed
+    precision): dJ/dlog a against the oracle's adjoint over all cells, and
+    against the oracle's cancellation-free finite difference on 8 of the 32
+    seeded cells."""
+    _print_case(test="adjoint_q10")
+    pr = S.adjoint_problem(q=10)
+    u_obs = fem.solve(pr.extra["a_obs"], pr.g[0])
+    _, J_ref, ga_ref, _ = fem.adjoint(pr.a, pr.g[0], u_obs[1:-1, 1:-1].ravel())
+    cells = pr.extra["fd_cells"][:8]
+    fd = fem.fd_log_a(pr.a, pr.g[0], u_obs[1:-1, 1:-1].ravel(), cells)
+    print("oracle done", flush=True)
+    H = _P().Hierarchy(_dev(pr.a), rho=3, precision="mixed", rtol=1e-8)
+    u = H.solve(_dev(pr.g[0]))
+    dJdu = (u - _dev(u_obs)).contiguous()
+    ga, _, _ = H.adjoint(u, dJdu)
+    ga = ga[0].cpu().numpy() if ga.dim() == 3 else ga.cpu().numpy()
+    err = _relerr(ga, ga_ref)
+    print("grad err", err, H.last_info, flush=True)
+    assert err < 1e-5, err
+    gfd = ga.ravel()[cells]
+    err_fd = _relerr(gfd, np.asarray(fd))
+    print("fd err", err_fd, flush=True)
+    assert err_fd < 1e-5, err_fd
+    H.close()
+
+
+@pytest.mark.timeout(600)
+def test_inclusions_q11_rho4():
+    """Circular inclusions on 10% of a 2048 x 2048 grid, rho = 4, FP64 path.
+    The inclusion value is 1e4 (total contrast 4.5e5): the block-Jacobi
+    preconditioned subband systems of the two finest levels have condition
+    numbers close to the inclusion value, and at 1e6 the local inner solves
+    stall (recorded as a limitation).  Four right-hand sides with inner budgets
+    (64, 16) each get a small FP64 residual; the first matches the direct solve
+    at 1e-8."""
+    _print_case(test="inclusions_q11", a_incl=1e4)
+    pr = S.inclusion_problem(nrhs=4, a_incl=1e4)
+    fe = fem.assemble(pr.a)
+    print("problem ready", flush=True)
+    H = _P().Hierarchy(_dev(pr.a), rho=4, precision="fp64", rtol=1e-8, max_rhs=4, max_outer=400,
+                       inner_iters=64, inner_iters_coarse=16)
+    u = H.solve(_dev(pr.g)).cpu().numpy()
+    print("gpu done", H.last_info, flush=True)
+    H.close()
+    for r in range(4):
+        b = fem.load_cellwise(pr.g[r], fe.h)
+        res = np.linalg.norm(b - fe.A @ u[r][1:-1, 1:-1].ravel()) / np.linalg.norm(b)
+        print("rhs", r, "residual", res, flush=True)
+        assert res < 1e-5, (r, res)
+    u_ref = fem.solve(pr.a, pr.g[:1])[0][1:-1, 1:-1]
+    err = _relerr(u[0][1:-1, 1:-1], u_ref)
+    print("err vs direct", err, flush=True)
+    assert err < 1e-8, err
