@@ -158,6 +158,32 @@ int gbl_adjoint(gbl_ctx* ctx, int nrhs, const double* u_dev, const double* dJdu_
                 double* dJdloga_dev, double* dJdg_dev, double* lambda_dev,
                 gbl_solve_info* info, void* stream);
 
+/* Batched build of independent problems of uneven depth (the workload of
+ * many small problems, each too small to fill the GPU alone).  Problem i has
+ * depth q[i] (2..12), coefficient a_dev[i] ([2^q_i][2^q_i]) and its own
+ * workspace ws_dev[i] of ws_bytes[i] >= gbl_workspace_bytes(q[i], opts)
+ * bytes; all problems share opts.  The problems are built concurrently by a
+ * pool of host threads (GBL_BATCH_WORKERS, default 8), each with its own HIP
+ * stream, largest first; the work starts after what is already enqueued on
+ * `stream`, and `stream` waits for all of it.  Returns when every build has
+ * finished.  ctx_out[i] receives the context of problem i (NULL if its build
+ * failed; release each with gbl_destroy) and status[i] its gbl_build status.
+ * Return value: GBL_OK if every problem built, else the first failing status
+ * in problem order (gbl_last_error(NULL) names the problem).  EINVAL on a
+ * null array or nprob < 1. */
+int gbl_build_batched(int nprob, const int* q, const double* const* a_dev, const gbl_opts* opts,
+                      void* const* ws_dev, const size_t* ws_bytes, gbl_ctx** ctx_out, int* status,
+                      void* stream);
+
+/* Batched solve: problem i solves nrhs[i] right-hand sides (<= its max_rhs),
+ * g_dev[i] [nrhs_i][n_i][n_i] into u_dev[i] [nrhs_i][n_i+1][n_i+1] (boundary
+ * values in, solution out) with context ctx[i], concurrently as in
+ * gbl_build_batched.  info (optional) is an array of nprob records; status[i]
+ * is problem i's gbl_solve status.  Return value as for gbl_build_batched.
+ * Two entries of ctx must not be the same context. */
+int gbl_solve_batched(int nprob, gbl_ctx* const* ctx, const int* nrhs, const double* const* g_dev,
+                      double* const* u_dev, gbl_solve_info* info, int* status, void* stream);
+
 /* Build flags (bit set).  GBL_FLAG_PIVOTS_REGULARIZED: in MIXED precision,
  * one or more pivots of a patch factorisation (scaled to a unit diagonal) or
  * of the coarse A^(1) factor fell below 1e-6 in FP32 -- a patch straddling a

@@ -14,7 +14,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <string>
 #include <utility>
@@ -812,6 +814,141 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
     return fail(c, worst, c->diverged ? "adjoint solve diverged (non-finite error estimate or residual)"
                                       : "adjoint solve did not reach rtol within max_outer iterations");
   return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems.  A problem of depth 6..8 leaves most of the
+// GPU idle (its kernels are latency-bound), so the problems of a batch run
+// concurrently: a pool of host threads, each with its own HIP stream, takes
+// problems largest first (work ~ 4^q x right-hand sides).  The pool's streams
+// start after the work already enqueued on the caller's stream and the caller's
+// stream waits for all of them before the call returns.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+int batch_workers(int nprob) {
+  int w = 8;
+  if (const char* e = getenv("GBL_BATCH_WORKERS")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 64) w = v;
+  }
+  return std::max(1, std::min(w, nprob));
+}
+
+// Runs job(i, stream) for every problem i on the pool; returns the first
+// non-OK status in problem order (status[i] holds each one) and the message
+// of that failure in msg.
+template <typename Job>
+int run_batch(int nprob, const std::vector<double>& work, int* status, hipStream_t caller, Job job,
+              std::string& msg) {
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  const int nw = batch_workers(nprob);
+  hipEvent_t start = nullptr;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess || hipEventRecord(start, caller) != hipSuccess) {
+    msg = "event creation failed";
+    return GBL_EHIP;
+  }
+  std::vector<hipStream_t> streams(nw, nullptr);
+  std::vector<hipEvent_t> done(nw, nullptr);
+  int setup = GBL_OK;
+  for (int w = 0; w < nw; ++w) {
+    if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&done[w], hipEventDisableTiming) != hipSuccess ||
+        hipStreamWaitEvent(streams[w], start, 0) != hipSuccess) {
+      setup = GBL_EHIP;
+    }
+  }
+  std::vector<std::string> msgs(nprob);
+  if (setup == GBL_OK) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nw; ++w) {
+      pool.emplace_back([&, w]() {
+        hipSetDevice(dev);
+        for (;;) {
+          const int k = next.fetch_add(1);
+          if (k >= nprob) break;
+          const int i = order[k];
+          status[i] = job(i, streams[w], msgs[i]);
+        }
+        hipEventRecord(done[w], streams[w]);
+      });
+    }
+    for (auto& t : pool) t.join();
+    for (int w = 0; w < nw; ++w) hipStreamWaitEvent(caller, done[w], 0);
+  }
+  for (int w = 0; w < nw; ++w) {
+    if (streams[w]) {
+      hipStreamSynchronize(streams[w]);
+      hipStreamDestroy(streams[w]);
+    }
+    if (done[w]) hipEventDestroy(done[w]);
+  }
+  hipEventDestroy(start);
+  if (setup != GBL_OK) {
+    msg = "stream creation for the batch failed";
+    return setup;
+  }
+  for (int i = 0; i < nprob; ++i) {
+    if (status[i] != GBL_OK) {
+      msg = "problem " + std::to_string(i) + ": " + msgs[i];
+      return status[i];
+    }
+  }
+  return GBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbl_build_batched(int nprob, const int* q, const double* const* a_dev, const gbl_opts* opts,
+                      void* const* ws_dev, const size_t* ws_bytes, gbl_ctx** ctx_out, int* status, void* stream) {
+  if (nprob < 1 || !q || !a_dev || !opts || !ws_dev || !ws_bytes || !ctx_out || !status)
+    return fail(nullptr, GBL_EINVAL, "batched build: null argument or nprob < 1");
+  std::vector<double> work(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    ctx_out[i] = nullptr;
+    status[i] = GBL_EINVAL;
+    work[i] = (q[i] >= 2 && q[i] <= 12) ? std::ldexp(1.0, 2 * q[i]) : 0.0;
+  }
+  std::string msg;
+  const int st = run_batch(nprob, work, status, static_cast<hipStream_t>(stream),
+                           [&](int i, hipStream_t s, std::string& m) {
+                             const int r = gbl_build(&ctx_out[i], q[i], a_dev[i], opts, ws_dev[i], ws_bytes[i], s);
+                             if (r != GBL_OK) m = gbl_last_error(nullptr);
+                             return r;
+                           },
+                           msg);
+  if (st != GBL_OK) return fail(nullptr, st, "batched build: " + msg);
+  return GBL_OK;
+}
+
+int gbl_solve_batched(int nprob, gbl_ctx* const* ctx, const int* nrhs, const double* const* g_dev,
+                      double* const* u_dev, gbl_solve_info* info, int* status, void* stream) {
+  if (nprob < 1 || !ctx || !nrhs || !g_dev || !u_dev || !status)
+    return fail(nullptr, GBL_EINVAL, "batched solve: null argument or nprob < 1");
+  std::vector<double> work(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    status[i] = GBL_EINVAL;
+    work[i] = ctx[i] ? std::ldexp(1.0, 2 * ctx[i]->L.q) * std::max(1, nrhs[i]) : 0.0;
+  }
+  std::string msg;
+  const int st = run_batch(nprob, work, status, static_cast<hipStream_t>(stream),
+                           [&](int i, hipStream_t s, std::string& m) {
+                             const int r = gbl_solve(ctx[i], nrhs[i], g_dev[i], u_dev[i], info ? &info[i] : nullptr, s);
+                             if (r != GBL_OK) m = gbl_last_error(ctx[i]);
+                             return r;
+                           },
+                           msg);
+  if (st != GBL_OK) return fail(nullptr, st, "batched solve: " + msg);
+  return GBL_OK;
 }
 
 int gbl_build_flags(const gbl_ctx* c, unsigned* flags) {

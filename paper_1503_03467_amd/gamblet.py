@@ -62,6 +62,11 @@ def lib() -> ctypes.CDLL:
         L.gbl_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(GblSolveInfo), vp]
         L.gbl_level_layout.argtypes = [vp, i, ctypes.POINTER(GblLevelDesc)]
         L.gbl_build_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
+        L.gbl_build_batched.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(GblOpts),
+                                        ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(vp),
+                                        ctypes.POINTER(i), vp]
+        L.gbl_solve_batched.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), ctypes.POINTER(GblSolveInfo), ctypes.POINTER(i), vp]
         L.gbl_destroy.argtypes = [vp]
         L.gbl_last_error.argtypes = [vp]
         L.gbl_last_error.restype = ctypes.c_char_p
@@ -69,8 +74,8 @@ def lib() -> ctypes.CDLL:
         L.gbl_profile_reset.argtypes = []
         L.gbl_profile_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
-                     "gbl_level_layout", "gbl_build_flags", "gbl_destroy", "gbl_profile_enable",
-                     "gbl_profile_reset", "gbl_profile_read"):
+                     "gbl_level_layout", "gbl_build_flags", "gbl_build_batched", "gbl_solve_batched",
+                     "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset", "gbl_profile_read"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -287,3 +292,82 @@ class GambletSolve(torch.autograd.Function):
         dloga, dg, _ = ctx.H.adjoint(u, grad_u.contiguous())
         ctx.H.close()
         return dloga, dg, None, None, None
+
+
+def _adopt(ctx_value: int, q: int, ws: torch.Tensor, opts: GblOpts) -> Hierarchy:
+    """Wrap a context built by gbl_build_batched in a Hierarchy (which then owns it)."""
+    h = Hierarchy.__new__(Hierarchy)
+    h.q, h.n, h.device = q, 1 << q, ws.device
+    h.opts, h.ws = opts, ws
+    h.ctx = ctypes.c_void_p(ctx_value)
+    h.last_info = None
+    return h
+
+
+def build_batched(coeffs: list, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
+                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
+                  inner_iters_coarse: int | None = None) -> list:
+    """Build the hierarchies of independent problems of uneven depth concurrently
+    (``gbl_build_batched``); ``coeffs`` holds [2^q][2^q] float64 CUDA tensors."""
+    P = len(coeffs)
+    if P == 0:
+        return []
+    opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse)
+    qs, wss = [], []
+    for a in coeffs:
+        n = a.shape[0]
+        q = n.bit_length() - 1
+        if n != (1 << q) or q < 2:
+            raise ValueError("every coefficient must be [2^q][2^q] with q >= 2")
+        _require(a, (n, n), "a")
+        qs.append(q)
+        wss.append(torch.empty(workspace_bytes(q, opts), dtype=torch.uint8, device=a.device))
+    vp = ctypes.c_void_p
+    q_arr = (ctypes.c_int * P)(*qs)
+    a_arr = (vp * P)(*[a.data_ptr() for a in coeffs])
+    ws_arr = (vp * P)(*[w.data_ptr() for w in wss])
+    wb_arr = (ctypes.c_size_t * P)(*[w.numel() for w in wss])
+    ctx_arr = (vp * P)()
+    st_arr = (ctypes.c_int * P)()
+    dev = coeffs[0].device
+    with torch.cuda.device(dev):
+        code = lib().gbl_build_batched(P, q_arr, a_arr, ctypes.byref(opts), ws_arr, wb_arr, ctx_arr, st_arr,
+                                       _stream_ptr(dev))
+    hs = [_adopt(ctx_arr[i], qs[i], wss[i], opts) if ctx_arr[i] else None for i in range(P)]
+    if code != GBL_OK:
+        for h in hs:
+            if h is not None:
+                h.close()
+        _check(code)
+    return hs
+
+
+def solve_batched(hiers: list, sources: list, check: bool = True) -> list:
+    """Solve problem i for the cell sources ``sources[i]`` ([nrhs][n][n]) with
+    ``hiers[i]``, all problems concurrently (``gbl_solve_batched``); returns the
+    nodal solutions and sets each hierarchy's ``last_info``."""
+    P = len(hiers)
+    if P == 0:
+        return []
+    us, nr = [], []
+    for h, g in zip(hiers, sources):
+        gg = g.unsqueeze(0) if g.dim() == 2 else g
+        _require(gg, (gg.shape[0], h.n, h.n), "g")
+        nr.append(gg.shape[0])
+        us.append(torch.zeros((gg.shape[0], h.n + 1, h.n + 1), dtype=torch.float64, device=h.device))
+    srcs = [g.unsqueeze(0) if g.dim() == 2 else g for g in sources]
+    vp = ctypes.c_void_p
+    ctx_arr = (vp * P)(*[h.ctx.value for h in hiers])
+    nr_arr = (ctypes.c_int * P)(*nr)
+    g_arr = (vp * P)(*[g.data_ptr() for g in srcs])
+    u_arr = (vp * P)(*[u.data_ptr() for u in us])
+    info_arr = (GblSolveInfo * P)()
+    st_arr = (ctypes.c_int * P)()
+    dev = hiers[0].device
+    with torch.cuda.device(dev):
+        code = lib().gbl_solve_batched(P, ctx_arr, nr_arr, g_arr, u_arr, info_arr, st_arr, _stream_ptr(dev))
+    for h, inf in zip(hiers, info_arr):
+        h.last_info = SolveInfo(inf.outer_iters, inf.status, inf.rel_update, inf.rel_residual)
+    if check or code not in (GBL_OK, GBL_ENOCONV):
+        _check(code)
+    return us

@@ -72,6 +72,11 @@ def test_null_arguments_rejected():
     assert L.gbl_destroy(None) == 0
     flags = ctypes.c_uint(7)
     assert L.gbl_build_flags(None, ctypes.byref(flags)) == -1
+    # batched calls validate their arrays before touching the device
+    assert L.gbl_build_batched(0, None, None, None, None, None, None, None, None) == -1
+    assert b"batched build" in L.gbl_last_error(None)
+    assert L.gbl_solve_batched(0, None, None, None, None, None, None, None) == -1
+    assert b"batched solve" in L.gbl_last_error(None)
 
 
 def test_short_workspace_rejected_before_any_device_work():

@@ -208,6 +208,30 @@ def test_iteration_graph_matches_direct_launches(monkeypatch, prec):
     H.close()
 
 
+def test_batched_uneven_problems_match_direct_and_single():
+    """Batch workload in miniature: six independent problems with q drawn from
+    {6, 7, 8}, four right-hand sides each, built and solved concurrently
+    through gbl_build_batched / gbl_solve_batched.  Each solution matches the
+    direct solve at 1e-8 and equals, bit for bit, the same problem built and
+    solved on its own."""
+    P = _P()
+    probs = S.batch_problems(count=6, nrhs=4)
+    _print_case(test="batched", qs=[p.q for p in probs])
+    hs = P.build_batched([_dev(p.a) for p in probs], rho=3, precision="mixed", rtol=1e-8, max_rhs=4)
+    us = P.solve_batched(hs, [_dev(p.g) for p in probs])
+    for p, h, u in zip(probs, hs, us):
+        u = u.cpu().numpy()
+        u_ref = fem.solve(p.a, p.g)
+        for r in range(4):
+            err = _relerr(u[r][1:-1, 1:-1], u_ref[r][1:-1, 1:-1])
+            assert err < 1e-8, (p.q, r, err, h.last_info)
+        H1 = P.Hierarchy(_dev(p.a), rho=3, precision="mixed", rtol=1e-8, max_rhs=4)
+        u1 = H1.solve(_dev(p.g)).cpu().numpy()
+        assert np.array_equal(u1, u), p.q
+        H1.close()
+        h.close()
+
+
 @pytest.mark.timeout(300)
 def test_full_size_q9_matches_direct():
     """The benchmark workload itself (512 x 512 cells, sigma = 2, rho = 3):
