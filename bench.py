@@ -34,8 +34,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--inner-iters", type=int, default=8)
-    ap.add_argument("--inner-iters-coarse", type=int, default=3)
+    ap.add_argument("--inner", choices=["chebyshev", "cg"], default="chebyshev",
+                    help="iteration on the subband systems (library default: chebyshev)")
+    ap.add_argument("--inner-iters", type=int, default=None, help="finest-level budget (default: library's)")
+    ap.add_argument("--inner-iters-coarse", type=int, default=None, help="coarser-level budget (default: library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
     return ap.parse_args()
@@ -45,7 +47,7 @@ def level_geometry(H):
     return {k: H.level(k) for k in range(1, H.q + 1)}
 
 
-def kernel_work(name, geo, q, elem):
+def kernel_work(name, geo, q, elem, inner="chebyshev"):
     """Algorithmic bytes (HBM-bound classes) or flops (arithmetic-bound) summed over one
     build (build kernels) or one launch (solve kernels).  Returns (kind, amount)."""
     if name == "patch_solve":
@@ -69,9 +71,13 @@ def kernel_work(name, geo, q, elem):
             fl += 2.0 * nc * nc * g["rw"] ** 2 * (Sk * Sk + Sc * Sc)
         return "flops", fl
     if name == "fine_cg":
+        np2 = (geo[q]["nk"] // 2) ** 2
+        if inner == "chebyshev":
+            # per parent and launch (several fused steps): r, d, x, block-Jacobi 3x3 and 4 cell
+            # coefficients read once; r, d, x written once
+            return "bytes", elem * np2 * (9 + 9 + 4 + 9)
         # per parent: r, w, s, u, p, x, block-Jacobi 3x3 and 4 cell coefficients read;
         # u, p, x, r, s, w written (one fused iteration of the finest subband CG)
-        np2 = (geo[q]["nk"] // 2) ** 2
         return "bytes", elem * np2 * (9 + 9 + 9 + 4 + 18)
     if name in ("cg_spmv", "cg_update", "cg_init"):
         by = 0.0
@@ -79,7 +85,10 @@ def kernel_work(name, geo, q, elem):
             g = geo[k]
             np2 = (g["nk"] // 2) ** 2
             T = 2 * g["t"] + 1
-            if name == "cg_spmv":
+            if name == "cg_spmv" and inner == "chebyshev":
+                # B blocks, d once, r read + written, block-Jacobi, d_new and x
+                by += elem * np2 * (9 * T * T + 3 + 6 + 9 + 3 + 6)
+            elif name == "cg_spmv":
                 # B blocks, z once, q and p read + written
                 by += elem * np2 * (9 * T * T + 3 + 12)
             elif name == "cg_update":
@@ -131,7 +140,7 @@ def main():
 
     def step(prec):
         H = P.Hierarchy(a, rho=pr.rho, precision=prec, rtol=args.rtol, inner_iters=args.inner_iters,
-                        inner_iters_coarse=args.inner_iters_coarse)
+                        inner_iters_coarse=args.inner_iters_coarse, inner=args.inner)
         u = H.solve(g, check=False)
         info = H.last_info
         return H, u, info
@@ -168,7 +177,9 @@ def main():
     value = dof / (ms_per_step * 1e-3)
 
     elem = 4 if args.precision == "mixed" else 8
-    kind, work = kernel_work(dominant, geo, q, elem)
+    kind, work = kernel_work(dominant, geo, q, elem, args.inner)
+    inner_iters = H.opts.inner_iters
+    inner_iters_coarse = H.opts.inner_iters_coarse
     build_kernel = dominant in ("patch_solve", "galerkin", "subband_operator", "assemble")
     launches_per_unit = (q - 1) if build_kernel else 1
     per_launch_work = work / launches_per_unit
@@ -267,8 +278,8 @@ def main():
         "config": {"workload": "q9 rough lognormal (sigma=2) product coefficient, 512x512 cells, 261121 DOF, "
                                "N(0,1) cell source, patch radius 3, build+solve to 1e-8",
                    "q": q, "dof": dof, "rho": pr.rho, "sigma": 2.0, "precision": args.precision,
-                   "rtol": args.rtol, "inner_iters": args.inner_iters,
-                   "inner_iters_coarse": args.inner_iters_coarse},
+                   "rtol": args.rtol, "inner": args.inner, "inner_iters": inner_iters,
+                   "inner_iters_coarse": inner_iters_coarse},
         "roofline": roof,
         "cpu_baseline": cpu,
         **extras,

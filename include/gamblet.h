@@ -70,15 +70,25 @@ enum gbl_precision {
   GBL_MIXED = 1   /* hierarchy and subband CG in FP32; fine residual, outer iteration and A^(1) in FP64 */
 };
 
+enum gbl_inner {
+  GBL_INNER_CHEBYSHEV = 0,  /* Chebyshev iteration: a fixed polynomial preconditioner, no inner products */
+  GBL_INNER_CG = 1          /* conjugate gradients */
+};
+
 typedef struct gbl_opts {
   int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3); 1..4 */
   int precision;      /* enum gbl_precision */
   double rtol;        /* target relative l2 error of u; the solve stops when the larger of ||S r|| and the
                          last correction, over the last two iterations, is below rtol / 3 of ||u|| */
   int max_outer;      /* maximum outer (flexible CG) iterations */
-  int inner_iters;    /* block-Jacobi PCG iterations on the finest subband system per outer iteration */
+  int inner_iters;    /* iterations on the finest subband system per outer iteration (Chebyshev: <= 32) */
   int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */
-  int inner_iters_coarse; /* block-Jacobi PCG iterations on each coarser subband system (k < q) */
+  int inner_iters_coarse; /* iterations on each coarser subband system (k < q) (Chebyshev: <= 32) */
+  int inner_kind;     /* enum gbl_inner: the iteration used on the subband systems B^(k) w = W g
+                         (Section 4.7), block-Jacobi (3 x 3 parent blocks) preconditioned */
+  double kappa;       /* Chebyshev: the interval is [G / kappa, G] on the finest level, G the block-
+                         Gershgorin bound of lambda_max computed at build time; > 1 */
+  double kappa_coarse;/* the same on the coarser levels */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -115,7 +125,8 @@ typedef struct gbl_ctx gbl_ctx;
 int gbl_version(void);
 
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
- * inner_iters 8, max_rhs 1, inner_iters_coarse 3. */
+ * Chebyshev inner iterations, inner_iters 12, inner_iters_coarse 4,
+ * kappa 200, kappa_coarse 30, max_rhs 1. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
@@ -211,7 +222,7 @@ enum gbl_prof_kernel {
   GBL_PROF_PROLONG = 8,           /* v^(k) = R^T v^(k-1) + W^T w^(k) */
   GBL_PROF_FINE_APPLY = 9,        /* FP64 fine operator in the outer iteration */
   GBL_PROF_GRADIENT = 10,         /* adjoint cell gradient */
-  GBL_PROF_FINE_CG = 11,          /* finest-level subband CG iteration (fused) */
+  GBL_PROF_FINE_CG = 11,          /* finest-level subband iteration (CG or Chebyshev, fused) */
   GBL_PROF_NUM_KERNELS = 12
 };
 

@@ -101,6 +101,7 @@ struct Layout {
   size_t acell_off = 0;      // element offset of the coefficient in the hierarchy arena (T)
   size_t L1_off = 0;         // 16 doubles
   size_t status_off = 0;     // 4 ints
+  size_t gersh_off = 0;      // per-level bound of lambda_max(M B^(k)) (float bits)
   size_t oscal_off = 0;      // outer scalars
   size_t dpart_off = 0;      // dot partials
   size_t opart_off = 0;      // per-block partials of the outer-iteration kernels (2 x 3 x nblk)
@@ -132,6 +133,20 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
     return GBL_EINVAL;
   }
   if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
+  if (o->inner_kind != GBL_INNER_CHEBYSHEV && o->inner_kind != GBL_INNER_CG) {
+    msg = "unknown inner_kind";
+    return GBL_EINVAL;
+  }
+  if (o->inner_kind == GBL_INNER_CHEBYSHEV) {
+    if (o->inner_iters > kMaxCheb || o->inner_iters_coarse > kMaxCheb) {
+      msg = "Chebyshev inner iterations must be at most 32";
+      return GBL_EINVAL;
+    }
+    if (!(o->kappa > 1.0) || !(o->kappa_coarse > 1.0) || !(o->kappa < 1e12) || !(o->kappa_coarse < 1e12)) {
+      msg = "kappa and kappa_coarse must be in (1, 1e12)";
+      return GBL_EINVAL;
+    }
+  }
   return GBL_OK;
 }
 
@@ -192,6 +207,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.hier_off = b; b = align_up(b + e * L.elem);
   L.L1_off = b; b = align_up(b + 16 * 8);
   L.status_off = b; b = align_up(b + 4 * sizeof(int));
+  L.gersh_off = b; b = align_up(b + kMaxLevels * sizeof(unsigned));
   L.oscal_off = b; b = align_up(b + kNumOuterScalars * 8);
   L.dpart_off = b; b = align_up(b + 3 * kDotBlocks * 8);
   L.dcnt_off = b; b = align_up(b + 4 * sizeof(unsigned));
@@ -247,6 +263,9 @@ struct gbl_ctx {
   hipGraphExec_t iter_graph = nullptr;
   bool graph_off = false;               // capture failed once: launch kernel by kernel
   unsigned build_flags = 0;             // GBL_FLAG_* of the build
+  float lmax[kMaxLevels] = {};          // bound of lambda_max(M B^(k)) per level
+  ChebCoef cheb_fine{};                 // Chebyshev coefficients, finest level
+  ChebStep cheb_coarse[kMaxCheb]{};     // Chebyshev coefficients per step, coarser levels
   bool diverged = false;                // the last solve produced a non-finite estimate or residual
 
   template <typename T>
@@ -348,6 +367,41 @@ FineCG<T> make_fine_cg(gbl_ctx* c) {
   return F;
 }
 
+// Chebyshev coefficients (recurrence documented with ChebCoef) for the
+// interval [G / kappa, G].  A small margin on G covers the FP32 rounding of
+// the bound itself.
+void cheb_coefs(double G, double kappa, int K, float& c0, float* ca, float* cb) {
+  const double lmax = (G > 0.0 && std::isfinite(G)) ? 1.001 * G : 1.0;
+  const double lmin = lmax / kappa;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho_prev = 1.0 / sigma;
+  c0 = (float)(1.0 / theta);
+  ca[0] = cb[0] = 0.0f;
+  for (int k = 1; k < K && k < kMaxCheb; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_prev);
+    ca[k] = (float)(rho * rho_prev);
+    cb[k] = (float)(2.0 * rho / delta);
+    rho_prev = rho;
+  }
+}
+
+void make_cheb_tables(gbl_ctx* c) {
+  const Layout& L = c->L;
+  ChebCoef& f = c->cheb_fine;
+  cheb_coefs(c->lmax[L.q], c->opts.kappa, c->opts.inner_iters, f.c0, f.ca, f.cb);
+  // coarser levels: slot l of the CG arguments is level q - 1 - l
+  for (int l = 0; l + 2 <= L.q - 1 && l < kMaxLevels; ++l) {
+    const int k = L.q - 1 - l;
+    ChebCoef t{};
+    cheb_coefs(c->lmax[k], c->opts.kappa_coarse, c->opts.inner_iters_coarse, t.c0, t.ca, t.cb);
+    for (int step = 0; step < kMaxCheb; ++step) {
+      c->cheb_coarse[step].c0[l] = t.c0;
+      c->cheb_coarse[step].ca[l] = t.ca[step];
+      c->cheb_coarse[step].cb[l] = t.cb[step];
+    }
+  }
+}
+
 template <typename T>
 int build_impl(gbl_ctx* c, hipStream_t st) {
   const Layout& L = c->L;
@@ -363,6 +417,7 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
     {
       ProfScope ps(GBL_PROF_SUBBAND_OPERATOR, st);
       launch_subband_operator<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offBJ), fine, st);
+      launch_gershgorin<T>(g, c->hier<T>(g.offB), reinterpret_cast<unsigned*>(c->ws + L.gersh_off) + k, st);
     }
     {
       ProfScope ps(GBL_PROF_PATCH_SOLVE, st);
@@ -431,29 +486,58 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   }
   // coarser levels on the second stream, enqueued first so that they start
   // together with the finest level
+  const bool cheb = c->opts.inner_kind == GBL_INNER_CHEBYSHEV;
   if (coarse) {
-    {
-      const CGLev<T>& last = cg.lv[cg.nlev - 1];
-      ProfScope ps(GBL_PROF_CG_INIT, cs);
-      launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
-    }
-    for (int it = 0; it < c->opts.inner_iters_coarse; ++it) {
-      const CGLev<T>& lv = cg.lv[cg.nlev - 1];
+    const CGLev<T>& last = cg.lv[cg.nlev - 1];
+    if (cheb) {
       {
-        ProfScope ps(GBL_PROF_CG_SPMV, cs);
-        launch_cg_spmv<T>(cg, lv.blk0s + lv.nblks, it, cs);
+        ProfScope ps(GBL_PROF_CG_INIT, cs);
+        launch_cheb_init<T>(cg, c->cheb_coarse[0], last.blk0 + last.nblk, cs);
       }
-      ProfScope ps(GBL_PROF_CG_UPDATE, cs);
-      launch_cg_update<T>(cg, lv.blk0 + lv.nblk, it, cs);
+      for (int k = 1; k < c->opts.inner_iters_coarse; ++k) {
+        ProfScope ps(GBL_PROF_CG_SPMV, cs);
+        launch_cheb_step<T>(cg, c->cheb_coarse[k], k, last.blk0s + last.nblks, cs);
+      }
+    } else {
+      {
+        ProfScope ps(GBL_PROF_CG_INIT, cs);
+        launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
+      }
+      for (int it = 0; it < c->opts.inner_iters_coarse; ++it) {
+        {
+          ProfScope ps(GBL_PROF_CG_SPMV, cs);
+          launch_cg_spmv<T>(cg, last.blk0s + last.nblks, it, cs);
+        }
+        ProfScope ps(GBL_PROF_CG_UPDATE, cs);
+        launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs);
+      }
     }
     if (c->side) hipEventRecord(c->ev_join, cs);
   } else {
     for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, st);
   }
-  // finest level (its last step x += alpha p is applied inside the prolongation)
-  for (int it = 0; it < c->opts.inner_iters; ++it) {
-    ProfScope ps(GBL_PROF_FINE_CG, st);
-    launch_fine_cg<T>(F, it, st);
+  // finest level: Chebyshev steps fused four per launch, or one CG iteration
+  // per launch (whose last step x += alpha p is applied inside the prolongation)
+  if (cheb) {
+    const int K = c->opts.inner_iters;
+    int fuse = 4;   // steps per launch (GBL_CHEB_FUSE = 1..4; the halo is 4 parents)
+    if (const char* e = getenv("GBL_CHEB_FUSE")) {
+      const int v = atoi(e);
+      if (v >= 1 && v <= 4) fuse = v;
+    }
+    int k0 = 0, rd = 0;
+    do {
+      const int ns = std::min(fuse, K - 1 - k0);
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_fine_cheb<T>(F, c->cheb_fine, K, k0, ns, rd, st);
+      k0 += ns;
+      rd ^= 1;
+    } while (k0 < K - 1);
+  } else {
+    for (int it = 0; it < c->opts.inner_iters; ++it) {
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_fine_cg<T>(F, it, st);
+    }
   }
   if (coarse && c->side) hipStreamWaitEvent(st, c->ev_join, 0);
   {
@@ -470,7 +554,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   // the partial sums (z, z), (u, u), (z, w) go to the second half of the outer partials
   double* opart = reinterpret_cast<double*>(c->ws + L.opart_off) + 3 * (size_t)L.onblk;
   launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z, opart,
-                              st);
+                              cheb ? 1 : 0, st);
   (void)part;
   (void)cnt;
 }
@@ -678,9 +762,12 @@ int gbl_default_opts(gbl_opts* o) {
   o->precision = GBL_MIXED;
   o->rtol = 1e-8;
   o->max_outer = 100;
-  o->inner_iters = 8;
+  o->inner_iters = 12;
   o->max_rhs = 1;
-  o->inner_iters_coarse = 3;
+  o->inner_iters_coarse = 4;
+  o->inner_kind = GBL_INNER_CHEBYSHEV;
+  o->kappa = 200.0;
+  o->kappa_coarse = 30.0;
   return GBL_OK;
 }
 
@@ -713,7 +800,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->ws = static_cast<char*>(ws_dev);
   c->ws_bytes = ws_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4 + kMaxChunk) * sizeof(double),
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4 + std::max(kMaxChunk, kMaxLevels)) * sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, GBL_EHIP, "hipHostMalloc failed");
@@ -747,11 +834,16 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   }
   st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
   if (st) return bail(st);
+  unsigned* hbits = reinterpret_cast<unsigned*>(c->host + kNumOuterScalars + 4);
   if (hipMemcpyAsync(c->host + kNumOuterScalars, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hbits, c->ws + L.gersh_off, kMaxLevels * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "status read failed";
     return bail(GBL_EHIP);
   }
+  for (int k = 0; k < kMaxLevels; ++k) std::memcpy(&c->lmax[k], &hbits[k], sizeof(float));
+  make_cheb_tables(c);
   int bits = 0;
   std::memcpy(&bits, c->host + kNumOuterScalars, sizeof(int));
   if (bits & kBadCoefficient) {

@@ -1090,8 +1090,81 @@ void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStrea
   hipLaunchKernelGGL(k_coarse_factor<T>, dim3(1), dim3(64), 0, st, A1, s1, L1, status);
 }
 
+// ---------------------------------------------------------------------------
+// Upper bound of lambda_max(M B^(k)), M the inverse 3 x 3 parent blocks D_p of
+// B^(k), for the Chebyshev inner iteration.  With D_p = L_p L_p^T the
+// eigenvalues of M B are those of C = L^{-1} B L^{-T}, whose blocks are
+// C_pq = L_p^{-1} B_pq L_q^{-T}; Gershgorin's theorem bounds them by the
+// largest absolute row sum of C.  One thread per parent; the level maximum is
+// kept with an integer atomic max on the bits of the non-negative float.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void chol3_inv(const double D[3][3], double Li[3][3]) {
+  double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = 0; j < 3; ++j) {
+    double dj = D[j][j];
+    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
+    const double lj = dj > 0.0 ? sqrt(dj) : 1.0;
+    L[j][j] = lj;
+    for (int i = j + 1; i < 3; ++i) {
+      double v = D[i][j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / lj;
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    for (int r = 0; r < 3; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) v -= L[r][k] * Li[k][c];
+      Li[r][c] = (r >= c) ? v / L[r][r] : 0.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_gershgorin(const T* __restrict__ B, int np, int t, unsigned* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np * np) return;
+  const int TT = 2 * t + 1;
+  const int px = p / np, py = p % np;
+  double D[3][3], Lp[3][3];
+  for (int e = 0; e < 9; ++e) D[e / 3][e % 3] = (double)B[b_index(t * TT + t, e, p, TT)];
+  chol3_inv<T>(D, Lp);
+  double rs[3] = {0.0, 0.0, 0.0};
+  for (int ox = 0; ox < TT; ++ox) {
+    const int qx = px + ox - t;
+    if (qx < 0 || qx >= np) continue;
+    for (int oy = 0; oy < TT; ++oy) {
+      const int qy = py + oy - t;
+      if (qy < 0 || qy >= np) continue;
+      const int qq = qx * np + qy;
+      double Bq[3][3], Dq[3][3], Lq[3][3];
+      for (int e = 0; e < 9; ++e) {
+        Bq[e / 3][e % 3] = (double)B[b_index(ox * TT + oy, e, p, TT)];
+        Dq[e / 3][e % 3] = (double)B[b_index(t * TT + t, e, qq, TT)];
+      }
+      chol3_inv<T>(Dq, Lq);
+      // C = Lp Bq Lq^T
+      double M1[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M1[i][j] = Lp[i][0] * Bq[0][j] + Lp[i][1] * Bq[1][j] + Lp[i][2] * Bq[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) rs[i] += fabs(M1[i][0] * Lq[j][0] + M1[i][1] * Lq[j][1] + M1[i][2] * Lq[j][2]);
+    }
+  }
+  const float g = (float)fmax(rs[0], fmax(rs[1], rs[2]));
+  if (g > 0.0f) atomicMax(out, __float_as_uint(g));
+}
+
+template <typename T>
+void launch_gershgorin(const LevelGeom& L, const T* B, unsigned* out, hipStream_t st) {
+  const int np = L.nk / 2;
+  hipLaunchKernelGGL(k_gershgorin<T>, dim3((np * np + 255) / 256), dim3(256), 0, st, B, np, L.t, out);
+}
+
 #define GBL_INST(T)                                                                                   \
   template void launch_assemble_fine<T>(const double*, T*, int, int*, hipStream_t);                  \
+  template void launch_gershgorin<T>(const LevelGeom&, const T*, unsigned*, hipStream_t);            \
   template void launch_subband_operator<T>(const LevelGeom&, const T*, T*, T*, bool, hipStream_t);   \
   template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, bool, int*,          \
                                       hipStream_t);                                                  \

@@ -486,11 +486,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__ R, const T* __restrict__ vc,
                                                            FineCG<T> F, int nk, int rho, double* __restrict__ z,
                                                            const double* __restrict__ uo,
-                                                           const double* __restrict__ wo, double* part) {
+                                                           const double* __restrict__ wo, double* part, int cheb) {
   __shared__ double sh[3 * 16];
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
-  const T alpha = T(F.scal[kFAlpha]), beta = T(F.scal[kFBeta]);
+  const T alpha = cheb ? T(0) : T(F.scal[kFAlpha]), beta = cheb ? T(0) : T(F.scal[kFBeta]);
   double v[3] = {0.0, 0.0, 0.0};
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id < nk * nk) {
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__
     const int pp = px * nc + py;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      const T wt = F.x[t * nc2 + pp] + alpha * (F.u[t * nc2 + pp] + beta * F.p[t * nc2 + pp]);
+      const T wt = cheb ? F.x[t * nc2 + pp] : F.x[t * nc2 + pp] + alpha * (F.u[t * nc2 + pp] + beta * F.p[t * nc2 + pp]);
       acc += T(wcoef(tp, t, d)) * wt;
     }
     const double zv = (double)acc;
@@ -518,10 +518,10 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__
 
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, hipStream_t st) {
+                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st) {
   const int tot = L.nk * L.nk;
   hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, F, L.nk, L.rho, z, uo,
-                     wo, part);
+                     wo, part, cheb);
 }
 
 template <typename T>
@@ -729,7 +729,8 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
 // stencil width TT (the oy loop is unrolled so that a row's loads are all
 // in flight together).
 template <typename T, int TT>
-__device__ __forceinline__ void coarse_rows(const CGLev<T>& L, int p, int wv, int nw, T& acc0, T& acc1, T& acc2) {
+__device__ __forceinline__ void coarse_rows(const CGLev<T>& L, const T* __restrict__ zs, int p, int wv, int nw,
+                                            T& acc0, T& acc1, T& acc2) {
   constexpr int t = TT / 2;
   const int np = L.np;
   const size_t np2 = (size_t)np * np;
@@ -745,12 +746,28 @@ __device__ __forceinline__ void coarse_rows(const CGLev<T>& L, int p, int wv, in
     for (int oy = 0; oy < TT; ++oy) {
       const int qy = min(max(py + oy - t, 0), np - 1);
       const int qn = qb + t + (qy - py);
-      const T z0 = L.z[qn], z1 = L.z[np2 + qn], z2 = L.z[2 * np2 + qn];
+      const T z0 = zs[qn], z1 = zs[np2 + qn], z2 = zs[2 * np2 + qn];
       const T* Bb = Bo + oy * 9 * 64;
       acc0 += Bb[0] * z0 + Bb[64] * z1 + Bb[128] * z2;
       acc1 += Bb[192] * z0 + Bb[256] * z1 + Bb[320] * z2;
       acc2 += Bb[384] * z0 + Bb[448] * z1 + Bb[512] * z2;
     }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void coarse_apply(const CGLev<T>& L, const T* zs, int TT, int p, int wv, int nw, T& acc0,
+                                             T& acc1, T& acc2) {
+  switch (TT) {
+    case 1: coarse_rows<T, 1>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 3: coarse_rows<T, 3>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 5: coarse_rows<T, 5>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 7: coarse_rows<T, 7>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 9: coarse_rows<T, 9>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 11: coarse_rows<T, 11>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 13: coarse_rows<T, 13>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    case 15: coarse_rows<T, 15>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
+    default: coarse_rows<T, 17>(L, zs, p, wv, nw, acc0, acc1, acc2); break;
   }
 }
 
@@ -771,17 +788,7 @@ __global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int bl
   const int p = blk * 64 + lane;
   T acc0 = T(0), acc1 = T(0), acc2 = T(0);
   if (p < np * np) {
-    switch (TT) {
-      case 1: coarse_rows<T, 1>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 3: coarse_rows<T, 3>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 5: coarse_rows<T, 5>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 7: coarse_rows<T, 7>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 9: coarse_rows<T, 9>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 11: coarse_rows<T, 11>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 13: coarse_rows<T, 13>(L, p, wv, nw, acc0, acc1, acc2); break;
-      case 15: coarse_rows<T, 15>(L, p, wv, nw, acc0, acc1, acc2); break;
-      default: coarse_rows<T, 17>(L, p, wv, nw, acc0, acc1, acc2); break;
-    }
+    coarse_apply<T>(L, L.z, TT, p, wv, nw, acc0, acc1, acc2);
   }
   red[(0 * 16 + wv) * 64 + lane] = acc0;
   red[(1 * 16 + wv) * 64 + lane] = acc1;
@@ -873,6 +880,246 @@ void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
 template <typename T>
 void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a, it);
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev iteration on the coarser subband levels (all levels in one grid;
+// coefficients of the step per level in ChebStep).  d_k alternates between
+// the z (k even) and p (k odd) vectors; x accumulates d_0 + ... + d_k.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs) {
+  const int l = find_level(args, blockIdx.x);
+  const CGLev<T>& L = args.lv[l];
+  const int p = (blockIdx.x - L.blk0) * 256 + threadIdx.x;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int nk = 2 * np;
+  if (p >= np * np) return;
+  const int px = p / np, py = p % np;
+  const int tp = parent_type(L.fine != 0, px, py);
+  T gch[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) gch[d] = L.g[(2 * px + (d >> 1)) * nk + 2 * py + (d & 1)];
+  T r[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) acc += T(wcoef(tp, t, d)) * gch[d];
+    r[t] = acc;
+  }
+  const T c0 = T(cs.c0[l]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc += L.BJ[(i * 3 + j) * np2 + p] * r[j];
+    const T d0 = c0 * acc;
+    L.r[i * np2 + p] = r[i];
+    L.z[i * np2 + p] = d0;
+    L.x[i * np2 + p] = d0;
+  }
+}
+
+// Step k >= 1: r -= B d_{k-1};  d_k = ca d_{k-1} + cb M r;  x += d_k.  The
+// operator part is that of k_cg_spmv (64 parents per workgroup, one
+// wavefront per stencil row).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs, int k, int blk_begin) {
+  __shared__ T red[3 * 16 * 64];
+  const int gb = blk_begin + (int)blockIdx.x;
+  const int l = find_level_s(args, gb);
+  const CGLev<T>& L = args.lv[l];
+  if (k >= L.iters) return;
+  const int blk = gb - L.blk0s;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int TT = 2 * L.t + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int p = blk * 64 + lane;
+  const T* dold = (k & 1) ? L.z : L.p;
+  T* dnew = (k & 1) ? L.p : L.z;
+  T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+  if (p < np * np) coarse_apply<T>(L, dold, TT, p, wv, nw, acc0, acc1, acc2);
+  red[(0 * 16 + wv) * 64 + lane] = acc0;
+  red[(1 * 16 + wv) * 64 + lane] = acc1;
+  red[(2 * 16 + wv) * 64 + lane] = acc2;
+  __syncthreads();
+  if (threadIdx.x < 64 && p < np * np) {
+    const T ca = T(cs.ca[l]), cb = T(cs.cb[l]);
+    T r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T sum = T(0);
+      for (int w = 0; w < nw; ++w) sum += red[(i * 16 + w) * 64 + lane];
+      r[i] = L.r[i * np2 + p] - sum;
+      L.r[i * np2 + p] = r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc += L.BJ[(i * 3 + j) * np2 + p] * r[j];
+      const T dn = ca * dold[i * np2 + p] + cb * acc;
+      dnew[i * np2 + p] = dn;
+      L.x[i * np2 + p] += dn;
+    }
+  }
+}
+
+template <typename T>
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks), dim3(256), 0, st, a, s);
+}
+template <typename T>
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int nblocks, hipStream_t st) {
+  const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
+  const int t0 = 2 * a.lv[0].t + 1;
+  hipLaunchKernelGGL(k_cheb_step<T>, dim3(n0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, 0);
+  if (nblocks > n0) {
+    int tmax = 1;
+    for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
+    hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks - n0), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, s, k, n0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev iteration on the finest subband level, several steps per launch.
+// A workgroup owns a tile of 8 x 8 parents and works on the tile plus a halo
+// of H parents (one thread per parent of the 16 x 16 region).  Each step needs
+// d on a one-parent halo of the region where r and d are formed, so after s
+// steps the values are exact on the region shrunk by s parents; with s <= H
+// the tile itself stays exact and only it is stored.  The operator B^(q) is
+// applied matrix-free: nodal W^T d in LDS (with a zero border), the Q1
+// stencil from the cell coefficients held in registers, then W.  The launch
+// with k0 = 0 starts from r_0 = W g, d_0 = M r_0 / theta, x = d_0.  r and d are
+// double buffered (buffer rd is read, rd ^ 1 written) because tiles read
+// their neighbours' values.
+// ---------------------------------------------------------------------------
+template <typename T, int H>
+__global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F, ChebCoef cf, int k0, int nsteps, int rd) {
+  constexpr int TPM = 8;
+  constexpr int VWM = 2 * (TPM + 2 * H) + 2;
+  __shared__ T vl[VWM * VWM];
+  const int np = F.np;
+  const int nk = 2 * np;
+  const size_t np2 = (size_t)np * np;
+  const int TP = np < TPM ? np : TPM;
+  const int ntx = np / TP;
+  const int RW = TP + 2 * H;
+  const int VW = 2 * RW + 2;
+  const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tx = blk / ntx, ty = blk - (blk / ntx) * ntx;
+  const int tid = threadIdx.x;
+  const bool act = tid < RW * RW;
+  const int rx = act ? tid / RW : 0, ry = act ? tid - (tid / RW) * RW : 0;
+  const int px = tx * TP - H + rx, py = ty * TP - H + ry;
+  const bool in = act && px >= 0 && py >= 0 && px < np && py < np;
+  const bool interior = act && rx >= H && rx < H + TP && ry >= H && ry < H + TP;
+  const int q = in ? px * np + py : 0;
+  const int tp = in ? parent_type(true, px, py) : 3;
+  for (int e = tid; e < VW * VW; e += blockDim.x) vl[e] = T(0);
+
+  T bj[9], ac[3][3], r[3], d[3], x[3];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) bj[e] = in ? F.BJ[e * np2 + q] : T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int cx = 2 * px - 1 + i, cy = 2 * py - 1 + j;
+      ac[i][j] = (in && cx >= 0 && cy >= 0 && cx < nk && cy < nk) ? F.acell[(size_t)cx * nk + cy] : T(0);
+    }
+  }
+  if (k0 == 0) {
+    T gc[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) gc[dd] = in ? F.g[(2 * px + (dd >> 1)) * nk + 2 * py + (dd & 1)] : T(0);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      r[t] = T(wcoef(tp, t, 0)) * gc[0] + T(wcoef(tp, t, 1)) * gc[1] + T(wcoef(tp, t, 2)) * gc[2] +
+             T(wcoef(tp, t, 3)) * gc[3];
+    const T c0 = T(cf.c0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      d[i] = c0 * (bj[3 * i] * r[0] + bj[3 * i + 1] * r[1] + bj[3 * i + 2] * r[2]);
+      x[i] = d[i];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      r[t] = in ? F.r[rd][t * np2 + q] : T(0);
+      d[t] = in ? F.w[rd][t * np2 + q] : T(0);
+      x[t] = interior ? F.x[t * np2 + q] : T(0);
+    }
+  }
+  __syncthreads();
+  for (int s2 = 0; s2 < nsteps; ++s2) {
+    const int k = k0 + 1 + s2;
+    if (act) {
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const T v = T(wcoef(tp, 0, dd)) * d[0] + T(wcoef(tp, 1, dd)) * d[1] + T(wcoef(tp, 2, dd)) * d[2];
+        vl[(2 * rx + (dd >> 1) + 1) * VW + 2 * ry + (dd & 1) + 1] = v;
+      }
+    }
+    __syncthreads();
+    if (in) {
+      T Av[4];
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const int dx = dd >> 1, dy = dd & 1;
+        if (2 * px + dx == 0 || 2 * py + dy == 0) {
+          Av[dd] = T(0);
+          continue;
+        }
+        const T a00 = ac[dx][dy], a10 = ac[dx + 1][dy], a01 = ac[dx][dy + 1], a11 = ac[dx + 1][dy + 1];
+        const T* vp = vl + (2 * rx + dx + 1) * VW + 2 * ry + dy + 1;
+        T acc = T(2.0 / 3.0) * (a00 + a10 + a01 + a11) * vp[0];
+        acc -= (a10 + a11) * T(1.0 / 6.0) * vp[VW];
+        acc -= (a00 + a01) * T(1.0 / 6.0) * vp[-VW];
+        acc -= (a01 + a11) * T(1.0 / 6.0) * vp[1];
+        acc -= (a00 + a10) * T(1.0 / 6.0) * vp[-1];
+        acc -= a11 * T(1.0 / 3.0) * vp[VW + 1];
+        acc -= a00 * T(1.0 / 3.0) * vp[-VW - 1];
+        acc -= a10 * T(1.0 / 3.0) * vp[VW - 1];
+        acc -= a01 * T(1.0 / 3.0) * vp[-VW + 1];
+        Av[dd] = acc;
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const T bd = is_pad_row(tp, t) ? d[t]
+                                        : T(wcoef(tp, t, 0)) * Av[0] + T(wcoef(tp, t, 1)) * Av[1] +
+                                              T(wcoef(tp, t, 2)) * Av[2] + T(wcoef(tp, t, 3)) * Av[3];
+        r[t] -= bd;
+      }
+      const T ca = T(cf.ca[k]), cb = T(cf.cb[k]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        d[i] = ca * d[i] + cb * (bj[3 * i] * r[0] + bj[3 * i + 1] * r[1] + bj[3 * i + 2] * r[2]);
+        x[i] += d[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (interior) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      F.r[rd ^ 1][t * np2 + q] = r[t];
+      F.w[rd ^ 1][t * np2 + q] = d[t];
+      F.x[t * np2 + q] = x[t];
+    }
+  }
+}
+
+template <typename T>
+void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st) {
+  (void)K;
+  const int TP = f.np < 8 ? f.np : 8;
+  const int nb = (f.np / TP) * (f.np / TP);
+  hipLaunchKernelGGL((k_fine_cheb<T, 4>), dim3(nb), dim3(256), 0, st, f, c, k0, nsteps, rd);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,8 +1408,12 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t);                           \
   template void launch_zero<T>(size_t, T*, hipStream_t);                                                \
   template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t);                                 \
+  template void launch_fine_cheb<T>(const FineCG<T>&, const ChebCoef&, int, int, int, int, hipStream_t); \
+  template void launch_cheb_init<T>(const CGArgs<T>&, const ChebStep&, int, hipStream_t);               \
+  template void launch_cheb_step<T>(const CGArgs<T>&, const ChebStep&, int, int, hipStream_t);          \
   template void launch_prolong_fine_dots<T>(const LevelGeom&, const T*, const T*, const FineCG<T>&,      \
-                                            double*, const double*, const double*, double*, hipStream_t); \
+                                            double*, const double*, const double*, double*, int,         \
+                                            hipStream_t);                                               \
   template void launch_outer_update_convert<T>(int, const double*, int, double*, double*, double*,      \
                                                const double*, const double*, T*, hipStream_t);          \
   template void launch_restrict_chain<T>(const ChainArgs<T>&, hipStream_t);                             \

@@ -85,11 +85,40 @@ struct FineCG {
   int nblk;          // tiles
 };
 
+// Chebyshev iteration for the subband systems (an alternative to CG with no
+// inner products: the preconditioner it defines is a fixed polynomial in
+// M B, so the outer iteration sees one linear operator).  With
+// [lmin, lmax] = [G / kappa, G], G an upper bound of lambda_max(M B),
+//   theta = (lmax + lmin) / 2, delta = (lmax - lmin) / 2, sigma = theta / delta,
+//   d_0 = M r_0 / theta,  r_k = r_{k-1} - B d_{k-1},
+//   rho_0 = 1 / sigma, rho_k = 1 / (2 sigma - rho_{k-1}),
+//   d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) M r_k,
+//   x = d_0 + ... + d_{K-1}.
+constexpr int kMaxCheb = 32;   // largest K
+struct ChebCoef {
+  float c0;              // 1 / theta
+  float ca[kMaxCheb];    // rho_k rho_{k-1}
+  float cb[kMaxCheb];    // 2 rho_k / delta
+};
+// One step of the coarser levels: coefficients of step k for every level.
+struct ChebStep {
+  float ca[kMaxLevels];
+  float cb[kMaxLevels];
+  float c0[kMaxLevels];
+};
+
+template <typename T>
+void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st);
+template <typename T>
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int nblocks, hipStream_t st);
+template <typename T>
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int nblocks, hipStream_t st);
+
 template <typename T>
 void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, hipStream_t st);
+                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st);
 template <typename T>
 void launch_outer_update_convert(int len, const double* part, int nblk, double* sc, double* u, double* r,
                                  const double* p, const double* w, T* g, hipStream_t st);

@@ -23,7 +23,8 @@ _STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "ENOME
 class GblOpts(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("inner_iters_coarse", ctypes.c_int)]
+                ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
+                ("kappa_coarse", ctypes.c_double)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -87,10 +88,20 @@ def _check(code: int, ctx=None):
         raise GambletError(code, msg)
 
 
+INNER_KINDS = {"chebyshev": 0, "cg": 1}
+
+
 def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 100,
-              inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None) -> GblOpts:
+              inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
+              inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
+    if inner is not None:
+        o.inner_kind = INNER_KINDS[inner]
+    if kappa is not None:
+        o.kappa = float(kappa)
+    if kappa_coarse is not None:
+        o.kappa_coarse = float(kappa_coarse)
     o.rho = int(rho)
     o.precision = GBL_FP64 if precision in ("fp64", "f64", "double") else GBL_MIXED
     o.rtol = float(rtol)
@@ -133,14 +144,16 @@ class Hierarchy:
 
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
-                 inner_iters_coarse: int | None = None):
+                 inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
+                 kappa_coarse: float | None = None):
         n = a.shape[0]
         q = n.bit_length() - 1
         if n != (1 << q) or q < 2:
             raise ValueError("a must be [2^q][2^q] with q >= 2")
         _require(a, (n, n), "a")
         self.q, self.n, self.device = q, n, a.device
-        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse)
+        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
+                              kappa_coarse)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -306,13 +319,15 @@ def _adopt(ctx_value: int, q: int, ws: torch.Tensor, opts: GblOpts) -> Hierarchy
 
 def build_batched(coeffs: list, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                   max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
-                  inner_iters_coarse: int | None = None) -> list:
+                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
+                  kappa_coarse: float | None = None) -> list:
     """Build the hierarchies of independent problems of uneven depth concurrently
     (``gbl_build_batched``); ``coeffs`` holds [2^q][2^q] float64 CUDA tensors."""
     P = len(coeffs)
     if P == 0:
         return []
-    opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse)
+    opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
+                     kappa_coarse)
     qs, wss = [], []
     for a in coeffs:
         n = a.shape[0]

@@ -44,7 +44,9 @@ def test_bad_q_rejected(q):
 
 
 @pytest.mark.parametrize("field,value", [("rho", 0), ("rho", 5), ("precision", 7), ("rtol", 0.0),
-                                         ("rtol", 2.0), ("max_outer", 0), ("max_rhs", 0)])
+                                         ("rtol", 2.0), ("max_outer", 0), ("max_rhs", 0), ("inner_kind", 2),
+                                         ("kappa", 1.0), ("kappa_coarse", 0.5), ("inner_iters", 33),
+                                         ("inner_iters_coarse", 33)])
 def test_bad_options_rejected(field, value):
     P, _ = _lib()
     o = P.make_opts()
@@ -88,3 +90,12 @@ def test_short_workspace_rejected_before_any_device_work():
                      need - 1, None)
     assert rc == -4
     assert b"workspace" in L.gbl_last_error(None)
+
+
+def test_default_options():
+    P, _ = _lib()
+    o = P.make_opts()
+    assert (o.rho, o.precision, o.max_outer, o.inner_kind) == (3, 1, 100, 0)
+    assert (o.inner_iters, o.inner_iters_coarse, o.kappa, o.kappa_coarse) == (12, 4, 200.0, 30.0)
+    cg = P.make_opts(inner="cg", inner_iters=40)
+    assert cg.inner_kind == 1 and P.workspace_bytes(6, cg) > 0   # CG budgets are not capped at 32

@@ -93,6 +93,43 @@ def test_dense_patch_kernels_match_oracle(monkeypatch, kernel, prec, tol):
     H.close()
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_fused_chebyshev_steps_match_single_steps(monkeypatch, prec):
+    """The finest-level Chebyshev kernel recomputes a halo of up to four parents
+    so that several steps share one launch; the halo holds exactly the values
+    a neighbouring tile computes, so one, two, three or four steps per launch
+    give bit-identical solves (q = 7 has 8 x 8 tiles of 8 x 8 parents; q = 3
+    a single tile smaller than the halo)."""
+    for q in (7, 3):
+        pr = S.rough_problem(q, 2.0, 25)
+        H = _P().Hierarchy(_dev(pr.a), rho=3, precision=prec, rtol=1e-9, inner_iters=11)
+        ref = None
+        for fuse in ("1", "2", "3", "4"):
+            monkeypatch.setenv("GBL_CHEB_FUSE", fuse)
+            _print_case(test="cheb_fuse", q=q, prec=prec, fuse=fuse)
+            u = H.solve(_dev(pr.g[0])).cpu().numpy()
+            if ref is None:
+                ref = u
+            assert np.array_equal(u, ref), (q, fuse)
+        H.close()
+
+
+@pytest.mark.parametrize("inner", ["cg", "chebyshev"])
+@pytest.mark.parametrize("q,rho,sigma,prec,tol", [(6, 3, 2.0, "mixed", 1e-8), (5, 2, 1.0, "fp64", 1e-10)])
+def test_solve_inner_kinds_match_direct(inner, q, rho, sigma, prec, tol):
+    """Both inner iterations on the subband systems (CG with its own budgets
+    8 / 3, Chebyshev with the defaults) reach the direct solve."""
+    _print_case(test="inner_kind", inner=inner, q=q, prec=prec)
+    pr = S.rough_problem(q, sigma, 26, nrhs=1)
+    u_ref = fem.solve(pr.a, pr.g)[0]
+    kw = dict(inner_iters=8, inner_iters_coarse=3) if inner == "cg" else {}
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec, rtol=tol, inner=inner, **kw)
+    u = H.solve(_dev(pr.g[0])).cpu().numpy()
+    err = _relerr(u[1:-1, 1:-1], u_ref[1:-1, 1:-1])
+    assert err < tol, (err, H.last_info)
+    H.close()
+
+
 @pytest.mark.parametrize("q,rho,sigma,prec,tol", [
     (6, 3, 1.0, "fp64", 1e-10), (6, 3, 2.0, "fp64", 1e-10), (6, 3, 2.0, "mixed", 1e-8),
     (7, 2, 2.0, "mixed", 1e-8), (5, 1, 1.0, "fp64", 1e-10), (2, 3, 1.0, "fp64", 1e-10),
@@ -283,15 +320,15 @@ def test_inclusions_q11_rho4():
     The inclusion value is 1e4 (total contrast 4.5e5): the block-Jacobi
     preconditioned subband systems of the two finest levels have condition
     numbers close to the inclusion value, and at 1e6 the local inner solves
-    stall (recorded as a limitation).  Four right-hand sides with inner budgets
-    (64, 16) each get a small FP64 residual; the first matches the direct solve
-    at 1e-8."""
+    stall (recorded as a limitation).  Four right-hand sides with CG inner
+    budgets (64, 16) each get a small FP64 residual; the first matches the
+    direct solve at 1e-8."""
     _print_case(test="inclusions_q11", a_incl=1e4)
     pr = S.inclusion_problem(nrhs=4, a_incl=1e4)
     fe = fem.assemble(pr.a)
     print("problem ready", flush=True)
     H = _P().Hierarchy(_dev(pr.a), rho=4, precision="fp64", rtol=1e-8, max_rhs=4, max_outer=400,
-                       inner_iters=64, inner_iters_coarse=16)
+                       inner="cg", inner_iters=64, inner_iters_coarse=16)
     u = H.solve(_dev(pr.g)).cpu().numpy()
     print("gpu done", H.last_info, flush=True)
     H.close()
