@@ -502,30 +502,41 @@ struct Mfma<double> {
   }
 };
 
-// tile coordinates of tile number tix = I (I + 1) / 2 + J
-__device__ __forceinline__ void tile_of(int tix, int& I, int& J) {
+template <typename T, int NT>
+struct CholLds {
+  T panel[NT][16][17];   // column-P tiles; rows of L_IP after the solve
+  T lpp[16][16];         // factored diagonal tile
+  T dinv[16];
+  T linvt[NT][16][16];   // rows of L_PP^{-T}
+  T sc[16 * NT];
+  T rhs[16 * NT];        // scaled right-hand side, later z, then x
+  T part[NT][16];
+  int rowinfo[16 * NT];  // patch row r: parent (x, y) and subband index, packed (x << 20 | y << 8 | t)
+  int bad;
+};
+
+// tile (I, J) of tile number tix = I (I + 1) / 2 + J; slots past the last tile get I = NT
+__host__ __device__ constexpr int tile_row(int tix, int ntile, int nt) {
   int i = 0;
   while ((i + 1) * (i + 2) / 2 <= tix) ++i;
-  I = i;
-  J = tix - i * (i + 1) / 2;
+  return tix < ntile ? i : nt;
+}
+__host__ __device__ constexpr int tile_col(int tix) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= tix) ++i;
+  return tix - i * (i + 1) / 2;
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(const T* __restrict__ A, const T* __restrict__ B,
-                                                         T* __restrict__ R, int nk, int s, int t, int rho,
-                                                         int fine, int* __restrict__ status) {
+// Body of the kernel for wavefront W: its slots m hold the tiles numbered
+// 4 m + W, so every tile coordinate is a compile-time constant.
+template <typename T, int NT, int W>
+__device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T* __restrict__ A,
+                                                     const T* __restrict__ B, T* __restrict__ R, int nk, int s,
+                                                     int t, int rho, int fine, int* __restrict__ status) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int SLOTS = (NTILE + 3) / 4;
   constexpr int P16 = 16 * NT;
-  __shared__ T panel[NT][16][17];   // column-P tiles; rows of L_IP after the solve
-  __shared__ T lpp[16][16];         // factored diagonal tile
-  __shared__ T dinv[16];
-  __shared__ T linvt[NT][16][16];   // rows of L_PP^{-T}
-  __shared__ T sc[P16];
-  __shared__ T rhs[P16];            // scaled right-hand side, later z, then x
-  __shared__ T part[NT][16];
-  __shared__ int bad;
 
   const int nc = nk / 2;
   const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -537,12 +548,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int p = 3 * npar;
   const int nta = (p + 1 + 15) / 16;    // tiles holding rows 0..p
   const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, lc = l & 15;
   const int TT = 2 * t + 1;
   const int S = 2 * s + 1;
   const int ti = parent_type(fine != 0, cx, cy);
-  if (tid == 0) bad = 0;
+  if (tid == 0) sm.bad = 0;
 
   // scaling and right-hand side
   for (int r = tid; r < P16; r += 256) {
@@ -550,6 +560,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (r < p) {
       const int lp = r / 3, tt = r - 3 * lp;
       const int px = x0 + lp / wy, py = y0 + lp % wy;
+      sm.rowinfo[r] = (px << 20) | (py << 8) | tt;
       const T d = B[b_index(t * TT + t, tt * 4, px * nc + py, TT)];
       if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
       else atomicOr(status, kBadPivot);
@@ -574,8 +585,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         rv = T(-acc);
       }
     }
-    sc[r] = scale;
-    rhs[r] = rv * scale;
+    sm.sc[r] = scale;
+    sm.rhs[r] = rv * scale;
   }
   __syncthreads();
 
@@ -583,31 +594,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   acc_t acc[SLOTS];
 #pragma unroll
   for (int m = 0; m < SLOTS; ++m) {
-    int I, J;
-    tile_of(4 * m + w, I, J);
+    const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[m][r] = T(0);
-    if (4 * m + w < NTILE && I < nta) {
+    if (I < nta) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + Mfma<T>::row(l, r), j = 16 * J + lc;
         T v;
         if (i < p && j < p) {
           if (i >= j) {
-            const int lr = i / 3, trr = i - 3 * lr;
-            const int lq = j / 3, tcc = j - 3 * lq;
-            const int rx = x0 + lr / wy, ry = y0 + lr % wy;
-            const int qx = x0 + lq / wy, qy = y0 + lq % wy;
+            const int ri = sm.rowinfo[i], rj = sm.rowinfo[j];
+            const int rx = ri >> 20, ry = (ri >> 8) & 0xfff, trr = ri & 0xff;
+            const int qx = rj >> 20, qy = (rj >> 8) & 0xfff, tcc = rj & 0xff;
             const int ox = qx - rx + t, oy = qy - ry + t;
             T bv = T(0);
             if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
               bv = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)];
-            v = bv * sc[i] * sc[j];
+            v = bv * sm.sc[i] * sm.sc[j];
           } else {
             v = T(0);
           }
         } else if (i == p && j < p) {
-          v = rhs[j];
+          v = sm.rhs[j];
         } else {
           v = (i == j) ? T(1) : T(0);
         }
@@ -620,21 +629,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // 1. panel tiles (I, P), I >= P, to LDS
 #pragma unroll
     for (int m = 0; m < SLOTS; ++m) {
-      int I, J;
-      tile_of(4 * m + w, I, J);
-      if (4 * m + w < NTILE && J == P && I < nta) {
+      const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
+      if (J == P && I < nta) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) panel[I][Mfma<T>::row(l, r)][lc] = acc[m][r];
+        for (int r = 0; r < 4; ++r) sm.panel[I][Mfma<T>::row(l, r)][lc] = acc[m][r];
       }
     }
     __syncthreads();
     // 2. diagonal tile in the registers of lanes 0..15 of wavefront 0 (lane i
     //    holds row i; entries right of the diagonal are never read).  Rows
     //    from p on are not part of the SPD system: their pivots are taken as 1.
-    if (w == 0) {
+    if (W == 0) {
       T a[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = panel[P][lc][c];
+      for (int c = 0; c < 16; ++c) a[c] = sm.panel[P][lc][c];
       int badl = 0, regl = 0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
@@ -652,12 +660,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       if (l < 16) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) lpp[lc][c] = (c <= lc) ? a[c] : T(0);
+        for (int c = 0; c < 16; ++c) sm.lpp[lc][c] = (c <= lc) ? a[c] : T(0);
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-          if (c == lc) dinv[lc] = T(1) / a[c];
+          if (c == lc) sm.dinv[lc] = T(1) / a[c];
       }
-      if (l == 0 && (badl | regl)) bad |= badl | (regl << 1);
+      if (l == 0 && (badl | regl)) sm.bad |= badl | (regl << 1);
     }
     __syncthreads();
     // 3. rows of L_IP (I > P) and of L_PP^{-T}: l[c] = (a[c] - sum_{m<c} l[m] L_PP[c][m]) / L_PP[c][c]
@@ -670,17 +678,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       T x[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        const T v = panel[I][i][c];
+        const T v = sm.panel[I][i][c];
         x[c] = unit ? ((c == i) ? T(1) : T(0)) : v;
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         T v = x[c];
 #pragma unroll
-        for (int m2 = 0; m2 < c; ++m2) v -= x[m2] * lpp[c][m2];
-        x[c] = v * dinv[c];
+        for (int m2 = 0; m2 < c; ++m2) v -= x[m2] * sm.lpp[c][m2];
+        x[c] = v * sm.dinv[c];
       }
-      T* dst = unit ? &linvt[P][i][0] : &panel[I][i][0];
+      T* dst = unit ? &sm.linvt[P][i][0] : &sm.panel[I][i][0];
 #pragma unroll
       for (int c = 0; c < 16; ++c) dst[c] = x[c];
     }
@@ -688,22 +696,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // 4. keep L_IP (I >= P) in the accumulators; A_IJ -= L_IP L_JP^T for J > P
 #pragma unroll
     for (int m = 0; m < SLOTS; ++m) {
-      int I, J;
-      tile_of(4 * m + w, I, J);
-      if (4 * m + w < NTILE && I < nta) {
+      const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
+      if (I < nta) {
         if (J == P) {
           if (I == P) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[m][r] = lpp[Mfma<T>::row(l, r)][lc];
+            for (int r = 0; r < 4; ++r) acc[m][r] = sm.lpp[Mfma<T>::row(l, r)][lc];
           } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[m][r] = panel[I][Mfma<T>::row(l, r)][lc];
+            for (int r = 0; r < 4; ++r) acc[m][r] = sm.panel[I][Mfma<T>::row(l, r)][lc];
           }
         } else if (J > P) {
 #pragma unroll
           for (int k4 = 0; k4 < 4; ++k4) {
-            const T av = -panel[I][lc][4 * k4 + (l >> 4)];
-            const T bv = panel[J][lc][4 * k4 + (l >> 4)];
+            const T av = -sm.panel[I][lc][4 * k4 + (l >> 4)];
+            const T bv = sm.panel[J][lc][4 * k4 + (l >> 4)];
             acc[m] = Mfma<T>::mma(av, bv, acc[m]);
           }
         }
@@ -715,13 +722,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // z = row p of L
 #pragma unroll
   for (int m = 0; m < SLOTS; ++m) {
-    int I, J;
-    tile_of(4 * m + w, I, J);
-    if (4 * m + w < NTILE && I == p / 16) {
+    const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
+    if (I == p / 16) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + Mfma<T>::row(l, r), j = 16 * J + lc;
-        if (i == p && j < p) rhs[j] = acc[m][r];
+        if (i == p && j < p) sm.rhs[j] = acc[m][r];
       }
     }
   }
@@ -732,40 +738,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // partial products L_IP^T x_I of the tiles below the diagonal
 #pragma unroll
     for (int m = 0; m < SLOTS; ++m) {
-      int I, J;
-      tile_of(4 * m + w, I, J);
-      if (4 * m + w < NTILE && J == P && I > P && I < ntz) {
+      const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
+      if (J == P && I > P && I < ntz) {
         T v = T(0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * I + Mfma<T>::row(l, r);
-          v += acc[m][r] * ((i < p) ? rhs[i] : T(0));
+          v += acc[m][r] * ((i < p) ? sm.rhs[i] : T(0));
         }
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
-        if (l < 16) part[I][lc] = v;
+        if (l < 16) sm.part[I][lc] = v;
       }
     }
     __syncthreads();
-    if (w == 0) {
+    if (W == 0) {
       T y = T(0);
       const int j = 16 * P + lc;
       if (j < p) {
-        y = rhs[j];
-        for (int I = P + 1; I < ntz; ++I) y -= part[I][lc];
+        y = sm.rhs[j];
+        for (int I = P + 1; I < ntz; ++I) y -= sm.part[I][lc];
       }
-      // x_P = L_PP^{-T} y: x_c = sum_i linvt[c][i] y_i
+      // x_P = L_PP^{-T} y: x_c = sum_i sm.linvt[c][i] y_i
       T xv = T(0);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) xv += linvt[P][lc][i] * __shfl(y, i, 64);
-      if (l < 16 && j < p) rhs[j] = xv;
+      for (int i = 0; i < 16; ++i) xv += sm.linvt[P][lc][i] * __shfl(y, i, 64);
+      if (l < 16 && j < p) sm.rhs[j] = xv;
     }
     __syncthreads();
   }
-  if (tid == 0 && (bad & 1)) atomicOr(status, kBadPivot);
-  if (tid == 0 && (bad & 2)) atomicOr(status, kRegularizedPivot);
+  if (tid == 0 && (sm.bad & 1)) atomicOr(status, kBadPivot);
+  if (tid == 0 && (sm.bad & 2)) atomicOr(status, kRegularizedPivot);
   // y = sc x, then the restriction row R_i = pibar_i + sum y_j W_j
-  for (int r = tid; r < p; r += 256) rhs[r] *= sc[r];
+  for (int r = tid; r < p; r += 256) sm.rhs[r] *= sm.sc[r];
   __syncthreads();
   const int rw = 2 * (2 * rho + 1);
   const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
@@ -781,9 +786,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int tp = parent_type(fine != 0, px, py);
       if (px == cx && py == cy) v = pibar(tp, d);
       const int lp = (px - x0) * wy + (py - y0);
-      for (int tt = 0; tt < 3; ++tt) v += (double)rhs[3 * lp + tt] * wcoef(tp, tt, d);
+      for (int tt = 0; tt < 3; ++tt) v += (double)sm.rhs[3 * lp + tt] * wcoef(tp, tt, d);
     }
     Ri[(size_t)e * nc2] = T(v);
+  }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ R, int nk, int s, int t, int rho, int fine,
+    int* __restrict__ status) {
+  __shared__ CholLds<T, NT> sm;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: patch_chol_mfma_body<T, NT, 0>(sm, A, B, R, nk, s, t, rho, fine, status); break;
+    case 1: patch_chol_mfma_body<T, NT, 1>(sm, A, B, R, nk, s, t, rho, fine, status); break;
+    case 2: patch_chol_mfma_body<T, NT, 2>(sm, A, B, R, nk, s, t, rho, fine, status); break;
+    default: patch_chol_mfma_body<T, NT, 3>(sm, A, B, R, nk, s, t, rho, fine, status); break;
   }
 }
 
