@@ -417,7 +417,9 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
     {
       ProfScope ps(GBL_PROF_SUBBAND_OPERATOR, st);
       launch_subband_operator<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offBJ), fine, st);
-      launch_gershgorin<T>(g, c->hier<T>(g.offB), reinterpret_cast<unsigned*>(c->ws + L.gersh_off) + k, st);
+      // scratch: the level's subband solve vectors, unused while building
+      T* scratch = reinterpret_cast<T*>(c->ws + (k == q ? L.fcg_off : L.cgv_off[k]));
+      launch_gershgorin<T>(g, c->hier<T>(g.offB), scratch, reinterpret_cast<unsigned*>(c->ws + L.gersh_off) + k, st);
     }
     {
       ProfScope ps(GBL_PROF_PATCH_SOLVE, st);

@@ -50,8 +50,9 @@ template <typename T>
 void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t st);
 template <typename T>
 void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool fine, hipStream_t st);
+// Bound of lambda_max(M B^(k)) (block Gershgorin); scratch holds 6 np^2 T values.
 template <typename T>
-void launch_gershgorin(const LevelGeom& L, const T* B, unsigned* out, hipStream_t st);
+void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out, hipStream_t st);
 template <typename T>
 void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
                         hipStream_t st);

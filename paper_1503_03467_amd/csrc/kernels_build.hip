@@ -1025,13 +1025,24 @@ __global__ __launch_bounds__(256) void k_galerkin(const T* __restrict__ A, const
     z[e] = acc;
   }
   __syncthreads();
+  // A^(k-1) is symmetric: this row computes the offsets (dx, dy) with dx > 0,
+  // or dx = 0 and dy >= 0, and also stores each of them, mirrored, in the row
+  // of the neighbour j; the other offsets are written by those neighbours,
+  // except where j lies outside the level (the entry is then zero).  Every
+  // location has exactly one writer.
   const int Sc = 2 * sc + 1;
   T* out = Ac + ci;   // Ac[e * nc2 + ci]
   for (int e = threadIdx.x; e < Sc * Sc; e += blockDim.x) {
     const int ox = e / Sc, oy = e % Sc;
     const int jx = cx + ox - sc, jy = cy + oy - sc;
+    const bool inside = jx >= 0 && jy >= 0 && jx < nc && jy < nc;
+    const bool upper = (ox > sc) || (ox == sc && oy >= sc);
+    if (!upper) {
+      if (!inside) out[(size_t)e * nc2] = T(0);
+      continue;
+    }
     T acc = T(0);
-    if (jx >= 0 && jy >= 0 && jx < nc && jy < nc) {
+    if (inside) {
       const T* Rj = R + (jx * nc + jy);
       const int ojx = 2 * (jx - rho), ojy = 2 * (jy - rho);
       // z index of R_j entry (bx, by): (ojx + bx) - (orgx - s)
@@ -1043,6 +1054,8 @@ __global__ __launch_bounds__(256) void k_galerkin(const T* __restrict__ A, const
         const T* zr = z + (shx + bx) * zw + shy;
         for (int by = byl; by <= byh; ++by) acc += Rr[by * nc2] * zr[by];
       }
+      // mirrored entry: row j, offset (-dx, -dy)
+      Ac[(size_t)(Sc * Sc - 1 - e) * nc2 + (jx * nc + jy)] = acc;
     }
     out[(size_t)e * nc2] = acc;
   }
@@ -1117,56 +1130,77 @@ void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStrea
 // kept with an integer atomic max on the bits of the non-negative float.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void chol3_inv(const double D[3][3], double Li[3][3]) {
-  double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int j = 0; j < 3; ++j) {
-    double dj = D[j][j];
-    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
-    const double lj = dj > 0.0 ? sqrt(dj) : 1.0;
-    L[j][j] = lj;
-    for (int i = j + 1; i < 3; ++i) {
-      double v = D[i][j];
-      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-      L[i][j] = v / lj;
-    }
-  }
-  for (int c = 0; c < 3; ++c) {
-    for (int r = 0; r < 3; ++r) {
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int k = c; k < r; ++k) v -= L[r][k] * Li[k][c];
-      Li[r][c] = (r >= c) ? v / L[r][r] : 0.0;
-    }
-  }
-}
-
-template <typename T>
-__global__ void k_gershgorin(const T* __restrict__ B, int np, int t, unsigned* __restrict__ out) {
+__global__ void k_chol3_inv(const T* __restrict__ B, int np, int t, T* __restrict__ Linv) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np * np) return;
   const int TT = 2 * t + 1;
+  const size_t np2 = (size_t)np * np;
+  T D[3][3];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) D[e / 3][e % 3] = B[b_index(t * TT + t, e, p, TT)];
+  // D = L L^T, then the lower triangle of L^{-1}: (0,0) (1,0) (1,1) (2,0) (2,1) (2,2)
+  const T l00 = my_sqrt<T>(D[0][0] > T(0) ? D[0][0] : T(1));
+  const T l10 = D[1][0] / l00, l20 = D[2][0] / l00;
+  const T d11 = D[1][1] - l10 * l10;
+  const T l11 = my_sqrt<T>(d11 > T(0) ? d11 : T(1));
+  const T l21 = (D[2][1] - l20 * l10) / l11;
+  const T d22 = D[2][2] - l20 * l20 - l21 * l21;
+  const T l22 = my_sqrt<T>(d22 > T(0) ? d22 : T(1));
+  const T i00 = T(1) / l00, i11 = T(1) / l11, i22 = T(1) / l22;
+  const T i10 = -l10 * i00 * i11;
+  const T i21 = -l21 * i11 * i22;
+  const T i20 = -(l20 * i00 + l21 * i10) * i22;
+  Linv[0 * np2 + p] = i00;
+  Linv[1 * np2 + p] = i10;
+  Linv[2 * np2 + p] = i11;
+  Linv[3 * np2 + p] = i20;
+  Linv[4 * np2 + p] = i21;
+  Linv[5 * np2 + p] = i22;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_linv(const T* __restrict__ Linv, size_t np2, int p, T L[3][3]) {
+  L[0][0] = Linv[p];
+  L[0][1] = T(0);
+  L[0][2] = T(0);
+  L[1][0] = Linv[np2 + p];
+  L[1][1] = Linv[2 * np2 + p];
+  L[1][2] = T(0);
+  L[2][0] = Linv[3 * np2 + p];
+  L[2][1] = Linv[4 * np2 + p];
+  L[2][2] = Linv[5 * np2 + p];
+}
+
+template <typename T>
+__global__ void k_gershgorin(const T* __restrict__ B, const T* __restrict__ Linv, int np, int t,
+                             unsigned* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np * np) return;
+  const int TT = 2 * t + 1;
+  const size_t np2 = (size_t)np * np;
   const int px = p / np, py = p % np;
-  double D[3][3], Lp[3][3];
-  for (int e = 0; e < 9; ++e) D[e / 3][e % 3] = (double)B[b_index(t * TT + t, e, p, TT)];
-  chol3_inv<T>(D, Lp);
-  double rs[3] = {0.0, 0.0, 0.0};
+  T Lp[3][3];
+  load_linv(Linv, np2, p, Lp);
+  T rs[3] = {T(0), T(0), T(0)};
   for (int ox = 0; ox < TT; ++ox) {
     const int qx = px + ox - t;
     if (qx < 0 || qx >= np) continue;
     for (int oy = 0; oy < TT; ++oy) {
       const int qy = py + oy - t;
       if (qy < 0 || qy >= np) continue;
-      const int qq = qx * np + qy;
-      double Bq[3][3], Dq[3][3], Lq[3][3];
-      for (int e = 0; e < 9; ++e) {
-        Bq[e / 3][e % 3] = (double)B[b_index(ox * TT + oy, e, p, TT)];
-        Dq[e / 3][e % 3] = (double)B[b_index(t * TT + t, e, qq, TT)];
-      }
-      chol3_inv<T>(Dq, Lq);
+      T Bq[3][3], Lq[3][3];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Bq[e / 3][e % 3] = B[b_index(ox * TT + oy, e, p, TT)];
+      load_linv(Linv, np2, qx * np + qy, Lq);
       // C = Lp Bq Lq^T
-      double M1[3][3];
+      T M1[3][3];
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) M1[i][j] = Lp[i][0] * Bq[0][j] + Lp[i][1] * Bq[1][j] + Lp[i][2] * Bq[2][j];
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) rs[i] += fabs(M1[i][0] * Lq[j][0] + M1[i][1] * Lq[j][1] + M1[i][2] * Lq[j][2]);
     }
   }
@@ -1175,14 +1209,16 @@ __global__ void k_gershgorin(const T* __restrict__ B, int np, int t, unsigned* _
 }
 
 template <typename T>
-void launch_gershgorin(const LevelGeom& L, const T* B, unsigned* out, hipStream_t st) {
+void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out, hipStream_t st) {
   const int np = L.nk / 2;
-  hipLaunchKernelGGL(k_gershgorin<T>, dim3((np * np + 255) / 256), dim3(256), 0, st, B, np, L.t, out);
+  const dim3 grid((np * np + 255) / 256), block(256);
+  hipLaunchKernelGGL(k_chol3_inv<T>, grid, block, 0, st, B, np, L.t, scratch);
+  hipLaunchKernelGGL(k_gershgorin<T>, grid, block, 0, st, B, scratch, np, L.t, out);
 }
 
 #define GBL_INST(T)                                                                                   \
   template void launch_assemble_fine<T>(const double*, T*, int, int*, hipStream_t);                  \
-  template void launch_gershgorin<T>(const LevelGeom&, const T*, unsigned*, hipStream_t);            \
+  template void launch_gershgorin<T>(const LevelGeom&, const T*, T*, unsigned*, hipStream_t);        \
   template void launch_subband_operator<T>(const LevelGeom&, const T*, T*, T*, bool, hipStream_t);   \
   template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, bool, int*,          \
                                       hipStream_t);                                                  \
