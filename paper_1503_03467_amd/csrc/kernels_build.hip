@@ -806,6 +806,209 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ---------------------------------------------------------------------------
+// Patch solves at the finest transition, band form held in registers
+// (rho <= 3).  One wavefront per patch; lane d holds the d-th subdiagonal of
+// the scaled patch matrix, M[c + d][c] for c = 0 .. p - 1, in registers (the
+// step loop is unrolled, so every register index is static).  Step j: lane 0
+// holds the pivot and every lane scales its entry of column j, giving
+// L[j + d][j]; for each later column j + e of the band the column is shifted
+// down one lane (DPP), its entry e is read out of lane 0's neighbourhood (lane
+// read) and lane d updates M[j + e + d][j + e].  The factor stays in place.
+// The right-hand side slides through the lanes so that the forward
+// substitution rides along; the back substitution sums over lanes.  Same
+// scaling, right-hand side and restriction row as the other patch kernels.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct WaveOps;
+template <>
+struct WaveOps<float> {
+  template <int CTRL, int ROWM, bool BC>
+  static __device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWM, 0xf, BC));
+  }
+  static __device__ __forceinline__ float lane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+  }
+};
+template <>
+struct WaveOps<double> {
+  template <int CTRL, int ROWM, bool BC>
+  static __device__ __forceinline__ double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWM, 0xf, BC);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWM, 0xf, BC);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  }
+  static __device__ __forceinline__ double lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  }
+};
+// lane i <- lane i + 1 (zero into lane 63)
+template <typename T>
+__device__ __forceinline__ T wave_down1(T v) { return WaveOps<T>::template dpp<0x130, 0xf, true>(v); }
+// lane i <- lane i - 1 (zero into lane 0)
+template <typename T>
+__device__ __forceinline__ T wave_up1(T v) { return WaveOps<T>::template dpp<0x138, 0xf, true>(v); }
+// sum over the 64 lanes (quad permutations, row mirrors, then row broadcasts)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += WaveOps<T>::template dpp<0xB1, 0xf, true>(v);
+  v += WaveOps<T>::template dpp<0x4E, 0xf, true>(v);
+  v += WaveOps<T>::template dpp<0x141, 0xf, true>(v);
+  v += WaveOps<T>::template dpp<0x140, 0xf, true>(v);
+  v += WaveOps<T>::template dpp<0x142, 0xa, false>(v);
+  v += WaveOps<T>::template dpp<0x143, 0xc, false>(v);
+  return WaveOps<T>::lane(v, 63);
+}
+
+template <typename T, int RHO>
+__global__ __launch_bounds__(64) void k_patch_band_reg(const T* __restrict__ A, const T* __restrict__ B,
+                                                       T* __restrict__ R, int nk, int s, int* __restrict__ status) {
+  constexpr int PMAX = 3 * (2 * RHO + 1) * (2 * RHO + 1);
+  constexpr int BWM = 3 * (2 * RHO + 2) + 2;   // largest half-bandwidth, < 64
+  constexpr int TT = 3;                        // parent stencil width at the finest level (t = 1)
+  __shared__ T sb[PMAX + 64];                  // b, then z, then x (zero beyond p)
+  __shared__ T sc[PMAX];
+  __shared__ int rowinfo[PMAX];
+  const int rho = RHO;
+  const int nc = nk / 2;
+  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = ci / nc, cy = ci % nc;
+  const int x0 = max(0, cx - rho), x1 = min(nc - 1, cx + rho);
+  const int y0 = max(0, cy - rho), y1 = min(nc - 1, cy + rho);
+  const int wy = y1 - y0 + 1;
+  const int npar = (x1 - x0 + 1) * wy;
+  const int p = 3 * npar;
+  const int bw = 3 * (wy + 1) + 2;
+  const int lane = threadIdx.x;
+  const int S = 2 * s + 1;
+  const int ti = parent_type(true, cx, cy);
+
+  for (int r = lane; r < PMAX + 64; r += 64) {
+    T scale = T(1), rv = T(0);
+    if (r < p) {
+      const int lp = r / 3, tt = r - 3 * lp;
+      const int px = x0 + lp / wy, py = y0 + lp % wy;
+      rowinfo[r] = (px << 20) | (py << 8) | tt;
+      const T d = B[b_index(TT + 1, tt * 4, px * nc + py, TT)];
+      if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
+      else atomicOr(status, kBadPivot);
+      const int tp = parent_type(true, px, py);
+      if (abs(px - cx) <= 1 && abs(py - cy) <= 1 && !is_pad_row(tp, tt)) {
+        double acc = 0.0;
+        for (int dd = 0; dd < 4; ++dd) {
+          const double wd = wcoef(tp, tt, dd);
+          if (wd == 0.0) continue;
+          const int fx = 2 * px + (dd >> 1), fy = 2 * py + (dd & 1);
+          double inner = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double pe = pibar(ti, e);
+            if (pe == 0.0) continue;
+            const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
+            const int ox = gx - fx + s, oy = gy - fy + s;
+            if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
+            inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
+          }
+          acc += wd * inner;
+        }
+        rv = T(-acc);
+      }
+    }
+    if (r < PMAX) sc[r] = scale;
+    sb[r] = rv * scale;
+  }
+  __syncthreads();
+
+  // this lane's subdiagonal d = lane: M[c + d][c]
+  T dg[PMAX];
+#pragma clang loop unroll(full)
+  for (int c = 0; c < PMAX; ++c) {
+    const int r = c + lane;
+    T v = T(0);
+    if (lane <= bw && r < p) {
+      const int ri = rowinfo[r], rj = rowinfo[c];
+      const int rx = ri >> 20, ry = (ri >> 8) & 0xfff, trr = ri & 0xff;
+      const int qx = rj >> 20, qy = (rj >> 8) & 0xfff, tcc = rj & 0xff;
+      const int ox = qx - rx + 1, oy = qy - ry + 1;
+      if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
+        v = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)] * sc[r] * sc[c];
+    }
+    dg[c] = v;
+  }
+
+  // factorisation with the forward substitution: bs holds b_{j + lane}
+  int bad = 0, reg = 0;
+  T bs = sb[lane];
+#pragma clang loop unroll(full)
+  for (int j = 0; j < PMAX; ++j) {
+    if (j < p) {
+      const T piv = patch_pivot<T>(WaveOps<T>::lane(dg[j], 0), bad, reg);
+      const T sq = my_sqrt<T>(piv);
+      const T inv = T(1) / sq;
+      const T col = (lane == 0) ? sq : dg[j] * inv;
+      dg[j] = col;
+      const T zj = WaveOps<T>::lane(bs, 0) * inv;
+      if (lane == 0) sb[j] = zj;
+      bs = wave_down1<T>(bs - col * zj);
+      const T nb = sb[j + 64];   // b_{j+64}, not yet overwritten
+      if (lane == 63) bs = nb;
+      T cs = col;
+#pragma clang loop unroll(full)
+      for (int e = 1; e <= BWM; ++e) {
+        if (j + e < PMAX) {
+          cs = wave_down1<T>(cs);                    // lane d: L[j + e + d][j]
+          const T ce = WaveOps<T>::lane(col, e);     // L[j + e][j]
+          dg[j + e] -= cs * ce;
+        }
+      }
+    }
+  }
+  // back substitution L^T x = z: xs holds x_{c + lane} (lane >= 1)
+  T xs = T(0);
+#pragma clang loop unroll(full)
+  for (int c = PMAX - 1; c >= 0; --c) {
+    if (c < p) {
+      const T sum = wave_sum<T>(lane >= 1 ? dg[c] * xs : T(0));
+      const T xc = (sb[c] - sum) / WaveOps<T>::lane(dg[c], 0);
+      if (lane == 0) sb[c] = xc;
+      xs = wave_up1<T>(lane == 0 ? xc : xs);
+    }
+  }
+  if (lane == 0 && bad) atomicOr(status, kBadPivot);
+  if (lane == 0 && reg) atomicOr(status, kRegularizedPivot);
+  __syncthreads();
+  for (int r = lane; r < p; r += 64) sb[r] *= sc[r];
+  __syncthreads();
+
+  const int rw = 2 * (2 * rho + 1);
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
+  const size_t nc2 = (size_t)nc * nc;
+  T* Ri = R + ci;
+  for (int e = lane; e < rw * rw; e += 64) {
+    const int bx = e / rw, by = e % rw;
+    const int fx = ox0 + bx, fy = oy0 + by;
+    double v = 0.0;
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      const int px = fx >> 1, py = fy >> 1;
+      const int d = 2 * (fx & 1) + (fy & 1);
+      const int tp = parent_type(true, px, py);
+      if (px == cx && py == cy) v = pibar(tp, d);
+      const int lp = (px - x0) * wy + (py - y0);
+      for (int tt = 0; tt < 3; ++tt) v += (double)sb[3 * lp + tt] * wcoef(tp, tt, d);
+    }
+    Ri[(size_t)e * nc2] = T(v);
+  }
+}
+
+static bool band_reg_enabled() {
+  const char* e = getenv("GBL_BAND_REG");
+  return !(e && e[0] == '0');
+}
+
+// ---------------------------------------------------------------------------
 // Patch solves at the finest transition (k = q), band form.
 //
 // B^(q) couples only neighbouring parents (its parent stencil is 3 x 3), so
@@ -975,6 +1178,13 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
 template <typename T>
 void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st) {
   const int nc = L.nk / 2;
+  if (band_reg_enabled() && L.rho <= 3) {
+    const dim3 grid(nc * nc), block(64);
+    if (L.rho == 3) hipLaunchKernelGGL((k_patch_band_reg<T, 3>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    else if (L.rho == 2) hipLaunchKernelGGL((k_patch_band_reg<T, 2>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    else hipLaunchKernelGGL((k_patch_band_reg<T, 1>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    return;
+  }
   const int pmax = 3 * (2 * L.rho + 1) * (2 * L.rho + 1);
   const int bwmax = 3 * (2 * L.rho + 2) + 2;
   const size_t shm = ((size_t)pmax * (bwmax + 1) + 2 * (size_t)pmax + (bwmax + 1)) * sizeof(T);

@@ -63,22 +63,24 @@ def test_hierarchy_levels_match_oracle_fp64(q, rho, sigma):
 
 @pytest.mark.parametrize("kernel", ["mfma", "registers"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
-def test_dense_patch_kernels_match_oracle(monkeypatch, kernel, prec, tol):
-    """Both dense patch kernels of the coarser levels (matrix-core blocked
-    Cholesky, register-tiled Cholesky) against the oracle's R and A^(k-1);
+def test_patch_kernels_match_oracle(monkeypatch, kernel, prec, tol):
+    """Both sets of patch kernels against the oracle's R and A^(k-1): matrix-core
+    blocked Cholesky (levels k < q) with the register-resident band kernel
+    (level q), and register-tiled Cholesky with the LDS band kernel;
     rho = 3 at q = 6 gives patches of up to 147 unknowns (10 tiles of 16).
     FP32 bound: unit roundoff 6e-8 times scaled patch condition numbers up to
     about 1e3, compounded over the FP32 Galerkin products of the finer levels."""
     monkeypatch.setenv("GBL_PATCH_MFMA", "1" if kernel == "mfma" else "0")
+    monkeypatch.setenv("GBL_BAND_REG", "1" if kernel == "mfma" else "0")
     q, rho = 6, 3
-    _print_case(test="dense_patch", kernel=kernel, prec=prec, q=q, rho=rho)
+    _print_case(test="patch_kernels", kernel=kernel, prec=prec, q=q, rho=rho)
     pr = S.rough_problem(q, 2.0, 23)
     fe = fem.assemble(pr.a)
     tree = G.Tree(q)
     ref = G.localized_hierarchy(fe.A, tree, rho)
     H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec)
     torch.cuda.synchronize()
-    for k in range(q - 1, 1, -1):
+    for k in range(q, 1, -1):
         lv = H.level(k)
         R_gpu = restriction_to_matrix(lv["R"].cpu().double().numpy(), lv["rho"], q, k, tree.size(k))
         R_ref = ref.levels[k].R
