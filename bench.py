@@ -47,19 +47,46 @@ def level_geometry(H):
     return {k: H.level(k) for k in range(1, H.q + 1)}
 
 
+# HBM traffic per launch of a kernel class, from rocprofv3 counter runs of this benchmark
+# (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the class's launches of one step,
+# scaled by the factors measured on a plain 1 GiB copy).  Valid only for the kernel source it was
+# measured on: the entry records the SHA-256 of that source file, and a mismatch reports None.
+MEASURED_TRAFFIC = {}
+
+
+def measured_traffic(name, q, precision):
+    import hashlib
+    e = MEASURED_TRAFFIC.get((name, q, precision))
+    if not e:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1503_03467_amd", "csrc", e["source"])
+    try:
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return e["bytes_per_launch"] if digest == e["sha256"] else None
+
+
 def kernel_work(name, geo, q, elem, inner="chebyshev"):
     """Algorithmic bytes (HBM-bound classes) or flops (arithmetic-bound) summed over one
     build (build kernels) or one launch (solve kernels).  Returns (kind, amount)."""
-    if name == "patch_solve":
+    if name in ("patch_solve", "patch_band"):
+        # dense Cholesky plus two triangular solves, p^3 / 3 + 2 p^2 per patch (levels k < q); at the
+        # finest transition the band Cholesky, p (bw^2 + 4 bw) with half-bandwidth bw = 3 (w_y + 1) + 2
+        import numpy as np
         fl = 0.0
-        for k in range(2, q + 1):
+        levels = [q] if name == "patch_band" else range(2, q)
+        for k in levels:
             g = geo[k]
             nc = g["nk"] // 2
             rho = g["rho"]
-            import numpy as np
             w = np.minimum(np.arange(nc) + rho, nc - 1) - np.maximum(np.arange(nc) - rho, 0) + 1
             p = 3.0 * np.outer(w, w)
-            fl += float((p ** 3 / 3.0 + 2.0 * p ** 2).sum())
+            if name == "patch_band":
+                bw = 3.0 * (w[None, :] + 1) + 2
+                fl += float((p * (bw ** 2 + 4 * bw)).sum())
+            else:
+                fl += float((p ** 3 / 3.0 + 2.0 * p ** 2).sum())
         return "flops", fl
     if name == "galerkin":
         fl = 0.0
@@ -180,9 +207,10 @@ def main():
     kind, work = kernel_work(dominant, geo, q, elem, args.inner)
     inner_iters = H.opts.inner_iters
     inner_iters_coarse = H.opts.inner_iters_coarse
-    build_kernel = dominant in ("patch_solve", "galerkin", "subband_operator", "assemble")
-    launches_per_unit = (q - 1) if build_kernel else 1
-    per_launch_work = work / launches_per_unit
+    # work is per build (build kernels: one launch per level) or per launch (solve kernels)
+    build_kernel = dominant in ("patch_solve", "patch_band", "galerkin", "subband_operator", "assemble")
+    launches_per_step = dom_launches / args.steps
+    per_launch_work = work / launches_per_step if build_kernel else work
     avg_launch_ms = dom_ms / max(dom_launches, 1)
     if kind == "flops":
         achieved = per_launch_work / (avg_launch_ms * 1e-3) / 1e12
@@ -192,8 +220,9 @@ def main():
         achieved = per_launch_work / (avg_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    roof.update({"kernel": dominant, "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_launches / args.steps,
+    roof.update({"kernel": dominant, "avg_launch_ms": avg_launch_ms, "launches_per_step": launches_per_step,
                  "algorithmic_per_launch": per_launch_work})
+    roof["traffic"] = measured_traffic(dominant, q, args.precision)
 
     # accuracy of the timed configuration against the CPU oracle's direct solve
     extras = {}

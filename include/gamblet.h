@@ -213,7 +213,7 @@ int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);
 enum gbl_prof_kernel {
   GBL_PROF_ASSEMBLE = 0,          /* fine stiffness A^(q) */
   GBL_PROF_SUBBAND_OPERATOR = 1,  /* B^(k) = W A^(k) W^T and block-Jacobi factors */
-  GBL_PROF_PATCH_SOLVE = 2,       /* patch Cholesky solves and R^(k-1,k) */
+  GBL_PROF_PATCH_SOLVE = 2,       /* patch Cholesky solves and R^(k-1,k), levels k < q */
   GBL_PROF_GALERKIN = 3,          /* A^(k-1) = R A^(k) R^T */
   GBL_PROF_RESTRICT = 4,          /* g^(k-1) = R g^(k) */
   GBL_PROF_CG_INIT = 5,           /* subband CG start, coarser levels */
@@ -223,7 +223,8 @@ enum gbl_prof_kernel {
   GBL_PROF_FINE_APPLY = 9,        /* FP64 fine operator in the outer iteration */
   GBL_PROF_GRADIENT = 10,         /* adjoint cell gradient */
   GBL_PROF_FINE_CG = 11,          /* finest-level subband iteration (CG or Chebyshev, fused) */
-  GBL_PROF_NUM_KERNELS = 12
+  GBL_PROF_PATCH_BAND = 12,       /* band patch solves and R^(q-1,q) at the finest transition */
+  GBL_PROF_NUM_KERNELS = 13
 };
 
 /* Process-wide kernel timing: every launch of a class whose bit (1 << class)

@@ -422,7 +422,7 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
       launch_gershgorin<T>(g, c->hier<T>(g.offB), scratch, reinterpret_cast<unsigned*>(c->ws + L.gersh_off) + k, st);
     }
     {
-      ProfScope ps(GBL_PROF_PATCH_SOLVE, st);
+      ProfScope ps(fine && g.t == 1 && g.nk / 2 > 2 * g.rho + 1 ? GBL_PROF_PATCH_BAND : GBL_PROF_PATCH_SOLVE, st);
       launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR), fine, c->status(),
                             st);
     }

@@ -252,7 +252,7 @@ class Hierarchy:
 
 
 PROF_KERNELS = ["assemble", "subband_operator", "patch_solve", "galerkin", "restrict", "cg_init", "cg_spmv",
-                "cg_update", "prolong", "fine_apply", "gradient", "fine_cg"]
+                "cg_update", "prolong", "fine_apply", "gradient", "fine_cg", "patch_band"]
 
 
 def profile_enable(kernels="all"):
