@@ -1271,11 +1271,148 @@ __global__ __launch_bounds__(256) void k_galerkin(const T* __restrict__ A, const
   }
 }
 
+static bool galerkin_strip_enabled() {
+  const char* e = getenv("GBL_GALERKIN_STRIP");
+  return !(e && e[0] == '0');
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product on strips of NS coarse rows (consecutive in y) per
+// workgroup.  Neighbouring coarse rows share most of their restriction
+// supports and stencil neighbours, so
+//   1. the strip's R rows go to LDS;
+//   2. z_m = R_m A^(k) (symmetric A: z_m[c'] = sum_c A[c'][c] R_m[c]) is formed
+//      over the union of the rows' windows, each A entry read once for all
+//      rows whose support covers it;
+//   3. each neighbour row R_j of the strip's stencils is read once and dotted
+//      with the z of every strip row it couples to;
+// and the strip's A^(k-1) rows are staged in LDS so that, for each stencil
+// offset, the NS consecutive coarse rows are written together.
+// ---------------------------------------------------------------------------
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_galerkin_strip(const T* __restrict__ A, const T* __restrict__ R,
+                                                        T* __restrict__ Ac, int nk, int s, int rho, int sc) {
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int nc = nk / 2;
+  const int nstrip = nc / NS;
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cx = b / nstrip, cy0 = (b - cx * nstrip) * NS;
+  const int rw = 2 * (2 * rho + 1);
+  const int S = 2 * s + 1;
+  const int Sc = 2 * sc + 1;
+  const int zw = rw + 2 * s;
+  const int uy = zw + 2 * (NS - 1);   // union window height (y) of the strip
+  T* Rl = smem;                        // [NS][rw][rw]
+  T* zl = Rl + NS * rw * rw;           // [NS][zw][zw]
+  T* ol = zl + NS * zw * zw;           // [Sc * Sc][NS]
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy0 - rho);   // support origin of row m: (ox0, oy0 + 2 m)
+  const size_t nc2 = (size_t)nc * nc;
+  const size_t nk2 = (size_t)nk * nk;
+  for (int e = threadIdx.x; e < NS * rw * rw; e += blockDim.x) {
+    const int m = e / (rw * rw), r = e - m * rw * rw;
+    Rl[e] = R[(size_t)r * nc2 + cx * nc + cy0 + m];
+  }
+  __syncthreads();
+  // 2. z over the union window: position (ux, uy) <-> fine slot (ox0 - s + ux, oy0 - s + uy)
+  for (int e = threadIdx.x; e < zw * uy; e += blockDim.x) {
+    const int ux = e / uy, uyy = e - ux * uy;
+    const int fx = ox0 - s + ux, fy = oy0 - s + uyy;
+    T acc[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) acc[m] = T(0);
+    if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
+      // neighbours c = (fx + ox - s, fy + oy - s) inside the union of supports
+      const int dx = fx - ox0, dy = fy - oy0;
+      const int oxl = max(0, s - dx), oxh = min(S - 1, s - dx + rw - 1);
+      const int oyl = max(0, s - dy), oyh = min(S - 1, s - dy + rw - 1 + 2 * (NS - 1));
+      const T* Arow = A + (size_t)(fx * nk + fy);
+      for (int ox = oxl; ox <= oxh; ++ox) {
+        const T* Ar = Arow + (size_t)ox * S * nk2;
+        const int bx = dx + ox - s;
+#pragma unroll 8
+        for (int oy = oyl; oy <= oyh; ++oy) {
+          const T a = Ar[oy * nk2];
+          const int cyr = dy + oy - s;   // support-relative y of c for row 0
+#pragma unroll
+          for (int m = 0; m < NS; ++m) {
+            const int by = cyr - 2 * m;
+            if (by >= 0 && by < rw) acc[m] += a * Rl[(m * rw + bx) * rw + by];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int zy = uyy - 2 * m;
+      if (zy >= 0 && zy < zw) zl[(m * zw + ux) * zw + zy] = acc[m];
+    }
+  }
+  __syncthreads();
+  // 3. neighbours j = (cx + dxj, cy0 + dyj), dxj in [-sc, sc], dyj in [-sc, sc + NS - 1]
+  const int jh = 2 * sc + NS;
+  for (int e = threadIdx.x; e < Sc * jh; e += blockDim.x) {
+    const int ejx = e / jh, ejy = e - ejx * jh;
+    const int jx = cx + ejx - sc, jy = cy0 + ejy - sc;
+    T acc[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) acc[m] = T(0);
+    const bool inside = jx >= 0 && jy >= 0 && jx < nc && jy < nc;
+    if (inside) {
+      const T* Rj = R + (jx * nc + jy);
+      // R_j entry (bx, by) sits at z_m index (shx + bx, shy - 2 m + by)
+      const int shx = 2 * (jx - rho) - ox0 + s, shy = 2 * (jy - rho) - oy0 + s;
+      const int bxl = max(0, -shx), bxh = min(rw - 1, zw - 1 - shx);
+      for (int bx = bxl; bx <= bxh; ++bx) {
+        const T* Rr = Rj + (size_t)bx * rw * nc2;
+        const T* zr = zl + (shx + bx) * zw;
+#pragma unroll 7
+        for (int by = 0; by < rw; ++by) {
+          const T rv = Rr[by * nc2];
+#pragma unroll
+          for (int m = 0; m < NS; ++m) {
+            const int zy = shy - 2 * m + by;
+            if (zy >= 0 && zy < zw) acc[m] += rv * zr[m * zw * zw + zy];
+          }
+        }
+      }
+    }
+    // stencil offset of j for row m: (ejx, ejy - m) when 0 <= ejy - m < Sc
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int oy = ejy - m;
+      if (oy >= 0 && oy < Sc) ol[(ejx * Sc + oy) * NS + m] = inside ? acc[m] : T(0);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < Sc * Sc * NS; e += blockDim.x) {
+    const int o = e / NS, m = e - o * NS;
+    Ac[(size_t)o * nc2 + cx * nc + cy0 + m] = ol[e];
+  }
+}
+
 template <typename T>
 void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
                      hipStream_t st) {
   const int nc = L.nk / 2;
   const int zw = L.rw + 2 * L.s;
+  const int Sc = 2 * C.s + 1;
+  // strip height: the largest of 8, 4, 2 whose LDS staging fits 64 KB
+  const size_t per_row = (size_t)(L.rw * L.rw + zw * zw + Sc * Sc) * sizeof(T);
+  int NS = 8;
+  while (NS > 1 && (NS > nc || (size_t)NS * per_row > 65536)) NS /= 2;
+  // strips pay off only with enough workgroups to fill the GPU
+  if (galerkin_strip_enabled() && NS >= 2 && nc * (nc / NS) >= 512) {
+    const size_t shm = (size_t)NS * per_row;
+    const dim3 grid(nc * (nc / NS)), block(256);
+    if (NS == 8)
+      hipLaunchKernelGGL((k_galerkin_strip<T, 8>), grid, block, shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
+    else if (NS == 4)
+      hipLaunchKernelGGL((k_galerkin_strip<T, 4>), grid, block, shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
+    else
+      hipLaunchKernelGGL((k_galerkin_strip<T, 2>), grid, block, shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
+    return;
+  }
   const size_t shm = (size_t)(L.rw * L.rw + zw * zw) * sizeof(T);
   hipLaunchKernelGGL(k_galerkin<T>, dim3(nc * nc), dim3(256), shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
 }
