@@ -542,7 +542,7 @@ void launch_apply_fine_dots(const double* a, int n, const double* p, const doubl
 // workgroup barrier between levels.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c) {
-  __shared__ T red[64 * 18];
+  __shared__ T red[256 * 18];   // (cell, row) partial sums of the largest chain level (16 x 16 cells, rw <= 18)
   for (int j = c.n - 1; j >= 0; --j) {
     const ChainLevel<T>& L = c.lv[j];
     const int nc = L.nk / 2;
@@ -973,16 +973,12 @@ template <typename T>
 void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int nblocks, hipStream_t st) {
   hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks), dim3(256), 0, st, a, s);
 }
+// One launch for all coarser levels: one wavefront per stencil row of the
+// largest level (its blocks dominate); wider stencils loop over their rows.
 template <typename T>
 void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int nblocks, hipStream_t st) {
-  const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
   const int t0 = 2 * a.lv[0].t + 1;
-  hipLaunchKernelGGL(k_cheb_step<T>, dim3(n0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, 0);
-  if (nblocks > n0) {
-    int tmax = 1;
-    for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
-    hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks - n0), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, s, k, n0);
-  }
+  hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, 0);
 }
 
 // ---------------------------------------------------------------------------
