@@ -38,6 +38,8 @@ def parse():
                     help="iteration on the subband systems (library default: chebyshev)")
     ap.add_argument("--inner-iters", type=int, default=None, help="finest-level budget (default: library's)")
     ap.add_argument("--inner-iters-coarse", type=int, default=None, help="coarser-level budget (default: library's)")
+    ap.add_argument("--kappa", type=float, default=None, help="Chebyshev interval ratio, finest level")
+    ap.add_argument("--kappa-coarse", type=float, default=None, help="Chebyshev interval ratio, coarser levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
     return ap.parse_args()
@@ -167,7 +169,8 @@ def main():
 
     def step(prec):
         H = P.Hierarchy(a, rho=pr.rho, precision=prec, rtol=args.rtol, inner_iters=args.inner_iters,
-                        inner_iters_coarse=args.inner_iters_coarse, inner=args.inner)
+                        inner_iters_coarse=args.inner_iters_coarse, inner=args.inner, kappa=args.kappa,
+                        kappa_coarse=args.kappa_coarse)
         u = H.solve(g, check=False)
         info = H.last_info
         return H, u, info
@@ -308,7 +311,8 @@ def main():
                                "N(0,1) cell source, patch radius 3, build+solve to 1e-8",
                    "q": q, "dof": dof, "rho": pr.rho, "sigma": 2.0, "precision": args.precision,
                    "rtol": args.rtol, "inner": args.inner, "inner_iters": inner_iters,
-                   "inner_iters_coarse": inner_iters_coarse},
+                   "inner_iters_coarse": inner_iters_coarse, "kappa": H.opts.kappa,
+                   "kappa_coarse": H.opts.kappa_coarse},
         "roofline": roof,
         "cpu_baseline": cpu,
         **extras,

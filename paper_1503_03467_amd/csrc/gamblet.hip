@@ -764,7 +764,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->precision = GBL_MIXED;
   o->rtol = 1e-8;
   o->max_outer = 100;
-  o->inner_iters = 12;
+  o->inner_iters = 16;
   o->max_rhs = 1;
   o->inner_iters_coarse = 4;
   o->inner_kind = GBL_INNER_CHEBYSHEV;
