@@ -110,6 +110,7 @@ struct Layout {
   size_t fine_off[5] = {};   // FP64 slot vectors u, r, z, p, w
   size_t lam_off = 0;        // FP64 nodal adjoint state
   size_t g_off[kMaxLevels] = {};     // T slot vectors per level
+  size_t gpad_off = 0, gpad_end = 0;  // the region of all slot vectors and their padding
   size_t cgv_off[kMaxLevels] = {};   // T CG vectors per level (5 x 3 np^2)
   size_t cgscal_off = 0;     // doubles
   size_t cgpart_off[kMaxLevels] = {};
@@ -215,10 +216,14 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.opart_off = b; b = align_up(b + 6 * (size_t)L.onblk * 8);
   for (int i = 0; i < 5; ++i) { L.fine_off[i] = b; b = align_up(b + n2 * 8); }
   L.lam_off = b; b = align_up(b + (size_t)(L.n + 1) * (L.n + 1) * 8);
+  // slot vectors with kGPad zero words on each side: the restriction reads up
+  // to 2 rho words beyond either end (where R is zero)
+  L.gpad_off = b;
   for (int k = 1; k <= q; ++k) {
-    L.g_off[k] = b;
-    b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * L.elem);
+    L.g_off[k] = b + kGPad * L.elem;
+    b = align_up(b + ((size_t)L.lv[k].nk * L.lv[k].nk + 2 * kGPad) * L.elem);
   }
+  L.gpad_end = b;
   {
     const size_t np2 = (size_t)L.lv[q].nk * L.lv[q].nk / 4;
     L.fcg_off = b;
@@ -472,51 +477,16 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     cl.fine = 0;
   }
   if (!r_converted) launch_convert<T, double>(n2, r, g[q], st);
-  for (int k = q; k > kc; --k) {
-    ProfScope ps(GBL_PROF_RESTRICT, st);
-    launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], st);
-  }
-  {
-    ProfScope ps(GBL_PROF_RESTRICT, st);
-    launch_restrict_chain<T>(chain, st);
-  }
-  const bool coarse = cg.nlev > 0 && c->opts.inner_iters_coarse > 0;
+  // The subband systems are independent (Section 4.7), so they run beside each
+  // other: the finest one on the caller's stream (it needs only g^(q)), and
+  // the restriction chain, the coarser systems and the prolongation down to
+  // level q - 1 on the second stream.
   hipStream_t cs = c->side ? c->side : st;
-  if (coarse && c->side) {
+  const bool cheb = c->opts.inner_kind == GBL_INNER_CHEBYSHEV;
+  const bool coarse = cg.nlev > 0 && c->opts.inner_iters_coarse > 0;
+  if (c->side) {
     hipEventRecord(c->ev_fork, st);
     hipStreamWaitEvent(cs, c->ev_fork, 0);
-  }
-  // coarser levels on the second stream, enqueued first so that they start
-  // together with the finest level
-  const bool cheb = c->opts.inner_kind == GBL_INNER_CHEBYSHEV;
-  if (coarse) {
-    const CGLev<T>& last = cg.lv[cg.nlev - 1];
-    if (cheb) {
-      {
-        ProfScope ps(GBL_PROF_CG_INIT, cs);
-        launch_cheb_init<T>(cg, c->cheb_coarse[0], last.blk0 + last.nblk, cs);
-      }
-      for (int k = 1; k < c->opts.inner_iters_coarse; ++k) {
-        ProfScope ps(GBL_PROF_CG_SPMV, cs);
-        launch_cheb_step<T>(cg, c->cheb_coarse[k], k, last.blk0s + last.nblks, cs);
-      }
-    } else {
-      {
-        ProfScope ps(GBL_PROF_CG_INIT, cs);
-        launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
-      }
-      for (int it = 0; it < c->opts.inner_iters_coarse; ++it) {
-        {
-          ProfScope ps(GBL_PROF_CG_SPMV, cs);
-          launch_cg_spmv<T>(cg, last.blk0s + last.nblks, it, cs);
-        }
-        ProfScope ps(GBL_PROF_CG_UPDATE, cs);
-        launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs);
-      }
-    }
-    if (c->side) hipEventRecord(c->ev_join, cs);
-  } else {
-    for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, st);
   }
   // finest level: Chebyshev steps fused four per launch, or one CG iteration
   // per launch (whose last step x += alpha p is applied inside the prolongation)
@@ -541,14 +511,54 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
       launch_fine_cg<T>(F, it, st);
     }
   }
-  if (coarse && c->side) hipStreamWaitEvent(st, c->ev_join, 0);
+  const int K = c->opts.inner_iters_coarse;
+  for (int k = q; k > kc; --k) {
+    ProfScope ps(GBL_PROF_RESTRICT, cs);
+    launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], cs);
+  }
   {
-    ProfScope ps(GBL_PROF_PROLONG, st);
-    launch_prolong_chain<T>(chain, c->L1(), st);
+    ProfScope ps(GBL_PROF_RESTRICT, cs);
+    launch_restrict_chain<T>(chain, cs);
+  }
+  if (coarse) {
+    if (cheb) {
+      {
+        ProfScope ps(GBL_PROF_CG_INIT, cs);
+        launch_cheb_init<T>(cg, c->cheb_coarse[0], 0, cg.nlev, cs);
+      }
+      for (int j = 1; j < K; ++j) {
+        ProfScope ps(GBL_PROF_CG_SPMV, cs);
+        launch_cheb_step<T>(cg, c->cheb_coarse[j], j, 0, cg.nlev, cs);
+      }
+    } else {
+      const CGLev<T>& last = cg.lv[cg.nlev - 1];
+      {
+        ProfScope ps(GBL_PROF_CG_INIT, cs);
+        launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
+      }
+      for (int it = 0; it < K; ++it) {
+        {
+          ProfScope ps(GBL_PROF_CG_SPMV, cs);
+          launch_cg_spmv<T>(cg, last.blk0s + last.nblks, it, cs);
+        }
+        ProfScope ps(GBL_PROF_CG_UPDATE, cs);
+        launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs);
+      }
+    }
+  } else {
+    for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, cs);
+  }
+  {
+    ProfScope ps(GBL_PROF_PROLONG, cs);
+    launch_prolong_chain<T>(chain, c->L1(), cs);
   }
   for (int k = kc + 1; k < q; ++k) {
-    ProfScope ps(GBL_PROF_PROLONG, st);
-    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, st);
+    ProfScope ps(GBL_PROF_PROLONG, cs);
+    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, cs);
+  }
+  if (c->side) {
+    hipEventRecord(c->ev_join, cs);
+    hipStreamWaitEvent(st, c->ev_join, 0);
   }
   ProfScope ps(GBL_PROF_PROLONG, st);
   double* part = reinterpret_cast<double*>(c->ws + L.dpart_off);
@@ -822,6 +832,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
     const size_t nz = (L.lam_off - L.L1_off) / 8;
     launch_fill(nz, 0.0, reinterpret_cast<double*>(c->ws + L.L1_off), s);
     launch_fill((L.total - L.cgscal_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.cgscal_off), s);
+    launch_fill((L.gpad_end - L.gpad_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.gpad_off), s);
   }
   c->cgf = make_cg_args<float>(c);
   c->cgd = make_cg_args<double>(c);

@@ -25,6 +25,9 @@ namespace gbl {
 
 constexpr int kMaxLevels = 13;     // q <= 12
 constexpr int kMaxRho = 4;
+// zero words before and after every level slot vector g^(k)
+constexpr int kGPad = 16;
+static_assert(kGPad >= 2 * kMaxRho, "the restriction reads 2 rho words beyond the slot vector");
 
 // Device status bits (or-ed into the workspace status word).
 constexpr int kBadCoefficient = 1;

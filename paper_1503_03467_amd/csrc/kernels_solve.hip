@@ -333,64 +333,59 @@ __global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__
 // ---------------------------------------------------------------------------
 template <typename T, int RHO>
 __device__ __forceinline__ T restrict_row(const T* __restrict__ R, const T* __restrict__ gf, int nk, int i, int bx) {
+  // Row bx of coarse slot i's restriction block (uniform over the wavefront in
+  // k_restrict, so the R addresses are scalar there).
+  // The patch solves store explicit zeros in R at support positions outside
+  // the level, so those terms need no mask: the row index is clamped into the
+  // level and y positions outside it read a neighbouring row of g^(k) or the
+  // zero padding around the vector (at most 2 RHO words past either end),
+  // each multiplied by a zero of R.  The loads of a row then share one
+  // address, with immediate offsets, and are all in flight together.
   constexpr int rw = 2 * (2 * RHO + 1);
   const int nc = nk / 2;
-  const size_t nc2 = (size_t)nc * nc;
+  const int nc2 = nc * nc;
   const int cx = i / nc, cy = i - (i / nc) * nc;
-  const int fx = 2 * (cx - RHO) + bx;
-  if (fx < 0 || fx >= nk) return T(0);
-  const int oy = 2 * (cy - RHO);
-  const T* Rr = R + (size_t)(bx * rw) * nc2 + i;
-  const T* gr = gf + (size_t)fx * nk;
+  const int fx = min(max(2 * (cx - RHO) + bx, 0), nk - 1);
+  const T* gr = gf + fx * nk + 2 * (cy - RHO);
+  const T* Rr = R + (size_t)(bx * rw) * nc2;
   T acc = T(0);
 #pragma unroll
-  for (int by = 0; by < rw; ++by) {
-    const int fy = oy + by;
-    const int fyc = min(max(fy, 0), nk - 1);
-    const T v = Rr[(size_t)by * nc2] * gr[fyc];
-    acc += (fy >= 0 && fy < nk) ? v : T(0);
-  }
+  for (int by = 0; by < rw; ++by) acc += Rr[by * nc2 + i] * gr[by];
   return acc;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ R, const T* __restrict__ gf,
-                                                  T* __restrict__ gc, int nk, int rho) {
-  // PP = 256 / rw coarse slots per workgroup; thread (bx, cl) sums row bx of
-  // the restriction block, the rows are added in LDS.
-  __shared__ T red[256];
+template <typename T, int RHO>
+__global__ __launch_bounds__(128) void k_restrict(const T* __restrict__ R, const T* __restrict__ gf,
+                                                  T* __restrict__ gc, int nk) {
+  // 64 consecutive coarse slots per workgroup, one per lane, so every load of
+  // R reads 64 consecutive words.  The restriction block has 2 (2 RHO + 1)
+  // rows: wavefront w sums rows w (2 RHO + 1) ... w (2 RHO + 1) + 2 RHO (a
+  // compile-time count, so all its loads are issued together) and the two
+  // partial sums are added in LDS.
+  constexpr int half = 2 * RHO + 1;
+  __shared__ T red[64];
   const int nc = nk / 2;
-  const int rw = 2 * (2 * rho + 1);
-  const int PP = 256 / rw;
-  const int tid = threadIdx.x;
-  const int bx = tid / PP, cl = tid - bx * PP;
-  const int i = blockIdx.x * PP + cl;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = min((int)blockIdx.x * 64 + lane, nc * nc - 1);
   T acc = T(0);
-  if (bx < rw && i < nc * nc) {
-    switch (rho) {
-      case 1: acc = restrict_row<T, 1>(R, gf, nk, i, bx); break;
-      case 2: acc = restrict_row<T, 2>(R, gf, nk, i, bx); break;
-      case 3: acc = restrict_row<T, 3>(R, gf, nk, i, bx); break;
-      default: acc = restrict_row<T, 4>(R, gf, nk, i, bx); break;
-    }
-  }
-  if (bx < rw) red[bx * PP + cl] = acc;
+  const int w0 = __builtin_amdgcn_readfirstlane(w * half);
+#pragma unroll
+  for (int j = 0; j < half; ++j) acc += restrict_row<T, RHO>(R, gf, nk, i, w0 + j);
+  if (w == 1) red[lane] = acc;
   __syncthreads();
-  if (tid < PP) {
-    const int ii = blockIdx.x * PP + tid;
-    if (ii < nc * nc) {
-      T sum = T(0);
-      for (int b = 0; b < rw; ++b) sum += red[b * PP + tid];
-      gc[ii] = sum;
-    }
-  }
+  if (w == 0 && (int)blockIdx.x * 64 + lane < nc * nc) gc[i] = acc + red[lane];
 }
 
 template <typename T>
 void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st) {
   const int nc = L.nk / 2;
-  const int PP = 256 / L.rw;
-  hipLaunchKernelGGL(k_restrict<T>, dim3((nc * nc + PP - 1) / PP), dim3(256), 0, st, R, gf, gc, L.nk, L.rho);
+  const dim3 grid((nc * nc + 63) / 64), block(128);
+  switch (L.rho) {
+    case 1: hipLaunchKernelGGL((k_restrict<T, 1>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    case 2: hipLaunchKernelGGL((k_restrict<T, 2>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    case 3: hipLaunchKernelGGL((k_restrict<T, 3>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    default: hipLaunchKernelGGL((k_restrict<T, 4>), grid, block, 0, st, R, gf, gc, L.nk); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -423,8 +418,10 @@ __device__ __forceinline__ T prolong_at_r(const T* __restrict__ R, const T* __re
       const int by = fy - 2 * (iyc - RHO);
       const int bxc = min(max(bx, 0), rw - 1), byc = min(max(by, 0), rw - 1);
       const int i = ixc * nc + iyc;
-      const T v = R[(size_t)(bxc * rw + byc) * nc2 + i] * vc[i];
-      acc += ok ? v : T(0);
+      // rows outside the level are clamped to real rows and weighted by zero:
+      // a product with a 0/1 factor (not a select) keeps every load
+      // unconditional, so they can all be in flight together
+      acc += R[(size_t)(bxc * rw + byc) * nc2 + i] * (vc[i] * T(ok ? 1 : 0));
     }
   }
   return acc;
@@ -546,19 +543,16 @@ __global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c) {
   for (int j = c.n - 1; j >= 0; --j) {
     const ChainLevel<T>& L = c.lv[j];
     const int nc = L.nk / 2;
-    const size_t nc2 = (size_t)nc * nc;
     const int rw = 2 * (2 * L.rho + 1);
     // work item (cell i, row bx): partial sum over the row, then rows are added
     for (int e = threadIdx.x; e < nc * nc * rw; e += blockDim.x) {
       const int i = e / rw, bx = e - (e / rw) * rw;
-      const int cx = i / nc, cy = i % nc;
-      const int ox = 2 * (cx - L.rho), oy = 2 * (cy - L.rho);
-      const int fx = ox + bx;
-      T acc = T(0);
-      if (fx >= 0 && fx < L.nk) {
-        const int byl = max(0, -oy), byh = min(rw - 1, L.nk - 1 - oy);
-        for (int by = byl; by <= byh; ++by)
-          acc += L.R[(size_t)(bx * rw + by) * nc2 + i] * L.gf[(size_t)fx * L.nk + oy + by];
+      T acc;
+      switch (L.rho) {
+        case 1: acc = restrict_row<T, 1>(L.R, L.gf, L.nk, i, bx); break;
+        case 2: acc = restrict_row<T, 2>(L.R, L.gf, L.nk, i, bx); break;
+        case 3: acc = restrict_row<T, 3>(L.R, L.gf, L.nk, i, bx); break;
+        default: acc = restrict_row<T, 4>(L.R, L.gf, L.nk, i, bx); break;
       }
       red[e] = acc;
     }
@@ -572,8 +566,30 @@ __global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c) {
   }
 }
 
+// One level of the prolongation chain, v^(k) = R^(k,k-1) v^(k-1) + W^(k)T w^(k),
+// by the whole workgroup.  The level's vectors come in as restrict-qualified
+// arguments (not through the chain structure) so that the gathers of a slot
+// can all be in flight together.
+template <typename T, int RHO>
+__device__ __forceinline__ void prolong_level(const T* __restrict__ R, const T* __restrict__ vc,
+                                              const T* __restrict__ w, T* __restrict__ vf, int nk, int fine) {
+  const int nc = nk / 2;
+  const int nc2 = nc * nc;
+  for (int id = threadIdx.x; id < nk * nk; id += blockDim.x) {
+    const int fx = id / nk, fy = id % nk;
+    T acc = prolong_at_r<T, RHO>(R, vc, nk, fx, fy);
+    const int px = fx >> 1, py = fy >> 1;
+    const int d = 2 * (fx & 1) + (fy & 1);
+    const int tp = parent_type(fine != 0, px, py);
+    const int p = px * nc + py;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc += T(wcoef(tp, t, d)) * w[t * nc2 + p];
+    vf[id] = acc;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_prolong_chain(ChainArgs<T> c, const double* __restrict__ L1) {
+__global__ __launch_bounds__(256) void k_prolong_chain(ChainArgs<T> c, const double* __restrict__ L1) {
   if (threadIdx.x == 0) {
     // coarsest system with the FP64 Cholesky factor of A^(1)
     double y[4];
@@ -592,18 +608,11 @@ __global__ __launch_bounds__(1024) void k_prolong_chain(ChainArgs<T> c, const do
   __syncthreads();
   for (int j = 0; j < c.n; ++j) {
     const ChainLevel<T>& L = c.lv[j];
-    const int nc = L.nk / 2;
-    const size_t nc2 = (size_t)nc * nc;
-    for (int id = threadIdx.x; id < L.nk * L.nk; id += blockDim.x) {
-      const int fx = id / L.nk, fy = id % L.nk;
-      T acc = prolong_at<T>(L.R, L.gc, L.nk, L.rho, fx, fy);
-      const int px = fx >> 1, py = fy >> 1;
-      const int d = 2 * (fx & 1) + (fy & 1);
-      const int tp = parent_type(L.fine != 0, px, py);
-      const int p = px * nc + py;
-#pragma unroll
-      for (int t = 0; t < 3; ++t) acc += T(wcoef(tp, t, d)) * L.w[t * nc2 + p];
-      L.gf[id] = acc;
+    switch (L.rho) {
+      case 1: prolong_level<T, 1>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
+      case 2: prolong_level<T, 2>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
+      case 3: prolong_level<T, 3>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
+      default: prolong_level<T, 4>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
     }
     __syncthreads();
   }
@@ -616,7 +625,7 @@ void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st) {
 }
 template <typename T>
 void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1), dim3(1024), 0, st, c, L1);
+  hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1), dim3(256), 0, st, c, L1);
 }
 
 // Coarsest system A^(1) U^(1) = g^(1) (last solve of Algorithm 2) with the FP64
@@ -888,10 +897,11 @@ void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
 // the z (k even) and p (k odd) vectors; x accumulates d_0 + ... + d_k.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs) {
-  const int l = find_level(args, blockIdx.x);
+__global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs, int blk_begin) {
+  const int gb = blk_begin + (int)blockIdx.x;
+  const int l = find_level(args, gb);
   const CGLev<T>& L = args.lv[l];
-  const int p = (blockIdx.x - L.blk0) * 256 + threadIdx.x;
+  const int p = (gb - L.blk0) * 256 + threadIdx.x;
   const int np = L.np;
   const size_t np2 = (size_t)np * np;
   const int nk = 2 * np;
@@ -970,15 +980,17 @@ __global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs,
 }
 
 template <typename T>
-void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks), dim3(256), 0, st, a, s);
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st) {
+  const int b0 = a.lv[l0].blk0, b1 = a.lv[l1 - 1].blk0 + a.lv[l1 - 1].nblk;
+  hipLaunchKernelGGL(k_cheb_init<T>, dim3(b1 - b0), dim3(256), 0, st, a, s, b0);
 }
-// One launch for all coarser levels: one wavefront per stencil row of the
-// largest level (its blocks dominate); wider stencils loop over their rows.
+// One launch for the levels l0 .. l1-1: one wavefront per stencil row of the
+// largest of them (its blocks dominate); wider stencils loop over their rows.
 template <typename T>
-void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int nblocks, hipStream_t st) {
-  const int t0 = 2 * a.lv[0].t + 1;
-  hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, 0);
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st) {
+  const int b0 = a.lv[l0].blk0s, b1 = a.lv[l1 - 1].blk0s + a.lv[l1 - 1].nblks;
+  const int t0 = 2 * a.lv[l0].t + 1;
+  hipLaunchKernelGGL(k_cheb_step<T>, dim3(b1 - b0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, b0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1405,8 +1417,8 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   template void launch_zero<T>(size_t, T*, hipStream_t);                                                \
   template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t);                                 \
   template void launch_fine_cheb<T>(const FineCG<T>&, const ChebCoef&, int, int, int, int, hipStream_t); \
-  template void launch_cheb_init<T>(const CGArgs<T>&, const ChebStep&, int, hipStream_t);               \
-  template void launch_cheb_step<T>(const CGArgs<T>&, const ChebStep&, int, int, hipStream_t);          \
+  template void launch_cheb_init<T>(const CGArgs<T>&, const ChebStep&, int, int, hipStream_t);          \
+  template void launch_cheb_step<T>(const CGArgs<T>&, const ChebStep&, int, int, int, hipStream_t);     \
   template void launch_prolong_fine_dots<T>(const LevelGeom&, const T*, const T*, const FineCG<T>&,      \
                                             double*, const double*, const double*, double*, int,         \
                                             hipStream_t);                                               \

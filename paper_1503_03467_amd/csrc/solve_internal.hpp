@@ -109,10 +109,11 @@ struct ChebStep {
 
 template <typename T>
 void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st);
+// levels l0 .. l1-1 of the coarser subband systems (CGArgs order)
 template <typename T>
-void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int nblocks, hipStream_t st);
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st);
 template <typename T>
-void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int nblocks, hipStream_t st);
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st);
 
 template <typename T>
 void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
