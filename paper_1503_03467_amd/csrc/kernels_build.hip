@@ -1280,17 +1280,30 @@ static bool galerkin_strip_enabled() {
 // Galerkin product on strips of NS coarse rows (consecutive in y) per
 // workgroup.  Neighbouring coarse rows share most of their restriction
 // supports and stencil neighbours, so
-//   1. the strip's R rows go to LDS;
-//   2. z_m = R_m A^(k) (symmetric A: z_m[c'] = sum_c A[c'][c] R_m[c]) is formed
+//   1. the strip's R rows go to LDS, each in the frame of the union of their
+//      supports (row m at y offset 2 m, zero elsewhere);
+//   2. z_m = R_m A^(k) (A symmetric: z_m[c'] = sum_c A[c'][c] R_m[c]) is formed
 //      over the union of the rows' windows, each A entry read once for all
-//      rows whose support covers it;
-//   3. each neighbour row R_j of the strip's stencils is read once and dotted
-//      with the z of every strip row it couples to;
-// and the strip's A^(k-1) rows are staged in LDS so that, for each stencil
-// offset, the NS consecutive coarse rows are written together.
+//      rows; z_m comes out zero outside its own window, so all rows share one
+//      frame and one index;
+//   3. A^(k-1) is symmetric: only the upper half of each row's stencil is
+//      formed (offsets (dx, dy) with dx > 0, or dx = 0 and dy >= 0), each
+//      neighbour row R_j read once and dotted with the z of every strip row;
+//   4. each entry is stored in its row and, mirrored, in the row of the
+//      neighbour j; for one stencil offset both stores cover NS consecutive
+//      coarse rows.  The remaining entries of the strip rows (lower offsets)
+//      are written by the strips of their neighbours, or are zero where the
+//      neighbour lies outside the level: every location has one writer.
 // ---------------------------------------------------------------------------
+constexpr int kStripThreads = 512;
+// parts of the neighbour rows per phase-3 work item: enough items for the workgroup, at most 3
+__host__ __device__ inline int strip_parts(int items, int threads) {
+  const int p = threads / items;
+  return p < 1 ? 1 : (p > 3 ? 3 : p);
+}
+
 template <typename T, int NS>
-__global__ __launch_bounds__(256) void k_galerkin_strip(const T* __restrict__ A, const T* __restrict__ R,
+__global__ __launch_bounds__(kStripThreads) void k_galerkin_strip(const T* __restrict__ A, const T* __restrict__ R,
                                                         T* __restrict__ Ac, int nk, int s, int rho, int sc) {
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -1302,22 +1315,28 @@ __global__ __launch_bounds__(256) void k_galerkin_strip(const T* __restrict__ A,
   const int S = 2 * s + 1;
   const int Sc = 2 * sc + 1;
   const int zw = rw + 2 * s;
-  const int uy = zw + 2 * (NS - 1);   // union window height (y) of the strip
-  T* Rl = smem;                        // [NS][rw][rw]
-  T* zl = Rl + NS * rw * rw;           // [NS][zw][zw]
-  T* ol = zl + NS * zw * zw;           // [Sc * Sc][NS]
-  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy0 - rho);   // support origin of row m: (ox0, oy0 + 2 m)
-  const size_t nc2 = (size_t)nc * nc;
+  const int ry = rw + 2 * (NS - 1);   // union of the strip rows' supports (y)
+  const int uy = zw + 2 * (NS - 1);   // union of their z windows (y)
+  const int ho = (Sc * Sc - 1) / 2;   // centre offset; ho .. Sc*Sc-1 is the upper half
+  T* Rf = smem;                       // [NS][rw][ry]
+  T* zu = Rf + NS * rw * ry;          // [NS][zw][uy]
+  T* ol = zu + NS * zw * uy;          // [P][Sc*Sc - ho][NS]
+  const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy0 - rho);   // union support origin
+  const int nc2 = nc * nc;
   const size_t nk2 = (size_t)nk * nk;
-  for (int e = threadIdx.x; e < NS * rw * rw; e += blockDim.x) {
-    const int m = e / (rw * rw), r = e - m * rw * rw;
-    Rl[e] = R[(size_t)r * nc2 + cx * nc + cy0 + m];
+  const int row0 = cx * nc + cy0;
+  // 1. R rows of the strip (m fastest: the NS rows of one entry are adjacent in R)
+  for (int e = threadIdx.x; e < NS * rw * ry; e += blockDim.x) {
+    const int m = e % NS, r = e / NS;
+    const int bx = r / ry, y = r - bx * ry, by = y - 2 * m;
+    Rf[m * (rw * ry) + r] = (by >= 0 && by < rw) ? R[(size_t)(bx * rw + by) * nc2 + row0 + m] : T(0);
   }
   __syncthreads();
-  // 2. z over the union window: position (ux, uy) <-> fine slot (ox0 - s + ux, oy0 - s + uy)
+  // 2. z at union position (ux, u) <-> level-k slot (ox0 - s + ux, oy0 - s + u)
+  const int mr = rw * ry, mz = zw * uy;
   for (int e = threadIdx.x; e < zw * uy; e += blockDim.x) {
-    const int ux = e / uy, uyy = e - ux * uy;
-    const int fx = ox0 - s + ux, fy = oy0 - s + uyy;
+    const int ux = e / uy, u = e - ux * uy;
+    const int fx = ox0 - s + ux, fy = oy0 - s + u;
     T acc[NS];
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc[m] = T(0);
@@ -1325,70 +1344,89 @@ __global__ __launch_bounds__(256) void k_galerkin_strip(const T* __restrict__ A,
       // neighbours c = (fx + ox - s, fy + oy - s) inside the union of supports
       const int dx = fx - ox0, dy = fy - oy0;
       const int oxl = max(0, s - dx), oxh = min(S - 1, s - dx + rw - 1);
-      const int oyl = max(0, s - dy), oyh = min(S - 1, s - dy + rw - 1 + 2 * (NS - 1));
+      const int oyl = max(0, s - dy), oyh = min(S - 1, s - dy + ry - 1);
       const T* Arow = A + (size_t)(fx * nk + fy);
       for (int ox = oxl; ox <= oxh; ++ox) {
         const T* Ar = Arow + (size_t)ox * S * nk2;
-        const int bx = dx + ox - s;
-#pragma unroll 8
+        const T* Rb = Rf + (dx + ox - s) * ry + (dy - s);
+#pragma unroll 4
         for (int oy = oyl; oy <= oyh; ++oy) {
           const T a = Ar[oy * nk2];
-          const int cyr = dy + oy - s;   // support-relative y of c for row 0
 #pragma unroll
-          for (int m = 0; m < NS; ++m) {
-            const int by = cyr - 2 * m;
-            if (by >= 0 && by < rw) acc[m] += a * Rl[(m * rw + bx) * rw + by];
-          }
+          for (int m = 0; m < NS; ++m) acc[m] += a * Rb[m * mr + oy];
         }
       }
     }
 #pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      const int zy = uyy - 2 * m;
-      if (zy >= 0 && zy < zw) zl[(m * zw + ux) * zw + zy] = acc[m];
-    }
+    for (int m = 0; m < NS; ++m) zu[m * mz + e] = acc[m];
   }
   __syncthreads();
-  // 3. neighbours j = (cx + dxj, cy0 + dyj), dxj in [-sc, sc], dyj in [-sc, sc + NS - 1]
+  // 3. neighbours j = (cx + dxj, cy0 + dyj), dxj in [0, sc], dyj in [-sc, sc + NS - 1];
+  //    with few neighbours per thread the rows bx of R_j are split into P parts
+  //    whose partial sums are added when storing
   const int jh = 2 * sc + NS;
-  for (int e = threadIdx.x; e < Sc * jh; e += blockDim.x) {
-    const int ejx = e / jh, ejy = e - ejx * jh;
+  const int items = (sc + 1) * jh;
+  const int P = strip_parts(items, blockDim.x);
+  const int nup = Sc * Sc - ho;
+  for (int e = threadIdx.x; e < items * P; e += blockDim.x) {
+    const int part = e / items, it = e - part * items;
+    const int ejx = sc + it / jh, ejy = it - (it / jh) * jh;
     const int jx = cx + ejx - sc, jy = cy0 + ejy - sc;
     T acc[NS];
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc[m] = T(0);
-    const bool inside = jx >= 0 && jy >= 0 && jx < nc && jy < nc;
-    if (inside) {
-      const T* Rj = R + (jx * nc + jy);
-      // R_j entry (bx, by) sits at z_m index (shx + bx, shy - 2 m + by)
+    if (jx >= 0 && jy >= 0 && jx < nc && jy < nc) {
+      // R_j entry (bx, by) sits at union position (shx + bx, shy + by)
       const int shx = 2 * (jx - rho) - ox0 + s, shy = 2 * (jy - rho) - oy0 + s;
-      const int bxl = max(0, -shx), bxh = min(rw - 1, zw - 1 - shx);
+      const int bxl = max(part * rw / P, -shx), bxh = min((part + 1) * rw / P - 1, zw - 1 - shx);
+      const int byl = max(0, -shy), byh = min(rw - 1, uy - 1 - shy);
+      const T* Rj = R + (jx * nc + jy);
       for (int bx = bxl; bx <= bxh; ++bx) {
         const T* Rr = Rj + (size_t)bx * rw * nc2;
-        const T* zr = zl + (shx + bx) * zw;
+        const T* zr = zu + (shx + bx) * uy + shy;
 #pragma unroll 7
-        for (int by = 0; by < rw; ++by) {
-          const T rv = Rr[by * nc2];
+        for (int by = byl; by <= byh; ++by) {
+          const T rv = Rr[(size_t)by * nc2];
 #pragma unroll
-          for (int m = 0; m < NS; ++m) {
-            const int zy = shy - 2 * m + by;
-            if (zy >= 0 && zy < zw) acc[m] += rv * zr[m * zw * zw + zy];
-          }
+          for (int m = 0; m < NS; ++m) acc[m] += rv * zr[m * mz + by];
         }
       }
     }
-    // stencil offset of j for row m: (ejx, ejy - m) when 0 <= ejy - m < Sc
+    // row m takes j at offset (ejx, ejy - m) when that offset is in the upper half
+    const int oyl = ejx > sc ? 0 : sc;
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
       const int oy = ejy - m;
-      if (oy >= 0 && oy < Sc) ol[(ejx * Sc + oy) * NS + m] = inside ? acc[m] : T(0);
+      if (oy >= oyl && oy < Sc) ol[(part * nup + ejx * Sc + oy - ho) * NS + m] = acc[m];
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < Sc * Sc * NS; e += blockDim.x) {
-    const int o = e / NS, m = e - o * NS;
-    Ac[(size_t)o * nc2 + cx * nc + cy0 + m] = ol[e];
+  // 4. stores
+  for (int e = threadIdx.x; e < nup * NS; e += blockDim.x) {
+    const int o = ho + e / NS, m = e - (e / NS) * NS;
+    T v = ol[e];
+    for (int pt = 1; pt < P; ++pt) v += ol[pt * nup * NS + e];
+    Ac[(size_t)o * nc2 + row0 + m] = v;
+    if (o != ho) {
+      const int ox = o / Sc, oy = o - ox * Sc;
+      const int jx = cx + ox - sc, jy = cy0 + m + oy - sc;
+      if (jx >= 0 && jy >= 0 && jx < nc && jy < nc) Ac[(size_t)(Sc * Sc - 1 - o) * nc2 + jx * nc + jy] = v;
+    }
   }
+  for (int e = threadIdx.x; e < ho * NS; e += blockDim.x) {
+    const int o = e / NS, m = e - (e / NS) * NS;
+    const int ox = o / Sc, oy = o - ox * Sc;
+    const int jx = cx + ox - sc, jy = cy0 + m + oy - sc;
+    if (!(jx >= 0 && jy >= 0 && jx < nc && jy < nc)) Ac[(size_t)o * nc2 + row0 + m] = T(0);
+  }
+}
+
+// LDS of a strip of NS rows
+static size_t strip_lds(const LevelGeom& L, const LevelGeom& C, int NS, size_t elem) {
+  const size_t zw = L.rw + 2 * L.s, Sc = 2 * C.s + 1;
+  const size_t ry = L.rw + 2 * (NS - 1), uy = zw + 2 * (NS - 1);
+  const int P = strip_parts((C.s + 1) * (2 * C.s + NS), kStripThreads);
+  return ((size_t)NS * (L.rw * ry + zw * uy) + (size_t)P * (Sc * Sc - (Sc * Sc - 1) / 2) * NS) * elem;
 }
 
 template <typename T>
@@ -1396,15 +1434,14 @@ void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T
                      hipStream_t st) {
   const int nc = L.nk / 2;
   const int zw = L.rw + 2 * L.s;
-  const int Sc = 2 * C.s + 1;
-  // strip height: the largest of 8, 4, 2 whose LDS staging fits 64 KB
-  const size_t per_row = (size_t)(L.rw * L.rw + zw * zw + Sc * Sc) * sizeof(T);
+  // strip height: the largest of 8, 4, 2 whose LDS staging fits 80 KB (two
+  // workgroups of 512 threads per compute unit)
   int NS = 8;
-  while (NS > 1 && (NS > nc || (size_t)NS * per_row > 65536)) NS /= 2;
+  while (NS > 1 && (NS > nc || strip_lds(L, C, NS, sizeof(T)) > 80 * 1024)) NS /= 2;
   // strips pay off only with enough workgroups to fill the GPU
   if (galerkin_strip_enabled() && NS >= 2 && nc * (nc / NS) >= 512) {
-    const size_t shm = (size_t)NS * per_row;
-    const dim3 grid(nc * (nc / NS)), block(256);
+    const size_t shm = strip_lds(L, C, NS, sizeof(T));
+    const dim3 grid(nc * (nc / NS)), block(kStripThreads);
     if (NS == 8)
       hipLaunchKernelGGL((k_galerkin_strip<T, 8>), grid, block, shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
     else if (NS == 4)

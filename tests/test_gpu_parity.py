@@ -61,6 +61,52 @@ def test_hierarchy_levels_match_oracle_fp64(q, rho, sigma):
     H.close()
 
 
+def test_galerkin_strips_match_oracle_fp64(monkeypatch):
+    """q = 7 is the smallest size at which the Galerkin product runs on strips
+    of coarse rows (level 7 -> 6: 64 x 8 strips); every level operator against
+    the oracle's R A R^T hierarchy."""
+    q, rho = 7, 3
+    _print_case(test="galerkin_strips_oracle", q=q, rho=rho)
+    monkeypatch.setenv("GBL_GALERKIN_STRIP", "1")
+    pr = S.rough_problem(q, 2.0, 27)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    ref = G.localized_hierarchy(fe.A, tree, rho)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision="fp64")
+    torch.cuda.synchronize()
+    for k in range(q - 1, 0, -1):
+        A_gpu = stencil_to_matrix(H.level(k)["A"].cpu().numpy(), q, k, tree.size(k))
+        A_ref = ref.levels[k].A
+        err = abs(A_gpu - A_ref).max() / abs(A_ref).max()
+        print(f"level {k} A err {err:.3e}")
+        assert err < 1e-10, (k, err)
+    H.close()
+
+
+@pytest.mark.parametrize("prec,tol,tol_deep", [("fp64", 1e-12, 1e-12), ("mixed", 1e-6, 1e-3)])
+def test_galerkin_strips_match_row_kernel(monkeypatch, prec, tol, tol_deep):
+    """At q = 8 the strip kernel covers levels 8 -> 7 and 7 -> 6; both kernels
+    compute the same coarse operators up to the summation order.  Level 7 comes
+    from identical inputs (FP32: a few units of roundoff); every coarser level
+    also goes through the patch solves of the level above, which amplify that
+    difference by their condition numbers (FP32: up to ~1e3, the bound of the
+    patch-kernel test)."""
+    q, rho = 8, 3
+    pr = S.rough_problem(q, 2.0, 28)
+    ops = {}
+    for strip in ("0", "1"):
+        _print_case(test="galerkin_strips_rows", q=q, prec=prec, strip=strip)
+        monkeypatch.setenv("GBL_GALERKIN_STRIP", strip)
+        H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec)
+        torch.cuda.synchronize()
+        ops[strip] = [H.level(k)["A"].cpu().numpy().astype(np.float64) for k in range(q - 1, 0, -1)]
+        H.close()
+    for k, (a0, a1) in zip(range(q - 1, 0, -1), zip(ops["0"], ops["1"])):
+        err = abs(a1 - a0).max() / abs(a0).max()
+        print(f"level {k} strip vs rows {err:.3e}")
+        assert err < (tol if k == q - 1 else tol_deep), (k, err)
+
+
 @pytest.mark.parametrize("kernel", ["mfma", "registers"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
 def test_patch_kernels_match_oracle(monkeypatch, kernel, prec, tol):
