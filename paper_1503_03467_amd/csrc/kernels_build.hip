@@ -1200,7 +1200,7 @@ void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, i
 // A^(k-1)_{i,i'} = z . R_{i'} of the coarse stencil.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_galerkin(const T* __restrict__ A, const T* __restrict__ R,
+__global__ __launch_bounds__(1024) void k_galerkin(const T* __restrict__ A, const T* __restrict__ R,
                                                   T* __restrict__ Ac, int nk, int s, int rho, int sc) {
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -1436,10 +1436,10 @@ void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T
   const int zw = L.rw + 2 * L.s;
   // strip height: the largest of 8, 4, 2 whose LDS staging fits 80 KB (two
   // workgroups of 512 threads per compute unit)
+  // and that still gives 512 workgroups (strips pay off only when they fill the GPU)
   int NS = 8;
-  while (NS > 1 && (NS > nc || strip_lds(L, C, NS, sizeof(T)) > 80 * 1024)) NS /= 2;
-  // strips pay off only with enough workgroups to fill the GPU
-  if (galerkin_strip_enabled() && NS >= 2 && nc * (nc / NS) >= 512) {
+  while (NS > 1 && (NS > nc || strip_lds(L, C, NS, sizeof(T)) > 80 * 1024 || nc * (nc / NS) < 512)) NS /= 2;
+  if (galerkin_strip_enabled() && NS >= 2) {
     const size_t shm = strip_lds(L, C, NS, sizeof(T));
     const dim3 grid(nc * (nc / NS)), block(kStripThreads);
     if (NS == 8)
@@ -1450,8 +1450,10 @@ void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T
       hipLaunchKernelGGL((k_galerkin_strip<T, 2>), grid, block, shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
     return;
   }
+  // few rows: more threads per row (the small levels are latency-bound)
   const size_t shm = (size_t)(L.rw * L.rw + zw * zw) * sizeof(T);
-  hipLaunchKernelGGL(k_galerkin<T>, dim3(nc * nc), dim3(256), shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
+  const int threads = nc * nc <= 256 ? 1024 : 256;
+  hipLaunchKernelGGL(k_galerkin<T>, dim3(nc * nc), dim3(threads), shm, st, A, R, Ac, L.nk, L.s, L.rho, C.s);
 }
 
 // ---------------------------------------------------------------------------

@@ -63,8 +63,9 @@ def test_hierarchy_levels_match_oracle_fp64(q, rho, sigma):
 
 def test_galerkin_strips_match_oracle_fp64(monkeypatch):
     """q = 7 is the smallest size at which the Galerkin product runs on strips
-    of coarse rows (level 7 -> 6: 64 x 8 strips); every level operator against
-    the oracle's R A R^T hierarchy."""
+    of coarse rows (level 7 -> 6: 64 x 8 strips of 8 rows; 6 -> 5: 32 x 16
+    strips of 2 rows); every level operator against the oracle's R A R^T
+    hierarchy."""
     q, rho = 7, 3
     _print_case(test="galerkin_strips_oracle", q=q, rho=rho)
     monkeypatch.setenv("GBL_GALERKIN_STRIP", "1")
@@ -85,7 +86,7 @@ def test_galerkin_strips_match_oracle_fp64(monkeypatch):
 
 @pytest.mark.parametrize("prec,tol,tol_deep", [("fp64", 1e-12, 1e-12), ("mixed", 1e-6, 1e-3)])
 def test_galerkin_strips_match_row_kernel(monkeypatch, prec, tol, tol_deep):
-    """At q = 8 the strip kernel covers levels 8 -> 7 and 7 -> 6; both kernels
+    """At q = 8 the strip kernel covers levels 8 -> 7, 7 -> 6 and 6 -> 5; both kernels
     compute the same coarse operators up to the summation order.  Level 7 comes
     from identical inputs (FP32: a few units of roundoff); every coarser level
     also goes through the patch solves of the level above, which amplify that
