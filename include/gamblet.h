@@ -125,8 +125,8 @@ typedef struct gbl_ctx gbl_ctx;
 int gbl_version(void);
 
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
- * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 4,
- * kappa 200, kappa_coarse 30, max_rhs 1. */
+ * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
+ * kappa 200, kappa_coarse 10, max_rhs 1. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

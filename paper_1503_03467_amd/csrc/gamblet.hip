@@ -776,10 +776,10 @@ int gbl_default_opts(gbl_opts* o) {
   o->max_outer = 100;
   o->inner_iters = 16;
   o->max_rhs = 1;
-  o->inner_iters_coarse = 4;
+  o->inner_iters_coarse = 2;
   o->inner_kind = GBL_INNER_CHEBYSHEV;
   o->kappa = 200.0;
-  o->kappa_coarse = 30.0;
+  o->kappa_coarse = 10.0;
   return GBL_OK;
 }
 

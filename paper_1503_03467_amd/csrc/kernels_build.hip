@@ -846,36 +846,55 @@ struct WaveOps<double> {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
   }
 };
-// lane i <- lane i + 1 (zero into lane 63)
+// 1 / sqrt(pivot) of a band Cholesky step: the hardware reciprocal square root
+// in FP32 (about one unit of roundoff, well inside the accuracy the conditioning
+// of the FP32 patch systems allows), correctly rounded operations in FP64
 template <typename T>
-__device__ __forceinline__ T wave_down1(T v) { return WaveOps<T>::template dpp<0x130, 0xf, true>(v); }
-// lane i <- lane i - 1 (zero into lane 0)
+__device__ __forceinline__ T pivot_rsqrt(T x);
+template <>
+__device__ __forceinline__ float pivot_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double pivot_rsqrt<double>(double x) { return 1.0 / my_sqrt<double>(x); }
+
+// four consecutive values from 16-byte aligned LDS
 template <typename T>
-__device__ __forceinline__ T wave_up1(T v) { return WaveOps<T>::template dpp<0x138, 0xf, true>(v); }
-// sum over the 64 lanes (quad permutations, row mirrors, then row broadcasts)
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  v += WaveOps<T>::template dpp<0xB1, 0xf, true>(v);
-  v += WaveOps<T>::template dpp<0x4E, 0xf, true>(v);
-  v += WaveOps<T>::template dpp<0x141, 0xf, true>(v);
-  v += WaveOps<T>::template dpp<0x140, 0xf, true>(v);
-  v += WaveOps<T>::template dpp<0x142, 0xa, false>(v);
-  v += WaveOps<T>::template dpp<0x143, 0xc, false>(v);
-  return WaveOps<T>::lane(v, 63);
+__device__ __forceinline__ void load4_lds(const T* src, T* dst);
+template <>
+__device__ __forceinline__ void load4_lds<float>(const float* src, float* dst) {
+  const float4 v = *reinterpret_cast<const float4*>(__builtin_assume_aligned(src, 16));
+  dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4_lds<double>(const double* src, double* dst) {
+  const double2 a = *reinterpret_cast<const double2*>(__builtin_assume_aligned(src, 16));
+  const double2 b = *reinterpret_cast<const double2*>(__builtin_assume_aligned(src + 2, 16));
+  dst[0] = a.x; dst[1] = a.y; dst[2] = b.x; dst[3] = b.y;
 }
 
+// Band Cholesky of the finest-level patch systems, two patches per wavefront:
+// lane 32 h + d (d < 32) holds subdiagonal d of patch h in registers (the
+// half-bandwidth is below 32 for rho <= 3).  The current column of L is
+// passed through a small LDS buffer, so lane d reads L[j+e+d][j] and the
+// broadcast L[j+e][j] at immediate offsets (several columns per read): a
+// trailing-update step is one FMA and a fraction of two LDS reads, with no
+// lane shifts or lane reads.  Forward substitution runs with the
+// factorisation; the back substitution sums each half with row-local DPP.
 template <typename T, int RHO>
-__global__ __launch_bounds__(64) void k_patch_band_reg(const T* __restrict__ A, const T* __restrict__ B,
-                                                       T* __restrict__ R, int nk, int s, int* __restrict__ status) {
+__global__ __launch_bounds__(64) void k_patch_band_pair(const T* __restrict__ A, const T* __restrict__ B,
+                                                        T* __restrict__ R, int nk, int s, int* __restrict__ status) {
   constexpr int PMAX = 3 * (2 * RHO + 1) * (2 * RHO + 1);
-  constexpr int BWM = 3 * (2 * RHO + 2) + 2;   // largest half-bandwidth, < 64
+  constexpr int BWM = 3 * (2 * RHO + 2) + 2;   // largest half-bandwidth
+  static_assert(BWM < 32, "two patches per wavefront need a half-bandwidth below 32");
   constexpr int TT = 3;                        // parent stencil width at the finest level (t = 1)
-  __shared__ T sb[PMAX + 64];                  // b, then z, then x (zero beyond p)
-  __shared__ T sc[PMAX];
-  __shared__ int rowinfo[PMAX];
+  __shared__ T sb[2][PMAX + 32];               // b, then z, then x (zero beyond p)
+  __shared__ T sc[2][PMAX];
+  __shared__ T ld[2][PMAX];                    // diagonal of L
+  __shared__ int rowinfo[2][PMAX];
+  __shared__ __align__(16) T colb[2][2][64];   // [step parity][patch]: column of L, zero from entry 32 on
   const int rho = RHO;
+  const int lane = threadIdx.x, h = lane >> 5, d = lane & 31;
   const int nc = nk / 2;
-  const int ci = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int ci = 2 * xcd_remap((int)blockIdx.x, (int)gridDim.x) + h;
   const int cx = ci / nc, cy = ci % nc;
   const int x0 = max(0, cx - rho), x1 = min(nc - 1, cx + rho);
   const int y0 = max(0, cy - rho), y1 = min(nc - 1, cy + rho);
@@ -883,18 +902,17 @@ __global__ __launch_bounds__(64) void k_patch_band_reg(const T* __restrict__ A, 
   const int npar = (x1 - x0 + 1) * wy;
   const int p = 3 * npar;
   const int bw = 3 * (wy + 1) + 2;
-  const int lane = threadIdx.x;
   const int S = 2 * s + 1;
   const int ti = parent_type(true, cx, cy);
 
-  for (int r = lane; r < PMAX + 64; r += 64) {
+  for (int r = d; r < PMAX + 32; r += 32) {
     T scale = T(1), rv = T(0);
     if (r < p) {
       const int lp = r / 3, tt = r - 3 * lp;
       const int px = x0 + lp / wy, py = y0 + lp % wy;
-      rowinfo[r] = (px << 20) | (py << 8) | tt;
-      const T d = B[b_index(TT + 1, tt * 4, px * nc + py, TT)];
-      if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
+      rowinfo[h][r] = (px << 20) | (py << 8) | tt;
+      const T dd0 = B[b_index(TT + 1, tt * 4, px * nc + py, TT)];
+      if (dd0 > T(0)) scale = T(1) / my_sqrt<T>(dd0);
       else atomicOr(status, kBadPivot);
       const int tp = parent_type(true, px, py);
       if (abs(px - cx) <= 1 && abs(py - cy) <= 1 && !is_pad_row(tp, tt)) {
@@ -917,87 +935,98 @@ __global__ __launch_bounds__(64) void k_patch_band_reg(const T* __restrict__ A, 
         rv = T(-acc);
       }
     }
-    if (r < PMAX) sc[r] = scale;
-    sb[r] = rv * scale;
+    if (r < PMAX) sc[h][r] = scale;
+    sb[h][r] = rv * scale;
   }
+  colb[0][h][d] = T(0);
+  colb[0][h][d + 32] = T(0);
+  colb[1][h][d] = T(0);
+  colb[1][h][d + 32] = T(0);
   __syncthreads();
 
-  // this lane's subdiagonal d = lane: M[c + d][c]
+  // this lane's subdiagonal d: M[c + d][c] (scaled to unit diagonal)
   T dg[PMAX];
 #pragma clang loop unroll(full)
   for (int c = 0; c < PMAX; ++c) {
-    const int r = c + lane;
+    const int r = c + d;
     T v = T(0);
-    if (lane <= bw && r < p) {
-      const int ri = rowinfo[r], rj = rowinfo[c];
+    if (d <= bw && r < p) {
+      const int ri = rowinfo[h][r], rj = rowinfo[h][c];
       const int rx = ri >> 20, ry = (ri >> 8) & 0xfff, trr = ri & 0xff;
       const int qx = rj >> 20, qy = (rj >> 8) & 0xfff, tcc = rj & 0xff;
       const int ox = qx - rx + 1, oy = qy - ry + 1;
       if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
-        v = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)] * sc[r] * sc[c];
+        v = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)] * sc[h][r] * sc[h][c];
     }
     dg[c] = v;
   }
 
-  // factorisation with the forward substitution: bs holds b_{j + lane}
   int bad = 0, reg = 0;
-  T bs = sb[lane];
 #pragma clang loop unroll(full)
   for (int j = 0; j < PMAX; ++j) {
-    if (j < p) {
-      const T piv = patch_pivot<T>(WaveOps<T>::lane(dg[j], 0), bad, reg);
-      const T sq = my_sqrt<T>(piv);
-      const T inv = T(1) / sq;
-      const T col = (lane == 0) ? sq : dg[j] * inv;
+    T* cb = &colb[j & 1][h][0];
+    const T pa = WaveOps<T>::lane(dg[j], 0), pb = WaveOps<T>::lane(dg[j], 32);
+    const bool act = j < p;
+    T col = T(0), inv = T(0);
+    if (act) {
+      const T piv = patch_pivot<T>(h ? pb : pa, bad, reg);
+      inv = pivot_rsqrt<T>(piv);
+      const T sq = piv * inv;
+      col = (d == 0) ? sq : (d <= bw ? dg[j] * inv : T(0));
+      if (d == 0) ld[h][j] = sq;
+      cb[d] = col;
+    }
+    __syncthreads();
+    if (act) {
       dg[j] = col;
-      const T zj = WaveOps<T>::lane(bs, 0) * inv;
-      if (lane == 0) sb[j] = zj;
-      bs = wave_down1<T>(bs - col * zj);
-      const T nb = sb[j + 64];   // b_{j+64}, not yet overwritten
-      if (lane == 63) bs = nb;
-      T cs = col;
+      const T zj = sb[h][j] * inv;
+      if (d == 0) sb[h][j] = zj;
+      else if (d <= bw) sb[h][j + d] -= col * zj;
+      // the broadcast entries L[j+e][j], four per 16-byte read
+      T ce[(BWM + 4) & ~3];
+#pragma clang loop unroll(full)
+      for (int e4 = 0; e4 < ((BWM + 4) & ~3); e4 += 4) load4_lds<T>(cb + e4, ce + e4);
 #pragma clang loop unroll(full)
       for (int e = 1; e <= BWM; ++e) {
-        if (j + e < PMAX) {
-          cs = wave_down1<T>(cs);                    // lane d: L[j + e + d][j]
-          const T ce = WaveOps<T>::lane(col, e);     // L[j + e][j]
-          dg[j + e] -= cs * ce;
-        }
+        if (j + e < PMAX) dg[j + e] -= cb[d + e] * ce[e];
       }
     }
   }
-  // back substitution L^T x = z: xs holds x_{c + lane} (lane >= 1)
-  T xs = T(0);
+  if (d == 0 && bad) atomicOr(status, kBadPivot);
+  if (d == 0 && reg) atomicOr(status, kRegularizedPivot);
+  __syncthreads();
+  // back substitution L^T x = z: the sum over the half's lanes d >= 1 ends in
+  // lanes 16..31 (patch 0) and 48..63 (patch 1)
 #pragma clang loop unroll(full)
   for (int c = PMAX - 1; c >= 0; --c) {
-    if (c < p) {
-      const T sum = wave_sum<T>(lane >= 1 ? dg[c] * xs : T(0));
-      const T xc = (sb[c] - sum) / WaveOps<T>::lane(dg[c], 0);
-      if (lane == 0) sb[c] = xc;
-      xs = wave_up1<T>(lane == 0 ? xc : xs);
-    }
+    const bool act = c < p;
+    T t = (act && d >= 1) ? dg[c] * sb[h][c + d] : T(0);
+    t += WaveOps<T>::template dpp<0xB1, 0xf, true>(t);
+    t += WaveOps<T>::template dpp<0x4E, 0xf, true>(t);
+    t += WaveOps<T>::template dpp<0x141, 0xf, true>(t);
+    t += WaveOps<T>::template dpp<0x140, 0xf, true>(t);
+    t += WaveOps<T>::template dpp<0x142, 0xa, false>(t);
+    if (act && d == 31) sb[h][c] = (sb[h][c] - t) / ld[h][c];
+    __syncthreads();
   }
-  if (lane == 0 && bad) atomicOr(status, kBadPivot);
-  if (lane == 0 && reg) atomicOr(status, kRegularizedPivot);
-  __syncthreads();
-  for (int r = lane; r < p; r += 64) sb[r] *= sc[r];
+  for (int r = d; r < p; r += 32) sb[h][r] *= sc[h][r];
   __syncthreads();
 
   const int rw = 2 * (2 * rho + 1);
   const int ox0 = 2 * (cx - rho), oy0 = 2 * (cy - rho);
   const size_t nc2 = (size_t)nc * nc;
   T* Ri = R + ci;
-  for (int e = lane; e < rw * rw; e += 64) {
+  for (int e = d; e < rw * rw; e += 32) {
     const int bx = e / rw, by = e % rw;
     const int fx = ox0 + bx, fy = oy0 + by;
     double v = 0.0;
     if (fx >= 0 && fy >= 0 && fx < nk && fy < nk) {
       const int px = fx >> 1, py = fy >> 1;
-      const int d = 2 * (fx & 1) + (fy & 1);
+      const int dd = 2 * (fx & 1) + (fy & 1);
       const int tp = parent_type(true, px, py);
-      if (px == cx && py == cy) v = pibar(tp, d);
+      if (px == cx && py == cy) v = pibar(tp, dd);
       const int lp = (px - x0) * wy + (py - y0);
-      for (int tt = 0; tt < 3; ++tt) v += (double)sb[3 * lp + tt] * wcoef(tp, tt, d);
+      for (int tt = 0; tt < 3; ++tt) v += (double)sb[h][3 * lp + tt] * wcoef(tp, tt, dd);
     }
     Ri[(size_t)e * nc2] = T(v);
   }
@@ -1179,10 +1208,11 @@ template <typename T>
 void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st) {
   const int nc = L.nk / 2;
   if (band_reg_enabled() && L.rho <= 3) {
-    const dim3 grid(nc * nc), block(64);
-    if (L.rho == 3) hipLaunchKernelGGL((k_patch_band_reg<T, 3>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
-    else if (L.rho == 2) hipLaunchKernelGGL((k_patch_band_reg<T, 2>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
-    else hipLaunchKernelGGL((k_patch_band_reg<T, 1>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    // two patches per wavefront (nc * nc is even)
+    const dim3 grid(nc * nc / 2), block(64);
+    if (L.rho == 3) hipLaunchKernelGGL((k_patch_band_pair<T, 3>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    else if (L.rho == 2) hipLaunchKernelGGL((k_patch_band_pair<T, 2>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
+    else hipLaunchKernelGGL((k_patch_band_pair<T, 1>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
     return;
   }
   const int pmax = 3 * (2 * L.rho + 1) * (2 * L.rho + 1);

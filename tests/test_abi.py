@@ -96,6 +96,6 @@ def test_default_options():
     P, _ = _lib()
     o = P.make_opts()
     assert (o.rho, o.precision, o.max_outer, o.inner_kind) == (3, 1, 100, 0)
-    assert (o.inner_iters, o.inner_iters_coarse, o.kappa, o.kappa_coarse) == (16, 4, 200.0, 30.0)
+    assert (o.inner_iters, o.inner_iters_coarse, o.kappa, o.kappa_coarse) == (16, 2, 200.0, 10.0)
     cg = P.make_opts(inner="cg", inner_iters=40)
     assert cg.inner_kind == 1 and P.workspace_bytes(6, cg) > 0   # CG budgets are not capped at 32
