@@ -502,6 +502,16 @@ struct Mfma<double> {
   }
 };
 
+// 1 / sqrt(pivot) of a Cholesky step: the hardware reciprocal square root
+// in FP32 (about one unit of roundoff, well inside the accuracy the conditioning
+// of the FP32 patch systems allows), correctly rounded operations in FP64
+template <typename T>
+__device__ __forceinline__ T pivot_rsqrt(T x);
+template <>
+__device__ __forceinline__ float pivot_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double pivot_rsqrt<double>(double x) { return 1.0 / my_sqrt<double>(x); }
+
 template <typename T, int NT>
 struct CholLds {
   T panel[NT][16][17];   // column-P tiles; rows of L_IP after the solve
@@ -644,6 +654,7 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[c] = sm.panel[P][lc][c];
       int badl = 0, regl = 0;
+      T rinv = T(1);   // 1 / L_PP[lc][lc]
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         T dk = Mfma<T>::lane_value(a[k], k);
@@ -652,8 +663,9 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
         } else {
           dk = patch_pivot<T>(dk, badl, regl);
         }
-        const T sk = my_sqrt<T>(dk);
-        const T rk = T(1) / sk;
+        const T rk = pivot_rsqrt<T>(dk);
+        const T sk = dk * rk;
+        if (lc == k) rinv = rk;
         a[k] = (lc > k) ? a[k] * rk : ((lc == k) ? sk : a[k]);
 #pragma unroll
         for (int c = k + 1; c < 16; ++c) a[c] -= a[k] * Mfma<T>::lane_value(a[k], c);
@@ -661,9 +673,7 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
       if (l < 16) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) sm.lpp[lc][c] = (c <= lc) ? a[c] : T(0);
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c == lc) sm.dinv[lc] = T(1) / a[c];
+        sm.dinv[lc] = rinv;
       }
       if (l == 0 && (badl | regl)) sm.bad |= badl | (regl << 1);
     }
@@ -846,16 +856,6 @@ struct WaveOps<double> {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
   }
 };
-// 1 / sqrt(pivot) of a band Cholesky step: the hardware reciprocal square root
-// in FP32 (about one unit of roundoff, well inside the accuracy the conditioning
-// of the FP32 patch systems allows), correctly rounded operations in FP64
-template <typename T>
-__device__ __forceinline__ T pivot_rsqrt(T x);
-template <>
-__device__ __forceinline__ float pivot_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <>
-__device__ __forceinline__ double pivot_rsqrt<double>(double x) { return 1.0 / my_sqrt<double>(x); }
-
 // four consecutive values from 16-byte aligned LDS
 template <typename T>
 __device__ __forceinline__ void load4_lds(const T* src, T* dst);
