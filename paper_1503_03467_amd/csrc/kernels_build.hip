@@ -69,7 +69,9 @@ void launch_assemble_fine(const double* a, T* A, int n, int* status, hipStream_t
 // parent p couples subband row (p, i) to (p + o - t, j); block-interleaved
 // layout, see b_index), plus the inverse of every 3x3 diagonal block
 // (block-Jacobi preconditioner of the subband CG).  One thread per
-// (parent, neighbour parent) pair.
+// (parent, neighbour parent) pair; the 64 lanes of a wavefront take 64
+// consecutive parents and one neighbour offset, so each store of B (and each
+// read of a stencil plane of A) covers consecutive words.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T a_entry(const T* __restrict__ A, int nk, int s, int cx, int cy, int dx,
@@ -89,9 +91,10 @@ __global__ void k_subband_operator(const T* __restrict__ A, T* __restrict__ B, T
   const int np = nk / 2;
   const int TT = 2 * t + 1;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= (long)np * np * TT * TT) return;
-  const int o = (int)(id % (TT * TT));
-  const int p = (int)(id / (TT * TT));
+  const long g = id >> 6;   // (group of 64 parents, offset)
+  const int o = (int)(g % (TT * TT));
+  const int p = (int)((g / (TT * TT)) * 64 + (id & 63));
+  if (p >= np * np) return;
   const int px = p / np, py = p % np;
   const int ox = o / TT, oy = o % TT;
   const int qx = px + ox - t, qy = py + oy - t;
@@ -155,7 +158,7 @@ template <typename T>
 void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool fine, hipStream_t st) {
   const int np = L.nk / 2;
   const int TT = 2 * L.t + 1;
-  const long tot = (long)np * np * TT * TT;
+  const long tot = (long)((np * np + 63) / 64) * 64 * TT * TT;   // whole groups of 64 parents
   hipLaunchKernelGGL(k_subband_operator<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, B,
                      BJ, L.nk, L.s, L.t, fine ? 1 : 0);
 }
@@ -1588,40 +1591,55 @@ __device__ __forceinline__ void load_linv(const T* __restrict__ Linv, size_t np2
 }
 
 template <typename T>
-__global__ void k_gershgorin(const T* __restrict__ B, const T* __restrict__ Linv, int np, int t,
-                             unsigned* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np * np) return;
+__global__ __launch_bounds__(1024) void k_gershgorin(const T* __restrict__ B, const T* __restrict__ Linv, int np,
+                                                     int t, unsigned* __restrict__ out) {
+  // 64 consecutive parents per workgroup, one per lane; wavefront w sums the
+  // stencil rows ox = w, w + nw, ... and the row sums are added in LDS
+  __shared__ T red[3][16][64];
   const int TT = 2 * t + 1;
   const size_t np2 = (size_t)np * np;
-  const int px = p / np, py = p % np;
-  T Lp[3][3];
-  load_linv(Linv, np2, p, Lp);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  const bool live = p < np * np;
   T rs[3] = {T(0), T(0), T(0)};
-  for (int ox = 0; ox < TT; ++ox) {
-    const int qx = px + ox - t;
-    if (qx < 0 || qx >= np) continue;
-    for (int oy = 0; oy < TT; ++oy) {
-      const int qy = py + oy - t;
-      if (qy < 0 || qy >= np) continue;
-      T Bq[3][3], Lq[3][3];
+  if (live) {
+    const int px = p / np, py = p % np;
+    T Lp[3][3];
+    load_linv(Linv, np2, p, Lp);
+    for (int ox = wv; ox < TT; ox += nw) {
+      const int qx = px + ox - t;
+      if (qx < 0 || qx >= np) continue;
+      for (int oy = 0; oy < TT; ++oy) {
+        const int qy = py + oy - t;
+        if (qy < 0 || qy >= np) continue;
+        T Bq[3][3], Lq[3][3];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) Bq[e / 3][e % 3] = B[b_index(ox * TT + oy, e, p, TT)];
-      load_linv(Linv, np2, qx * np + qy, Lq);
-      // C = Lp Bq Lq^T
-      T M1[3][3];
+        for (int e = 0; e < 9; ++e) Bq[e / 3][e % 3] = B[b_index(ox * TT + oy, e, p, TT)];
+        load_linv(Linv, np2, qx * np + qy, Lq);
+        // C = Lp Bq Lq^T
+        T M1[3][3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) M1[i][j] = Lp[i][0] * Bq[0][j] + Lp[i][1] * Bq[1][j] + Lp[i][2] * Bq[2][j];
+          for (int j = 0; j < 3; ++j) M1[i][j] = Lp[i][0] * Bq[0][j] + Lp[i][1] * Bq[1][j] + Lp[i][2] * Bq[2][j];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) rs[i] += fabs(M1[i][0] * Lq[j][0] + M1[i][1] * Lq[j][1] + M1[i][2] * Lq[j][2]);
+          for (int j = 0; j < 3; ++j) rs[i] += fabs(M1[i][0] * Lq[j][0] + M1[i][1] * Lq[j][1] + M1[i][2] * Lq[j][2]);
+      }
     }
   }
-  const float g = (float)fmax(rs[0], fmax(rs[1], rs[2]));
-  if (g > 0.0f) atomicMax(out, __float_as_uint(g));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) red[i][wv][lane] = rs[i];
+  __syncthreads();
+  if (wv == 0 && live) {
+    T s[3] = {T(0), T(0), T(0)};
+    for (int w = 0; w < nw; ++w)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) s[i] += red[i][w][lane];
+    const float g = (float)fmax(s[0], fmax(s[1], s[2]));
+    if (g > 0.0f) atomicMax(out, __float_as_uint(g));
+  }
 }
 
 template <typename T>
@@ -1629,7 +1647,9 @@ void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out
   const int np = L.nk / 2;
   const dim3 grid((np * np + 255) / 256), block(256);
   hipLaunchKernelGGL(k_chol3_inv<T>, grid, block, 0, st, B, np, L.t, scratch);
-  hipLaunchKernelGGL(k_gershgorin<T>, grid, block, 0, st, B, scratch, np, L.t, out);
+  const int TT = 2 * L.t + 1;
+  hipLaunchKernelGGL(k_gershgorin<T>, dim3((np * np + 63) / 64), dim3(64 * (TT < 16 ? TT : 16)), 0, st, B, scratch,
+                     np, L.t, out);
 }
 
 #define GBL_INST(T)                                                                                   \
