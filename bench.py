@@ -201,12 +201,16 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
+    marks = [t0]
     for _ in range(args.steps):
         H, u, info = step(args.precision)
         infos.append(info)
         H.close()
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print("# step wall times (ms, host clock; a solve ends with a host read of its status): "
+          + " ".join("%.3f" % ((b - a) * 1e3) for a, b in zip(marks, marks[1:])), file=sys.stderr, flush=True)
     P.profile_enable(None)
     dom_ms, dom_launches = P.profile_read()[dominant]
     ms_per_step = (t1 - t0) * 1e3 / args.steps

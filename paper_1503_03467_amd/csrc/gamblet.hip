@@ -262,6 +262,7 @@ struct gbl_ctx {
   FineCG<double> fcgd;
   hipStream_t side = nullptr;           // second stream: coarser subband CG runs beside the finest
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int device = -1;                      // device whose streams and events these are
   // One outer iteration recorded as a graph (captured on its own stream, so
   // that the caller may pass the null stream) and replayed per iteration.
   hipStream_t cap = nullptr;
@@ -295,16 +296,75 @@ int fail(gbl_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail((ctx), GBL_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-void release(gbl_ctx* c) {
-  if (c->side) {
-    hipStreamSynchronize(c->side);
-    hipStreamDestroy(c->side);
+// The streams, events and pinned host words of a context.  Creating and
+// destroying them costs several hundred microseconds of host time, so a
+// freed context leaves them, per device, for the next one.
+struct CtxResources {
+  int device = -1;
+  hipStream_t side = nullptr, cap = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double* host = nullptr;
+};
+constexpr size_t kHostWords = kNumOuterScalars + 4 + (kMaxChunk > kMaxLevels ? kMaxChunk : kMaxLevels);
+constexpr size_t kMaxPooledResources = 64;
+std::mutex g_res_mu;
+std::vector<CtxResources> g_res_pool;
+
+void destroy_resources(CtxResources& r) {
+  if (r.side) hipStreamDestroy(r.side);
+  if (r.cap) hipStreamDestroy(r.cap);
+  if (r.ev_fork) hipEventDestroy(r.ev_fork);
+  if (r.ev_join) hipEventDestroy(r.ev_join);
+  if (r.host) hipHostFree(r.host);
+  r = CtxResources{};
+}
+
+bool acquire_resources(CtxResources& r) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    for (size_t i = 0; i < g_res_pool.size(); ++i) {
+      if (g_res_pool[i].device == dev) {
+        r = g_res_pool[i];
+        g_res_pool[i] = g_res_pool.back();
+        g_res_pool.pop_back();
+        return true;
+      }
+    }
   }
+  r.device = dev;
+  if (hipHostMalloc(reinterpret_cast<void**>(&r.host), kHostWords * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&r.ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r.ev_join, hipEventDisableTiming) != hipSuccess) {
+    destroy_resources(r);
+    return false;
+  }
+  return true;
+}
+
+void release(gbl_ctx* c) {
+  // no work of this context may still run on the second stream
+  if (c->side) hipStreamSynchronize(c->side);
   if (c->iter_graph) hipGraphExecDestroy(c->iter_graph);
-  if (c->cap) hipStreamDestroy(c->cap);
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_join) hipEventDestroy(c->ev_join);
-  if (c->host) hipHostFree(c->host);
+  CtxResources r;
+  r.device = c->device;
+  r.side = c->side;
+  r.cap = c->cap;
+  r.ev_fork = c->ev_fork;
+  r.ev_join = c->ev_join;
+  r.host = c->host;
+  if (r.side && r.cap && r.ev_fork && r.ev_join && r.host) {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    if (g_res_pool.size() < kMaxPooledResources) {
+      g_res_pool.push_back(r);
+      r = CtxResources{};
+    }
+  }
+  destroy_resources(r);
   delete c;
 }
 
@@ -812,10 +872,18 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->ws = static_cast<char*>(ws_dev);
   c->ws_bytes = ws_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), (kNumOuterScalars + 4 + std::max(kMaxChunk, kMaxLevels)) * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return fail(nullptr, GBL_EHIP, "hipHostMalloc failed");
+  {
+    CtxResources r;
+    if (!acquire_resources(r)) {
+      delete c;
+      return fail(nullptr, GBL_EHIP, "stream, event or pinned host allocation failed");
+    }
+    c->device = r.device;
+    c->side = r.side;
+    c->cap = r.cap;
+    c->ev_fork = r.ev_fork;
+    c->ev_join = r.ev_join;
+    c->host = r.host;
   }
   auto bail = [&](int code) {
     g_last_error = c->err;
@@ -838,13 +906,6 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->cgd = make_cg_args<double>(c);
   c->fcgf = make_fine_cg<float>(c);
   c->fcgd = make_fine_cg<double>(c);
-  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-    c->err = "stream or event creation failed";
-    return bail(GBL_EHIP);
-  }
   st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
   if (st) return bail(st);
   unsigned* hbits = reinterpret_cast<unsigned*>(c->host + kNumOuterScalars + 4);
