@@ -859,21 +859,6 @@ struct WaveOps<double> {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
   }
 };
-// four consecutive values from 16-byte aligned LDS
-template <typename T>
-__device__ __forceinline__ void load4_lds(const T* src, T* dst);
-template <>
-__device__ __forceinline__ void load4_lds<float>(const float* src, float* dst) {
-  const float4 v = *reinterpret_cast<const float4*>(__builtin_assume_aligned(src, 16));
-  dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
-}
-template <>
-__device__ __forceinline__ void load4_lds<double>(const double* src, double* dst) {
-  const double2 a = *reinterpret_cast<const double2*>(__builtin_assume_aligned(src, 16));
-  const double2 b = *reinterpret_cast<const double2*>(__builtin_assume_aligned(src + 2, 16));
-  dst[0] = a.x; dst[1] = a.y; dst[2] = b.x; dst[3] = b.y;
-}
-
 // Band Cholesky of the finest-level patch systems, two patches per wavefront:
 // lane 32 h + d (d < 32) holds subdiagonal d of patch h in registers (the
 // half-bandwidth is below 32 for rho <= 3).  The current column of L is
@@ -883,7 +868,7 @@ __device__ __forceinline__ void load4_lds<double>(const double* src, double* dst
 // lane shifts or lane reads.  Forward substitution runs with the
 // factorisation; the back substitution sums each half with row-local DPP.
 template <typename T, int RHO>
-__global__ __launch_bounds__(64) void k_patch_band_pair(const T* __restrict__ A, const T* __restrict__ B,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_patch_band_pair(const T* __restrict__ A, const T* __restrict__ B,
                                                         T* __restrict__ R, int nk, int s, int* __restrict__ status) {
   constexpr int PMAX = 3 * (2 * RHO + 1) * (2 * RHO + 1);
   constexpr int BWM = 3 * (2 * RHO + 2) + 2;   // largest half-bandwidth
@@ -985,13 +970,9 @@ __global__ __launch_bounds__(64) void k_patch_band_pair(const T* __restrict__ A,
       const T zj = sb[h][j] * inv;
       if (d == 0) sb[h][j] = zj;
       else if (d <= bw) sb[h][j + d] -= col * zj;
-      // the broadcast entries L[j+e][j], four per 16-byte read
-      T ce[(BWM + 4) & ~3];
-#pragma clang loop unroll(full)
-      for (int e4 = 0; e4 < ((BWM + 4) & ~3); e4 += 4) load4_lds<T>(cb + e4, ce + e4);
 #pragma clang loop unroll(full)
       for (int e = 1; e <= BWM; ++e) {
-        if (j + e < PMAX) dg[j + e] -= cb[d + e] * ce[e];
+        if (j + e < PMAX) dg[j + e] -= cb[d + e] * cb[e];
       }
     }
   }
