@@ -182,17 +182,23 @@ def main():
         return H, u, info
 
     print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    # warm-up with every kernel class timed, to find the dominant one
+    # first warm-up step with every kernel class timed, to find the dominant one
+    # (timing the iteration classes launches the iterations kernel by kernel)
     P.profile_reset()
     P.profile_enable("all")
-    for _ in range(max(1, args.warmup)):
-        H, u, info = step(args.precision)
-        geo = level_geometry(H)
-        H.close()
+    H, u, info = step(args.precision)
+    geo = level_geometry(H)
+    H.close()
     torch.cuda.synchronize()
     prof_all = P.profile_read()
     P.profile_enable(None)
     P.profile_reset()
+    # the other warm-up steps as timed, so that the replayed iteration graph is
+    # set up before the timed region
+    for _ in range(max(1, args.warmup - 1)):
+        H, u, info = step(args.precision)
+        H.close()
+    torch.cuda.synchronize()
     dominant = max((k for k in prof_all if k in ROOFLINE_CLASSES), key=lambda k: prof_all[k][0])
 
     # timed region: only the dominant class is bracketed by events
@@ -253,7 +259,7 @@ def main():
     rel_err = float(np.linalg.norm(u_int - u_ref) / np.linalg.norm(u_ref))
     extras["rel_err_vs_oracle"] = rel_err
     extras["outer_iters"] = max(i.outer_iters for i in infos)
-    extras["profile_warmup_ms_per_step"] = {k: v[0] / max(1, args.warmup) for k, v in prof_all.items() if v[1]}
+    extras["profile_warmup_ms_per_step"] = {k: v[0] for k, v in prof_all.items() if v[1]}   # one profiled step
 
     if not args.no_extras:
         # plain FP64 GPU path at the same accuracy
