@@ -548,29 +548,6 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     hipEventRecord(c->ev_fork, st);
     hipStreamWaitEvent(cs, c->ev_fork, 0);
   }
-  // finest level: Chebyshev steps fused four per launch, or one CG iteration
-  // per launch (whose last step x += alpha p is applied inside the prolongation)
-  if (cheb) {
-    const int K = c->opts.inner_iters;
-    int fuse = 4;   // steps per launch (GBL_CHEB_FUSE = 1..4; the halo is 4 parents)
-    if (const char* e = getenv("GBL_CHEB_FUSE")) {
-      const int v = atoi(e);
-      if (v >= 1 && v <= 4) fuse = v;
-    }
-    int k0 = 0, rd = 0;
-    do {
-      const int ns = std::min(fuse, K - 1 - k0);
-      ProfScope ps(GBL_PROF_FINE_CG, st);
-      launch_fine_cheb<T>(F, c->cheb_fine, K, k0, ns, rd, st);
-      k0 += ns;
-      rd ^= 1;
-    } while (k0 < K - 1);
-  } else {
-    for (int it = 0; it < c->opts.inner_iters; ++it) {
-      ProfScope ps(GBL_PROF_FINE_CG, st);
-      launch_fine_cg<T>(F, it, st);
-    }
-  }
   const int K = c->opts.inner_iters_coarse;
   for (int k = q; k > kc; --k) {
     ProfScope ps(GBL_PROF_RESTRICT, cs);
@@ -615,6 +592,31 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   for (int k = kc + 1; k < q; ++k) {
     ProfScope ps(GBL_PROF_PROLONG, cs);
     launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, cs);
+  }
+  // finest level (enqueued after the coarser chain, the longer of the two
+  // branches, so that a replayed graph starts that chain first): Chebyshev
+  // steps fused four per launch, or one CG iteration per launch (whose last
+  // step x += alpha p is applied inside the prolongation)
+  if (cheb) {
+    const int K = c->opts.inner_iters;
+    int fuse = 4;   // steps per launch (GBL_CHEB_FUSE = 1..4; the halo is 4 parents)
+    if (const char* e = getenv("GBL_CHEB_FUSE")) {
+      const int v = atoi(e);
+      if (v >= 1 && v <= 4) fuse = v;
+    }
+    int k0 = 0, rd = 0;
+    do {
+      const int ns = std::min(fuse, K - 1 - k0);
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_fine_cheb<T>(F, c->cheb_fine, K, k0, ns, rd, st);
+      k0 += ns;
+      rd ^= 1;
+    } while (k0 < K - 1);
+  } else {
+    for (int it = 0; it < c->opts.inner_iters; ++it) {
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_fine_cg<T>(F, it, st);
+    }
   }
   if (c->side) {
     hipEventRecord(c->ev_join, cs);
