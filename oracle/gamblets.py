@@ -347,6 +347,85 @@ def subbands(h: Hierarchy, b: np.ndarray) -> list:
     return out
 
 
+# ----------------------------------------------------------------------------
+# Gamblet transform of a given vector and compression (the representation of
+# u in the basis psi^(1)_i / ||psi^(1)_i||_a, chi^(k)_j / ||chi^(k)_j||_a of
+# the discussion of Example 5.1 and Figures 10-11).
+# ----------------------------------------------------------------------------
+
+def gamblet_transform(h: Hierarchy, u: np.ndarray):
+    """Coefficients (U^(1), {k: w^(k)}) of a level-q vector u in the basis
+    {psi^(1)_i} + {chi^(k)_j, k = 2..q}.
+
+    The level-(k-1) measurement of a vector is the sum of its level-k
+    measurements over the children (R^(k-1,k) pi^(k-1,k)T = I for every
+    R = pibar + D W, since pibar pi^T = I and W pi^T = 0), so the level-(k-1)
+    coefficients are U^(k-1) = pi U^(k), and the detail U^(k) - R^T U^(k-1)
+    lies in the range of W^T: it is W^T w^(k) with w^(k) = (W W^T)^-1 W
+    (U^(k) - R^T U^(k-1)).  Telescoping the levels reproduces u through the
+    reconstruction of Theorem 4.15 (``inverse_transform``).
+    """
+    q = h.tree.q
+    Uk = np.asarray(u, dtype=np.float64)
+    w = {}
+    for k in range(q, 1, -1):
+        lv = h.levels[k]
+        Ukm1 = h.tree.pi(k) @ Uk
+        d = Uk - lv.R.T @ Ukm1
+        WWt = (lv.W @ lv.W.T).tocsc()
+        w[k] = spla.spsolve(WWt, lv.W @ d) if WWt.shape[0] else np.zeros(0)
+        Uk = Ukm1
+    return Uk, w
+
+
+def inverse_transform(h: Hierarchy, U1: np.ndarray, w: dict) -> np.ndarray:
+    """v^(1) = U^(1), v^(k) = R^(k,k-1) v^(k-1) + W^(k)T w^(k) (Theorem 4.15)."""
+    v = np.asarray(U1, dtype=np.float64)
+    for k in range(2, h.tree.q + 1):
+        lv = h.levels[k]
+        v = lv.R.T @ v + lv.W.T @ w[k]
+    return v
+
+
+def energy_scales(h: Hierarchy):
+    """||psi^(1)_i||_a = sqrt(A^(1)_ii) and ||chi^(k)_j||_a = sqrt(B^(k)_jj)
+    (chi^(k) = W^(k) psi^(k), so the Gram matrix of the chi^(k) is W A^(k) W^T)."""
+    def diag(M):
+        return M.diagonal() if sp.issparse(M) else np.diag(M)
+    s1 = np.sqrt(diag(h.levels[1].A))
+    sk = {k: np.sqrt(diag(h.levels[k].B)) for k in range(2, h.tree.q + 1)}
+    return s1, sk
+
+
+def normalized_coefficients(h: Hierarchy, u: np.ndarray):
+    """Coefficients of u on psi^(1)/||psi^(1)||_a and chi^(k)/||chi^(k)||_a."""
+    U1, w = gamblet_transform(h, u)
+    s1, sk = energy_scales(h)
+    return U1 * s1, {k: w[k] * sk[k] for k in w}
+
+
+def compress(c1: np.ndarray, ck: dict, keep: int):
+    """Keep the ``keep`` largest normalized coefficients (by magnitude, over all
+    levels) and set the others to zero; coefficients equal to the smallest kept
+    magnitude are kept as well."""
+    allc = np.concatenate([np.abs(c1)] + [np.abs(ck[k]) for k in sorted(ck)])
+    if keep <= 0:
+        thr = np.inf
+    elif keep >= allc.size:
+        thr = -np.inf
+    else:
+        thr = np.sort(allc)[::-1][keep - 1]
+    return (np.where(np.abs(c1) >= thr, c1, 0.0),
+            {k: np.where(np.abs(ck[k]) >= thr, ck[k], 0.0) for k in ck})
+
+
+def reconstruct_normalized(h: Hierarchy, c1: np.ndarray, ck: dict) -> np.ndarray:
+    """Level-q vector from normalized coefficients."""
+    s1, sk = energy_scales(h)
+    return inverse_transform(h, c1 / s1, {k: np.divide(ck[k], sk[k], out=np.zeros_like(ck[k]),
+                                                           where=sk[k] > 0) for k in ck})
+
+
 def refine_solve(h: Hierarchy, A: sp.spmatrix, b: np.ndarray, tol: float = 1e-10,
                  max_sweeps: int = 50):
     """Iterative refinement with the localized subband solve as approximate inverse.
