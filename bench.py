@@ -303,6 +303,39 @@ def main():
         torch.cuda.synchronize()
         extras["adjoint_grad_ms"] = (time.perf_counter() - tt) * 1e3 / nadj
         H.close()
+        # gamblet transform of a solution, compression by thresholding and the
+        # reconstruction (discussion of Example 5.1, Figures 10-11): the smooth
+        # source of the example on this grid, and the benchmark's white-noise source
+        print("# gamblet transform", file=sys.stderr, flush=True)
+        H, u, _ = step(args.precision)
+        us = H.solve(torch.as_tensor(S.smooth_cell_source(q), device=dev))
+        total = H.transform_size()
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / reps, out
+
+        tr = {"coefficients": total}
+        tr["transform_ms"], c = timed(lambda: H.transform(us))
+        tr["inverse_ms"], _ = timed(lambda: H.inverse_transform(c))
+        tr["compress_1pct_ms"], _ = timed(lambda: H.compress(c.clone(), total // 100))
+        errs = {}
+        for name, uu in (("smooth_source", us), ("white_noise_source", u)):
+            nrm = H.energy_norm(uu)
+            e = {}
+            for frac in (0.01, 0.05, 0.25):
+                cc = H.transform(uu)
+                H.compress(cc, int(round(frac * total)))
+                e[f"{frac:g}"] = H.energy_norm(uu - H.inverse_transform(cc)) / nrm
+            errs[name] = e
+        tr["energy_err_vs_kept_fraction"] = errs
+        extras["gamblet_transform"] = tr
+        H.close()
 
     cpu = None
     if not args.no_cpu_baseline:

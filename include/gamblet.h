@@ -209,6 +209,51 @@ int gbl_build_flags(const gbl_ctx* ctx, unsigned* flags);
 /* Describe level k (1 <= k <= q) of a built hierarchy.  EINVAL on a bad k. */
 int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);
 
+/* ---- Gamblet transform and compression ------------------------------------
+ * The representation of a level-q vector u in the basis of normalized
+ * gamblets psi^(1)_i / ||psi^(1)_i||_a and chi^(k)_j / ||chi^(k)_j||_a,
+ * k = 2..q, of the built (localized) hierarchy (discussion of Example 5.1 and
+ * Figures 10-11; chi^(k) = W^(k) psi^(k), psi^(k-1) = R^(k-1,k) psi^(k)).
+ * Level-(k-1) measurements are child sums of level-k ones (R pi^T = I for
+ * R = pibar + D W, Section 4.7), so U^(k-1) = pi U^(k) and
+ * w^(k) = W^(k) (U^(k) - R^T U^(k-1)); the coefficients are U^(1)_i
+ * sqrt(A^(1)_ii) and w^(k)_j sqrt(B^(k)_jj).  The inverse is the
+ * reconstruction of Theorem 4.15.  All arithmetic is FP64 (the operators are
+ * read in the hierarchy's precision).
+ *
+ * Coefficient layout (device, FP64, 4^q values, owned by the caller): level 1
+ * at offset 0 (4 values, slot x * 2 + y); level k >= 2 at offset 4^(k-1)
+ * (3 * 4^(k-1) values, entry t * 4^(k-1) + parent, parent = px * 2^(k-1) + py,
+ * t = 0..2 the subband index of the parent; entries of padding rows -- parents
+ * on the low edges of level q with fewer than four children -- are zero).
+ * u is nodal, [(2^q + 1)^2] FP64 on the device; boundary entries are ignored on
+ * input and written as zero on output.  Calls on one context must not overlap
+ * (they use its workspace). */
+
+/* Number of coefficients, 4^q.  EINVAL on NULL arguments. */
+int gbl_transform_size(const gbl_ctx* ctx, size_t* count);
+
+/* coef = normalized gamblet coefficients of u.  Asynchronous on stream.
+ * EINVAL on NULL arguments, EHIP on a launch failure. */
+int gbl_transform(gbl_ctx* ctx, const double* u_dev, double* coef_dev, void* stream);
+
+/* u = sum of the coefficients times the normalized gamblets (the inverse of
+ * gbl_transform up to rounding).  Asynchronous on stream.  Errors as above. */
+int gbl_inverse_transform(gbl_ctx* ctx, const double* coef_dev, double* u_dev, void* stream);
+
+/* Compression by thresholding (Figure 11): keep the keep largest |coef| over
+ * all levels and set the others to zero, in place; coefficients equal to the
+ * smallest kept magnitude are kept too, NaN entries are zeroed.  keep <= 0
+ * zeroes all, keep >= 4^q changes nothing.  threshold (host, may be NULL)
+ * receives the smallest kept magnitude (+inf for keep <= 0, 0 for keep >= 4^q);
+ * when it is given the call waits for the stream.  EINVAL on NULL ctx / coef. */
+int gbl_compress(gbl_ctx* ctx, double* coef_dev, long keep, double* threshold, void* stream);
+
+/* Energy norm sqrt(u^T A u) of a nodal u (boundary entries ignored) with the
+ * FP64 fine stiffness matrix of the hierarchy's coefficient.  Waits for the
+ * stream; *norm is a host double.  EINVAL on NULL arguments. */
+int gbl_energy_norm(gbl_ctx* ctx, const double* u_dev, double* norm, void* stream);
+
 /* Kernel classes for the optional timing of gbl_profile_*. */
 enum gbl_prof_kernel {
   GBL_PROF_ASSEMBLE = 0,          /* fine stiffness A^(q) */

@@ -119,6 +119,7 @@ struct Layout {
   size_t fcgpart_off = 0;    // tile partials (2 per tile)
   size_t fcgscal_off = 0;    // kNumFineScalars doubles + ticket
   size_t elog_off = 0;       // per-iteration error estimates of the outer iteration (max_outer + 2 doubles)
+  size_t tr_off[kMaxLevels] = {};   // FP64 level vectors of the gamblet transform (nk^2 each)
   size_t total = 0;
 };
 
@@ -243,6 +244,10 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
   L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
   L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
+  for (int k = 1; k <= q; ++k) {
+    L.tr_off[k] = b;
+    b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * 8);
+  }
   L.total = b;
   return GBL_OK;
 }
@@ -826,6 +831,25 @@ int solve_many(gbl_ctx* c, int nrhs, int mode, const double* src, size_t src_str
 
 }  // namespace
 
+// Geometry, hierarchy operators and FP64 level vectors of the gamblet transform
+template <typename T>
+TransformArgs transform_args(const gbl_ctx* c) {
+  const Layout& L = c->L;
+  TransformArgs a;
+  a.q = L.q;
+  a.n = L.n;
+  for (int k = 1; k <= L.q; ++k) {
+    a.lv[k] = L.lv[k];
+    a.U[k] = reinterpret_cast<double*>(c->ws + L.tr_off[k]);
+    if (k >= 2) {
+      a.R[k] = c->hier<T>(L.lv[k].offR);
+      a.B[k] = c->hier<T>(L.lv[k].offB);
+    }
+  }
+  a.A1 = c->hier<T>(L.lv[1].offA);
+  return a;
+}
+
 extern "C" {
 
 int gbl_version(void) { return GBL_VERSION; }
@@ -1166,6 +1190,76 @@ int gbl_profile_read(int kernel, double* total_ms, long* launches) {
   g_prof.drain();
   *total_ms = g_prof.total_ms[kernel];
   *launches = g_prof.launches[kernel];
+  return GBL_OK;
+}
+
+int gbl_transform_size(const gbl_ctx* c, size_t* count) {
+  if (!c || !count) return fail(nullptr, GBL_EINVAL, "ctx or count is NULL");
+  *count = (size_t)1 << (2 * c->L.q);
+  return GBL_OK;
+}
+
+int gbl_transform(gbl_ctx* c, const double* u_dev, double* coef_dev, void* stream) {
+  if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
+  if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->L.prec == GBL_FP64) launch_transform<double>(transform_args<double>(c), u_dev, coef_dev, s);
+  else launch_transform<float>(transform_args<float>(c), u_dev, coef_dev, s);
+  HIPCHK(c, hipGetLastError());
+  return GBL_OK;
+}
+
+int gbl_inverse_transform(gbl_ctx* c, const double* coef_dev, double* u_dev, void* stream) {
+  if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
+  if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->L.prec == GBL_FP64) launch_inverse_transform<double>(transform_args<double>(c), coef_dev, u_dev, s);
+  else launch_inverse_transform<float>(transform_args<float>(c), coef_dev, u_dev, s);
+  HIPCHK(c, hipGetLastError());
+  return GBL_OK;
+}
+
+int gbl_compress(gbl_ctx* c, double* coef_dev, long keep, double* threshold, void* stream) {
+  if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
+  if (!coef_dev) return fail(c, GBL_EINVAL, "coef must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long n = (long)1 << (2 * c->L.q);
+  double* thr = c->oscal() + kSSpare;   // device scalar
+  if (keep <= 0) {
+    launch_fill((size_t)n, 0.0, coef_dev, s);
+    if (threshold) *threshold = HUGE_VAL;
+  } else if (keep >= n) {
+    if (threshold) *threshold = 0.0;
+  } else {
+    launch_select_threshold(coef_dev, n, keep, thr, s);
+    launch_zero_below(thr, n, coef_dev, s);
+    if (threshold) {
+      HIPCHK(c, hipMemcpyAsync(c->host, thr, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      *threshold = c->host[0];
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return GBL_OK;
+}
+
+int gbl_energy_norm(gbl_ctx* c, const double* u_dev, double* norm, void* stream) {
+  if (!c || !norm) return fail(c, GBL_EINVAL, "ctx and norm must not be NULL");
+  if (!u_dev) return fail(c, GBL_EINVAL, "u must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = c->L;
+  const int n = L.n;
+  double* sl = c->fine(0);
+  double* w = c->fine(1);
+  double* out = c->oscal() + kSSpare + 1;
+  launch_nodal_to_slots(n, u_dev, sl, s);
+  launch_apply_fine(c->a(), n, sl, w, s);
+  launch_dots(n * n, 1, sl, w, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<double*>(c->ws + L.dpart_off),
+              reinterpret_cast<unsigned*>(c->ws + L.dcnt_off), out, s);
+  HIPCHK(c, hipMemcpyAsync(c->host, out, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipGetLastError());
+  *norm = std::sqrt(std::max(c->host[0], 0.0));
   return GBL_OK;
 }
 

@@ -75,4 +75,26 @@ void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* 
 template <typename T>
 void launch_coarse_solve(const double* L1, const T* g1, T* v1, hipStream_t st);
 
+// Gamblet transform of a level-q vector and its inverse (kernels_transform.hip).
+// Level k's normalized coefficients sit at offset 4^(k-1) of the coefficient
+// vector (level 1: 4 values by slot; level k >= 2: 3 (nk/2)^2 values, entry
+// t (nk/2)^2 + parent, zero on padding rows); 4^q values in all.
+struct TransformArgs {
+  int q = 0;
+  int n = 0;                        // cells per dimension (2^q)
+  LevelGeom lv[kMaxLevels];
+  const void* A1 = nullptr;         // A^(1) stencil (hierarchy scalar)
+  const void* R[kMaxLevels] = {};   // R^(k-1,k), k >= 2
+  const void* B[kMaxLevels] = {};   // B^(k), k >= 2
+  double* U[kMaxLevels] = {};       // FP64 level vectors, nk^2 slots each
+};
+template <typename T>
+void launch_transform(const TransformArgs& a, const double* u_nodal, double* coef, hipStream_t st);
+template <typename T>
+void launch_inverse_transform(const TransformArgs& a, const double* coef, double* u_nodal, hipStream_t st);
+// threshold = the keep-th largest |c| (keep >= 1), written to *thr on the device
+void launch_select_threshold(const double* c, long n, long keep, double* thr, hipStream_t st);
+void launch_zero_below(const double* thr, long n, double* c, hipStream_t st);
+void launch_nodal_to_slots(int n, const double* u_nodal, double* s, hipStream_t st);
+
 }  // namespace gbl

@@ -1,0 +1,243 @@
+// Gamblet transform of a given level-q vector, its inverse, and the
+// selection used to compress it: the representation of u in the basis
+// psi^(1)_i / ||psi^(1)_i||_a, chi^(k)_j / ||chi^(k)_j||_a (discussion of
+// Example 5.1, Figures 10-11).
+//
+// Measurements of level k-1 are sums of level-k measurements over the
+// children (R^(k-1,k) pi^(k-1,k)T = I for every R = pibar + D W), so the
+// level-(k-1) coefficients of u are U^(k-1) = pi U^(k), and the detail
+// U^(k) - R^T U^(k-1) lies in the range of W^T: w^(k) = W (U^(k) - R^T U^(k-1))
+// (the rows of W are orthonormal, Construction 4.13).  The inverse is the
+// reconstruction of Theorem 4.15.  ||chi^(k)_j||_a^2 = B^(k)_jj and
+// ||psi^(1)_i||_a^2 = A^(1)_ii scale the coefficients.  All arithmetic is
+// FP64; the hierarchy operators are read in their stored precision.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.hpp"
+#include "gamblet_internal.hpp"
+
+namespace gbl {
+
+// sum_i R_{i,(fx,fy)} v_i over the level-(k-1) rows whose restriction block
+// covers level-k slot (fx, fy); rows outside the level are weighted by zero
+template <typename T, int RHO>
+__device__ __forceinline__ double rt_apply_r(const T* __restrict__ R, const double* __restrict__ vc, int nk, int fx,
+                                             int fy) {
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int px = fx >> 1, py = fy >> 1;
+  constexpr int rw = 2 * (2 * RHO + 1);
+  double acc = 0.0;
+#pragma unroll
+  for (int dx = -RHO; dx <= RHO; ++dx) {
+    const int ix = px + dx;
+    const bool okx = ix >= 0 && ix < nc;
+    const int ixc = min(max(ix, 0), nc - 1);
+    const int bx = fx - 2 * (ixc - RHO);
+#pragma unroll
+    for (int dy = -RHO; dy <= RHO; ++dy) {
+      const int iy = py + dy;
+      const bool ok = okx && iy >= 0 && iy < nc;
+      const int iyc = min(max(iy, 0), nc - 1);
+      const int by = fy - 2 * (iyc - RHO);
+      const int bxc = min(max(bx, 0), rw - 1), byc = min(max(by, 0), rw - 1);
+      const int i = ixc * nc + iyc;
+      acc += (double)R[(size_t)(bxc * rw + byc) * nc2 + i] * (vc[i] * (ok ? 1.0 : 0.0));
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ double rt_apply(const T* __restrict__ R, const double* __restrict__ vc, int nk, int rho,
+                                           int fx, int fy) {
+  switch (rho) {
+    case 1: return rt_apply_r<T, 1>(R, vc, nk, fx, fy);
+    case 2: return rt_apply_r<T, 2>(R, vc, nk, fx, fy);
+    case 3: return rt_apply_r<T, 3>(R, vc, nk, fx, fy);
+    default: return rt_apply_r<T, 4>(R, vc, nk, fx, fy);
+  }
+}
+
+// level-q slots from nodal values: slot (x, y) is node (x, y); the slots of
+// row or column 0 are boundary nodes, not unknowns, and hold zero
+__global__ void k_nodal_to_slots(int n, const double* __restrict__ u, double* __restrict__ s) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  s[id] = (x == 0 || y == 0) ? 0.0 : u[x * (n + 1) + y];
+}
+
+// interior nodes from level-q slots; boundary nodes are set to zero
+__global__ void k_slots_to_nodal_all(int n, const double* __restrict__ s, double* __restrict__ u) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = n + 1;
+  if (id >= m * m) return;
+  const int x = id / m, y = id % m;
+  u[id] = (x == 0 || y == 0 || x == n || y == n) ? 0.0 : s[x * n + y];
+}
+
+// U^(k-1) = pi U^(k): each parent sums its four child slots
+__global__ void k_child_sum(int nc, const double* __restrict__ f, double* __restrict__ c) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc * nc) return;
+  const int px = p / nc, py = p % nc, nk = 2 * nc;
+  const double* r0 = f + (size_t)(2 * px) * nk + 2 * py;
+  c[p] = (r0[0] + r0[1]) + (r0[nk] + r0[nk + 1]);
+}
+
+// level-k normalized coefficients of one parent: w = W (U^(k) - R^T U^(k-1)),
+// times sqrt(B^(k)_jj); padding rows are zero
+template <typename T>
+__global__ void k_detail(const T* __restrict__ R, const T* __restrict__ B, const double* __restrict__ f,
+                         const double* __restrict__ c, double* __restrict__ out, int nk, int rho, int t, int fine) {
+  const int np = nk / 2;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np * np) return;
+  const int px = p / np, py = p % np;
+  const int tp = parent_type(fine != 0, px, py);
+  double r[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int fx = 2 * px + (d >> 1), fy = 2 * py + (d & 1);
+    r[d] = f[(size_t)fx * nk + fy] - rt_apply<T>(R, c, nk, rho, fx, fy);
+  }
+  const int TT = 2 * t + 1;
+  const size_t np2 = (size_t)np * np;
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt) {
+    double w = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) w += wcoef(tp, tt, d) * r[d];
+    const double bd = is_pad_row(tp, tt) ? 0.0 : (double)B[b_index(t * TT + t, 4 * tt, p, TT)];
+    out[tt * np2 + p] = bd > 0.0 ? w * sqrt(bd) : 0.0;
+  }
+}
+
+// level 1: c = U sqrt(A^(1)_ii) (forward) or U = c / sqrt(A^(1)_ii) (inverse)
+template <typename T>
+__global__ void k_level1(const T* __restrict__ A1, int s1, const double* __restrict__ in, double* __restrict__ out,
+                         int inverse) {
+  const int i = threadIdx.x;
+  if (i >= 4) return;
+  const int S1 = 2 * s1 + 1;
+  const double d = (double)A1[(size_t)(s1 * S1 + s1) * 4 + i];
+  const double sc = d > 0.0 ? sqrt(d) : 0.0;
+  out[i] = inverse ? (sc > 0.0 ? in[i] / sc : 0.0) : in[i] * sc;
+}
+
+// v^(k) = R^(k,k-1) v^(k-1) + W^(k)T w^(k), w from the normalized coefficients
+template <typename T>
+__global__ void k_recon(const T* __restrict__ R, const T* __restrict__ B, const double* __restrict__ vc,
+                        const double* __restrict__ cf, double* __restrict__ vf, int nk, int rho, int t, int fine) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nk * nk) return;
+  const int fx = id / nk, fy = id % nk;
+  const int np = nk / 2;
+  double acc = rt_apply<T>(R, vc, nk, rho, fx, fy);
+  const int px = fx >> 1, py = fy >> 1;
+  const int d = 2 * (fx & 1) + (fy & 1);
+  const int tp = parent_type(fine != 0, px, py);
+  const int p = px * np + py;
+  const int TT = 2 * t + 1;
+  const size_t np2 = (size_t)np * np;
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt) {
+    if (is_pad_row(tp, tt)) continue;
+    const double bd = (double)B[b_index(t * TT + t, 4 * tt, p, TT)];
+    if (bd > 0.0) acc += wcoef(tp, tt, d) * (cf[tt * np2 + p] / sqrt(bd));
+  }
+  vf[id] = acc;
+}
+
+// The keep-th largest |c| (keep >= 1): the largest tau with count(|c| >= tau)
+// >= keep, by bisection on the bit pattern of tau (non-negative doubles order
+// like their bit patterns).  One workgroup; every thread takes the same
+// decisions from the block-wide count.  NaN entries are never counted.
+__global__ __launch_bounds__(1024) void k_select_threshold(const double* __restrict__ c, long n, long keep,
+                                                           double* __restrict__ thr) {
+  __shared__ unsigned long long part[16];
+  __shared__ unsigned long long total;
+  unsigned long long lo = 0ull;                      // count(|c| >= 0) = n >= keep (NaN aside)
+  unsigned long long hi = 0x7FF0000000000000ull;     // +inf: count = 0 < keep
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  while (hi - lo > 1ull) {
+    const unsigned long long mid = lo + (hi - lo) / 2ull;
+    const double tau = __longlong_as_double((long long)mid);
+    unsigned long long cnt = 0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) cnt += (fabs(c[i]) >= tau) ? 1ull : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+    if (lane == 0) part[wv] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long s = 0;
+      for (int w = 0; w < nw; ++w) s += part[w];
+      total = s;
+    }
+    __syncthreads();
+    if (total >= (unsigned long long)keep) lo = mid;
+    else hi = mid;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *thr = __longlong_as_double((long long)lo);
+}
+
+__global__ void k_zero_below(const double* __restrict__ thr, long n, double* __restrict__ c) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double t = *thr;
+  if (!(fabs(c[i]) >= t)) c[i] = 0.0;
+}
+
+template <typename T>
+void launch_transform(const TransformArgs& a, const double* u_nodal, double* coef, hipStream_t st) {
+  const int q = a.q;
+  const int nq = a.n;
+  hipLaunchKernelGGL(k_nodal_to_slots, dim3((nq * nq + 255) / 256), dim3(256), 0, st, nq, u_nodal, a.U[q]);
+  for (int k = q; k >= 2; --k) {
+    const LevelGeom& g = a.lv[k];
+    const int nc = g.nk / 2;
+    hipLaunchKernelGGL(k_child_sum, dim3((nc * nc + 255) / 256), dim3(256), 0, st, nc, a.U[k], a.U[k - 1]);
+    double* out = coef + (size_t)nc * nc;   // level k starts at 4^(k-1) = (nk/2)^2
+    hipLaunchKernelGGL((k_detail<T>), dim3((nc * nc + 255) / 256), dim3(256), 0, st, static_cast<const T*>(a.R[k]),
+                       static_cast<const T*>(a.B[k]), a.U[k], a.U[k - 1], out, g.nk, g.rho, g.t, k == q ? 1 : 0);
+  }
+  hipLaunchKernelGGL((k_level1<T>), dim3(1), dim3(64), 0, st, static_cast<const T*>(a.A1), a.lv[1].s, a.U[1], coef, 0);
+}
+
+template <typename T>
+void launch_inverse_transform(const TransformArgs& a, const double* coef, double* u_nodal, hipStream_t st) {
+  const int q = a.q;
+  hipLaunchKernelGGL((k_level1<T>), dim3(1), dim3(64), 0, st, static_cast<const T*>(a.A1), a.lv[1].s, coef, a.U[1], 1);
+  for (int k = 2; k <= q; ++k) {
+    const LevelGeom& g = a.lv[k];
+    const int nc = g.nk / 2;
+    const double* cf = coef + (size_t)nc * nc;
+    hipLaunchKernelGGL((k_recon<T>), dim3((g.nk * g.nk + 255) / 256), dim3(256), 0, st, static_cast<const T*>(a.R[k]),
+                       static_cast<const T*>(a.B[k]), a.U[k - 1], cf, a.U[k], g.nk, g.rho, g.t, k == q ? 1 : 0);
+  }
+  const int m = a.n + 1;
+  hipLaunchKernelGGL(k_slots_to_nodal_all, dim3((m * m + 255) / 256), dim3(256), 0, st, a.n, a.U[q], u_nodal);
+}
+
+void launch_select_threshold(const double* c, long n, long keep, double* thr, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, st, c, n, keep, thr);
+}
+
+void launch_zero_below(const double* thr, long n, double* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_below, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, thr, n, c);
+}
+
+void launch_nodal_to_slots(int n, const double* u_nodal, double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_nodal_to_slots, dim3((n * n + 255) / 256), dim3(256), 0, st, n, u_nodal, s);
+}
+
+template void launch_transform<float>(const TransformArgs&, const double*, double*, hipStream_t);
+template void launch_transform<double>(const TransformArgs&, const double*, double*, hipStream_t);
+template void launch_inverse_transform<float>(const TransformArgs&, const double*, double*, hipStream_t);
+template void launch_inverse_transform<double>(const TransformArgs&, const double*, double*, hipStream_t);
+
+}  // namespace gbl

@@ -74,9 +74,16 @@ def lib() -> ctypes.CDLL:
         L.gbl_profile_enable.argtypes = [ctypes.c_uint]
         L.gbl_profile_reset.argtypes = []
         L.gbl_profile_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
+        L.gbl_transform_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.gbl_transform.argtypes = [vp, vp, vp, vp]
+        L.gbl_inverse_transform.argtypes = [vp, vp, vp, vp]
+        L.gbl_compress.argtypes = [vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_double), vp]
+        L.gbl_energy_norm.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
                      "gbl_level_layout", "gbl_build_flags", "gbl_build_batched", "gbl_solve_batched",
-                     "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset", "gbl_profile_read"):
+                     "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset", "gbl_profile_read",
+                     "gbl_transform_size", "gbl_transform", "gbl_inverse_transform", "gbl_compress",
+                     "gbl_energy_norm"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -223,6 +230,51 @@ class Hierarchy:
         f = ctypes.c_uint(0)
         _check(lib().gbl_build_flags(self.ctx, ctypes.byref(f)), self.ctx)
         return int(f.value)
+
+    def transform_size(self) -> int:
+        """Number of gamblet coefficients, 4^q."""
+        c = ctypes.c_size_t(0)
+        _check(lib().gbl_transform_size(self.ctx, ctypes.byref(c)), self.ctx)
+        return int(c.value)
+
+    def transform(self, u: torch.Tensor) -> torch.Tensor:
+        """Normalized gamblet coefficients of a nodal u ([n+1, n+1] FP64; layout in ``gamblet.h``)."""
+        m = self.n + 1
+        _require(u, (m, m), "u")
+        c = torch.empty(self.transform_size(), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().gbl_transform(self.ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                       _stream_ptr(self.device)), self.ctx)
+        return c
+
+    def inverse_transform(self, c: torch.Tensor) -> torch.Tensor:
+        """Nodal u ([n+1, n+1], zero boundary) from normalized gamblet coefficients."""
+        _require(c, (self.transform_size(),), "coefficients")
+        m = self.n + 1
+        u = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().gbl_inverse_transform(self.ctx, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                               _stream_ptr(self.device)), self.ctx)
+        return u
+
+    def compress(self, c: torch.Tensor, keep: int) -> float:
+        """Keep the ``keep`` largest |c| in place (others zero); returns the smallest kept magnitude."""
+        _require(c, (self.transform_size(),), "coefficients")
+        thr = ctypes.c_double(0.0)
+        with torch.cuda.device(self.device):
+            _check(lib().gbl_compress(self.ctx, ctypes.c_void_p(c.data_ptr()), int(keep), ctypes.byref(thr),
+                                      _stream_ptr(self.device)), self.ctx)
+        return float(thr.value)
+
+    def energy_norm(self, u: torch.Tensor) -> float:
+        """sqrt(u^T A u) of a nodal u with the FP64 fine stiffness matrix."""
+        m = self.n + 1
+        _require(u, (m, m), "u")
+        out = ctypes.c_double(0.0)
+        with torch.cuda.device(self.device):
+            _check(lib().gbl_energy_norm(self.ctx, ctypes.c_void_p(u.data_ptr()), ctypes.byref(out),
+                                         _stream_ptr(self.device)), self.ctx)
+        return float(out.value)
 
     def level(self, k: int) -> dict:
         """A^(k) [S,S,nk,nk] and R^(k-1,k) [rw,rw,nc,nc] as device views, B^(k) as a

@@ -93,6 +93,16 @@ def example51_nodal_source() -> np.ndarray:
     return np.cos(3 * z1 + z2) + np.sin(3 * z2) + np.sin(7 * z1 - 5 * z2)
 
 
+def smooth_cell_source(q: int) -> np.ndarray:
+    """The source of Example 5.1, g = cos(3 z1 + z2) + sin(3 z2) + sin(7 z1 - 5 z2),
+    at the centres of the 2^q x 2^q cells of the unit square (a smooth source for
+    the compression measurements; the example itself uses 65 x 65 cells)."""
+    n = 1 << q
+    z = (np.arange(n, dtype=np.float64) + 0.5) / n
+    z1, z2 = z[:, None], z[None, :]
+    return np.cos(3 * z1 + z2) + np.sin(3 * z2) + np.sin(7 * z1 - 5 * z2)
+
+
 @dataclass
 class Problem:
     """One synthetic elliptic problem on ``2^q x 2^q`` cells."""

@@ -119,3 +119,26 @@ def test_compression_keeps_the_largest_and_converges():
         errs.append(_energy(fe.A, u - v) / _energy(fe.A, u))
     assert errs[-1] < 1e-12
     assert all(x >= y - 1e-12 for x, y in zip(errs, errs[1:])), errs
+
+
+def test_exact_basis_compresses_a_smooth_solution():
+    """With the exact gamblets (the setting of Example 5.1 and Figures 10-11),
+    the solution for a smooth source keeps most of its energy in the coarse
+    levels, so 1% of the normalized coefficients leave an energy error of a few
+    percent (white noise in the source, by contrast, spreads the energy over all
+    levels)."""
+    q = 6
+    pr = S.rough_problem(q, 2.0, 34)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    h = G.exact_hierarchy(fe.A, tree)
+    errs = {}
+    for label, g in (("smooth", S.smooth_cell_source(q)), ("noise", pr.g[0])):
+        u = fem.DirectSolver(fe.A).solve(fem.load_cellwise(g, fe.h))
+        c1, ck = G.normalized_coefficients(h, u)
+        n = c1.size + sum(v.size for v in ck.values())
+        a1, ak = G.compress(c1, ck, int(round(0.01 * n)))
+        v = G.reconstruct_normalized(h, a1, ak)
+        errs[label] = _energy(fe.A, u - v) / _energy(fe.A, u)
+    assert errs["smooth"] < 0.1
+    assert errs["noise"] > 5 * errs["smooth"]
