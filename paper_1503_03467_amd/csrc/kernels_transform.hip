@@ -88,11 +88,22 @@ __global__ void k_child_sum(int nc, const double* __restrict__ f, double* __rest
   c[p] = (r0[0] + r0[1]) + (r0[nk] + r0[nk + 1]);
 }
 
-// level-k normalized coefficients of one parent: w = W (U^(k) - R^T U^(k-1)),
-// times sqrt(B^(k)_jj); padding rows are zero
+// detail of every level-k slot, in place: f = U^(k) - R^T U^(k-1) (U^(k) is
+// no longer needed once the child sums are formed)
 template <typename T>
-__global__ void k_detail(const T* __restrict__ R, const T* __restrict__ B, const double* __restrict__ f,
-                         const double* __restrict__ c, double* __restrict__ out, int nk, int rho, int t, int fine) {
+__global__ void k_detail_slots(const T* __restrict__ R, const double* __restrict__ c, double* __restrict__ f, int nk,
+                               int rho) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nk * nk) return;
+  const int fx = id / nk, fy = id % nk;
+  f[id] -= rt_apply<T>(R, c, nk, rho, fx, fy);
+}
+
+// level-k normalized coefficients of one parent: w = W (detail of its four
+// children), times sqrt(B^(k)_jj); padding rows are zero
+template <typename T>
+__global__ void k_detail(const T* __restrict__ B, const double* __restrict__ f, double* __restrict__ out, int nk,
+                         int t, int fine) {
   const int np = nk / 2;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np * np) return;
@@ -100,10 +111,7 @@ __global__ void k_detail(const T* __restrict__ R, const T* __restrict__ B, const
   const int tp = parent_type(fine != 0, px, py);
   double r[4];
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    const int fx = 2 * px + (d >> 1), fy = 2 * py + (d & 1);
-    r[d] = f[(size_t)fx * nk + fy] - rt_apply<T>(R, c, nk, rho, fx, fy);
-  }
+  for (int d = 0; d < 4; ++d) r[d] = f[(size_t)(2 * px + (d >> 1)) * nk + 2 * py + (d & 1)];
   const int TT = 2 * t + 1;
   const size_t np2 = (size_t)np * np;
 #pragma unroll
@@ -202,8 +210,10 @@ void launch_transform(const TransformArgs& a, const double* u_nodal, double* coe
     const int nc = g.nk / 2;
     hipLaunchKernelGGL(k_child_sum, dim3((nc * nc + 255) / 256), dim3(256), 0, st, nc, a.U[k], a.U[k - 1]);
     double* out = coef + (size_t)nc * nc;   // level k starts at 4^(k-1) = (nk/2)^2
-    hipLaunchKernelGGL((k_detail<T>), dim3((nc * nc + 255) / 256), dim3(256), 0, st, static_cast<const T*>(a.R[k]),
-                       static_cast<const T*>(a.B[k]), a.U[k], a.U[k - 1], out, g.nk, g.rho, g.t, k == q ? 1 : 0);
+    hipLaunchKernelGGL((k_detail_slots<T>), dim3((g.nk * g.nk + 255) / 256), dim3(256), 0, st,
+                       static_cast<const T*>(a.R[k]), a.U[k - 1], a.U[k], g.nk, g.rho);
+    hipLaunchKernelGGL((k_detail<T>), dim3((nc * nc + 255) / 256), dim3(256), 0, st, static_cast<const T*>(a.B[k]),
+                       a.U[k], out, g.nk, g.t, k == q ? 1 : 0);
   }
   hipLaunchKernelGGL((k_level1<T>), dim3(1), dim3(64), 0, st, static_cast<const T*>(a.A1), a.lv[1].s, a.U[1], coef, 0);
 }
