@@ -254,6 +254,53 @@ int gbl_compress(gbl_ctx* ctx, double* coef_dev, long keep, double* threshold, v
  * stream; *norm is a host double.  EINVAL on NULL arguments. */
 int gbl_energy_norm(gbl_ctx* ctx, const double* u_dev, double* norm, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Level-q gamblets from the localized inverse of the mass matrix (Algorithm
+ * 2: the mass matrix, the localized mass inverse, the level-q gamblets, their
+ * load and their stiffness matrix; Definition 5.2).  For every interior node
+ * i the patch is the box of interior nodes within rho_q node steps of i;
+ * y^(i) solves M^(i,rho_q) y = e_i on it (M_ij = int phi_i phi_j, Q1 on the
+ * 2^q x 2^q cell grid of the unit square), psi^(q)_i = sum_j y^(i)_j phi_j,
+ * g^(q)_i = int psi^(q)_i g = sum_j y^(i)_j b_j and A^(q) = Minv^T A Minv.
+ * On this grid y^(i) is the outer product of two one-dimensional factors.
+ *
+ * Common to all calls: q in [2, 12], rho_q in [1, 4], n = 2^q, m = n - 1;
+ * interior vectors are FP64 [m][m], node (ix, iy) at ix * m + iy, node
+ * coordinates 1 + ix, 1 + iy on the (n+1) x (n+1) grid.  All pointers are
+ * device memory owned by the caller; no call allocates.  Every call is
+ * asynchronous on stream and returns GBL_EINVAL for a bad q, rho_q or a NULL
+ * pointer (message via gbl_last_error(NULL)), GBL_EHIP if a launch fails.
+ * ------------------------------------------------------------------------ */
+
+/* The table of one-dimensional factors (Definition 5.2):
+ * table[x][d + rho_q], x in [0, m), d in [-rho_q, rho_q], is the entry at
+ * x + d of the inverse of the 1-D mass matrix h tridiag(1, 4, 1)/6 on the
+ * interval of interior coordinates within rho_q of x, applied to e_x (zero
+ * outside the interval).  Output table_dev: [m][2 rho_q + 1]. */
+int gbl_mass_inverse(int q, int rho_q, double* table_dev, void* stream);
+
+/* psi^(q)_i in the nodal basis: psi_dev[i][(dx + rho_q)(2 rho_q + 1) + dy +
+ * rho_q] = table[ix][dx + rho_q] * table[iy][dy + rho_q], the weight of
+ * phi at node i + (dx, dy).  Output: [m^2][(2 rho_q + 1)^2]. */
+int gbl_level_q_gamblets(int q, int rho_q, const double* table_dev, double* psi_dev, void* stream);
+
+/* g^(q) = Minv^T b for a nodal load b_j = int phi_j g (interior vectors).
+ * b and gq must not overlap (GBL_EINVAL if they are the same pointer). */
+int gbl_level_q_load(int q, int rho_q, const double* table_dev, const double* b_dev, double* gq_dev, void* stream);
+
+/* A^(q)_ij = int grad psi_i . a grad psi_j for the cell coefficient a_dev
+ * ([n][n] FP64, a[ex][ey] on cell ex*n + ey, positive; not checked here).
+ * Output aq_dev: [m^2][(2S + 1)^2], S = 2 rho_q + 1, entry (dx + S)(2S + 1)
+ * + dy + S of row i couples node i with i + (dx, dy); zero where that node
+ * is not interior.  The operator is symmetric positive definite. */
+int gbl_level_q_operator(int q, int rho_q, const double* a_dev, const double* table_dev, double* aq_dev,
+                         void* stream);
+
+/* Nodal values u = Minv U of the level-q combination sum_i U_i psi^(q)_i.
+ * U and u must not overlap. */
+int gbl_level_q_to_nodal(int q, int rho_q, const double* table_dev, const double* U_dev, double* u_dev,
+                         void* stream);
+
 /* Kernel classes for the optional timing of gbl_profile_*. */
 enum gbl_prof_kernel {
   GBL_PROF_ASSEMBLE = 0,          /* fine stiffness A^(q) */

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgamblet.so")
-SOURCES = ["gamblet.hip", "kernels_build.hip", "kernels_solve.hip", "kernels_transform.hip"]
+SOURCES = ["gamblet.hip", "kernels_build.hip", "kernels_solve.hip", "kernels_transform.hip",
+           "kernels_level_q.hip"]
 ARCH = os.environ.get("GBL_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

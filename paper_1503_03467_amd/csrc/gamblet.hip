@@ -120,6 +120,7 @@ struct Layout {
   size_t fcgscal_off = 0;    // kNumFineScalars doubles + ticket
   size_t elog_off = 0;       // per-iteration error estimates of the outer iteration (max_outer + 2 doubles)
   size_t tr_off[kMaxLevels] = {};   // FP64 level vectors of the gamblet transform (nk^2 each)
+  size_t sel_off = 0;        // selection state of the compression threshold (4 x 64-bit words + histogram)
   size_t total = 0;
 };
 
@@ -248,6 +249,8 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     L.tr_off[k] = b;
     b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * 8);
   }
+  L.sel_off = b;
+  b = align_up(b + 4 * 8 + (size_t)kSelHistBins * 4);
   L.total = b;
   return GBL_OK;
 }
@@ -1231,7 +1234,8 @@ int gbl_compress(gbl_ctx* c, double* coef_dev, long keep, double* threshold, voi
   } else if (keep >= n) {
     if (threshold) *threshold = 0.0;
   } else {
-    launch_select_threshold(coef_dev, n, keep, thr, s);
+    auto* sel = reinterpret_cast<unsigned long long*>(c->ws + c->L.sel_off);
+    launch_select_threshold(coef_dev, n, keep, sel, reinterpret_cast<unsigned*>(sel + 4), thr, s);
     launch_zero_below(thr, n, coef_dev, s);
     if (threshold) {
       HIPCHK(c, hipMemcpyAsync(c->host, thr, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1261,6 +1265,60 @@ int gbl_energy_norm(gbl_ctx* c, const double* u_dev, double* norm, void* stream)
   HIPCHK(c, hipGetLastError());
   *norm = std::sqrt(std::max(c->host[0], 0.0));
   return GBL_OK;
+}
+
+// Level-q gamblets from the localized mass inverse (Algorithm 2; Definition
+// 5.2).  These calls need no hierarchy: they take q, the patch radius and
+// device pointers, and launch on stream.
+static int check_level_q(int q, int rho_q) {
+  if (q < 2 || q > 12) return fail(nullptr, GBL_EINVAL, "q must be in [2, 12]");
+  if (rho_q < 1 || rho_q > kMaxRhoQ) return fail(nullptr, GBL_EINVAL, "rho_q must be in [1, 4]");
+  return GBL_OK;
+}
+
+static int launched() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, GBL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return GBL_OK;
+}
+
+int gbl_mass_inverse(int q, int rho_q, double* table_dev, void* stream) {
+  if (int st = check_level_q(q, rho_q)) return st;
+  if (!table_dev) return fail(nullptr, GBL_EINVAL, "table must not be NULL");
+  launch_mass_inverse_table(1 << q, rho_q, table_dev, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+int gbl_level_q_gamblets(int q, int rho_q, const double* table_dev, double* psi_dev, void* stream) {
+  if (int st = check_level_q(q, rho_q)) return st;
+  if (!table_dev || !psi_dev) return fail(nullptr, GBL_EINVAL, "table and psi must not be NULL");
+  launch_level_q_weights(1 << q, rho_q, table_dev, psi_dev, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+int gbl_level_q_load(int q, int rho_q, const double* table_dev, const double* b_dev, double* gq_dev, void* stream) {
+  if (int st = check_level_q(q, rho_q)) return st;
+  if (!table_dev || !b_dev || !gq_dev) return fail(nullptr, GBL_EINVAL, "table, b and gq must not be NULL");
+  if (b_dev == gq_dev) return fail(nullptr, GBL_EINVAL, "b and gq must not overlap");
+  launch_level_q_load(1 << q, rho_q, table_dev, b_dev, gq_dev, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+int gbl_level_q_operator(int q, int rho_q, const double* a_dev, const double* table_dev, double* aq_dev,
+                         void* stream) {
+  if (int st = check_level_q(q, rho_q)) return st;
+  if (!a_dev || !table_dev || !aq_dev) return fail(nullptr, GBL_EINVAL, "a, table and aq must not be NULL");
+  launch_level_q_operator(1 << q, rho_q, a_dev, table_dev, aq_dev, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+int gbl_level_q_to_nodal(int q, int rho_q, const double* table_dev, const double* U_dev, double* u_dev,
+                         void* stream) {
+  if (int st = check_level_q(q, rho_q)) return st;
+  if (!table_dev || !U_dev || !u_dev) return fail(nullptr, GBL_EINVAL, "table, U and u must not be NULL");
+  if (U_dev == u_dev) return fail(nullptr, GBL_EINVAL, "U and u must not overlap");
+  launch_level_q_to_nodal(1 << q, rho_q, table_dev, U_dev, u_dev, static_cast<hipStream_t>(stream));
+  return launched();
 }
 
 int gbl_destroy(gbl_ctx* c) {

@@ -25,6 +25,7 @@ namespace gbl {
 
 constexpr int kMaxLevels = 13;     // q <= 12
 constexpr int kMaxRho = 4;
+constexpr int kMaxRhoQ = 4;   // patch radius of the localized mass inverse
 // zero words before and after every level slot vector g^(k)
 constexpr int kGPad = 16;
 static_assert(kGPad >= 2 * kMaxRho, "the restriction reads 2 rho words beyond the slot vector");
@@ -93,8 +94,21 @@ void launch_transform(const TransformArgs& a, const double* u_nodal, double* coe
 template <typename T>
 void launch_inverse_transform(const TransformArgs& a, const double* coef, double* u_nodal, hipStream_t st);
 // threshold = the keep-th largest |c| (keep >= 1), written to *thr on the device
-void launch_select_threshold(const double* c, long n, long keep, double* thr, hipStream_t st);
+// Selection state for launch_select_threshold: 4 words of 64 bits, then
+// kSelHistBins counters of 32 bits (caller-provided device memory).
+constexpr int kSelHistBins = 2048;
+void launch_select_threshold(const double* c, long n, long keep, unsigned long long* state, unsigned* hist,
+                             double* thr, hipStream_t st);
 void launch_zero_below(const double* thr, long n, double* c, hipStream_t st);
 void launch_nodal_to_slots(int n, const double* u_nodal, double* s, hipStream_t st);
+
+// Level-q gamblets from the localized mass inverse (kernels_level_q.hip).
+// n = 2^q cells per side; vectors over the (n-1)^2 interior nodes; Y is the
+// [(n-1)][2 rho + 1] table of one-dimensional factors.
+void launch_mass_inverse_table(int n, int rho, double* Y, hipStream_t st);
+void launch_level_q_weights(int n, int rho, const double* Y, double* W, hipStream_t st);
+void launch_level_q_load(int n, int rho, const double* Y, const double* b, double* gq, hipStream_t st);
+void launch_level_q_to_nodal(int n, int rho, const double* Y, const double* U, double* u, hipStream_t st);
+void launch_level_q_operator(int n, int rho, const double* a, const double* Y, double* AQ, hipStream_t st);
 
 }  // namespace gbl

@@ -13,6 +13,7 @@
 // FP64; the hierarchy operators are read in their stored precision.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.hpp"
@@ -160,37 +161,112 @@ __global__ void k_recon(const T* __restrict__ R, const T* __restrict__ B, const 
   vf[id] = acc;
 }
 
-// The keep-th largest |c| (keep >= 1): the largest tau with count(|c| >= tau)
-// >= keep, by bisection on the bit pattern of tau (non-negative doubles order
-// like their bit patterns).  One workgroup; every thread takes the same
-// decisions from the block-wide count.  NaN entries are never counted.
-__global__ __launch_bounds__(1024) void k_select_threshold(const double* __restrict__ c, long n, long keep,
-                                                           double* __restrict__ thr) {
-  __shared__ unsigned long long part[16];
-  __shared__ unsigned long long total;
-  unsigned long long lo = 0ull;                      // count(|c| >= 0) = n >= keep (NaN aside)
-  unsigned long long hi = 0x7FF0000000000000ull;     // +inf: count = 0 < keep
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  while (hi - lo > 1ull) {
-    const unsigned long long mid = lo + (hi - lo) / 2ull;
-    const double tau = __longlong_as_double((long long)mid);
-    unsigned long long cnt = 0;
-    for (long i = threadIdx.x; i < n; i += blockDim.x) cnt += (fabs(c[i]) >= tau) ? 1ull : 0ull;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_down(cnt, off, 64);
-    if (lane == 0) part[wv] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long s = 0;
-      for (int w = 0; w < nw; ++w) s += part[w];
-      total = s;
-    }
-    __syncthreads();
-    if (total >= (unsigned long long)keep) lo = mid;
-    else hi = mid;
-    __syncthreads();
+// The keep-th largest |c| (1 <= keep <= n): the largest tau with
+// count(|c| >= tau) >= keep.  Non-negative doubles order like their bit
+// patterns, so tau is found digit by digit on the 63-bit pattern of |c|, from
+// the top (radix selection): for each digit a histogram of the entries that
+// agree with the digits fixed so far, built by many workgroups (LDS counts,
+// then one global atomic per non-empty bin), then one workgroup walks the bins
+// from the top and fixes the digit at which the running count reaches the
+// rank still needed.  NaN entries are never counted; if fewer than keep
+// entries are numbers, tau = 0 (every number is kept).
+//
+// Selection state: st[0] digits fixed so far, st[1] rank still needed within
+// them, st[2] set when no bin reaches that rank; then hist[kSelBins].
+constexpr int kSelBins = kSelHistBins;
+constexpr unsigned long long kAbsMask = 0x7FFFFFFFFFFFFFFFull;
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;
+
+__global__ void k_sel_init(unsigned long long* __restrict__ st, unsigned* __restrict__ hist, long keep) {
+  for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) hist[b] = 0u;
+  if (threadIdx.x == 0) {
+    st[0] = 0ull;
+    st[1] = (unsigned long long)keep;
+    st[2] = 0ull;
   }
-  if (threadIdx.x == 0) *thr = __longlong_as_double((long long)lo);
+}
+
+__global__ __launch_bounds__(256) void k_sel_hist(const double* __restrict__ c, long n, int shift, int width,
+                                                  const unsigned long long* __restrict__ st,
+                                                  unsigned* __restrict__ hist) {
+  __shared__ unsigned h[kSelBins];
+  const int nb = 1 << width;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const int top = shift + width;   // <= 63
+  const unsigned long long want = st[0] >> top;
+  const unsigned mask = (unsigned)nb - 1u;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const unsigned long long key = (unsigned long long)__double_as_longlong(c[i]) & kAbsMask;
+    if (key <= kInfBits && (key >> top) == want) atomicAdd(&h[(unsigned)(key >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// 256 threads; thread t holds bins nb-1-per*t ... (descending), so the
+// exclusive scan of the per-thread sums gives every bin's count of entries in
+// higher bins.  The histogram is cleared for the next digit.
+__global__ __launch_bounds__(256) void k_sel_pick(unsigned long long* __restrict__ st, unsigned* __restrict__ hist,
+                                                  int shift, int width, int last, double* __restrict__ thr) {
+  __shared__ unsigned long long wsum[4];
+  __shared__ unsigned long long pick[2];   // bin found, rank still needed within it
+  __shared__ int found;
+  const int nb = 1 << width;
+  const int per = nb / 256;   // 8 or 4
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) found = 0;
+  unsigned cnt[8];
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    cnt[j] = j < per ? hist[nb - 1 - (tid * per + j)] : 0u;
+    mine += cnt[j];
+  }
+  // inclusive scan over the wavefront, then over the four wavefronts
+  unsigned long long incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  unsigned long long before = incl - mine;
+  for (int w = 0; w < wv; ++w) before += wsum[w];
+  const unsigned long long need = st[1];
+  if (st[2] == 0ull && before < need && before + mine >= need) {
+    unsigned long long run = before;
+    for (int j = 0; j < per; ++j) {
+      if (run + cnt[j] >= need) {
+        pick[0] = (unsigned long long)(nb - 1 - (tid * per + j));
+        pick[1] = need - run;
+        found = 1;
+        break;
+      }
+      run += cnt[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < per) hist[nb - 1 - (tid * per + j)] = 0u;
+  __syncthreads();
+  if (tid == 0) {
+    // no bin reaches the rank: fewer numbers than keep (first digit only)
+    unsigned long long failed = st[2];
+    unsigned long long prefix = st[0];
+    if (!failed && found) {
+      prefix |= pick[0] << shift;
+      st[0] = prefix;
+      st[1] = pick[1];
+    } else {
+      failed = 1ull;
+      st[2] = 1ull;
+    }
+    if (last) *thr = failed ? 0.0 : __longlong_as_double((long long)prefix);
+  }
 }
 
 __global__ void k_zero_below(const double* __restrict__ thr, long n, double* __restrict__ c) {
@@ -233,8 +309,18 @@ void launch_inverse_transform(const TransformArgs& a, const double* coef, double
   hipLaunchKernelGGL(k_slots_to_nodal_all, dim3((m * m + 255) / 256), dim3(256), 0, st, a.n, a.U[q], u_nodal);
 }
 
-void launch_select_threshold(const double* c, long n, long keep, double* thr, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, st, c, n, keep, thr);
+void launch_select_threshold(const double* c, long n, long keep, unsigned long long* state, unsigned* hist,
+                             double* thr, hipStream_t st) {
+  // digits of the 63-bit pattern, top first: 11 (exponent), 11, 11, 10, 10, 10
+  static const int kShift[6] = {52, 41, 30, 20, 10, 0};
+  static const int kWidth[6] = {11, 11, 11, 10, 10, 10};
+  const long per_block = 256L * 4;
+  const unsigned grid = (unsigned)std::max(1L, std::min(1024L, (n + per_block - 1) / per_block));
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, st, state, hist, keep);
+  for (int d = 0; d < 6; ++d) {
+    hipLaunchKernelGGL(k_sel_hist, dim3(grid), dim3(256), 0, st, c, n, kShift[d], kWidth[d], state, hist);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, st, state, hist, kShift[d], kWidth[d], d == 5 ? 1 : 0, thr);
+  }
 }
 
 void launch_zero_below(const double* thr, long n, double* c, hipStream_t st) {

@@ -79,11 +79,17 @@ def lib() -> ctypes.CDLL:
         L.gbl_inverse_transform.argtypes = [vp, vp, vp, vp]
         L.gbl_compress.argtypes = [vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_double), vp]
         L.gbl_energy_norm.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+        L.gbl_mass_inverse.argtypes = [i, i, vp, vp]
+        L.gbl_level_q_gamblets.argtypes = [i, i, vp, vp, vp]
+        L.gbl_level_q_load.argtypes = [i, i, vp, vp, vp, vp]
+        L.gbl_level_q_operator.argtypes = [i, i, vp, vp, vp, vp]
+        L.gbl_level_q_to_nodal.argtypes = [i, i, vp, vp, vp, vp]
         for name in ("gbl_default_opts", "gbl_workspace_bytes", "gbl_build", "gbl_solve", "gbl_adjoint",
                      "gbl_level_layout", "gbl_build_flags", "gbl_build_batched", "gbl_solve_batched",
                      "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset", "gbl_profile_read",
                      "gbl_transform_size", "gbl_transform", "gbl_inverse_transform", "gbl_compress",
-                     "gbl_energy_norm"):
+                     "gbl_energy_norm", "gbl_mass_inverse", "gbl_level_q_gamblets", "gbl_level_q_load",
+                     "gbl_level_q_operator", "gbl_level_q_to_nodal"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -305,6 +311,59 @@ class Hierarchy:
 
 PROF_KERNELS = ["assemble", "subband_operator", "patch_solve", "galerkin", "restrict", "cg_init", "cg_spmv",
                 "cg_update", "prolong", "fine_apply", "gradient", "fine_cg", "patch_band"]
+
+
+class LevelQ:
+    """Level-q gamblets from the localized mass inverse (Algorithm 2;
+    Definition 5.2) on the 2^q x 2^q cell grid, patch radius ``rho_q`` node
+    steps.  Holds the table of one-dimensional factors on the device; every
+    method is one C-ABI call on the current stream.  Interior vectors are
+    float64 ``[(2^q - 1)^2]`` tensors."""
+
+    def __init__(self, q: int, rho_q: int = 3, device=None):
+        self.q, self.rho_q = int(q), int(rho_q)
+        self.n = 1 << self.q
+        self.m = self.n - 1
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        w = 2 * self.rho_q + 1
+        self.table = torch.empty((max(self.m, 1), w), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().gbl_mass_inverse(self.q, self.rho_q, ctypes.c_void_p(self.table.data_ptr()),
+                                          _stream_ptr(self.device)))
+
+    def _call(self, name, *ptrs):
+        with torch.cuda.device(self.device):
+            _check(getattr(lib(), name)(self.q, self.rho_q, *[ctypes.c_void_p(p) for p in ptrs],
+                                        _stream_ptr(self.device)))
+
+    def gamblets(self) -> torch.Tensor:
+        """psi^(q)_i in the nodal basis, ``[m^2][(2 rho_q + 1)^2]``."""
+        w = 2 * self.rho_q + 1
+        out = torch.empty((self.m * self.m, w * w), dtype=torch.float64, device=self.device)
+        self._call("gbl_level_q_gamblets", self.table.data_ptr(), out.data_ptr())
+        return out
+
+    def load(self, b: torch.Tensor) -> torch.Tensor:
+        """g^(q) = Minv^T b for the nodal load b (``[m^2]``)."""
+        _require(b, (self.m * self.m,), "b")
+        out = torch.empty_like(b)
+        self._call("gbl_level_q_load", self.table.data_ptr(), b.data_ptr(), out.data_ptr())
+        return out
+
+    def operator(self, a: torch.Tensor) -> torch.Tensor:
+        """A^(q) = Minv^T A Minv as stencil rows ``[m^2][(2S + 1)^2]``, S = 2 rho_q + 1."""
+        _require(a, (self.n, self.n), "a")
+        W = 4 * self.rho_q + 3
+        out = torch.empty((self.m * self.m, W * W), dtype=torch.float64, device=self.device)
+        self._call("gbl_level_q_operator", a.data_ptr(), self.table.data_ptr(), out.data_ptr())
+        return out
+
+    def to_nodal(self, U: torch.Tensor) -> torch.Tensor:
+        """Nodal values Minv U of sum_i U_i psi^(q)_i."""
+        _require(U, (self.m * self.m,), "U")
+        out = torch.empty_like(U)
+        self._call("gbl_level_q_to_nodal", self.table.data_ptr(), U.data_ptr(), out.data_ptr())
+        return out
 
 
 def profile_enable(kernels="all"):

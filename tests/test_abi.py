@@ -99,3 +99,23 @@ def test_default_options():
     assert (o.inner_iters, o.inner_iters_coarse, o.kappa, o.kappa_coarse) == (16, 2, 200.0, 10.0)
     cg = P.make_opts(inner="cg", inner_iters=40)
     assert cg.inner_kind == 1 and P.workspace_bytes(6, cg) > 0   # CG budgets are not capped at 32
+
+
+def test_level_q_calls_validate_arguments():
+    """The level-q gamblet calls reject a bad q, patch radius or NULL pointer
+    before any device work."""
+    _, L = _lib()
+    p = ctypes.c_void_p(16)
+    assert L.gbl_mass_inverse(1, 3, p, None) == -1
+    assert b"q must be" in L.gbl_last_error(None)
+    assert L.gbl_mass_inverse(6, 0, p, None) == -1
+    assert L.gbl_mass_inverse(6, 5, p, None) == -1
+    assert b"rho_q" in L.gbl_last_error(None)
+    assert L.gbl_mass_inverse(6, 3, None, None) == -1
+    assert L.gbl_level_q_gamblets(6, 3, p, None, None) == -1
+    assert L.gbl_level_q_load(6, 3, p, None, p, None) == -1
+    assert L.gbl_level_q_load(6, 3, p, p, p, None) == -1
+    assert b"overlap" in L.gbl_last_error(None)
+    assert L.gbl_level_q_operator(13, 3, p, p, p, None) == -1
+    assert L.gbl_level_q_operator(6, 3, None, p, p, None) == -1
+    assert L.gbl_level_q_to_nodal(6, 3, p, p, p, None) == -1

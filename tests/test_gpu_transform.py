@@ -206,3 +206,39 @@ def test_materialized_gamblets_have_unit_energy(prec, tol_e, tol):
         ref = np.zeros(total); ref[j] = 1.0
         assert np.abs(back - ref).max() < tol, j
     H.close()
+
+
+def test_compress_selects_exactly_on_hard_inputs():
+    """The threshold search on vectors built to stress it: magnitudes over the
+    whole double range, repeated values at the threshold, zeros, infinities and
+    NaNs.  The kept set must be {|c| >= the keep-th largest number}, NaNs
+    zeroed; the reported threshold is that magnitude (0 when fewer than keep
+    entries are numbers)."""
+    _case(test="compress_hard_inputs")
+    pr = S.rough_problem(5, 1.0, 36)
+    H = _P().Hierarchy(_dev(pr.a), rho=2, precision="fp64")
+    total = H.transform_size()
+    rng = np.random.default_rng(12)
+    for trial in range(6):
+        c = rng.standard_normal(total) * 10.0 ** rng.integers(-300, 300, total).astype(float)
+        if trial >= 1:
+            c[rng.integers(0, total, total // 8)] = c[3]          # ties
+        if trial >= 2:
+            c[rng.integers(0, total, total // 4)] = 0.0
+        if trial >= 3:
+            c[rng.integers(0, total, 5)] = np.nan
+            c[rng.integers(0, total, 2)] = -np.inf
+        if trial == 5:
+            c[:] = np.nan
+            c[:7] = rng.standard_normal(7)
+        a = np.abs(c[~np.isnan(c)])
+        for keep in (1, 17, total // 100, total // 3, total - 1):
+            ref_thr = np.sort(a)[::-1][keep - 1] if keep <= a.size else 0.0
+            d = _dev(c)
+            thr = H.compress(d, keep)
+            out = d.cpu().numpy()
+            expect = np.where(np.abs(c) >= ref_thr, c, 0.0)
+            expect[np.isnan(c)] = 0.0
+            assert thr == ref_thr, (trial, keep, thr, ref_thr)
+            assert np.array_equal(out, expect), (trial, keep)
+    H.close()
