@@ -303,6 +303,58 @@ def main():
         torch.cuda.synchronize()
         extras["adjoint_grad_ms"] = (time.perf_counter() - tt) * 1e3 / nadj
         H.close()
+        # patch radius against outer iterations: gamblets with a smaller radius
+        # as the preconditioner of the FP64 flexible CG (build and solve timed
+        # apart, the minimum of three runs each)
+        print("# patch radius trade-off", file=sys.stderr, flush=True)
+        trade = {}
+        for prec in ("mixed", "fp64"):
+            for rho in (1, 2, 3, 4):
+                best_b, best_s = float("inf"), float("inf")
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    tb = time.perf_counter()
+                    Hr = P.Hierarchy(a, rho=rho, precision=prec, rtol=args.rtol if prec == "mixed" else 1e-10,
+                                     max_outer=2000)
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter()
+                    ur = Hr.solve(g, check=False)
+                    torch.cuda.synchronize()
+                    te = time.perf_counter()
+                    info_r = Hr.last_info
+                    Hr.close()
+                    best_b, best_s = min(best_b, (ts - tb) * 1e3), min(best_s, (te - ts) * 1e3)
+                err_r = float(np.linalg.norm(ur.cpu().numpy()[1:-1, 1:-1].ravel() - u_ref) / np.linalg.norm(u_ref))
+                trade[f"{prec}_rho{rho}"] = {"build_ms": best_b, "solve_ms": best_s, "total_ms": best_b + best_s,
+                                             "outer_iters": info_r.outer_iters, "rel_err_vs_oracle": err_r}
+        extras["patch_radius_tradeoff"] = trade
+        # level-q gamblets from the localized mass inverse (radius 3): the
+        # table of 1-D factors, the level-q operator and load
+        print("# level-q gamblets (localized mass inverse)", file=sys.stderr, flush=True)
+        lq = P.LevelQ(q, 3)
+        bq = torch.as_tensor(fem.load_cellwise(pr.g[0], 1.0 / pr.n), device=dev)
+        w1, w2 = lq.operator(a), lq.operator(a)   # two output blocks cached by the allocator
+        del w1, w2
+        torch.cuda.synchronize()
+
+        def event_ms(fn, reps=5):
+            # the library launches on torch's current stream, where the events are recorded
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps, out
+
+        t_table, _ = event_ms(lambda: P.LevelQ(q, 3))
+        t_op, aq = event_ms(lambda: lq.operator(a))
+        t_load, _ = event_ms(lambda: lq.load(bq))
+        op_bytes = aq.numel() * 8 + pr.n * pr.n * 8
+        extras["level_q_mass_inverse"] = {"rho_q": 3, "table_ms": t_table, "operator_ms": t_op, "load_ms": t_load,
+                                          "operator_bytes": op_bytes,
+                                          "operator_GBps": op_bytes / (t_op * 1e-3) / 1e9}
+        del aq
         # gamblet transform of a solution, compression by thresholding and the
         # reconstruction (discussion of Example 5.1, Figures 10-11): the smooth
         # source of the example on this grid, and the benchmark's white-noise source

@@ -79,7 +79,10 @@ typedef struct gbl_opts {
   int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3); 1..4 */
   int precision;      /* enum gbl_precision */
   double rtol;        /* target relative l2 error of u; the solve stops when the larger of ||S r|| and the
-                         last correction, over the last two iterations, is below rtol / 3 of ||u|| */
+                         last correction, over the last two iterations, is below rtol / f of ||u||, with
+                         f = max(3, 1 / (1 - c)) and c the per-iteration contraction of these estimates
+                         (the larger of the geometric means over the last 16 iterations
+                         and over the whole solve, capped at 0.995) */
   int max_outer;      /* maximum outer (flexible CG) iterations */
   int inner_iters;    /* iterations on the finest subband system per outer iteration (Chebyshev: <= 32) */
   int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */

@@ -182,6 +182,7 @@ def test_solve_inner_kinds_match_direct(inner, q, rho, sigma, prec, tol):
 @pytest.mark.parametrize("q,rho,sigma,prec,tol", [
     (6, 3, 1.0, "fp64", 1e-10), (6, 3, 2.0, "fp64", 1e-10), (6, 3, 2.0, "mixed", 1e-8),
     (7, 2, 2.0, "mixed", 1e-8), (5, 1, 1.0, "fp64", 1e-10), (2, 3, 1.0, "fp64", 1e-10),
+    (6, 1, 2.0, "mixed", 1e-8), (6, 4, 2.0, "mixed", 1e-8),
 ])
 def test_solve_matches_direct(q, rho, sigma, prec, tol):
     _print_case(test="solve", q=q, rho=rho, sigma=sigma, prec=prec)
@@ -333,6 +334,29 @@ def test_full_size_q9_matches_direct():
         print(prec, "err", err, H.last_info, flush=True)
         assert err < tol, (prec, err)
         H.close()
+
+
+@pytest.mark.timeout(300)
+def test_smaller_patch_radius_as_preconditioner_q9():
+    """Gamblets with a smaller patch radius as the preconditioner of the FP64
+    flexible CG (the paper's remark on gamblets as a preconditioner): on the
+    benchmark problem (512 x 512 cells, sigma = 2) rho = 1 and rho = 2 still
+    reach 1e-8 against the direct solve, with more outer iterations than
+    rho = 3; the stopping rule accounts for their slower contraction."""
+    _print_case(test="small_rho_q9")
+    pr = S.q9_rough_problem()
+    u_ref = fem.solve(pr.a, pr.g)[0][1:-1, 1:-1]
+    print("oracle done", flush=True)
+    iters = {}
+    for rho in (1, 2, 3):
+        H = _P().Hierarchy(_dev(pr.a), rho=rho, precision="mixed", rtol=1e-8, max_outer=2000)
+        u = H.solve(_dev(pr.g[0])).cpu().numpy()
+        err = _relerr(u[1:-1, 1:-1], u_ref)
+        iters[rho] = H.last_info.outer_iters
+        print("rho", rho, "err", err, H.last_info, flush=True)
+        assert err < 1e-8, (rho, err)
+        H.close()
+    assert iters[1] > iters[2] > iters[3]
 
 
 @pytest.mark.timeout(400)
