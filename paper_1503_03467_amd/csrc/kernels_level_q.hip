@@ -107,24 +107,27 @@ __global__ void k_level_q_to_nodal(int m, int rho, const double* __restrict__ Y,
   u[l] = acc;
 }
 
-// A_{l, l+s} of the Q1 stiffness matrix, l = (Lx, Ly) in full node
-// coordinates (interior: 1 .. n-1), s in {-1, 0, 1}^2, from the cell
-// coefficient a[cx][cy] and the unit element matrix (diagonal 4/6, edge
-// neighbour -1/6 per shared cell, diagonal neighbour -2/6).
-__device__ __forceinline__ double stiffness(const double* __restrict__ a, int n, int Lx, int Ly, int sx, int sy) {
+// A_{l, l+s} of the Q1 stiffness matrix, s in {-1, 0, 1}^2, from the cell
+// coefficient and the unit element matrix (diagonal 4/6, edge neighbour
+// -1/6 per shared cell, diagonal neighbour -2/6).  The cells are a block held
+// in LDS: sa[u * CA + v] is the cell (x0 + u, y0 + v), and (LX, LY) are the
+// node coordinates of l relative to (x0, y0) (node (X, Y) is the corner
+// shared by cells X-1 .. X and Y-1 .. Y).
+template <int CA>
+__device__ __forceinline__ double stiffness_lds(const double* __restrict__ sa, int LX, int LY, int sx, int sy) {
   if (sx == 0 && sy == 0)
-    return (4.0 / 6.0) * (a[(size_t)(Lx - 1) * n + Ly - 1] + a[(size_t)Lx * n + Ly - 1] + a[(size_t)(Lx - 1) * n + Ly] +
-                          a[(size_t)Lx * n + Ly]);
-  const int cx = sx < 0 ? Lx - 1 : Lx;
-  const int cy = sy < 0 ? Ly - 1 : Ly;
-  if (sy == 0) return (-1.0 / 6.0) * (a[(size_t)cx * n + Ly - 1] + a[(size_t)cx * n + Ly]);
-  if (sx == 0) return (-1.0 / 6.0) * (a[(size_t)(Lx - 1) * n + cy] + a[(size_t)Lx * n + cy]);
-  return (-2.0 / 6.0) * a[(size_t)cx * n + cy];
+    return (4.0 / 6.0) * (sa[(LX - 1) * CA + LY - 1] + sa[LX * CA + LY - 1] + sa[(LX - 1) * CA + LY] + sa[LX * CA + LY]);
+  const int cx = sx < 0 ? LX - 1 : LX;
+  const int cy = sy < 0 ? LY - 1 : LY;
+  if (sy == 0) return (-1.0 / 6.0) * (sa[cx * CA + LY - 1] + sa[cx * CA + LY]);
+  if (sx == 0) return (-1.0 / 6.0) * (sa[(LX - 1) * CA + cy] + sa[LX * CA + cy]);
+  return (-2.0 / 6.0) * sa[cx * CA + cy];
 }
 
 // One wavefront per interior node i, four nodes per workgroup.  Output row i
 // of A^(q): AQ[i][(dx + S)(2S + 1) + dy + S], S = 2 RHO + 1, zero where
-// i + (dx, dy) is not an interior node.
+// i + (dx, dy) is not an interior node.  The cells under the grown patch
+// (2 RHO + 4 per side) are staged in LDS first.
 template <int RHO>
 __global__ __launch_bounds__(256) void k_level_q_operator(int n, const double* __restrict__ a,
                                                           const double* __restrict__ Y, double* __restrict__ AQ) {
@@ -135,11 +138,21 @@ __global__ __launch_bounds__(256) void k_level_q_operator(int n, const double* _
   __shared__ double sy[4][2][AW][P];  // 1-D factors at ix + dx and iy + dy, dx, dy in [-S, S]
   __shared__ double sc[4][CW][CW];
   __shared__ double st[4][AW][CW];
+  constexpr int CA = 2 * RHO + 4;     // cells under the grown patch, per side
+  __shared__ double sa[4][CA * CA];
   const int m = n - 1;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long i = (long)blockIdx.x * 4 + wv;
   const bool valid = i < (long)m * m;
   const int ix = valid ? (int)(i / m) : 0, iy = valid ? (int)(i % m) : 0;
+  // node (ix + ox, iy + oy), interior coordinates, has node coordinates
+  // (ix + ox + 1, ...) and touches cells ix + ox .. ix + ox + 1: the block
+  // starts at cell x0 = ix - RHO - 1
+  const int x0 = ix - RHO - 1, y0 = iy - RHO - 1;
+  for (int e = lane; e < CA * CA; e += 64) {
+    const int cx = x0 + e / CA, cy = y0 + e % CA;
+    sa[wv][e] = (cx >= 0 && cx < n && cy >= 0 && cy < n) ? a[(size_t)cx * n + cy] : 0.0;
+  }
   // 1. factors of the patches of the nodes in the stencil's reach
   for (int e = lane; e < 2 * AW * P; e += 64) {
     const int dim = e / (AW * P), k = (e / P) % AW, d = e % P;
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(256) void k_level_q_operator(int n, const double* _
           const int wy = oy + sy_;
           if (wy < -RHO || wy > RHO) continue;
           const double f = fx * sy[wv][1][S][wy + RHO];
-          if (f != 0.0) acc += stiffness(a, n, lx + 1, ly + 1, sx, sy_) * f;
+          if (f != 0.0) acc += stiffness_lds<CA>(sa[wv], ox + RHO + 2, oy + RHO + 2, sx, sy_) * f;
         }
       }
     }
