@@ -92,6 +92,11 @@ typedef struct gbl_opts {
   double kappa;       /* Chebyshev: the interval is [G / kappa, G] on the finest level, G the block-
                          Gershgorin bound of lambda_max computed at build time; > 1 */
   double kappa_coarse;/* the same on the coarser levels */
+  int level_q_mass;   /* level-q gamblets: 0 = the nodal basis (psi^(q)_i = phi_i, the default); 1..4 = the
+                         localized mass inverse of Algorithm 2 and Definition 5.2 with this patch radius in
+                         node steps (psi^(q)_i = sum_j Minv_ji phi_j; see gbl_mass_inverse), with
+                         A^(q) = Minv^T A Minv; needs Chebyshev inner iterations and q >= 3 + (level_q_mass
+                         > 3); the gamblet transform calls reject such a hierarchy */
 } gbl_opts;
 
 typedef struct gbl_solve_info {

@@ -93,6 +93,7 @@ constexpr int kMaxChunk = 8;   // outer iterations launched between two looks at
 
 struct Layout {
   int q = 0, n = 0, rho = 0, prec = 0, max_rhs = 1;
+  int mass = 0;              // patch radius of the localized mass inverse at level q (0: nodal basis)
   size_t elem = 8;
   LevelGeom lv[kMaxLevels];
   size_t a_off = 0;          // copy of the coefficient (FP64, n^2)
@@ -121,6 +122,7 @@ struct Layout {
   size_t elog_off = 0;       // per-iteration error estimates of the outer iteration (max_outer + 2 doubles)
   size_t tr_off[kMaxLevels] = {};   // FP64 level vectors of the gamblet transform (nk^2 each)
   size_t sel_off = 0;        // selection state of the compression threshold (4 x 64-bit words + histogram)
+  size_t lqtab_off = 0;      // 1-D factors of the localized mass inverse ((n - 1) x (2 kMaxRhoQ + 1) doubles)
   size_t total = 0;
 };
 
@@ -136,6 +138,11 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
     return GBL_EINVAL;
   }
   if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
+  if (o->level_q_mass < 0 || o->level_q_mass > kMaxRhoQ) { msg = "level_q_mass must be in [0, 4]"; return GBL_EINVAL; }
+  if (o->level_q_mass > 0 && o->inner_kind != GBL_INNER_CHEBYSHEV) {
+    msg = "level_q_mass needs Chebyshev inner iterations";
+    return GBL_EINVAL;
+  }
   if (o->inner_kind != GBL_INNER_CHEBYSHEV && o->inner_kind != GBL_INNER_CG) {
     msg = "unknown inner_kind";
     return GBL_EINVAL;
@@ -171,6 +178,13 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     L.lv[k].nk = 1 << k;
   }
   L.lv[q].s = std::min(1, L.lv[q].nk - 1);
+  if (o->level_q_mass > 0) {
+    // A^(q) = Minv^T A Minv couples nodes up to 2 rho_q + 1 steps apart
+    const int S = 2 * o->level_q_mass + 1;
+    if (L.n - 1 < S) { msg = "level_q_mass needs 2^q - 1 >= 2 level_q_mass + 1"; return GBL_EINVAL; }
+    L.lv[q].s = S;
+    L.mass = o->level_q_mass;
+  }
   for (int k = q; k >= 2; --k) {
     LevelGeom& g = L.lv[k];
     const int nc = g.nk / 2;
@@ -251,6 +265,8 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   }
   L.sel_off = b;
   b = align_up(b + 4 * 8 + (size_t)kSelHistBins * 4);
+  L.lqtab_off = b;
+  b = align_up(b + (size_t)(L.n - 1) * (2 * kMaxRhoQ + 1) * 8);
   L.total = b;
   return GBL_OK;
 }
@@ -268,6 +284,8 @@ struct gbl_ctx {
   CGArgs<double> cgd;
   FineCG<float> fcgf;    // finest subband level
   FineCG<double> fcgd;
+  CGArgs<float> cgqf;    // finest level with a stored B^(q) (level-q gamblets from the mass inverse)
+  CGArgs<double> cgqd;
   hipStream_t side = nullptr;           // second stream: coarser subband CG runs beside the finest
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = -1;                      // device whose streams and events these are
@@ -280,6 +298,7 @@ struct gbl_ctx {
   float lmax[kMaxLevels] = {};          // bound of lambda_max(M B^(k)) per level
   ChebCoef cheb_fine{};                 // Chebyshev coefficients, finest level
   ChebStep cheb_coarse[kMaxCheb]{};     // Chebyshev coefficients per step, coarser levels
+  ChebStep cheb_q[kMaxCheb]{};          // the same for the stored finest level (slot 0)
   bool diverged = false;                // the last solve produced a non-finite estimate or residual
 
   template <typename T>
@@ -287,6 +306,7 @@ struct gbl_ctx {
   double* fine(int i) const { return reinterpret_cast<double*>(ws + L.fine_off[i]); }
   int* status() const { return reinterpret_cast<int*>(ws + L.status_off); }
   double* oscal() const { return reinterpret_cast<double*>(ws + L.oscal_off); }
+  double* lqtab() const { return reinterpret_cast<double*>(ws + L.lqtab_off); }
   const double* a() const { return reinterpret_cast<const double*>(ws + L.a_off); }
   double* L1() const { return reinterpret_cast<double*>(ws + L.L1_off); }
 };
@@ -412,6 +432,42 @@ CGArgs<T> make_cg_args(gbl_ctx* c) {
   return A;
 }
 
+// The finest subband system as a one-level CGArgs over its stored B^(q), for
+// hierarchies whose level-q gamblets come from the localized mass inverse
+// (their A^(q) is not the nine-point stencil the matrix-free kernels rebuild).
+template <typename T>
+CGArgs<T> make_cgq_args(gbl_ctx* c) {
+  const Layout& L = c->L;
+  const int k = L.q;
+  const LevelGeom& g = L.lv[k];
+  const size_t np2 = (size_t)g.nk * g.nk / 4;
+  CGArgs<T> A{};
+  CGLev<T>& v = A.lv[0];
+  v.B = c->hier<T>(g.offB);
+  v.BJ = c->hier<T>(g.offBJ);
+  v.g = reinterpret_cast<const T*>(c->ws + L.g_off[k]);
+  T* base = reinterpret_cast<T*>(c->ws + L.cgv_off[k]);
+  v.x = base;
+  v.r = base + 3 * np2;
+  v.z = base + 6 * np2;
+  v.p = base + 9 * np2;
+  v.q = base + 12 * np2;
+  // Chebyshev steps use no inner products; the scalar slot is level q - 1's
+  v.scal = reinterpret_cast<double*>(c->ws + L.cgscal_off);
+  v.part = reinterpret_cast<double*>(c->ws + L.cgpart_off[k]);
+  v.cnt = reinterpret_cast<unsigned*>(c->ws + L.cgcnt_off);
+  v.np = g.nk / 2;
+  v.t = g.t;
+  v.fine = 1;
+  v.iters = c->opts.inner_iters;
+  v.blk0 = 0;
+  v.nblk = (int)((np2 + 255) / 256);
+  v.blk0s = 0;
+  v.nblks = (int)((np2 + 63) / 64);
+  A.nlev = 1;
+  return A;
+}
+
 template <typename T>
 FineCG<T> make_fine_cg(gbl_ctx* c) {
   const Layout& L = c->L;
@@ -462,6 +518,11 @@ void make_cheb_tables(gbl_ctx* c) {
   const Layout& L = c->L;
   ChebCoef& f = c->cheb_fine;
   cheb_coefs(c->lmax[L.q], c->opts.kappa, c->opts.inner_iters, f.c0, f.ca, f.cb);
+  for (int step = 0; step < kMaxCheb; ++step) {
+    c->cheb_q[step].c0[0] = f.c0;
+    c->cheb_q[step].ca[0] = f.ca[step];
+    c->cheb_q[step].cb[0] = f.cb[step];
+  }
   // coarser levels: slot l of the CG arguments is level q - 1 - l
   for (int l = 0; l + 2 <= L.q - 1 && l < kMaxLevels; ++l) {
     const int k = L.q - 1 - l;
@@ -481,7 +542,15 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
   const int q = L.q;
   {
     ProfScope ps(GBL_PROF_ASSEMBLE, st);
-    launch_assemble_fine<T>(c->a(), c->hier<T>(L.lv[q].offA), L.n, c->status(), st);
+    if (L.mass > 0) {
+      // level-q gamblets from the localized mass inverse (Algorithm 2;
+      // Definition 5.2): A^(q) = Minv^T A Minv on the empty-slot grid
+      launch_mass_inverse_table(L.n, L.mass, c->lqtab(), st);
+      launch_zero<T>(L.lv[q].nA, c->hier<T>(L.lv[q].offA), st);
+      launch_level_q_operator_arena<T>(L.n, L.mass, c->a(), c->lqtab(), c->hier<T>(L.lv[q].offA), c->status(), st);
+    } else {
+      launch_assemble_fine<T>(c->a(), c->hier<T>(L.lv[q].offA), L.n, c->status(), st);
+    }
     launch_convert<T, double>((size_t)L.n * L.n, c->a(), c->hier<T>(L.acell_off), st);
   }
   for (int k = q; k >= 2; --k) {
@@ -516,6 +585,8 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
 // a second stream (the subband systems are independent, Section 4.7).
 template <typename T>
 const FineCG<T>& fcg_of(const gbl_ctx* c);
+template <typename T>
+const CGArgs<T>& cgq_of(const gbl_ctx* c);
 
 // r_converted: g^(q) already holds T(r).  When dots is set, the finest
 // prolongation also forms (z, z), (u, u), (z, w) into dots[0..3).
@@ -544,7 +615,10 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     cl.rho = L.lv[k].rho;
     cl.fine = 0;
   }
-  if (!r_converted) launch_convert<T, double>(n2, r, g[q], st);
+  if (L.mass > 0)
+    launch_mass_load_slots<T>(L.n, L.mass, c->lqtab(), r, g[q], st);   // g^(q) = Minv^T r
+  else if (!r_converted)
+    launch_convert<T, double>(n2, r, g[q], st);
   // The subband systems are independent (Section 4.7), so they run beside each
   // other: the finest one on the caller's stream (it needs only g^(q)), and
   // the restriction chain, the coarser systems and the prolongation down to
@@ -605,7 +679,18 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   // branches, so that a replayed graph starts that chain first): Chebyshev
   // steps fused four per launch, or one CG iteration per launch (whose last
   // step x += alpha p is applied inside the prolongation)
-  if (cheb) {
+  if (cheb && L.mass > 0) {
+    // stored B^(q): the generic Chebyshev kernels on a one-level argument set
+    const CGArgs<T>& Q = cgq_of<T>(c);
+    {
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_cheb_init<T>(Q, c->cheb_q[0], 0, 1, st);
+    }
+    for (int j = 1; j < c->opts.inner_iters; ++j) {
+      ProfScope ps(GBL_PROF_FINE_CG, st);
+      launch_cheb_step<T>(Q, c->cheb_q[j], j, 0, 1, st);
+    }
+  } else if (cheb) {
     const int K = c->opts.inner_iters;
     int fuse = 4;   // steps per launch (GBL_CHEB_FUSE = 1..4; the halo is 4 parents)
     if (const char* e = getenv("GBL_CHEB_FUSE")) {
@@ -635,8 +720,14 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
   // the partial sums (z, z), (u, u), (z, w) go to the second half of the outer partials
   double* opart = reinterpret_cast<double*>(c->ws + L.opart_off) + 3 * (size_t)L.onblk;
-  launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z, opart,
-                              cheb ? 1 : 0, st);
+  if (L.mass > 0) {
+    // v^(q) in the level-q slots, then the nodal vector z = Minv v^(q)
+    launch_prolong<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], cgq_of<T>(c).lv[0].x, g[q], true, st);
+    launch_mass_nodal_dots<T>(L.n, L.mass, c->lqtab(), g[q], z, dots ? uo : z, dots ? wo : z, opart, st);
+  } else {
+    launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z,
+                                opart, cheb ? 1 : 0, st);
+  }
   (void)part;
   (void)cnt;
 }
@@ -843,6 +934,10 @@ template <>
 const FineCG<float>& fcg_of<float>(const gbl_ctx* c) { return c->fcgf; }
 template <>
 const FineCG<double>& fcg_of<double>(const gbl_ctx* c) { return c->fcgd; }
+template <>
+const CGArgs<float>& cgq_of<float>(const gbl_ctx* c) { return c->cgqf; }
+template <>
+const CGArgs<double>& cgq_of<double>(const gbl_ctx* c) { return c->cgqd; }
 
 template <typename T>
 int solve_many(gbl_ctx* c, int nrhs, int mode, const double* src, size_t src_stride, double* u,
@@ -894,6 +989,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->inner_kind = GBL_INNER_CHEBYSHEV;
   o->kappa = 200.0;
   o->kappa_coarse = 10.0;
+  o->level_q_mass = 0;
   return GBL_OK;
 }
 
@@ -958,6 +1054,8 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   }
   c->cgf = make_cg_args<float>(c);
   c->cgd = make_cg_args<double>(c);
+  c->cgqf = make_cgq_args<float>(c);
+  c->cgqd = make_cgq_args<double>(c);
   c->fcgf = make_fine_cg<float>(c);
   c->fcgd = make_fine_cg<double>(c);
   st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
@@ -1230,6 +1328,7 @@ int gbl_transform_size(const gbl_ctx* c, size_t* count) {
 int gbl_transform(gbl_ctx* c, const double* u_dev, double* coef_dev, void* stream) {
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
+  if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (c->L.prec == GBL_FP64) launch_transform<double>(transform_args<double>(c), u_dev, coef_dev, s);
   else launch_transform<float>(transform_args<float>(c), u_dev, coef_dev, s);
@@ -1240,6 +1339,7 @@ int gbl_transform(gbl_ctx* c, const double* u_dev, double* coef_dev, void* strea
 int gbl_inverse_transform(gbl_ctx* c, const double* coef_dev, double* u_dev, void* stream) {
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
+  if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (c->L.prec == GBL_FP64) launch_inverse_transform<double>(transform_args<double>(c), coef_dev, u_dev, s);
   else launch_inverse_transform<float>(transform_args<float>(c), coef_dev, u_dev, s);

@@ -110,5 +110,10 @@ void launch_level_q_weights(int n, int rho, const double* Y, double* W, hipStrea
 void launch_level_q_load(int n, int rho, const double* Y, const double* b, double* gq, hipStream_t st);
 void launch_level_q_to_nodal(int n, int rho, const double* Y, const double* U, double* u, hipStream_t st);
 void launch_level_q_operator(int n, int rho, const double* a, const double* Y, double* AQ, hipStream_t st);
+// the same operator into the hierarchy's level-q stencil (offset-major, half
+// width 2 rho + 1, slots shifted by one), after a check of the coefficient
+template <typename T>
+void launch_level_q_operator_arena(int n, int rho, const double* a, const double* Y, T* A, int* status,
+                                   hipStream_t st);
 
 }  // namespace gbl

@@ -128,9 +128,13 @@ __device__ __forceinline__ double stiffness_lds(const double* __restrict__ sa, i
 // of A^(q): AQ[i][(dx + S)(2S + 1) + dy + S], S = 2 RHO + 1, zero where
 // i + (dx, dy) is not an interior node.  The cells under the grown patch
 // (2 RHO + 4 per side) are staged in LDS first.
-template <int RHO>
+// With ARENA set the row goes to the hierarchy's offset-major level-q
+// operator instead: AQ[(dx + S)(2S + 1) + dy + S][slot], slot = (ix + 1) n +
+// iy + 1, in the hierarchy's precision T (the empty slots x = 0 or y = 0 are
+// left to the caller).
+template <int RHO, typename T = double, bool ARENA = false>
 __global__ __launch_bounds__(256) void k_level_q_operator(int n, const double* __restrict__ a,
-                                                          const double* __restrict__ Y, double* __restrict__ AQ) {
+                                                          const double* __restrict__ Y, T* __restrict__ AQ) {
   constexpr int P = 2 * RHO + 1;      // patch width
   constexpr int CW = 2 * RHO + 3;     // width of the support of c = A Minv e_i
   constexpr int S = 2 * RHO + 1;      // half width of the level-q stencil
@@ -207,7 +211,10 @@ __global__ __launch_bounds__(256) void k_level_q_operator(int n, const double* _
         const int d = (cy - (RHO + 1)) - dy;
         if (d >= -RHO && d <= RHO) acc += st[wv][kx][cy] * sy[wv][1][ky][d + RHO];
       }
-      AQ[(size_t)i * AW * AW + e] = acc;
+      if (ARENA)
+        AQ[(size_t)e * n * n + (size_t)(ix + 1) * n + iy + 1] = T(acc);
+      else
+        AQ[(size_t)i * AW * AW + e] = T(acc);
     }
   }
 }
@@ -243,5 +250,32 @@ void launch_level_q_operator(int n, int rho, const double* a, const double* Y, d
     default: hipLaunchKernelGGL(k_level_q_operator<4>, grid, block, 0, st, n, a, Y, AQ); break;
   }
 }
+
+// Positive, finite cell coefficients (the nodal-basis build checks them in
+// its assembly kernel).
+__global__ void k_check_cells(const double* __restrict__ a, int n, int* __restrict__ status) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const double v = a[id];
+  if (!(v > 0.0) || !(v < INFINITY)) atomicOr(status, kBadCoefficient);
+}
+
+template <typename T>
+void launch_level_q_operator_arena(int n, int rho, const double* a, const double* Y, T* A, int* status,
+                                   hipStream_t st) {
+  const long m2 = (long)(n - 1) * (n - 1);
+  const dim3 grid((unsigned)((m2 + 3) / 4)), block(256);
+  hipLaunchKernelGGL(k_check_cells, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, status);
+  switch (rho) {
+    case 1: hipLaunchKernelGGL((k_level_q_operator<1, T, true>), grid, block, 0, st, n, a, Y, A); break;
+    case 2: hipLaunchKernelGGL((k_level_q_operator<2, T, true>), grid, block, 0, st, n, a, Y, A); break;
+    case 3: hipLaunchKernelGGL((k_level_q_operator<3, T, true>), grid, block, 0, st, n, a, Y, A); break;
+    default: hipLaunchKernelGGL((k_level_q_operator<4, T, true>), grid, block, 0, st, n, a, Y, A); break;
+  }
+}
+template void launch_level_q_operator_arena<float>(int, int, const double*, const double*, float*, int*,
+                                                   hipStream_t);
+template void launch_level_q_operator_arena<double>(int, int, const double*, const double*, double*, int*,
+                                                    hipStream_t);
 
 }  // namespace gbl

@@ -1407,7 +1407,95 @@ void launch_cell_gradient(const double* a, int n, const double* u, const double*
   hipLaunchKernelGGL(k_cell_gradient, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, u, lam, dloga, dg);
 }
 
+// ---------------------------------------------------------------------------
+// Level-q gamblets from the localized mass inverse (Algorithm 2; Definition
+// 5.2): the finest subband right-hand side is g^(q) = Minv^T r and the finest
+// prolongation v^(q) stands for the nodal vector z = Minv v^(q).  Slot (x, y),
+// x, y >= 1, holds interior node (x - 1, y - 1); Y is the table of 1-D
+// factors ([n - 1][2 rho + 1]) and a node's weight at offset (dx, dy) is
+// Y[ix][dx] Y[iy][dy].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_mass_load_slots(int n, int rho, const double* __restrict__ Y, const double* __restrict__ r,
+                                  T* __restrict__ g) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * n) return;
+  const int x = id / n, y = id % n;
+  if (x == 0 || y == 0) {
+    g[id] = T(0);
+    return;
+  }
+  const int m = n - 1, w = 2 * rho + 1;
+  const int ix = x - 1, iy = y - 1;
+  double acc = 0.0;
+  for (int dx = -rho; dx <= rho; ++dx) {
+    const int lx = ix + dx;
+    if (lx < 0 || lx >= m) continue;
+    double row = 0.0;
+    for (int dy = -rho; dy <= rho; ++dy) {
+      const int ly = iy + dy;
+      if (ly < 0 || ly >= m) continue;
+      row += Y[(size_t)iy * w + dy + rho] * r[(size_t)(lx + 1) * n + ly + 1];
+    }
+    acc += Y[(size_t)ix * w + dx + rho] * row;
+  }
+  g[id] = T(acc);
+}
+
+// z = Minv v (FP64 slots, zero on the empty slots) and the partial sums
+// (z, z), (u, u), (z, w) of k_prolong_fine_dots, in its layout.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass_nodal_dots(int n, int rho, const double* __restrict__ Y,
+                                                         const T* __restrict__ v, double* __restrict__ z,
+                                                         const double* __restrict__ uo,
+                                                         const double* __restrict__ wo, double* part) {
+  __shared__ double sh[3 * 16];
+  double acc3[3] = {0.0, 0.0, 0.0};
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n * n) {
+    const int x = id / n, y = id % n;
+    double zv = 0.0;
+    if (x > 0 && y > 0) {
+      const int m = n - 1, w = 2 * rho + 1;
+      const int lx = x - 1, ly = y - 1;
+      for (int dx = -rho; dx <= rho; ++dx) {
+        const int ix = lx - dx;
+        if (ix < 0 || ix >= m) continue;
+        double row = 0.0;
+        for (int dy = -rho; dy <= rho; ++dy) {
+          const int iy = ly - dy;
+          if (iy < 0 || iy >= m) continue;
+          row += Y[(size_t)iy * w + dy + rho] * (double)v[(size_t)(ix + 1) * n + iy + 1];
+        }
+        zv += Y[(size_t)ix * w + dx + rho] * row;
+      }
+    }
+    z[id] = zv;
+    const double uv = uo[id];
+    acc3[0] = zv * zv;
+    acc3[1] = uv * uv;
+    acc3[2] = zv * wo[id];
+  }
+  block_sum<3>(acc3, sh);
+  write_partials<3>(acc3, part, gridDim.x, blockIdx.x);
+}
+
+template <typename T>
+void launch_mass_load_slots(int n, int rho, const double* Y, const double* r, T* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_mass_load_slots<T>, dim3((n * n + 255) / 256), dim3(256), 0, st, n, rho, Y, r, g);
+}
+
+template <typename T>
+void launch_mass_nodal_dots(int n, int rho, const double* Y, const T* v, double* z, const double* uo,
+                            const double* wo, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_mass_nodal_dots<T>, dim3((n * n + 255) / 256), dim3(256), 0, st, n, rho, Y, v, z, uo, wo,
+                     part);
+}
+
 #define GBL_INST(T)                                                                                      \
+  template void launch_mass_load_slots<T>(int, int, const double*, const double*, T*, hipStream_t);     \
+  template void launch_mass_nodal_dots<T>(int, int, const double*, const T*, double*, const double*,    \
+                                          const double*, double*, hipStream_t);                         \
   template void launch_restrict<T>(const LevelGeom&, const T*, const T*, T*, hipStream_t);              \
   template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t); \
   template void launch_coarse_solve<T>(const double*, const T*, T*, hipStream_t);                       \

@@ -117,6 +117,13 @@ void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int 
 
 template <typename T>
 void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
+// Level-q gamblets from the localized mass inverse: g^(q) = Minv^T r, and
+// z = Minv v^(q) with the partial sums of launch_prolong_fine_dots.
+template <typename T>
+void launch_mass_load_slots(int n, int rho, const double* Y, const double* r, T* g, hipStream_t st);
+template <typename T>
+void launch_mass_nodal_dots(int n, int rho, const double* Y, const T* v, double* z, const double* uo,
+                            const double* wo, double* part, hipStream_t st);
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
                               const double* uo, const double* wo, double* part, int cheb, hipStream_t st);

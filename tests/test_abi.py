@@ -119,3 +119,15 @@ def test_level_q_calls_validate_arguments():
     assert L.gbl_level_q_operator(13, 3, p, p, p, None) == -1
     assert L.gbl_level_q_operator(6, 3, None, p, p, None) == -1
     assert L.gbl_level_q_to_nodal(6, 3, p, p, p, None) == -1
+
+
+def test_level_q_mass_option_validated():
+    P, L = _lib()
+    o = P.make_opts(level_q_mass=5)
+    assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1
+    assert b"level_q_mass" in L.gbl_last_error(None)
+    o = P.make_opts(level_q_mass=2, inner="cg")
+    assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1
+    o = P.make_opts(level_q_mass=3)
+    assert L.gbl_workspace_bytes(2, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1   # 2^2 - 1 < 7
+    assert P.workspace_bytes(6, P.make_opts(level_q_mass=3)) > P.workspace_bytes(6, P.make_opts())
