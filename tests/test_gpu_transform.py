@@ -183,7 +183,7 @@ def test_compression_full_size_q9():
 def test_materialized_gamblets_have_unit_energy(prec, tol_e, tol):
     """The inverse transform of a one-hot coefficient vector is the normalized
     gamblet psi^(1)_i / ||psi^(1)_i||_a or chi^(k)_j / ||chi^(k)_j||_a on the
-    fine mesh (Algorithm 2, lines 9 and 14): its energy norm is 1, measured with
+    fine mesh (Algorithm 2, the steps that form chi^(k) and psi^(k-1)): its energy norm is 1, measured with
     the FP64 fine operator.  In the mixed path the normalizing B^(k)_jj comes
     from the FP32 Galerkin products, hence the same 1e-3 as the coefficients."""
     q = 7
