@@ -39,7 +39,7 @@ def _relerr(x, y):
     return float(np.linalg.norm(np.ravel(x) - np.ravel(y)) / max(np.linalg.norm(np.ravel(y)), 1e-300))
 
 
-@pytest.mark.parametrize("q,rho,rho_q,sigma", [(4, 2, 2, 1.0), (5, 3, 1, 2.0), (5, 3, 3, 2.0)])
+@pytest.mark.parametrize("q,rho,rho_q,sigma", [(4, 2, 2, 1.0), (5, 3, 1, 2.0), (5, 3, 3, 2.0), (5, 2, 4, 1.0), (3, 1, 1, 1.0)])
 def test_hierarchy_levels_match_oracle_fp64(q, rho, rho_q, sigma):
     _case(test="mass_hierarchy", q=q, rho=rho, rho_q=rho_q, sigma=sigma)
     pr = S.rough_problem(q, sigma, 61)
