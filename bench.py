@@ -407,13 +407,11 @@ def main():
         total = H.transform_size()
 
         def timed(fn, reps=5):
+            # HIP events on torch's current stream (the library's stream); a
+            # compression includes its host read of the threshold
             fn()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                out = fn()
-            torch.cuda.synchronize()
-            return (time.perf_counter() - t0) * 1e3 / reps, out
+            return event_ms(fn, reps)
 
         tr = {"coefficients": total}
         tr["transform_ms"], c = timed(lambda: H.transform(us))
