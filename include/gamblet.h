@@ -242,7 +242,8 @@ int gbl_level_layout(const gbl_ctx* ctx, int k, gbl_level_desc* desc);
 int gbl_transform_size(const gbl_ctx* ctx, size_t* count);
 
 /* coef = normalized gamblet coefficients of u.  Asynchronous on stream.
- * EINVAL on NULL arguments, EHIP on a launch failure. */
+ * EINVAL on NULL arguments or a hierarchy built with level_q_mass > 0 (its
+ * level-q measurements are not nodal values), EHIP on a launch failure. */
 int gbl_transform(gbl_ctx* ctx, const double* u_dev, double* coef_dev, void* stream);
 
 /* u = sum of the coefficients times the normalized gamblets (the inverse of
