@@ -398,6 +398,61 @@ def main():
                                           "operator_bytes": op_bytes,
                                           "operator_GBps": op_bytes / (t_op * 1e-3) / 1e9}
         del aq
+        # the adjoint workload (1024 x 1024 cells, sigma = 1, J = |u - u_obs|^2 / 2):
+        # build, solve and adjoint gradient timed apart (minimum of two runs)
+        print("# adjoint workload, 1024 x 1024 cells", file=sys.stderr, flush=True)
+        pa = S.adjoint_problem(q=10)
+        a10 = torch.as_tensor(pa.a, device=dev)
+        g10 = torch.as_tensor(pa.g[0], device=dev)
+        Ho = P.Hierarchy(torch.as_tensor(pa.extra["a_obs"], device=dev), rho=3, precision=args.precision,
+                         rtol=args.rtol)
+        uo10 = Ho.solve(g10)
+        Ho.close()
+        best = [float("inf")] * 3
+        for _ in range(3):   # the first run sets up the iteration graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H10 = P.Hierarchy(a10, rho=3, precision=args.precision, rtol=args.rtol)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            u10 = H10.solve(g10, check=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            H10.adjoint(u10, (u10 - uo10).contiguous(), check=False)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            it10 = H10.last_info.outer_iters
+            H10.close()
+            best = [min(b, v) for b, v in zip(best, ((t1 - t0) * 1e3, (t2 - t1) * 1e3, (t3 - t2) * 1e3))]
+        dof10 = ((1 << 10) - 1) ** 2
+        extras["adjoint_workload_q10"] = {"dof": dof10, "build_ms": best[0], "solve_ms": best[1],
+                                          "adjoint_grad_ms": best[2], "adjoint_outer_iters": it10,
+                                          "build_solve_dof_per_s": dof10 / ((best[0] + best[1]) * 1e-3)}
+        del a10, g10, uo10, u10
+        # batch workload: independent problems of 64 x 64 to 256 x 256 cells
+        # with 64 right-hand sides each, built and solved concurrently; a
+        # sample of 32 of the 256 problems keeps the run short
+        print("# batch workload sample", file=sys.stderr, flush=True)
+        probs = S.batch_problems(count=32, nrhs=64)
+        coeffs = [torch.as_tensor(pb.a, device=dev) for pb in probs]
+        srcs = [torch.as_tensor(pb.g, device=dev) for pb in probs]
+        hs = P.build_batched(coeffs, rho=3, precision=args.precision, rtol=args.rtol, max_rhs=64)
+        P.solve_batched(hs, [x[:1].contiguous() for x in srcs], check=False)   # warm-up: streams, graphs
+        for h in hs:
+            h.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hs = P.build_batched(coeffs, rho=3, precision=args.precision, rtol=args.rtol, max_rhs=64)
+        P.solve_batched(hs, srcs, check=False)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) * 1e3
+        for h in hs:
+            h.close()
+        dofs = sum(((1 << pb.q) - 1) ** 2 * 64 for pb in probs)
+        extras["batch_workload_sample"] = {"problems": len(probs), "rhs_per_problem": 64,
+                                           "q_counts": {str(qq): sum(1 for pb in probs if pb.q == qq) for qq in (6, 7, 8)},
+                                           "build_solve_ms": tb, "dof_per_s": dofs / (tb * 1e-3)}
+        del coeffs, srcs, hs
         # gamblet transform of a solution, compression by thresholding and the
         # reconstruction (discussion of Example 5.1, Figures 10-11): the smooth
         # source of the example on this grid, and the benchmark's white-noise source
