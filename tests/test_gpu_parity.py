@@ -414,3 +414,52 @@ def test_inclusions_q11_rho4():
     err = _relerr(u[0][1:-1, 1:-1], u_ref)
     print("err vs direct", err, flush=True)
     assert err < 1e-8, err
+
+
+def _torch_residual(a, g, u):
+    """b - A u over the interior nodes for the Q1 stiffness matrix of the cell
+    coefficient a and the cell-wise load b_i = (h^2/4) sum_{e ni i} g_e,
+    formed element by element with torch on the device (test-side; no library
+    or oracle code).  u is the full nodal array with zero boundary values."""
+    n = a.shape[0]
+    h = 1.0 / n
+    K = torch.tensor([[4.0, -1.0, -1.0, -2.0], [-1.0, 4.0, -2.0, -1.0],
+                      [-1.0, -2.0, 4.0, -1.0], [-2.0, -1.0, -1.0, 4.0]], dtype=torch.float64, device=a.device) / 6.0
+    loc = torch.stack([u[:-1, :-1], u[1:, :-1], u[:-1, 1:], u[1:, 1:]])          # local nodes (0,0) (1,0) (0,1) (1,1)
+    y = [sum(K[k, l] * loc[l] for l in range(4)) * a for k in range(4)]           # element contributions
+    Au = torch.zeros_like(u)
+    Au[:-1, :-1] += y[0]
+    Au[1:, :-1] += y[1]
+    Au[:-1, 1:] += y[2]
+    Au[1:, 1:] += y[3]
+    b = torch.zeros_like(u)
+    q4 = 0.25 * h * h * g
+    b[:-1, :-1] += q4
+    b[1:, :-1] += q4
+    b[:-1, 1:] += q4
+    b[1:, 1:] += q4
+    r = (b - Au)[1:-1, 1:-1]
+    return float(torch.linalg.norm(r) / torch.linalg.norm(b[1:-1, 1:-1]))
+
+
+@pytest.mark.timeout(300)
+def test_largest_grid_q12():
+    """The largest grid the library accepts (4096 x 4096 cells, 16.8M DOF),
+    mixed precision, patch radius 3: no direct solve of this size fits the
+    test budget, so the check is the FP64 residual of the returned solution,
+    formed independently on the device, against the library's own report;
+    the solve must also have converged (status OK)."""
+    _print_case(test="largest_q12")
+    pr = S.rough_problem(12, 1.0, 71)
+    a = _dev(pr.a)
+    g = _dev(pr.g[0])
+    H = _P().Hierarchy(a, rho=3, precision="mixed", rtol=1e-8, max_outer=400)
+    u = H.solve(g)
+    info = H.last_info
+    print("info", info, flush=True)
+    res = _torch_residual(a, g, u)
+    print("residual", res, flush=True)
+    assert info.status == 0
+    assert res < 1e-6
+    assert abs(res - info.rel_residual) <= 0.01 * res + 1e-15
+    H.close()
