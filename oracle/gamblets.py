@@ -209,6 +209,9 @@ def localized_hierarchy(A: sp.spmatrix, tree: Tree, rho: int, construction: int 
     For every coarse index i of level k-1 the patch system
     B^(i,rho) y = -(W A^(k) pibar^T)_{i^chi, i} of Definition 5.3 is solved by a
     dense Cholesky factorisation; y fills column i of D^(k,k-1) on i^chi.
+    ``rho`` is one radius for every transition, or a dict k -> rho_(k-1), the
+    radius of the patches of the transition from level k to level k-1
+    (Algorithm 2 allows a radius per level).
     """
     q = tree.q
     Ak = sp.csr_matrix(A)
@@ -220,8 +223,9 @@ def localized_hierarchy(A: sp.spmatrix, tree: Tree, rho: int, construction: int 
         rhs = -(W @ Ak @ pibar.T).tocsc()
         jpar = tree.jparent(k)
         rows, cols, vals = [], [], []
+        rho_k = rho[k] if isinstance(rho, dict) else rho
         for i in range(tree.size(k - 1)):
-            chi = patch_index_set(tree, k, i, rho, jpar)
+            chi = patch_index_set(tree, k, i, rho_k, jpar)
             if chi.size == 0:
                 continue
             Bp = B[chi][:, chi].toarray()

@@ -211,3 +211,24 @@ def test_example51_exact_transform():
     tree = G.Tree(6, offset=1)
     H = G.exact_hierarchy(fe.A, tree)
     assert np.linalg.norm(G.solve(H, b) - u) / np.linalg.norm(u) < 1e-12
+
+
+def test_per_level_radii():
+    """Algorithm 2 with one patch radius per transition: equal radii given per
+    level reproduce the single-radius hierarchy, and radii that cover every
+    level reproduce the exact hierarchy (Algorithm 1)."""
+    q = 4
+    pr = S.rough_problem(q, 1.5, 24)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    one = G.localized_hierarchy(fe.A, tree, 2)
+    per = G.localized_hierarchy(fe.A, tree, {k: 2 for k in range(2, q + 1)})
+    for k in range(1, q + 1):
+        assert abs(one.levels[k].A - per.levels[k].A).max() == 0.0
+    cover = G.localized_hierarchy(fe.A, tree, {k: 1 << (k - 1) for k in range(2, q + 1)})
+    ex = G.exact_hierarchy(fe.A, tree)
+    for k in range(1, q + 1):
+        d = abs(cover.levels[k].A - ex.levels[k].A).max() / abs(ex.levels[k].A).max()
+        assert d < 1e-10, (k, d)
+    mixed = G.localized_hierarchy(fe.A, tree, {q: 2, 3: 1, 2: 1})
+    assert abs(mixed.levels[2].A - one.levels[2].A).max() > 0.0
