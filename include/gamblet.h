@@ -97,6 +97,8 @@ typedef struct gbl_opts {
                          node steps (psi^(q)_i = sum_j Minv_ji phi_j; see gbl_mass_inverse), with
                          A^(q) = Minv^T A Minv; needs Chebyshev inner iterations and q >= 3 + (level_q_mass
                          > 3); the gamblet transform calls reject such a hierarchy */
+  int rho_coarse;     /* patch radius of the transitions below the finest (levels k < q, Algorithm 2 allows
+                         one radius per level); 0 = rho; 1..4 */
 } gbl_opts;
 
 typedef struct gbl_solve_info {

@@ -139,6 +139,7 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   }
   if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
   if (o->level_q_mass < 0 || o->level_q_mass > kMaxRhoQ) { msg = "level_q_mass must be in [0, 4]"; return GBL_EINVAL; }
+  if (o->rho_coarse < 0 || o->rho_coarse > kMaxRho) { msg = "rho_coarse must be in [0, 4]"; return GBL_EINVAL; }
   if (o->level_q_mass > 0 && o->inner_kind != GBL_INNER_CHEBYSHEV) {
     msg = "level_q_mass needs Chebyshev inner iterations";
     return GBL_EINVAL;
@@ -188,7 +189,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   for (int k = q; k >= 2; --k) {
     LevelGeom& g = L.lv[k];
     const int nc = g.nk / 2;
-    g.rho = std::min(o->rho, nc - 1);
+    g.rho = std::min((k == q || o->rho_coarse == 0) ? o->rho : o->rho_coarse, nc - 1);
     g.rw = 2 * (2 * g.rho + 1);
     g.t = std::min((g.s + 1) / 2, nc - 1);
     L.lv[k - 1].s = std::min((4 * g.rho + 1 + g.s) / 2, nc - 1);
@@ -990,6 +991,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->kappa = 200.0;
   o->kappa_coarse = 10.0;
   o->level_q_mass = 0;
+  o->rho_coarse = 0;
   return GBL_OK;
 }
 

@@ -24,7 +24,8 @@ class GblOpts(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
-                ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int)]
+                ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
+                ("rho_coarse", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -107,7 +108,7 @@ INNER_KINDS = {"chebyshev": 0, "cg": 1}
 def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 100,
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
-              level_q_mass: int = 0) -> GblOpts:
+              level_q_mass: int = 0, rho_coarse: int = 0) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -126,6 +127,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
         o.inner_iters_coarse = int(inner_iters_coarse)
     o.max_rhs = int(max_rhs)
     o.level_q_mass = int(level_q_mass)
+    o.rho_coarse = int(rho_coarse)
     return o
 
 
@@ -160,7 +162,7 @@ class Hierarchy:
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
-                 kappa_coarse: float | None = None, level_q_mass: int = 0):
+                 kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0):
         n = a.shape[0]
         q = n.bit_length() - 1
         if n != (1 << q) or q < 2:
@@ -168,7 +170,7 @@ class Hierarchy:
         _require(a, (n, n), "a")
         self.q, self.n, self.device = q, n, a.device
         self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
-                              kappa_coarse, level_q_mass)
+                              kappa_coarse, level_q_mass, rho_coarse)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):

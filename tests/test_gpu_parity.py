@@ -359,6 +359,46 @@ def test_smaller_patch_radius_as_preconditioner_q9():
     assert iters[1] > iters[2] > iters[3]
 
 
+@pytest.mark.parametrize("q,rho,rho_c", [(5, 3, 2), (5, 2, 3), (6, 3, 1)])
+def test_per_level_radius_hierarchy_matches_oracle_fp64(q, rho, rho_c):
+    """A different patch radius below the finest transition (rho_coarse):
+    every level's A^(k), B^(k), R^(k-1,k) against the oracle's per-level
+    localized hierarchy at 1e-10 (FP64)."""
+    _print_case(test="per_level_rho", q=q, rho=rho, rho_c=rho_c)
+    pr = S.rough_problem(q, 2.0, 25)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    ref = G.localized_hierarchy(fe.A, tree, {k: (rho if k == q else rho_c) for k in range(2, q + 1)})
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision="fp64", rho_coarse=rho_c)
+    torch.cuda.synchronize()
+    for k in range(q, 0, -1):
+        lv = H.level(k)
+        A_gpu = stencil_to_matrix(lv["A"].cpu().numpy(), q, k, tree.size(k))
+        err = abs(A_gpu - ref.levels[k].A).max() / abs(ref.levels[k].A).max()
+        assert err < 1e-10, (k, "A", err)
+        if k >= 2:
+            R_gpu = restriction_to_matrix(lv["R"].cpu().numpy(), lv["rho"], q, k, tree.size(k))
+            err = abs(R_gpu - ref.levels[k].R).max() / abs(ref.levels[k].R).max()
+            assert err < 1e-10, (k, "R", err)
+    H.close()
+
+
+@pytest.mark.timeout(300)
+def test_per_level_radius_full_size_q9():
+    """The benchmark problem with radius 3 at the finest transition and 2 or 1
+    below it reaches 1e-8 against the direct solve (mixed)."""
+    _print_case(test="per_level_rho_q9")
+    pr = S.q9_rough_problem()
+    u_ref = fem.solve(pr.a, pr.g)[0][1:-1, 1:-1]
+    for rho_c in (2, 1):
+        H = _P().Hierarchy(_dev(pr.a), rho=3, precision="mixed", rtol=1e-8, max_outer=2000, rho_coarse=rho_c)
+        u = H.solve(_dev(pr.g[0])).cpu().numpy()
+        err = _relerr(u[1:-1, 1:-1], u_ref)
+        print("rho_coarse", rho_c, "err", err, H.last_info, flush=True)
+        assert err < 1e-8, (rho_c, err)
+        H.close()
+
+
 @pytest.mark.timeout(400)
 def test_adjoint_q10_matches_oracle_and_fd():
     """Adjoint workload (1024 x 1024 cells, J = |u - u_obs|^2 / 2, mixed
