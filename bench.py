@@ -9,7 +9,17 @@ restrictions, Galerkin coarsening) and solve to a relative error of 1e-8
 (flexible CG on the FP64 fine residual, subband solves in FP32).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-cpu-baseline]
+Besides the timed steps the line carries: the roofline figure of the
+dominant build kernel (HIP events in the timed region, HBM traffic from
+counters taken on the same kernel source), the CPU oracle's direct solve as
+the baseline (and as the error reference), and unless --no-extras: the FP64
+path, the adjoint gradient, patch radii 1-4 and a smaller radius below the
+finest transition, the hierarchy on the level-q gamblets of the localized
+mass inverse and its level-q operator, the 1024 x 1024-cell adjoint workload,
+a 32-problem sample of the batch workload, and the gamblet transform with
+compression.
+
+    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
