@@ -70,12 +70,13 @@ def level_geometry(H):
 # scaled by the factors measured on a plain 1 GiB copy).  Valid only for the kernel source it was
 # measured on: the entry records the SHA-256 of that source file, and a mismatch reports None.
 MEASURED_TRAFFIC = {
-    # matrix-core patch solves, levels 8..2 of the 512x512-cell benchmark: 70,048 KiB fetched and
-    # 41,663 KiB written per build over 7 launches (FETCH x 2.0 + WRITE x 1.0)
+    # matrix-core patch solves, levels 8..2 of the 512x512-cell benchmark (parent-major copy of B^(k),
+    # then the patch kernel): 107,953 KiB fetched and 118,215 KiB written per build over 7 launches
+    # (FETCH x 2.0 + WRITE x 1.0)
     ("patch_solve", 9, "mixed"): {
-        "bytes_per_launch": 26588803,
+        "bytes_per_launch": 48877129,
         "source": "kernels_build.hip",
-        "sha256": "e85c3eeef265da70f663d58a5ae02f39db8018ccfbc868ca016bcf3dd47730dc",
+        "sha256": "1f792bf7e55d8ceda8952f3b13cddcf49bb02f298851d232b8ac3a2db4a0c3ac",
     },
 }
 

@@ -123,6 +123,7 @@ struct Layout {
   size_t tr_off[kMaxLevels] = {};   // FP64 level vectors of the gamblet transform (nk^2 each)
   size_t sel_off = 0;        // selection state of the compression threshold (4 x 64-bit words + histogram)
   size_t lqtab_off = 0;      // 1-D factors of the localized mass inverse ((n - 1) x (2 kMaxRhoQ + 1) doubles)
+  size_t bp_off = 0;         // parent-major copy of one level's B^(k) for the matrix-core patch solves (T)
   size_t total = 0;
 };
 
@@ -268,6 +269,15 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   b = align_up(b + 4 * 8 + (size_t)kSelHistBins * 4);
   L.lqtab_off = b;
   b = align_up(b + (size_t)(L.n - 1) * (2 * kMaxRhoQ + 1) * 8);
+  {
+    size_t most = 0;
+    for (int k = 2; k <= q; ++k) {
+      const size_t TT = 2 * L.lv[k].t + 1;
+      most = std::max(most, TT * TT * 9 * ((size_t)L.lv[k].nk * L.lv[k].nk / 4));
+    }
+    L.bp_off = b;
+    b = align_up(b + most * L.elem);
+  }
   L.total = b;
   return GBL_OK;
 }
@@ -566,8 +576,8 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
     }
     {
       ProfScope ps(fine && g.t == 1 && g.nk / 2 > 2 * g.rho + 1 ? GBL_PROF_PATCH_BAND : GBL_PROF_PATCH_SOLVE, st);
-      launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR), fine, c->status(),
-                            st);
+      launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR),
+                            reinterpret_cast<T*>(c->ws + L.bp_off), fine, c->status(), st);
     }
     {
       ProfScope ps(GBL_PROF_GALERKIN, st);

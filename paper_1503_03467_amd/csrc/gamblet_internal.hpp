@@ -57,8 +57,10 @@ void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool f
 // Bound of lambda_max(M B^(k)) (block Gershgorin); scratch holds 6 np^2 T values.
 template <typename T>
 void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out, hipStream_t st);
+// Bp: scratch of TT^2 * 9 * (nk/2)^2 T values for a parent-major copy of B^(k)
+// (read by the matrix-core kernel's patch gather)
 template <typename T>
-void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
+void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, T* Bp, bool fine, int* status,
                         hipStream_t st);
 template <typename T>
 void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,

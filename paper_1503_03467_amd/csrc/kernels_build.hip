@@ -413,8 +413,32 @@ template <typename T>
 void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st);
 template <typename T, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(const T* __restrict__ A, const T* __restrict__ B,
-                                                         T* __restrict__ R, int nk, int s, int t, int rho,
-                                                         int fine, int* __restrict__ status);
+                                                         const T* __restrict__ Bp, T* __restrict__ R, int nk,
+                                                         int s, int t, int rho, int fine,
+                                                         int* __restrict__ status);
+
+// B^(k) with the (2t+1)^2 x 9 entries of each parent contiguous, Bp[p][o][e]
+// (the operators keep 64 parents fastest; a patch gathers one parent's
+// entries at a time).  Tiles of 64 parents x 32 entries through LDS, so that
+// both the reads and the writes are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_b_parent_major(const T* __restrict__ B, T* __restrict__ Bp, int np2,
+                                                        int per) {
+  __shared__ T tile[32][65];
+  const int grp = blockIdx.x;
+  const int oe0 = blockIdx.y * 32;
+  for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+    const int r = e >> 6, pl = e & 63;
+    const int oe = oe0 + r;
+    tile[r][pl] = (oe < per) ? B[((size_t)grp * per + oe) * 64 + pl] : T(0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+    const int pl = e >> 5, r = e & 31;
+    const int p = grp * 64 + pl, oe = oe0 + r;
+    if (p < np2 && oe < per) Bp[(size_t)p * per + oe] = tile[r][pl];
+  }
+}
 
 // Dense patch kernel choice: the matrix-core kernel for FP32 patches, the
 // register-tiled kernel for FP64 ones (whose accumulator tiles would leave one
@@ -429,7 +453,7 @@ static bool patch_mfma_enabled() {
 }
 
 template <typename T>
-void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool fine, int* status,
+void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, T* Bp, bool fine, int* status,
                         hipStream_t st) {
   const int nc = L.nk / 2;
   if (fine && L.t == 1 && nc > 2 * L.rho + 1) {
@@ -441,7 +465,10 @@ void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, bool f
   const dim3 grid(nc * nc), block(256);
   const int f = fine ? 1 : 0;
   if (patch_mfma_enabled<T>() && need <= 160) {
-    hipLaunchKernelGGL((k_patch_chol_mfma<T, 10>), grid, block, 0, st, A, B, R, L.nk, L.s, L.t, L.rho, f, status);
+    const int np2 = nc * nc, TT = 2 * L.t + 1, per = TT * TT * 9;
+    hipLaunchKernelGGL(k_b_parent_major<T>, dim3((np2 + 63) / 64, (per + 31) / 32), dim3(256), 0, st, B, Bp, np2, per);
+    hipLaunchKernelGGL((k_patch_chol_mfma<T, 10>), grid, block, 0, st, A, B, Bp, R, L.nk, L.s, L.t, L.rho, f,
+                       status);
     return;
   }
   if (need <= 32) {
@@ -544,8 +571,9 @@ __host__ __device__ constexpr int tile_col(int tix) {
 // 4 m + W, so every tile coordinate is a compile-time constant.
 template <typename T, int NT, int W>
 __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T* __restrict__ A,
-                                                     const T* __restrict__ B, T* __restrict__ R, int nk, int s,
-                                                     int t, int rho, int fine, int* __restrict__ status) {
+                                                     const T* __restrict__ B, const T* __restrict__ Bp,
+                                                     T* __restrict__ R, int nk, int s, int t, int rho, int fine,
+                                                     int* __restrict__ status) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int SLOTS = (NTILE + 3) / 4;
@@ -623,7 +651,7 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
             const int ox = qx - rx + t, oy = qy - ry + t;
             T bv = T(0);
             if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
-              bv = B[b_index(ox * TT + oy, trr * 3 + tcc, rx * nc + ry, TT)];
+              bv = Bp[(size_t)(rx * nc + ry) * (TT * TT * 9) + (ox * TT + oy) * 9 + trr * 3 + tcc];
             v = bv * sm.sc[i] * sm.sc[j];
           } else {
             v = T(0);
@@ -807,14 +835,14 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
 
 template <typename T, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(
-    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ R, int nk, int s, int t, int rho, int fine,
-    int* __restrict__ status) {
+    const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ Bp, T* __restrict__ R, int nk, int s,
+    int t, int rho, int fine, int* __restrict__ status) {
   __shared__ CholLds<T, NT> sm;
   switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: patch_chol_mfma_body<T, NT, 0>(sm, A, B, R, nk, s, t, rho, fine, status); break;
-    case 1: patch_chol_mfma_body<T, NT, 1>(sm, A, B, R, nk, s, t, rho, fine, status); break;
-    case 2: patch_chol_mfma_body<T, NT, 2>(sm, A, B, R, nk, s, t, rho, fine, status); break;
-    default: patch_chol_mfma_body<T, NT, 3>(sm, A, B, R, nk, s, t, rho, fine, status); break;
+    case 0: patch_chol_mfma_body<T, NT, 0>(sm, A, B, Bp, R, nk, s, t, rho, fine, status); break;
+    case 1: patch_chol_mfma_body<T, NT, 1>(sm, A, B, Bp, R, nk, s, t, rho, fine, status); break;
+    case 2: patch_chol_mfma_body<T, NT, 2>(sm, A, B, Bp, R, nk, s, t, rho, fine, status); break;
+    default: patch_chol_mfma_body<T, NT, 3>(sm, A, B, Bp, R, nk, s, t, rho, fine, status); break;
   }
 }
 
@@ -1637,7 +1665,7 @@ void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out
   template void launch_assemble_fine<T>(const double*, T*, int, int*, hipStream_t);                  \
   template void launch_gershgorin<T>(const LevelGeom&, const T*, T*, unsigned*, hipStream_t);        \
   template void launch_subband_operator<T>(const LevelGeom&, const T*, T*, T*, bool, hipStream_t);   \
-  template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, bool, int*,          \
+  template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, T*, bool, int*,      \
                                       hipStream_t);                                                  \
   template void launch_galerkin<T>(const LevelGeom&, const LevelGeom&, const T*, const T*, T*,      \
                                    hipStream_t);                                                     \
