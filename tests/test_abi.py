@@ -131,3 +131,14 @@ def test_level_q_mass_option_validated():
     o = P.make_opts(level_q_mass=3)
     assert L.gbl_workspace_bytes(2, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1   # 2^2 - 1 < 7
     assert P.workspace_bytes(6, P.make_opts(level_q_mass=3)) > P.workspace_bytes(6, P.make_opts())
+
+
+def test_rho_coarse_option_validated():
+    P, L = _lib()
+    o = P.make_opts(rho_coarse=5)
+    assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1
+    assert b"rho_coarse" in L.gbl_last_error(None)
+    o = P.make_opts(rho_coarse=-1)
+    assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1
+    # a smaller radius below the finest level needs less workspace
+    assert P.workspace_bytes(8, P.make_opts(rho=3, rho_coarse=1)) < P.workspace_bytes(8, P.make_opts(rho=3))
