@@ -426,7 +426,8 @@ def main():
         op_bytes = aq.numel() * 8 + pr.n * pr.n * 8
         extras["level_q_mass_inverse"] = {"rho_q": 3, "table_ms": t_table, "operator_ms": t_op, "load_ms": t_load,
                                           "operator_bytes": op_bytes,
-                                          "operator_GBps": op_bytes / (t_op * 1e-3) / 1e9}
+                                          "operator_GBps": op_bytes / (t_op * 1e-3) / 1e9,
+                                          "operator_hbm_frac": op_bytes / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del aq
         # the adjoint workload (1024 x 1024 cells, sigma = 1, J = |u - u_obs|^2 / 2):
         # build, solve and adjoint gradient timed apart (minimum of two runs)
