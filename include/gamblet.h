@@ -260,6 +260,21 @@ int gbl_inverse_transform(gbl_ctx* ctx, const double* coef_dev, double* u_dev, v
  * when it is given the call waits for the stream.  EINVAL on NULL ctx / coef. */
 int gbl_compress(gbl_ctx* ctx, double* coef_dev, long keep, double* threshold, void* stream);
 
+/* Allocation-free compression, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops).  The same
+ * selection as gbl_compress on any FP64 device vector of `count` entries, no
+ * hierarchy needed: keep the `keep` largest |coef| in place, zero the others
+ * (ties at the smallest kept magnitude kept, NaN zeroed; keep <= 0 zeroes all,
+ * keep >= count changes nothing); threshold (host, may be NULL) as for
+ * gbl_compress, and when given the call waits for the stream.  Its selection
+ * state (about 8.4 KB) lives in a fixed array of the library's device memory,
+ * one per GPU, held until the process ends; the call allocates nothing.
+ * Calls that overlap on one GPU (concurrent streams or host threads) share
+ * that array and race; serialise them.  Limit: count <= 4294967295 (the
+ * histogram counters are 32-bit), else GBL_EINVAL; GBL_EINVAL on a NULL coef,
+ * GBL_EHIP on a launch or copy failure (message via gbl_last_error(NULL)). */
+int gbl_compress_noalloc(double* coef_dev, long count, long keep, double* threshold, void* stream);
+
 /* Energy norm sqrt(u^T A u) of a nodal u (boundary entries ignored) with the
  * FP64 fine stiffness matrix of the hierarchy's coefficient.  Waits for the
  * stream; *norm is a host double.  EINVAL on NULL arguments. */

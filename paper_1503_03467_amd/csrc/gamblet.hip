@@ -1384,6 +1384,81 @@ int gbl_compress(gbl_ctx* c, double* coef_dev, long keep, double* threshold, voi
   return GBL_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Compression without allocation: the selection of gbl_compress with its
+// state words, histogram and threshold in a fixed array of this library's
+// device memory instead of a hierarchy workspace.  Host code never passes
+// `scratch` itself to a kernel: the array's device address on the current
+// device comes from hipGetSymbolAddress, taken once per device on the first
+// call there.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNaStateOff = 0;      // 4 words of 64 bits
+constexpr size_t kNaThrOff = 64;       // the threshold (one double)
+constexpr size_t kNaHistOff = 256;     // kSelHistBins counters of 32 bits
+constexpr size_t kNaScratchBytes = kNaHistOff + (size_t)kSelHistBins * sizeof(unsigned);
+constexpr long kNaMaxCount = 4294967295L;   // the histogram counters are 32-bit
+constexpr int kNaMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+std::mutex g_na_mu;
+unsigned char* g_na_ptr[kNaMaxDevices] = {};
+
+int noalloc_scratch(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, GBL_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kNaMaxDevices) return fail(nullptr, GBL_EINVAL, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, GBL_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_na_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_na_ptr[dev];
+  return GBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbl_compress_noalloc(double* coef_dev, long count, long keep, double* threshold, void* stream) {
+  if (!coef_dev) return fail(nullptr, GBL_EINVAL, "coef must not be NULL");
+  if (count < 1 || count > kNaMaxCount)
+    return fail(nullptr, GBL_EINVAL, "count must be in [1, 4294967295] (32-bit histogram counters)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (keep <= 0) {
+    launch_fill((size_t)count, 0.0, coef_dev, s);
+    if (threshold) *threshold = HUGE_VAL;
+  } else if (keep >= count) {
+    if (threshold) *threshold = 0.0;
+  } else {
+    unsigned char* base = nullptr;
+    const int st = noalloc_scratch(&base);
+    if (st) return st;
+    auto* state = reinterpret_cast<unsigned long long*>(base + kNaStateOff);
+    auto* hist = reinterpret_cast<unsigned*>(base + kNaHistOff);
+    double* thr = reinterpret_cast<double*>(base + kNaThrOff);
+    launch_select_threshold(coef_dev, count, keep, state, hist, thr, s);
+    launch_zero_below(thr, count, coef_dev, s);
+    if (threshold) {
+      hipError_t e = hipMemcpyAsync(threshold, thr, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return fail(nullptr, GBL_EHIP, std::string("threshold read: ") + hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, GBL_EHIP, std::string("launch: ") + hipGetErrorString(e));
+  return GBL_OK;
+}
+
 int gbl_energy_norm(gbl_ctx* c, const double* u_dev, double* norm, void* stream) {
   if (!c || !norm) return fail(c, GBL_EINVAL, "ctx and norm must not be NULL");
   if (!u_dev) return fail(c, GBL_EINVAL, "u must not be NULL");

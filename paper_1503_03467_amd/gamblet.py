@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         L.gbl_inverse_transform.argtypes = [vp, vp, vp, vp]
         L.gbl_compress.argtypes = [vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_double), vp]
         L.gbl_energy_norm.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+        L.gbl_compress_noalloc.argtypes = [vp, ctypes.c_long, ctypes.c_long, ctypes.POINTER(ctypes.c_double), vp]
         L.gbl_mass_inverse.argtypes = [i, i, vp, vp]
         L.gbl_level_q_gamblets.argtypes = [i, i, vp, vp, vp]
         L.gbl_level_q_load.argtypes = [i, i, vp, vp, vp, vp]
@@ -89,7 +90,7 @@ def lib() -> ctypes.CDLL:
                      "gbl_level_layout", "gbl_build_flags", "gbl_build_batched", "gbl_solve_batched",
                      "gbl_destroy", "gbl_profile_enable", "gbl_profile_reset", "gbl_profile_read",
                      "gbl_transform_size", "gbl_transform", "gbl_inverse_transform", "gbl_compress",
-                     "gbl_energy_norm", "gbl_mass_inverse", "gbl_level_q_gamblets", "gbl_level_q_load",
+                     "gbl_energy_norm", "gbl_compress_noalloc", "gbl_mass_inverse", "gbl_level_q_gamblets", "gbl_level_q_load",
                      "gbl_level_q_operator", "gbl_level_q_to_nodal"):
             getattr(L, name).restype = i
         _lib = L
@@ -368,6 +369,19 @@ class LevelQ:
         out = torch.empty_like(U)
         self._call("gbl_level_q_to_nodal", self.table.data_ptr(), U.data_ptr(), out.data_ptr())
         return out
+
+
+def compress_noalloc(c: torch.Tensor, keep: int) -> float:
+    """Keep the ``keep`` largest |c| of an FP64 device vector in place (others zero) through
+    ``gbl_compress_noalloc``, which allocates no device memory; returns the smallest kept magnitude."""
+    if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64 and c.dim() == 1
+            and c.is_contiguous()):
+        raise ValueError("c must be a contiguous 1-D float64 CUDA tensor")
+    thr = ctypes.c_double(0.0)
+    with torch.cuda.device(c.device):
+        _check(lib().gbl_compress_noalloc(ctypes.c_void_p(c.data_ptr()), int(c.numel()), int(keep),
+                                          ctypes.byref(thr), _stream_ptr(c.device)))
+    return float(thr.value)
 
 
 def profile_enable(kernels="all"):

@@ -142,3 +142,14 @@ def test_rho_coarse_option_validated():
     assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == -1
     # a smaller radius below the finest level needs less workspace
     assert P.workspace_bytes(8, P.make_opts(rho=3, rho_coarse=1)) < P.workspace_bytes(8, P.make_opts(rho=3))
+
+
+def test_noalloc_compression_rejects_bad_sizes():
+    """gbl_compress_noalloc validates on the host before touching the device."""
+    _, L = _lib()
+    thr = ctypes.c_double(0.0)
+    dummy = ctypes.c_void_p(4096)   # never dereferenced: every call below fails validation first
+    assert L.gbl_compress_noalloc(None, 10, 1, ctypes.byref(thr), None) == -1
+    assert L.gbl_compress_noalloc(dummy, 0, 1, ctypes.byref(thr), None) == -1
+    assert L.gbl_compress_noalloc(dummy, 1 << 32, 1, ctypes.byref(thr), None) == -1
+    assert b"count" in L.gbl_last_error(None)
