@@ -67,12 +67,17 @@ enum gbl_status {
 
 enum gbl_precision {
   GBL_FP64 = 0,   /* hierarchy, patch solves and subband CG in FP64 */
-  GBL_MIXED = 1   /* hierarchy and subband CG in FP32; fine residual, outer iteration and A^(1) in FP64 */
+  GBL_MIXED = 1,  /* hierarchy and subband CG in FP32; fine residual, outer iteration and A^(1) in FP64 */
+  GBL_MIXED_FP64_BUILD = 2  /* hierarchy built in FP64 (patch solves, Galerkin products, A^(1)), then copied to
+                               FP32 for the subband iterations; fine residual and outer iteration in FP64.  For
+                               coefficients whose contrast exceeds FP32's resolution (about 1e7), where FP32
+                               Galerkin products lose positive definiteness.  The workspace holds both copies */
 };
 
 enum gbl_inner {
   GBL_INNER_CHEBYSHEV = 0,  /* Chebyshev iteration: a fixed polynomial preconditioner, no inner products */
-  GBL_INNER_CG = 1          /* conjugate gradients */
+  GBL_INNER_CG = 1,         /* conjugate gradients */
+  GBL_INNER_CHEB_CG = 2     /* Chebyshev on the finest subband system, conjugate gradients on the coarser ones */
 };
 
 typedef struct gbl_opts {
@@ -99,6 +104,19 @@ typedef struct gbl_opts {
                          > 3); the gamblet transform calls reject such a hierarchy */
   int rho_coarse;     /* patch radius of the transitions below the finest (levels k < q, Algorithm 2 allows
                          one radius per level); 0 = rho; 1..4 */
+  double window_tol;  /* window corrections of the subband preconditioner on the levels k < q (0 = off, the
+                         default; needs conjugate gradients there: inner_kind GBL_INNER_CG or
+                         GBL_INNER_CHEB_CG).  Section 4.8 bounds the condition number of B^(k) by a constant
+                         that grows with the contrast of a; with inclusions of very high coefficient the
+                         block-Jacobi preconditioned B^(k) keeps a few localized modes of tiny Rayleigh quotient
+                         (an inclusion spanning several parents moving almost rigidly).  For every 3 x 3 group
+                         of parents (27 subband unknowns) the build factorizes the principal submatrix B_w in
+                         FP64 and keeps B_w^-1 when tr(D_w B_w^-1) > window_tol, D_w the block diagonal of B_w
+                         (the trace lies between 1 / lambda_min and 27 / lambda_min of the pencil (B_w, D_w));
+                         the preconditioner becomes D^-1 + sum over kept windows of P_w^T B_w^-1 P_w (additive
+                         Schwarz, symmetric positive definite).  1000 keeps the windows whose pencil has an
+                         eigenvalue below 0.027 and always those below 0.001.  Costs 27^2 words per window of
+                         workspace on every level k in [3, q - 1] */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -127,6 +145,9 @@ typedef struct gbl_level_desc {
   const void* A;      /* A^(k) */
   const void* B;      /* B^(k), NULL for k = 1 */
   const void* R;      /* R^(k-1,k), NULL for k = 1 */
+  int nwin;           /* kept windows of the preconditioner (window_tol > 0, 3 <= k < q), else 0 */
+  const int* wlist;   /* [nwin] window origins x0 * (nk/2) + y0 (parents x0..x0+2, y0..y0+2), any order */
+  const void* winv;   /* [nwin][27][27] B_w^-1, unknown (3 dx + dy) * 3 + t of parent (x0 + dx, y0 + dy) */
 } gbl_level_desc;
 
 typedef struct gbl_ctx gbl_ctx;
@@ -136,7 +157,7 @@ int gbl_version(void);
 
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
- * kappa 200, kappa_coarse 10, max_rhs 1. */
+ * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

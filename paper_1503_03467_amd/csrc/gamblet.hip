@@ -93,6 +93,9 @@ constexpr int kMaxChunk = 8;   // outer iterations launched between two looks at
 
 struct Layout {
   int q = 0, n = 0, rho = 0, prec = 0, max_rhs = 1;
+  int build64 = 0;           // MIXED_FP64_BUILD: the arena is FP64, the solve reads an FP32 copy of it
+  size_t selem = 8;          // bytes of the solve-phase scalar (slot, CG and window vectors)
+  size_t hier32_off = 0;     // FP32 copy of the arena (build64 only)
   int mass = 0;              // patch radius of the localized mass inverse at level q (0: nodal basis)
   size_t elem = 8;
   LevelGeom lv[kMaxLevels];
@@ -124,13 +127,25 @@ struct Layout {
   size_t sel_off = 0;        // selection state of the compression threshold (4 x 64-bit words + histogram)
   size_t lqtab_off = 0;      // 1-D factors of the localized mass inverse ((n - 1) x (2 kMaxRhoQ + 1) doubles)
   size_t bp_off = 0;         // parent-major copy of one level's B^(k) for the matrix-core patch solves (T)
+  // window corrections of the preconditioner (levels 3 <= k < q when window_tol > 0)
+  int win_cap[kMaxLevels] = {};      // windows the arrays of level k hold: all (nk/2 - 2)^2
+  size_t win_list_off[kMaxLevels] = {}, win_idx_off[kMaxLevels] = {};   // int arrays
+  size_t win_inv_off[kMaxLevels] = {}, win_y_off[kMaxLevels] = {};      // T arrays
+  size_t wcnt_off = 0;       // kept-window counters (kMaxLevels unsigned)
   size_t total = 0;
 };
 
 int validate_opts(const gbl_opts* o, std::string& msg) {
   if (!o) { msg = "opts is NULL"; return GBL_EINVAL; }
   if (o->rho < 1 || o->rho > kMaxRho) { msg = "rho must be in [1, 4]"; return GBL_EINVAL; }
-  if (o->precision != GBL_FP64 && o->precision != GBL_MIXED) { msg = "unknown precision"; return GBL_EINVAL; }
+  if (o->precision != GBL_FP64 && o->precision != GBL_MIXED && o->precision != GBL_MIXED_FP64_BUILD) {
+    msg = "unknown precision";
+    return GBL_EINVAL;
+  }
+  if (o->precision == GBL_MIXED_FP64_BUILD && o->level_q_mass > 0) {
+    msg = "level_q_mass is not available with MIXED_FP64_BUILD";
+    return GBL_EINVAL;
+  }
   if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) { msg = "rtol must be in (0, 1)"; return GBL_EINVAL; }
   if (o->max_outer < 1 || o->max_outer > 100000) { msg = "max_outer must be in [1, 100000]"; return GBL_EINVAL; }
   if (o->inner_iters < 1 || o->inner_iters > 100000) { msg = "inner_iters must be in [1, 100000]"; return GBL_EINVAL; }
@@ -145,12 +160,20 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
     msg = "level_q_mass needs Chebyshev inner iterations";
     return GBL_EINVAL;
   }
-  if (o->inner_kind != GBL_INNER_CHEBYSHEV && o->inner_kind != GBL_INNER_CG) {
+  if (o->inner_kind != GBL_INNER_CHEBYSHEV && o->inner_kind != GBL_INNER_CG && o->inner_kind != GBL_INNER_CHEB_CG) {
     msg = "unknown inner_kind";
     return GBL_EINVAL;
   }
-  if (o->inner_kind == GBL_INNER_CHEBYSHEV) {
-    if (o->inner_iters > kMaxCheb || o->inner_iters_coarse > kMaxCheb) {
+  if (!(o->window_tol >= 0.0) || !(o->window_tol < 1e300)) {
+    msg = "window_tol must be finite and >= 0";
+    return GBL_EINVAL;
+  }
+  if (o->window_tol > 0.0 && o->inner_kind == GBL_INNER_CHEBYSHEV) {
+    msg = "window_tol needs conjugate gradients on the coarser levels (inner_kind CG or CHEB_CG)";
+    return GBL_EINVAL;
+  }
+  if (o->inner_kind != GBL_INNER_CG) {
+    if (o->inner_iters > kMaxCheb || (o->inner_kind == GBL_INNER_CHEBYSHEV && o->inner_iters_coarse > kMaxCheb)) {
       msg = "Chebyshev inner iterations must be at most 32";
       return GBL_EINVAL;
     }
@@ -171,7 +194,9 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.rho = o->rho;
   L.prec = o->precision;
   L.max_rhs = o->max_rhs;
-  L.elem = (o->precision == GBL_FP64) ? 8 : 4;
+  L.elem = (o->precision == GBL_MIXED) ? 4 : 8;
+  L.selem = (o->precision == GBL_FP64) ? 8 : 4;
+  L.build64 = (o->precision == GBL_MIXED_FP64_BUILD) ? 1 : 0;
   // stencil widths: A^(q) is the 9-point Q1 stencil; a restriction row of
   // level k-1 spans 2(2 rho_k + 1) level-k slots, so A^(k-1) = R A R^T
   // couples coarse slots up to (4 rho_k + 1 + s_k) / 2 apart.
@@ -224,6 +249,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   size_t b = 0;
   L.a_off = b; b = align_up(b + n2 * 8);
   L.hier_off = b; b = align_up(b + e * L.elem);
+  if (L.build64) { L.hier32_off = b; b = align_up(b + e * 4); }
   L.L1_off = b; b = align_up(b + 16 * 8);
   L.status_off = b; b = align_up(b + 4 * sizeof(int));
   L.gersh_off = b; b = align_up(b + kMaxLevels * sizeof(unsigned));
@@ -238,27 +264,40 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   // to 2 rho words beyond either end (where R is zero)
   L.gpad_off = b;
   for (int k = 1; k <= q; ++k) {
-    L.g_off[k] = b + kGPad * L.elem;
-    b = align_up(b + ((size_t)L.lv[k].nk * L.lv[k].nk + 2 * kGPad) * L.elem);
+    L.g_off[k] = b + kGPad * L.selem;
+    b = align_up(b + ((size_t)L.lv[k].nk * L.lv[k].nk + 2 * kGPad) * L.selem);
   }
   L.gpad_end = b;
   {
     const size_t np2 = (size_t)L.lv[q].nk * L.lv[q].nk / 4;
     L.fcg_off = b;
-    b = align_up(b + 9 * 3 * np2 * L.elem);
+    b = align_up(b + 9 * 3 * np2 * L.selem);
     L.fcgpart_off = b;
     b = align_up(b + 2 * std::max<size_t>(1, np2 / 256 + 1) * 8);
   }
   for (int k = 2; k <= q; ++k) {
     const size_t np2 = (size_t)L.lv[k].nk * L.lv[k].nk / 4;
     L.cgv_off[k] = b;
-    b = align_up(b + 5 * 3 * np2 * L.elem);
+    b = align_up(b + 5 * 3 * np2 * L.selem);
     const size_t nb = std::max((np2 + 255) / 256, (np2 + 63) / 64);
     L.cgpart_off[k] = b;
     b = align_up(b + nb * 8);
   }
+  if (o->window_tol > 0.0) {
+    for (int k = 3; k < q; ++k) {
+      const size_t np = (size_t)L.lv[k].nk / 2;
+      const size_t cap = (np - 2) * (np - 2);
+      L.win_cap[k] = (int)cap;
+      L.win_list_off[k] = b; b = align_up(b + cap * sizeof(int));
+      L.win_idx_off[k] = b; b = align_up(b + np * np * sizeof(int));
+      L.win_inv_off[k] = b; b = align_up(b + cap * 27 * 27 * L.selem);
+      L.win_y_off[k] = b; b = align_up(b + cap * 27 * L.selem);
+    }
+  }
+  // everything from here on is zeroed at the start of a build
   L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
   L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
+  L.wcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
   L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
   L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
   for (int k = 1; k <= q; ++k) {
@@ -311,9 +350,15 @@ struct gbl_ctx {
   ChebStep cheb_coarse[kMaxCheb]{};     // Chebyshev coefficients per step, coarser levels
   ChebStep cheb_q[kMaxCheb]{};          // the same for the stored finest level (slot 0)
   bool diverged = false;                // the last solve produced a non-finite estimate or residual
+  int nwin[kMaxLevels] = {};            // kept windows of the preconditioner per level
 
+  // The arena in the scalar T: the build's own (FP64 or FP32), or with
+  // MIXED_FP64_BUILD the FP32 copy the solve reads.
   template <typename T>
-  T* hier(size_t off) const { return reinterpret_cast<T*>(ws + L.hier_off) + off; }
+  T* hier(size_t off) const {
+    const size_t base = (sizeof(T) == L.elem) ? L.hier_off : L.hier32_off;
+    return reinterpret_cast<T*>(ws + base) + off;
+  }
   double* fine(int i) const { return reinterpret_cast<double*>(ws + L.fine_off[i]); }
   int* status() const { return reinterpret_cast<int*>(ws + L.status_off); }
   double* oscal() const { return reinterpret_cast<double*>(ws + L.oscal_off); }
@@ -438,9 +483,29 @@ CGArgs<T> make_cg_args(gbl_ctx* c) {
     v.blk0s = blks;
     v.nblks = (int)((np2 + 63) / 64);
     blks += v.nblks;
+    if (L.win_cap[k] > 0) {
+      v.wlist = reinterpret_cast<const int*>(c->ws + L.win_list_off[k]);
+      v.widx = reinterpret_cast<const int*>(c->ws + L.win_idx_off[k]);
+      v.winv = reinterpret_cast<const T*>(c->ws + L.win_inv_off[k]);
+      v.Y = reinterpret_cast<T*>(c->ws + L.win_y_off[k]);
+    }
+    v.nwin = 0;   // set from the build's counts (set_windows)
+    v.win0 = 0;
   }
   A.nlev = l;
   return A;
+}
+
+// The kept-window counts of the build into the CG arguments of the coarser levels.
+template <typename T>
+void set_windows(const gbl_ctx* c, CGArgs<T>& A) {
+  int w0 = 0;
+  for (int l = 0; l < A.nlev; ++l) {
+    const int k = c->L.q - 1 - l;
+    A.lv[l].nwin = c->nwin[k];
+    A.lv[l].win0 = w0;
+    w0 += c->nwin[k];
+  }
 }
 
 // The finest subband system as a one-level CGArgs over its stored B^(q), for
@@ -573,6 +638,12 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
       // scratch: the level's subband solve vectors, unused while building
       T* scratch = reinterpret_cast<T*>(c->ws + (k == q ? L.fcg_off : L.cgv_off[k]));
       launch_gershgorin<T>(g, c->hier<T>(g.offB), scratch, reinterpret_cast<unsigned*>(c->ws + L.gersh_off) + k, st);
+      if (L.win_cap[k] > 0 && sizeof(T) == L.selem)
+        launch_win_build<T>(g, c->hier<T>(g.offB), c->opts.window_tol, L.win_cap[k],
+                            reinterpret_cast<int*>(c->ws + L.win_list_off[k]),
+                            reinterpret_cast<int*>(c->ws + L.win_idx_off[k]),
+                            reinterpret_cast<T*>(c->ws + L.win_inv_off[k]),
+                            reinterpret_cast<unsigned*>(c->ws + L.wcnt_off) + k, c->status(), st);
     }
     {
       ProfScope ps(fine && g.t == 1 && g.nk / 2 > 2 * g.rho + 1 ? GBL_PROF_PATCH_BAND : GBL_PROF_PATCH_SOLVE, st);
@@ -635,8 +706,11 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   // the restriction chain, the coarser systems and the prolongation down to
   // level q - 1 on the second stream.
   hipStream_t cs = c->side ? c->side : st;
-  const bool cheb = c->opts.inner_kind == GBL_INNER_CHEBYSHEV;
+  const bool cheb = c->opts.inner_kind != GBL_INNER_CG;                // finest level
+  const bool cheb_coarse = c->opts.inner_kind == GBL_INNER_CHEBYSHEV;  // coarser levels
   const bool coarse = cg.nlev > 0 && c->opts.inner_iters_coarse > 0;
+  bool windows = false;
+  for (int l = 0; l < cg.nlev; ++l) windows = windows || cg.lv[l].nwin > 0;
   if (c->side) {
     hipEventRecord(c->ev_fork, st);
     hipStreamWaitEvent(cs, c->ev_fork, 0);
@@ -651,7 +725,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     launch_restrict_chain<T>(chain, cs);
   }
   if (coarse) {
-    if (cheb) {
+    if (cheb_coarse) {
       {
         ProfScope ps(GBL_PROF_CG_INIT, cs);
         launch_cheb_init<T>(cg, c->cheb_coarse[0], 0, cg.nlev, cs);
@@ -665,6 +739,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
       {
         ProfScope ps(GBL_PROF_CG_INIT, cs);
         launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
+        if (windows) launch_win_correct<T>(cg, 0, true, cs);
       }
       for (int it = 0; it < K; ++it) {
         {
@@ -673,6 +748,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
         }
         ProfScope ps(GBL_PROF_CG_UPDATE, cs);
         launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs);
+        if (windows && it + 1 < K) launch_win_correct<T>(cg, it, false, cs);
       }
     }
   } else {
@@ -1002,6 +1078,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->kappa_coarse = 10.0;
   o->level_q_mass = 0;
   o->rho_coarse = 0;
+  o->window_tol = 0.0;
   return GBL_OK;
 }
 
@@ -1070,11 +1147,34 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   c->cgqd = make_cgq_args<double>(c);
   c->fcgf = make_fine_cg<float>(c);
   c->fcgd = make_fine_cg<double>(c);
-  st = (L.prec == GBL_FP64) ? build_impl<double>(c, s) : build_impl<float>(c, s);
+  st = (L.elem == 8) ? build_impl<double>(c, s) : build_impl<float>(c, s);
   if (st) return bail(st);
+  if (L.build64) {
+    // the solve reads an FP32 copy of the FP64 hierarchy; its window
+    // corrections are formed from that copy (the operator the solve applies)
+    launch_convert<float, double>(L.hier_elems, c->hier<double>(0), c->hier<float>(0), s);
+    for (int k = 3; k < L.q; ++k) {
+      if (L.win_cap[k] <= 0) continue;
+      const LevelGeom& g = L.lv[k];
+      launch_win_build<float>(g, c->hier<float>(g.offB), opts->window_tol, L.win_cap[k],
+                              reinterpret_cast<int*>(c->ws + L.win_list_off[k]),
+                              reinterpret_cast<int*>(c->ws + L.win_idx_off[k]),
+                              reinterpret_cast<float*>(c->ws + L.win_inv_off[k]),
+                              reinterpret_cast<unsigned*>(c->ws + L.wcnt_off) + k, c->status(), s);
+    }
+    if (hipGetLastError() != hipSuccess) {
+      c->err = "launch failed";
+      return bail(GBL_EHIP);
+    }
+  }
   unsigned* hbits = reinterpret_cast<unsigned*>(c->host + kNumOuterScalars + 4);
+  unsigned* wbits = hbits + kMaxLevels;
+  static_assert(2 * kMaxLevels * sizeof(unsigned) <= (kHostWords - kNumOuterScalars - 4) * sizeof(double),
+                "pinned host words hold the bounds and the window counts");
   if (hipMemcpyAsync(c->host + kNumOuterScalars, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(hbits, c->ws + L.gersh_off, kMaxLevels * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(wbits, c->ws + L.wcnt_off, kMaxLevels * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     c->err = "status read failed";
@@ -1089,6 +1189,13 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
     return bail(GBL_EINVAL);
   }
   if (bits & kRegularizedPivot) c->build_flags |= GBL_FLAG_PIVOTS_REGULARIZED;
+  if (bits & kWindowOverflow) {
+    c->err = "more kept windows than the workspace holds";
+    return bail(GBL_ENOMEM);
+  }
+  for (int k = 0; k < kMaxLevels; ++k) c->nwin[k] = (int)std::min<unsigned>(wbits[k], (unsigned)L.win_cap[k]);
+  set_windows(c, c->cgf);
+  set_windows(c, c->cgd);
   if (bits & kBadPivot) {
     c->err = "non-positive pivot in a patch or coarse matrix";
     return bail(GBL_ENOTSPD);
@@ -1105,7 +1212,7 @@ int gbl_solve(gbl_ctx* c, int nrhs, const double* g_dev, double* u_dev, gbl_solv
   c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t n2 = (size_t)c->L.n * c->L.n;
-  const int st = (c->L.prec == GBL_FP64) ? solve_many<double>(c, nrhs, 0, g_dev, n2, u_dev, info, s)
+  const int st = (c->L.selem == 8) ? solve_many<double>(c, nrhs, 0, g_dev, n2, u_dev, info, s)
                                          : solve_many<float>(c, nrhs, 0, g_dev, n2, u_dev, info, s);
   if (info) info->status = st;
   if (st == GBL_ENOCONV)
@@ -1128,7 +1235,7 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
   for (int r = 0; r < nrhs; ++r) {
     double* lam = lambda_dev ? lambda_dev + r * us : reinterpret_cast<double*>(c->ws + c->L.lam_off);
     launch_fill(us, 0.0, lam, s);
-    const int st = (c->L.prec == GBL_FP64)
+    const int st = (c->L.selem == 8)
                        ? fcg_solve<double>(c, c->cgd, 1, dJdu_dev + r * us, lam, info, s)
                        : fcg_solve<float>(c, c->cgf, 1, dJdu_dev + r * us, lam, info, s);
     if (st == GBL_EHIP) return st;
@@ -1302,6 +1409,9 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
   d->A = base + g.offA * c->L.elem;
   d->B = k >= 2 ? base + g.offB * c->L.elem : nullptr;
   d->R = k >= 2 ? base + g.offR * c->L.elem : nullptr;
+  d->nwin = (k >= 2 && k < c->L.q) ? c->nwin[k] : 0;
+  d->wlist = d->nwin > 0 ? reinterpret_cast<const int*>(c->ws + c->L.win_list_off[k]) : nullptr;
+  d->winv = d->nwin > 0 ? c->ws + c->L.win_inv_off[k] : nullptr;
   return GBL_OK;
 }
 
@@ -1342,7 +1452,7 @@ int gbl_transform(gbl_ctx* c, const double* u_dev, double* coef_dev, void* strea
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
   if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->L.prec == GBL_FP64) launch_transform<double>(transform_args<double>(c), u_dev, coef_dev, s);
+  if (c->L.elem == 8) launch_transform<double>(transform_args<double>(c), u_dev, coef_dev, s);
   else launch_transform<float>(transform_args<float>(c), u_dev, coef_dev, s);
   HIPCHK(c, hipGetLastError());
   return GBL_OK;
@@ -1353,7 +1463,7 @@ int gbl_inverse_transform(gbl_ctx* c, const double* coef_dev, double* u_dev, voi
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
   if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->L.prec == GBL_FP64) launch_inverse_transform<double>(transform_args<double>(c), coef_dev, u_dev, s);
+  if (c->L.elem == 8) launch_inverse_transform<double>(transform_args<double>(c), coef_dev, u_dev, s);
   else launch_inverse_transform<float>(transform_args<float>(c), coef_dev, u_dev, s);
   HIPCHK(c, hipGetLastError());
   return GBL_OK;

@@ -35,6 +35,7 @@ constexpr int kBadCoefficient = 1;
 constexpr int kBadPivot = 2;
 constexpr int kBadInput = 4;
 constexpr int kRegularizedPivot = 8;   // FP32 patch or coarse pivots raised to the floor (not an error)
+constexpr int kWindowOverflow = 16;    // more kept windows than their arrays hold
 
 struct LevelGeom {
   int k = 0;       // level
@@ -65,6 +66,13 @@ void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, T* Bp,
 template <typename T>
 void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
                      hipStream_t st);
+// Window corrections of the subband preconditioner (kernels_window.hip):
+// for every 3 x 3 group of parents of level k < q, B_w^-1 is kept when
+// tr(D_w B_w^-1) > tol (D_w the 3 x 3 parent blocks of B_w).  cap windows fit
+// in wlist / winv; widx has one slot index (or -1) per parent position.
+template <typename T>
+void launch_win_build(const LevelGeom& g, const T* B, double tol, int cap, int* wlist, int* widx, T* winv,
+                      unsigned* count, int* status, hipStream_t st);
 template <typename T>
 void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStream_t st);
 

@@ -28,7 +28,8 @@ constexpr int kCRZ = 0;
 constexpr int kCPQ = 1;
 constexpr int kCALPHA = 2;
 constexpr int kCBETA = 3;
-constexpr int kNumCGScalars = 4;
+constexpr int kCRZD = 4;   // (r, D^-1 r) of a level with window corrections, before their part
+constexpr int kNumCGScalars = 5;
 
 template <typename T>
 struct CGLev {
@@ -51,6 +52,13 @@ struct CGLev {
   int nblk;        // update/init blocks of this level
   int blk0s;       // first block of this level in the operator grid (64 parents per block)
   int nblks;       // operator blocks of this level
+  // window corrections of the preconditioner (levels k < q; nwin = 0: none)
+  const T* winv;   // [nwin][27][27] B_w^-1
+  T* Y;            // [nwin][27] B_w^-1 r_w of the current iteration
+  const int* wlist;   // window origins x0 * np + y0
+  const int* widx;    // [np^2] slot of the window with that origin, or -1
+  int nwin;
+  int win0;        // first window of this level in the window grid
 };
 
 template <typename T>
@@ -58,6 +66,11 @@ struct CGArgs {
   CGLev<T> lv[kMaxLevels];
   int nlev;
 };
+
+// After the CG start (init) or CG iteration it: z += sum_w P_w^T B_w^-1 P_w r
+// on the levels with kept windows, and their (r, z) / beta update.
+template <typename T>
+void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st);
 
 // Finest subband level, conjugate gradients in the Chronopoulos-Gear form
 // (one reduction and one launch per iteration).  r, w (= B u) and s (= B p)

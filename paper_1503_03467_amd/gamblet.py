@@ -16,7 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgamblet.so")
 
 GBL_OK, GBL_EINVAL, GBL_ENOTSPD, GBL_ENOCONV, GBL_ENOMEM, GBL_EHIP = 0, -1, -2, -3, -4, -5
-GBL_FP64, GBL_MIXED = 0, 1
+GBL_FP64, GBL_MIXED, GBL_MIXED_FP64_BUILD = 0, 1, 2
+PRECISIONS = {"fp64": GBL_FP64, "f64": GBL_FP64, "double": GBL_FP64, "mixed": GBL_MIXED,
+              "mixed-fp64-build": GBL_MIXED_FP64_BUILD}
 _STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "ENOMEM", -5: "EHIP"}
 
 
@@ -25,7 +27,7 @@ class GblOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
-                ("rho_coarse", ctypes.c_int)]
+                ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -36,7 +38,8 @@ class GblSolveInfo(ctypes.Structure):
 class GblLevelDesc(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("nk", ctypes.c_int), ("s", ctypes.c_int), ("t", ctypes.c_int),
                 ("rw", ctypes.c_int), ("rho", ctypes.c_int), ("elem_bytes", ctypes.c_int),
-                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("R", ctypes.c_void_p)]
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("R", ctypes.c_void_p),
+                ("nwin", ctypes.c_int), ("wlist", ctypes.c_void_p), ("winv", ctypes.c_void_p)]
 
 
 class GambletError(RuntimeError):
@@ -103,13 +106,13 @@ def _check(code: int, ctx=None):
         raise GambletError(code, msg)
 
 
-INNER_KINDS = {"chebyshev": 0, "cg": 1}
+INNER_KINDS = {"chebyshev": 0, "cg": 1, "cheb-cg": 2}
 
 
 def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 100,
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
-              level_q_mass: int = 0, rho_coarse: int = 0) -> GblOpts:
+              level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -119,7 +122,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     if kappa_coarse is not None:
         o.kappa_coarse = float(kappa_coarse)
     o.rho = int(rho)
-    o.precision = GBL_FP64 if precision in ("fp64", "f64", "double") else GBL_MIXED
+    o.precision = PRECISIONS[precision]
     o.rtol = float(rtol)
     o.max_outer = int(max_outer)
     if inner_iters is not None:
@@ -129,6 +132,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.max_rhs = int(max_rhs)
     o.level_q_mass = int(level_q_mass)
     o.rho_coarse = int(rho_coarse)
+    o.window_tol = float(window_tol)
     return o
 
 
@@ -163,7 +167,8 @@ class Hierarchy:
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
-                 kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0):
+                 kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0,
+                 window_tol: float = 0.0):
         n = a.shape[0]
         q = n.bit_length() - 1
         if n != (1 << q) or q < 2:
@@ -171,7 +176,7 @@ class Hierarchy:
         _require(a, (n, n), "a")
         self.q, self.n, self.device = q, n, a.device
         self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
-                              kappa_coarse, level_q_mass, rho_coarse)
+                              kappa_coarse, level_q_mass, rho_coarse, window_tol)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -311,6 +316,13 @@ class Hierarchy:
             out["B"] = Bg.permute(1, 2, 3, 4, 0, 5).reshape(T, T, 3, 3, ng * 64)[..., :np_ * np_].reshape(
                 T, T, 3, 3, np_, np_)
             out["R"] = view(d.R, d.rw * d.rw * np_ * np_).view(d.rw, d.rw, np_, np_)
+            out["nwin"] = d.nwin
+            if d.nwin > 0:
+                out["wlist"] = self.ws[d.wlist - base: d.wlist - base + 4 * d.nwin].view(torch.int32)
+                wdt = torch.float64 if self.opts.precision == GBL_FP64 else torch.float32
+                wb = 8 if wdt == torch.float64 else 4
+                out["winv"] = self.ws[d.winv - base: d.winv - base + wb * d.nwin * 27 * 27].view(wdt).view(
+                    d.nwin, 27, 27)
         return out
 
 

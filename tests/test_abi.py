@@ -44,7 +44,8 @@ def test_bad_q_rejected(q):
 
 
 @pytest.mark.parametrize("field,value", [("rho", 0), ("rho", 5), ("precision", 7), ("rtol", 0.0),
-                                         ("rtol", 2.0), ("max_outer", 0), ("max_rhs", 0), ("inner_kind", 2),
+                                         ("rtol", 2.0), ("max_outer", 0), ("max_rhs", 0), ("inner_kind", 3),
+                                         ("window_tol", -1.0), ("window_tol", 1000.0),
                                          ("kappa", 1.0), ("kappa_coarse", 0.5), ("inner_iters", 33),
                                          ("inner_iters_coarse", 33)])
 def test_bad_options_rejected(field, value):
