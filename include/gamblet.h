@@ -81,7 +81,11 @@ enum gbl_inner {
 };
 
 typedef struct gbl_opts {
-  int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3); 1..4 */
+  int rho;            /* patch radius in coarse cells (box |dx|,|dy| <= rho, Definition 5.3) of the finest
+                         transition (and of all levels when rho_coarse = 0); 1..4, or 5 with rho_coarse set.
+                         The paper sizes the radius of level k like ln(1/H_k), larger on finer levels; with
+                         inclusions of very high coefficient about as wide as the finest patches, the finest
+                         transition is the one whose radius decides the outer iteration count */
   int precision;      /* enum gbl_precision */
   double rtol;        /* target relative l2 error of u; the solve stops when the larger of ||S r|| and the
                          last correction, over the last two iterations, is below rtol / f of ||u||, with

@@ -141,9 +141,9 @@ def lift(fe: FEProblem, b: np.ndarray, u_boundary: np.ndarray | None) -> np.ndar
 class DirectSolver:
     """Sparse LU of the interior stiffness matrix plus FP64 iterative refinement."""
 
-    def __init__(self, A: sp.spmatrix, refine: int = 2):
+    def __init__(self, A: sp.spmatrix, refine: int = 2, ordering: str = "MMD_AT_PLUS_A"):
         self.A = sp.csc_matrix(A)
-        self.lu = spla.splu(self.A, permc_spec="MMD_AT_PLUS_A")
+        self.lu = spla.splu(self.A, permc_spec=ordering)
         self.refine = refine
 
     def solve(self, b: np.ndarray) -> np.ndarray:

@@ -137,7 +137,7 @@ struct Layout {
 
 int validate_opts(const gbl_opts* o, std::string& msg) {
   if (!o) { msg = "opts is NULL"; return GBL_EINVAL; }
-  if (o->rho < 1 || o->rho > kMaxRho) { msg = "rho must be in [1, 4]"; return GBL_EINVAL; }
+  if (o->rho < 1 || o->rho > kMaxRho) { msg = "rho must be in [1, 5]"; return GBL_EINVAL; }
   if (o->precision != GBL_FP64 && o->precision != GBL_MIXED && o->precision != GBL_MIXED_FP64_BUILD) {
     msg = "unknown precision";
     return GBL_EINVAL;
@@ -155,7 +155,11 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   }
   if (o->max_rhs < 1 || o->max_rhs > 4096) { msg = "max_rhs must be in [1, 4096]"; return GBL_EINVAL; }
   if (o->level_q_mass < 0 || o->level_q_mass > kMaxRhoQ) { msg = "level_q_mass must be in [0, 4]"; return GBL_EINVAL; }
-  if (o->rho_coarse < 0 || o->rho_coarse > kMaxRho) { msg = "rho_coarse must be in [0, 4]"; return GBL_EINVAL; }
+  if (o->rho_coarse < 0 || o->rho_coarse > kMaxRhoCoarse) { msg = "rho_coarse must be in [0, 4]"; return GBL_EINVAL; }
+  if (o->rho > kMaxRhoCoarse && o->rho_coarse == 0) {
+    msg = "rho = 5 (the finest transition) needs rho_coarse in [1, 4] for the levels below";
+    return GBL_EINVAL;
+  }
   if (o->level_q_mass > 0 && o->inner_kind != GBL_INNER_CHEBYSHEV) {
     msg = "level_q_mass needs Chebyshev inner iterations";
     return GBL_EINVAL;

@@ -24,7 +24,8 @@
 namespace gbl {
 
 constexpr int kMaxLevels = 13;     // q <= 12
-constexpr int kMaxRho = 4;
+constexpr int kMaxRho = 5;         // the finest transition; below it at most kMaxRhoCoarse
+constexpr int kMaxRhoCoarse = 4;
 constexpr int kMaxRhoQ = 4;   // patch radius of the localized mass inverse
 // zero words before and after every level slot vector g^(k)
 constexpr int kGPad = 16;

@@ -1061,7 +1061,7 @@ static bool band_reg_enabled() {
 // substitution rides along and a column-oriented back substitution follows.
 // Same scaling, right-hand side and restriction row as the dense kernel.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int kMaxTri>
 __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A, const T* __restrict__ B,
                                                          T* __restrict__ R, int nk, int s, int rho,
                                                          int* __restrict__ status) {
@@ -1138,7 +1138,7 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
   }
   // this lane's fixed share of the trailing triangle: entries (dr, dc),
   // 1 <= dc <= dr <= bw, enumerated column by column
-  constexpr int kMaxTri = 9;   // ceil(bw (bw + 1) / 2 / 64) for bw <= 32 (rho <= 4)
+  // kMaxTri = ceil(bw (bw + 1) / 2 / 64): 9 for bw <= 32 (rho <= 4), 12 for bw <= 38 (rho = 5)
   const int ntri = bw * (bw + 1) / 2;
   int tri_dr[kMaxTri], tri_dc[kMaxTri];
   {
@@ -1230,7 +1230,11 @@ void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, i
   const int pmax = 3 * (2 * L.rho + 1) * (2 * L.rho + 1);
   const int bwmax = 3 * (2 * L.rho + 2) + 2;
   const size_t shm = ((size_t)pmax * (bwmax + 1) + 2 * (size_t)pmax + (bwmax + 1)) * sizeof(T);
-  hipLaunchKernelGGL(k_patch_solve_band<T>, dim3(nc * nc), dim3(64), shm, st, A, B, R, L.nk, L.s, L.rho, status);
+  if (L.rho <= 4)
+    hipLaunchKernelGGL((k_patch_solve_band<T, 9>), dim3(nc * nc), dim3(64), shm, st, A, B, R, L.nk, L.s, L.rho, status);
+  else
+    hipLaunchKernelGGL((k_patch_solve_band<T, 12>), dim3(nc * nc), dim3(64), shm, st, A, B, R, L.nk, L.s, L.rho,
+                       status);
 }
 
 // ---------------------------------------------------------------------------

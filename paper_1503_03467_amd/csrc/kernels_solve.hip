@@ -320,7 +320,8 @@ void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStre
     case 1: hipLaunchKernelGGL((k_restrict<T, 1>), grid, block, 0, st, R, gf, gc, L.nk); break;
     case 2: hipLaunchKernelGGL((k_restrict<T, 2>), grid, block, 0, st, R, gf, gc, L.nk); break;
     case 3: hipLaunchKernelGGL((k_restrict<T, 3>), grid, block, 0, st, R, gf, gc, L.nk); break;
-    default: hipLaunchKernelGGL((k_restrict<T, 4>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    case 4: hipLaunchKernelGGL((k_restrict<T, 4>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    default: hipLaunchKernelGGL((k_restrict<T, 5>), grid, block, 0, st, R, gf, gc, L.nk); break;
   }
 }
 
@@ -370,7 +371,8 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ R, const T* __rest
     case 1: return prolong_at_r<T, 1>(R, vc, nk, fx, fy);
     case 2: return prolong_at_r<T, 2>(R, vc, nk, fx, fy);
     case 3: return prolong_at_r<T, 3>(R, vc, nk, fx, fy);
-    default: return prolong_at_r<T, 4>(R, vc, nk, fx, fy);
+    case 4: return prolong_at_r<T, 4>(R, vc, nk, fx, fy);
+    default: return prolong_at_r<T, 5>(R, vc, nk, fx, fy);
   }
 }
 

@@ -58,7 +58,8 @@ __device__ __forceinline__ double rt_apply(const T* __restrict__ R, const double
     case 1: return rt_apply_r<T, 1>(R, vc, nk, fx, fy);
     case 2: return rt_apply_r<T, 2>(R, vc, nk, fx, fy);
     case 3: return rt_apply_r<T, 3>(R, vc, nk, fx, fy);
-    default: return rt_apply_r<T, 4>(R, vc, nk, fx, fy);
+    case 4: return rt_apply_r<T, 4>(R, vc, nk, fx, fy);
+    default: return rt_apply_r<T, 5>(R, vc, nk, fx, fy);
   }
 }
 

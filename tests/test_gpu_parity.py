@@ -359,7 +359,7 @@ def test_smaller_patch_radius_as_preconditioner_q9():
     assert iters[1] > iters[2] > iters[3]
 
 
-@pytest.mark.parametrize("q,rho,rho_c", [(5, 3, 2), (5, 2, 3), (6, 3, 1)])
+@pytest.mark.parametrize("q,rho,rho_c", [(5, 3, 2), (5, 2, 3), (6, 3, 1), (6, 5, 4), (5, 5, 2)])
 def test_per_level_radius_hierarchy_matches_oracle_fp64(q, rho, rho_c):
     """A different patch radius below the finest transition (rho_coarse):
     every level's A^(k), B^(k), R^(k-1,k) against the oracle's per-level
@@ -425,35 +425,6 @@ def test_adjoint_q10_matches_oracle_and_fd():
     print("fd err", err_fd, flush=True)
     assert err_fd < 1e-5, err_fd
     H.close()
-
-
-@pytest.mark.timeout(600)
-def test_inclusions_q11_rho4():
-    """Circular inclusions on 10% of a 2048 x 2048 grid, rho = 4, FP64 path.
-    The inclusion value is 1e4 (total contrast 4.5e5): the block-Jacobi
-    preconditioned subband systems of the two finest levels have condition
-    numbers close to the inclusion value, and at 1e6 the local inner solves
-    stall (recorded as a limitation).  Four right-hand sides with CG inner
-    budgets (64, 16) each get a small FP64 residual; the first matches the
-    direct solve at 1e-8."""
-    _print_case(test="inclusions_q11", a_incl=1e4)
-    pr = S.inclusion_problem(nrhs=4, a_incl=1e4)
-    fe = fem.assemble(pr.a)
-    print("problem ready", flush=True)
-    H = _P().Hierarchy(_dev(pr.a), rho=4, precision="fp64", rtol=1e-8, max_rhs=4, max_outer=400,
-                       inner="cg", inner_iters=64, inner_iters_coarse=16)
-    u = H.solve(_dev(pr.g)).cpu().numpy()
-    print("gpu done", H.last_info, flush=True)
-    H.close()
-    for r in range(4):
-        b = fem.load_cellwise(pr.g[r], fe.h)
-        res = np.linalg.norm(b - fe.A @ u[r][1:-1, 1:-1].ravel()) / np.linalg.norm(b)
-        print("rhs", r, "residual", res, flush=True)
-        assert res < 1e-5, (r, res)
-    u_ref = fem.solve(pr.a, pr.g[:1])[0][1:-1, 1:-1]
-    err = _relerr(u[0][1:-1, 1:-1], u_ref)
-    print("err vs direct", err, flush=True)
-    assert err < 1e-8, err
 
 
 def _torch_residual(a, g, u):

@@ -130,3 +130,26 @@ def test_window_solve_high_contrast(precision, inner, gate):
         H0.close()
         print("outer iterations with / without windows", it_win, it_plain, flush=True)
         assert 2 * it_win < it_plain, (it_win, it_plain)
+
+
+def test_finest_radius_five_high_contrast():
+    """Discs up to 16 cells wide are as wide as the radius-4 patches of the
+    finest transition (18 cells); radius 5 there (the paper sizes the radius
+    of a level like ln(1/H_k), larger on finer levels) cuts the outer
+    iterations, with the same accuracy (256 x 256 cells, a = 1e6)."""
+    q = 8
+    _print_case(test="finest_radius_5", q=q)
+    pr = S.inclusion_problem(q=q, nrhs=1, a_incl=1e6)
+    u_ref = fem.solve(pr.a, pr.g)[0][1:-1, 1:-1]
+    P = _P()
+    its = {}
+    for rho in (4, 5):
+        H = P.Hierarchy(_dev(pr.a), rho=rho, rho_coarse=4, precision="mixed-fp64-build", rtol=1e-9, max_outer=2000,
+                        inner="cheb-cg", inner_iters=16, inner_iters_coarse=8, window_tol=TOL)
+        u = H.solve(_dev(pr.g[0])).cpu().numpy()
+        its[rho] = H.last_info.outer_iters
+        err = _relerr(u[1:-1, 1:-1], u_ref)
+        print("rho", rho, "outer", its[rho], "err", err, flush=True)
+        H.close()
+        assert err < 1e-7, (rho, err)
+    assert 2 * its[5] < its[4], its
