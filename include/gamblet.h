@@ -94,7 +94,10 @@ typedef struct gbl_opts {
                          and over the whole solve, capped at 0.995) */
   int max_outer;      /* maximum outer (flexible CG) iterations */
   int inner_iters;    /* iterations on the finest subband system per outer iteration (Chebyshev: <= 32) */
-  int max_rhs;        /* right-hand sides one gbl_solve call may carry (sizes the workspace) */
+  int max_rhs;        /* right-hand sides solved together: a solve or adjoint call takes any number of right-
+                         hand sides and runs them in blocks of min(max_rhs, 16), every kernel of an iteration
+                         launched once for the whole block (each right-hand side with its own copy of the
+                         solve vectors, so the workspace grows with it); 1..4096 */
   int inner_iters_coarse; /* iterations on each coarser subband system (k < q) (Chebyshev: <= 32) */
   int inner_kind;     /* enum gbl_inner: the iteration used on the subband systems B^(k) w = W g
                          (Section 4.7), block-Jacobi (3 x 3 parent blocks) preconditioned */
@@ -165,7 +168,7 @@ int gbl_version(void);
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
- * these options, including solve buffers for opts->max_rhs right-hand sides.
+ * these options, including min(opts->max_rhs, 16) copies of the solve buffers.
  * Pure host computation.  EINVAL on a bad q or options. */
 int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
 
@@ -178,7 +181,8 @@ int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
 int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts,
               void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Solve for nrhs right-hand sides (nrhs <= opts->max_rhs).
+/* Solve for nrhs >= 1 right-hand sides (in blocks of min(opts->max_rhs, 16); a block
+ * iterates until all its right-hand sides meet rtol).
  * g_dev : [nrhs][n][n] cell source.
  * u_dev : [nrhs][n+1][n+1] nodal; on entry its boundary entries hold the
  *         Dirichlet data (interior entries are ignored), on exit the interior
@@ -221,7 +225,7 @@ int gbl_build_batched(int nprob, const int* q, const double* const* a_dev, const
                       void* const* ws_dev, const size_t* ws_bytes, gbl_ctx** ctx_out, int* status,
                       void* stream);
 
-/* Batched solve: problem i solves nrhs[i] right-hand sides (<= its max_rhs),
+/* Batched solve: problem i solves nrhs[i] right-hand sides (blocks as in gbl_solve),
  * g_dev[i] [nrhs_i][n_i][n_i] into u_dev[i] [nrhs_i][n_i+1][n_i+1] (boundary
  * values in, solution out) with context ctx[i], concurrently as in
  * gbl_build_batched.  info (optional) is an array of nprob records; status[i]

@@ -132,8 +132,16 @@ struct Layout {
   size_t win_list_off[kMaxLevels] = {}, win_idx_off[kMaxLevels] = {};   // int arrays
   size_t win_inv_off[kMaxLevels] = {}, win_y_off[kMaxLevels] = {};      // T arrays
   size_t wcnt_off = 0;       // kept-window counters (kMaxLevels unsigned)
+  // Right-hand sides solved together: the per-solve region [solve_off,
+  // solve_off + solve_stride) (outer scalars and vectors, slot vectors, subband
+  // iteration vectors, scalars, partial sums, tickets, window apply buffers,
+  // error log) is repeated M times, solve_stride bytes apart.
+  int M = 1;
+  size_t solve_off = 0, solve_stride = 0;
   size_t total = 0;
 };
+
+constexpr int kMaxBlock = 16;   // right-hand sides per block solve
 
 int validate_opts(const gbl_opts* o, std::string& msg) {
   if (!o) { msg = "opts is NULL"; return GBL_EINVAL; }
@@ -257,6 +265,9 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   L.L1_off = b; b = align_up(b + 16 * 8);
   L.status_off = b; b = align_up(b + 4 * sizeof(int));
   L.gersh_off = b; b = align_up(b + kMaxLevels * sizeof(unsigned));
+  // ---- per-solve region (repeated M times)
+  L.M = (o->level_q_mass > 0) ? 1 : std::min(o->max_rhs, kMaxBlock);
+  L.solve_off = b;
   L.oscal_off = b; b = align_up(b + kNumOuterScalars * 8);
   L.dpart_off = b; b = align_up(b + 3 * kDotBlocks * 8);
   L.dcnt_off = b; b = align_up(b + 4 * sizeof(unsigned));
@@ -290,20 +301,28 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
   if (o->window_tol > 0.0) {
     for (int k = 3; k < q; ++k) {
       const size_t np = (size_t)L.lv[k].nk / 2;
-      const size_t cap = (np - 2) * (np - 2);
-      L.win_cap[k] = (int)cap;
+      L.win_cap[k] = (int)((np - 2) * (np - 2));
+      L.win_y_off[k] = b; b = align_up(b + (size_t)L.win_cap[k] * 27 * L.selem);
+    }
+  }
+  L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
+  L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
+  L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
+  L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
+  L.solve_stride = align_up(b - L.solve_off);
+  b = L.solve_off + (size_t)L.M * L.solve_stride;
+  // ---- shared again
+  if (o->window_tol > 0.0) {
+    for (int k = 3; k < q; ++k) {
+      const size_t np = (size_t)L.lv[k].nk / 2;
+      const size_t cap = (size_t)L.win_cap[k];
       L.win_list_off[k] = b; b = align_up(b + cap * sizeof(int));
       L.win_idx_off[k] = b; b = align_up(b + np * np * sizeof(int));
       L.win_inv_off[k] = b; b = align_up(b + cap * 27 * 27 * L.selem);
-      L.win_y_off[k] = b; b = align_up(b + cap * 27 * L.selem);
     }
   }
   // everything from here on is zeroed at the start of a build
-  L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
-  L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
   L.wcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
-  L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
-  L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
   for (int k = 1; k <= q; ++k) {
     L.tr_off[k] = b;
     b = align_up(b + (size_t)L.lv[k].nk * L.lv[k].nk * 8);
@@ -347,6 +366,7 @@ struct gbl_ctx {
   // that the caller may pass the null stream) and replayed per iteration.
   hipStream_t cap = nullptr;
   hipGraphExec_t iter_graph = nullptr;
+  int iter_graph_m = 0;                 // right-hand sides of the recorded iteration
   bool graph_off = false;               // capture failed once: launch kernel by kernel
   unsigned build_flags = 0;             // GBL_FLAG_* of the build
   float lmax[kMaxLevels] = {};          // bound of lambda_max(M B^(k)) per level
@@ -393,7 +413,13 @@ struct CtxResources {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* host = nullptr;
 };
-constexpr size_t kHostWords = kNumOuterScalars + 4 + (kMaxChunk > kMaxLevels ? kMaxChunk : kMaxLevels);
+// Pinned host words: outer scalars of every right-hand side of a block, the
+// status word, the build's bounds and window counts, then the error
+// estimates of a chunk of iterations for every right-hand side.
+constexpr size_t kHostStatus = (size_t)kMaxBlock * kNumOuterScalars;
+constexpr size_t kHostBits = kHostStatus + 4;
+constexpr size_t kHostLog = kHostBits + kMaxLevels;
+constexpr size_t kHostWords = kHostLog + (size_t)kMaxBlock * kMaxChunk;
 constexpr size_t kMaxPooledResources = 64;
 std::mutex g_res_mu;
 std::vector<CtxResources> g_res_pool;
@@ -679,7 +705,7 @@ const CGArgs<T>& cgq_of(const gbl_ctx* c);
 template <typename T>
 void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, hipStream_t st,
                   bool r_converted = false, const double* uo = nullptr, const double* wo = nullptr,
-                  double* dots = nullptr) {
+                  double* dots = nullptr, Zb zb = Zb()) {
   const Layout& L = c->L;
   const int q = L.q;
   const size_t n2 = (size_t)L.n * L.n;
@@ -704,7 +730,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   if (L.mass > 0)
     launch_mass_load_slots<T>(L.n, L.mass, c->lqtab(), r, g[q], st);   // g^(q) = Minv^T r
   else if (!r_converted)
-    launch_convert<T, double>(n2, r, g[q], st);
+    launch_convert<T, double>(n2, r, g[q], st, zb);
   // The subband systems are independent (Section 4.7), so they run beside each
   // other: the finest one on the caller's stream (it needs only g^(q)), and
   // the restriction chain, the coarser systems and the prolongation down to
@@ -722,49 +748,49 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
   const int K = c->opts.inner_iters_coarse;
   for (int k = q; k > kc; --k) {
     ProfScope ps(GBL_PROF_RESTRICT, cs);
-    launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], cs);
+    launch_restrict<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k], g[k - 1], cs, zb);
   }
   {
     ProfScope ps(GBL_PROF_RESTRICT, cs);
-    launch_restrict_chain<T>(chain, cs);
+    launch_restrict_chain<T>(chain, cs, zb);
   }
   if (coarse) {
     if (cheb_coarse) {
       {
         ProfScope ps(GBL_PROF_CG_INIT, cs);
-        launch_cheb_init<T>(cg, c->cheb_coarse[0], 0, cg.nlev, cs);
+        launch_cheb_init<T>(cg, c->cheb_coarse[0], 0, cg.nlev, cs, zb);
       }
       for (int j = 1; j < K; ++j) {
         ProfScope ps(GBL_PROF_CG_SPMV, cs);
-        launch_cheb_step<T>(cg, c->cheb_coarse[j], j, 0, cg.nlev, cs);
+        launch_cheb_step<T>(cg, c->cheb_coarse[j], j, 0, cg.nlev, cs, zb);
       }
     } else {
       const CGLev<T>& last = cg.lv[cg.nlev - 1];
       {
         ProfScope ps(GBL_PROF_CG_INIT, cs);
-        launch_cg_init<T>(cg, last.blk0 + last.nblk, cs);
-        if (windows) launch_win_correct<T>(cg, 0, true, cs);
+        launch_cg_init<T>(cg, last.blk0 + last.nblk, cs, zb);
+        if (windows) launch_win_correct<T>(cg, 0, true, cs, zb);
       }
       for (int it = 0; it < K; ++it) {
         {
           ProfScope ps(GBL_PROF_CG_SPMV, cs);
-          launch_cg_spmv<T>(cg, last.blk0s + last.nblks, it, cs);
+          launch_cg_spmv<T>(cg, last.blk0s + last.nblks, it, cs, zb);
         }
         ProfScope ps(GBL_PROF_CG_UPDATE, cs);
-        launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs);
-        if (windows && it + 1 < K) launch_win_correct<T>(cg, it, false, cs);
+        launch_cg_update<T>(cg, last.blk0 + last.nblk, it, cs, zb);
+        if (windows && it + 1 < K) launch_win_correct<T>(cg, it, false, cs, zb);
       }
     }
   } else {
-    for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, cs);
+    for (int l = 0; l < cg.nlev; ++l) launch_zero<T>(3 * (size_t)cg.lv[l].np * cg.lv[l].np, cg.lv[l].x, cs, zb);
   }
   {
     ProfScope ps(GBL_PROF_PROLONG, cs);
-    launch_prolong_chain<T>(chain, c->L1(), cs);
+    launch_prolong_chain<T>(chain, c->L1(), cs, zb);
   }
   for (int k = kc + 1; k < q; ++k) {
     ProfScope ps(GBL_PROF_PROLONG, cs);
-    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, cs);
+    launch_prolong<T>(L.lv[k], c->hier<T>(L.lv[k].offR), g[k - 1], cg.lv[q - 1 - k].x, g[k], false, cs, zb);
   }
   // finest level (enqueued after the coarser chain, the longer of the two
   // branches, so that a replayed graph starts that chain first): Chebyshev
@@ -792,14 +818,14 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     do {
       const int ns = std::min(fuse, K - 1 - k0);
       ProfScope ps(GBL_PROF_FINE_CG, st);
-      launch_fine_cheb<T>(F, c->cheb_fine, K, k0, ns, rd, st);
+      launch_fine_cheb<T>(F, c->cheb_fine, K, k0, ns, rd, st, zb);
       k0 += ns;
       rd ^= 1;
     } while (k0 < K - 1);
   } else {
     for (int it = 0; it < c->opts.inner_iters; ++it) {
       ProfScope ps(GBL_PROF_FINE_CG, st);
-      launch_fine_cg<T>(F, it, st);
+      launch_fine_cg<T>(F, it, st, zb);
     }
   }
   if (c->side) {
@@ -817,7 +843,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
     launch_mass_nodal_dots<T>(L.n, L.mass, c->lqtab(), g[q], z, dots ? uo : z, dots ? wo : z, opart, st);
   } else {
     launch_prolong_fine_dots<T>(L.lv[q], c->hier<T>(L.lv[q].offR), g[q - 1], F, z, dots ? uo : z, dots ? wo : z,
-                                opart, cheb ? 1 : 0, st);
+                                opart, cheb ? 1 : 0, st, zb);
   }
   (void)part;
   (void)cnt;
@@ -828,7 +854,7 @@ void precondition(gbl_ctx* c, const CGArgs<T>& cg, const double* r, double* z, h
 // the new direction p = z + beta p, whose kernel also logs the iteration's
 // error estimate on the device.
 template <typename T>
-void outer_iteration(gbl_ctx* c, const CGArgs<T>& cg, hipStream_t st) {
+void outer_iteration(gbl_ctx* c, const CGArgs<T>& cg, hipStream_t st, Zb zb) {
   const Layout& L = c->L;
   const int n = L.n;
   const int len = n * n;
@@ -844,11 +870,11 @@ void outer_iteration(gbl_ctx* c, const CGArgs<T>& cg, hipStream_t st) {
   T* gq = reinterpret_cast<T*>(c->ws + L.g_off[L.q]);
   {
     ProfScope ps(GBL_PROF_FINE_APPLY, st);
-    launch_apply_fine_dots(c->a(), n, p, r, w, partA, st);
+    launch_apply_fine_dots(c->a(), n, p, r, w, partA, st, zb);
   }
-  launch_outer_update_convert<T>(len, partA, L.onblk, sc, u, r, p, w, gq, st);
-  precondition<T>(c, cg, r, z, st, true, u, w, sc);
-  launch_outer_direction(len, sc, partB, L.onblk, z, p, elog, 0, st);
+  launch_outer_update_convert<T>(len, partA, L.onblk, sc, u, r, p, w, gq, st, zb);
+  precondition<T>(c, cg, r, z, st, true, u, w, sc, zb);
+  launch_outer_direction(len, sc, partB, L.onblk, z, p, elog, 0, st, zb);
 }
 
 // Kernel classes launched inside the outer iteration: while any of them is
@@ -865,16 +891,21 @@ bool iteration_graph_enabled() {
 }
 
 template <typename T>
-int run_iterations(gbl_ctx* c, const CGArgs<T>& cg, int m, hipStream_t st) {
+int run_iterations(gbl_ctx* c, const CGArgs<T>& cg, int m, hipStream_t st, Zb zb) {
   if (!(g_prof.mask & kIterationClasses) && !c->graph_off && iteration_graph_enabled()) {
+    if (c->iter_graph && c->iter_graph_m != zb.m) {
+      hipGraphExecDestroy(c->iter_graph);   // recorded for another number of right-hand sides
+      c->iter_graph = nullptr;
+    }
     if (!c->iter_graph) {
       hipGraph_t g = nullptr;
       bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
-        outer_iteration<T>(c, cg, c->cap);
+        outer_iteration<T>(c, cg, c->cap, zb);
         ok = hipStreamEndCapture(c->cap, &g) == hipSuccess && g != nullptr;
       }
       if (ok) ok = hipGraphInstantiate(&c->iter_graph, g, nullptr, nullptr, 0) == hipSuccess;
+      c->iter_graph_m = zb.m;
       if (g) hipGraphDestroy(g);
       if (!ok) {
         c->iter_graph = nullptr;
@@ -887,7 +918,7 @@ int run_iterations(gbl_ctx* c, const CGArgs<T>& cg, int m, hipStream_t st) {
       return GBL_OK;
     }
   }
-  for (int j = 0; j < m; ++j) outer_iteration<T>(c, cg, st);
+  for (int j = 0; j < m; ++j) outer_iteration<T>(c, cg, st, zb);
   return GBL_OK;
 }
 
@@ -931,13 +962,20 @@ int next_chunk(const std::vector<double>& h, double rtol) {
 }
 
 // Flexible CG on the FP64 fine system with the subband solve as
-// preconditioner.  mode 0: source given per cell; mode 1: nodal right-hand side.
+// preconditioner, for zb.m right-hand sides at once (each with its own
+// scalars in its copy of the per-solve region).  mode 0: source given per
+// cell; mode 1: nodal right-hand side.  src and u_nodal hold the right-hand
+// sides src_stride and u_stride doubles apart.  The block stops when every
+// right-hand side has met the stopping rule (or produced a non-finite
+// estimate); right-hand sides that finished earlier keep iterating, which only
+// lowers their error.
 template <typename T>
-int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, double* u_nodal,
-              gbl_solve_info* info, hipStream_t st) {
+int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, size_t src_stride, double* u_nodal,
+              size_t u_stride, gbl_solve_info* info, hipStream_t st, Zb zb) {
   const Layout& L = c->L;
   const int n = L.n;
   const int len = n * n;
+  const int m = zb.m;
   double* u = c->fine(0);
   double* r = c->fine(1);
   double* z = c->fine(2);
@@ -948,12 +986,12 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   unsigned* cnt = reinterpret_cast<unsigned*>(c->ws + L.dcnt_off);
   double* partB = reinterpret_cast<double*>(c->ws + L.opart_off) + 3 * (size_t)L.onblk;
   const double* elog = reinterpret_cast<const double*>(c->ws + L.elog_off);
-  launch_residual(c->a(), n, mode, src, u_nodal, nullptr, r, st);
-  launch_fill((size_t)len, 0.0, u, st);
-  launch_fill(1, 0.0, sc + kSIter, st);
-  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSBB, st);
-  precondition<T>(c, cg, r, z, st, false, u, w, sc);
-  launch_outer_direction(len, sc, partB, L.onblk, z, p, nullptr, 1, st);
+  launch_residual(c->a(), n, mode, src, u_nodal, nullptr, r, st, zb, src_stride, u_stride);
+  launch_fill((size_t)len, 0.0, u, st, zb);
+  launch_fill(1, 0.0, sc + kSIter, st, zb);
+  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSBB, st, zb);
+  precondition<T>(c, cg, r, z, st, false, u, w, sc, zb);
+  launch_outer_direction(len, sc, partB, L.onblk, z, p, nullptr, 1, st, zb);
   // Error estimate of iteration i (logged by the direction kernel): z = S r
   // approximates the error and alpha p is the last correction; either alone
   // can under-read the error when the inner solves are loose, so the larger
@@ -961,56 +999,69 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, doub
   // against rtol.  Iterations that run past the first passing one only lower
   // the A-norm error further.
   const double rtol = c->opts.rtol;
-  double* hl = c->host + kNumOuterScalars + 4;   // host copy of a chunk of estimates
-  std::vector<double> hist;
-  int status = GBL_ENOCONV;
-  double est = 1.0, prev = INFINITY;
+  double* hl = c->host + kHostLog;   // host copy of a chunk of estimates, kMaxChunk per right-hand side
+  std::vector<std::vector<double>> hist(m);
+  std::vector<int> done_rhs(m, 0), status(m, GBL_ENOCONV);
+  std::vector<double> est(m, 1.0), prev(m, INFINITY);
   int done = 0;
   while (done < c->opts.max_outer) {
-    const int m = std::min(next_chunk(hist, rtol), c->opts.max_outer - done);
-    const int rs = run_iterations<T>(c, cg, m, st);
+    int chunk = kMaxChunk;
+    for (int j = 0; j < m; ++j)
+      if (!done_rhs[j]) chunk = std::min(chunk, next_chunk(hist[j], rtol));
+    chunk = std::min(chunk, c->opts.max_outer - done);
+    const int rs = run_iterations<T>(c, cg, chunk, st, zb);
     if (rs) return rs;
-    HIPCHK(c, hipMemcpyAsync(hl, elog + done, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpy2DAsync(hl, kMaxChunk * sizeof(double), elog + done, L.solve_stride,
+                               (size_t)chunk * sizeof(double), m, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    done += m;
-    bool stop = false;
-    for (int j = 0; j < m && !stop; ++j) {
-      const double cur = hl[j];
-      hist.push_back(cur);
-      if (!std::isfinite(cur)) {
-        est = cur;
-        status = GBL_ENOCONV;
-        stop = true;
-      } else {
-        est = std::max(cur, prev);
-        prev = cur;
-        if (est * tail_factor(hist) <= rtol) {
-          status = GBL_OK;
-          stop = true;
+    done += chunk;
+    int open = 0;
+    for (int j = 0; j < m; ++j) {
+      for (int i = 0; i < chunk && !done_rhs[j]; ++i) {
+        const double cur = hl[j * kMaxChunk + i];
+        hist[j].push_back(cur);
+        if (!std::isfinite(cur)) {
+          est[j] = cur;
+          status[j] = GBL_ENOCONV;
+          done_rhs[j] = 1;
+        } else {
+          est[j] = std::max(cur, prev[j]);
+          prev[j] = cur;
+          if (est[j] * tail_factor(hist[j]) <= rtol) {
+            status[j] = GBL_OK;
+            done_rhs[j] = 1;
+          }
         }
       }
+      open += done_rhs[j] ? 0 : 1;
     }
-    if (stop) break;
+    if (!open) break;
   }
   const int it = done;
-  launch_slots_to_nodal(n, u, u_nodal, st);
+  launch_slots_to_nodal(n, u, u_nodal, st, zb, u_stride);
   // final residual of the returned iterate
-  launch_residual(c->a(), n, mode, src, u_nodal, u, r, st);
-  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSRR, st);
-  HIPCHK(c, hipMemcpyAsync(c->host, sc, kNumOuterScalars * sizeof(double), hipMemcpyDeviceToHost, st));
+  launch_residual(c->a(), n, mode, src, u_nodal, u, r, st, zb, src_stride, u_stride);
+  launch_dots(len, 1, r, r, nullptr, nullptr, nullptr, nullptr, part, cnt, sc + kSRR, st, zb);
+  HIPCHK(c, hipMemcpy2DAsync(c->host, kNumOuterScalars * sizeof(double), sc, L.solve_stride,
+                             kNumOuterScalars * sizeof(double), m, hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   HIPCHK(c, hipGetLastError());
-  const double bb = c->host[kSBB], rr = c->host[kSRR];
-  const double rel_res = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-  if (info) {
-    // maxima over right-hand sides that keep a NaN visible
-    auto worst = [](double a, double b) { return (std::isnan(a) || std::isnan(b)) ? NAN : std::max(a, b); };
-    info->outer_iters = std::max(info->outer_iters, it);
-    info->rel_update = worst(info->rel_update, est);
-    info->rel_residual = worst(info->rel_residual, rel_res);
+  int worst = GBL_OK;
+  for (int j = 0; j < m; ++j) {
+    const double* hs = c->host + (size_t)j * kNumOuterScalars;
+    const double bb = hs[kSBB], rr = hs[kSRR];
+    const double rel_res = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    if (info) {
+      // maxima over right-hand sides that keep a NaN visible
+      auto worse = [](double a, double b) { return (std::isnan(a) || std::isnan(b)) ? NAN : std::max(a, b); };
+      info->outer_iters = std::max(info->outer_iters, it);
+      info->rel_update = worse(info->rel_update, est[j]);
+      info->rel_residual = worse(info->rel_residual, rel_res);
+    }
+    if (!std::isfinite(est[j]) || !std::isfinite(rel_res)) c->diverged = true;
+    if (status[j] != GBL_OK) worst = status[j];
   }
-  if (!std::isfinite(est) || !std::isfinite(rel_res)) c->diverged = true;
-  return status;
+  return worst;
 }
 
 template <typename T>
@@ -1031,12 +1082,18 @@ template <>
 const CGArgs<double>& cgq_of<double>(const gbl_ctx* c) { return c->cgqd; }
 
 template <typename T>
+// Right-hand sides in blocks of up to M solved together (M copies of the
+// per-solve region).
 int solve_many(gbl_ctx* c, int nrhs, int mode, const double* src, size_t src_stride, double* u,
                gbl_solve_info* info, hipStream_t st) {
   int worst = GBL_OK;
   const size_t us = (size_t)(c->L.n + 1) * (c->L.n + 1);
-  for (int r = 0; r < nrhs; ++r) {
-    const int s = fcg_solve<T>(c, cg_of<T>(c), mode, src + r * src_stride, u + r * us, info, st);
+  for (int r0 = 0; r0 < nrhs; r0 += c->L.M) {
+    Zb zb;
+    zb.m = std::min(c->L.M, nrhs - r0);
+    zb.zs = c->L.solve_stride;
+    const int s = fcg_solve<T>(c, cg_of<T>(c), mode, src + r0 * src_stride, src_stride, u + r0 * us, us, info, st,
+                               zb);
     if (s == GBL_EHIP) return s;
     if (s != GBL_OK) worst = s;
   }
@@ -1140,10 +1197,10 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   }
   // zero the status word, reduction tickets and the coarse factor
   {
-    const size_t nz = (L.lam_off - L.L1_off) / 8;
-    launch_fill(nz, 0.0, reinterpret_cast<double*>(c->ws + L.L1_off), s);
-    launch_fill((L.total - L.cgscal_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.cgscal_off), s);
-    launch_fill((L.gpad_end - L.gpad_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.gpad_off), s);
+    // coarse factor, status, bounds and every copy of the per-solve region
+    launch_fill((L.solve_off + (size_t)L.M * L.solve_stride - L.L1_off) / 8, 0.0,
+                reinterpret_cast<double*>(c->ws + L.L1_off), s);
+    launch_fill((L.total - L.wcnt_off) / 8, 0.0, reinterpret_cast<double*>(c->ws + L.wcnt_off), s);
   }
   c->cgf = make_cg_args<float>(c);
   c->cgd = make_cg_args<double>(c);
@@ -1171,11 +1228,11 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
       return bail(GBL_EHIP);
     }
   }
-  unsigned* hbits = reinterpret_cast<unsigned*>(c->host + kNumOuterScalars + 4);
+  unsigned* hbits = reinterpret_cast<unsigned*>(c->host + kHostBits);
   unsigned* wbits = hbits + kMaxLevels;
-  static_assert(2 * kMaxLevels * sizeof(unsigned) <= (kHostWords - kNumOuterScalars - 4) * sizeof(double),
+  static_assert(2 * kMaxLevels * sizeof(unsigned) <= (kHostLog - kHostBits) * sizeof(double),
                 "pinned host words hold the bounds and the window counts");
-  if (hipMemcpyAsync(c->host + kNumOuterScalars, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(c->host + kHostStatus, c->status(), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(hbits, c->ws + L.gersh_off, kMaxLevels * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
       hipMemcpyAsync(wbits, c->ws + L.wcnt_off, kMaxLevels * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
@@ -1187,7 +1244,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   for (int k = 0; k < kMaxLevels; ++k) std::memcpy(&c->lmax[k], &hbits[k], sizeof(float));
   make_cheb_tables(c);
   int bits = 0;
-  std::memcpy(&bits, c->host + kNumOuterScalars, sizeof(int));
+  std::memcpy(&bits, c->host + kHostStatus, sizeof(int));
   if (bits & kBadCoefficient) {
     c->err = "coefficient must be positive and finite in every cell";
     return bail(GBL_EINVAL);
@@ -1211,7 +1268,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
 int gbl_solve(gbl_ctx* c, int nrhs, const double* g_dev, double* u_dev, gbl_solve_info* info, void* stream) {
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!g_dev || !u_dev) return fail(c, GBL_EINVAL, "g_dev and u_dev must not be NULL");
-  if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
+  if (nrhs < 1) return fail(c, GBL_EINVAL, "nrhs must be at least 1");
   if (info) std::memset(info, 0, sizeof(*info));
   c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1229,24 +1286,32 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
                 double* dJdg_dev, double* lambda_dev, gbl_solve_info* info, void* stream) {
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!u_dev || !dJdu_dev || !dJdloga_dev) return fail(c, GBL_EINVAL, "u, dJdu and dJdloga must not be NULL");
-  if (nrhs < 1 || nrhs > c->L.max_rhs) return fail(c, GBL_EINVAL, "nrhs out of range");
+  if (nrhs < 1) return fail(c, GBL_EINVAL, "nrhs must be at least 1");
   if (info) std::memset(info, 0, sizeof(*info));
   c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = c->L.n;
   const size_t n2 = (size_t)n * n, us = (size_t)(n + 1) * (n + 1);
   int worst = GBL_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    double* lam = lambda_dev ? lambda_dev + r * us : reinterpret_cast<double*>(c->ws + c->L.lam_off);
-    launch_fill(us, 0.0, lam, s);
+  for (int r0 = 0; r0 < nrhs; r0 += c->L.M) {
+    Zb zb;
+    zb.m = std::min(c->L.M, nrhs - r0);
+    zb.zs = c->L.solve_stride;
+    // the adjoint states: the caller's array, or the per-solve copies of the workspace
+    double* lam = lambda_dev ? lambda_dev + r0 * us : reinterpret_cast<double*>(c->ws + c->L.lam_off);
+    const size_t ls = lambda_dev ? us : c->L.solve_stride / sizeof(double);
+    for (int j = 0; j < zb.m; ++j) launch_fill(us, 0.0, lam + j * ls, s);
     const int st = (c->L.selem == 8)
-                       ? fcg_solve<double>(c, c->cgd, 1, dJdu_dev + r * us, lam, info, s)
-                       : fcg_solve<float>(c, c->cgf, 1, dJdu_dev + r * us, lam, info, s);
+                       ? fcg_solve<double>(c, c->cgd, 1, dJdu_dev + r0 * us, us, lam, ls, info, s, zb)
+                       : fcg_solve<float>(c, c->cgf, 1, dJdu_dev + r0 * us, us, lam, ls, info, s, zb);
     if (st == GBL_EHIP) return st;
     if (st != GBL_OK) worst = st;
     ProfScope ps(GBL_PROF_GRADIENT, s);
-    launch_cell_gradient(c->a(), n, u_dev + r * us, lam, dJdloga_dev + r * n2, dJdg_dev ? dJdg_dev + r * n2 : nullptr,
-                         s);
+    for (int j = 0; j < zb.m; ++j) {
+      const int r = r0 + j;
+      launch_cell_gradient(c->a(), n, u_dev + r * us, lam + j * ls, dJdloga_dev + r * n2,
+                           dJdg_dev ? dJdg_dev + r * n2 : nullptr, s);
+    }
   }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));

@@ -77,13 +77,7 @@ void launch_win_build(const LevelGeom& g, const T* B, double tol, int cap, int* 
 template <typename T>
 void launch_coarse_factor(const T* A1, int s1, double* L1, int* status, hipStream_t st);
 
-// Solve-phase launchers.
-struct CGLevelArgs;
-template <typename T>
-void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st);
-template <typename T>
-void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
-                    hipStream_t st);
+// Solve-phase launchers (declared with their batching argument in solve_internal.hpp).
 template <typename T>
 void launch_coarse_solve(const double* L1, const T* g1, T* v1, hipStream_t st);
 

@@ -65,7 +65,12 @@ __device__ __forceinline__ double apply_fine(const double* __restrict__ a, int n
 // values are read from u_slot when given (else taken as zero).
 __global__ void k_residual(const double* __restrict__ a, int n, int mode, const double* __restrict__ src,
                            const double* __restrict__ u_nodal, const double* __restrict__ u_slot,
-                           double* __restrict__ r) {
+                           double* __restrict__ r, size_t zs, size_t src_stride, size_t u_stride) {
+  const size_t zo = blockIdx.z * zs;
+  src += blockIdx.z * src_stride;
+  u_nodal += blockIdx.z * u_stride;
+  u_slot = zsh(u_slot, zo);
+  r = zsh(r, zo);
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= n * n) return;
   const int x = id / n, y = id % n;
@@ -111,8 +116,18 @@ __global__ __launch_bounds__(256) void k_dots(int len, int nv, const double* __r
                                               const double* __restrict__ y0, const double* __restrict__ x1,
                                               const double* __restrict__ y1, const double* __restrict__ x2,
                                               const double* __restrict__ y2, double* part, unsigned* cnt,
-                                              double* out) {
+                                              double* out, size_t zs) {
   __shared__ double sh[3 * 16];
+  const size_t zo = blockIdx.z * zs;
+  x0 = zsh(x0, zo);
+  y0 = zsh(y0, zo);
+  x1 = zsh(x1, zo);
+  y1 = zsh(y1, zo);
+  x2 = zsh(x2, zo);
+  y2 = zsh(y2, zo);
+  part = zsh(part, zo);
+  cnt = zsh(cnt, zo);
+  out = zsh(out, zo);
   double v[3] = {0.0, 0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
     v[0] += x0[i] * y0[i];
@@ -129,18 +144,6 @@ __global__ __launch_bounds__(256) void k_dots(int len, int nv, const double* __r
 }
 
 // Outer flexible CG steps (scalars live on the device).
-//   alpha = (p, r) / (p, w);  u += alpha p;  r -= alpha w
-__global__ void k_outer_update(int len, const double* __restrict__ sc, double* __restrict__ u,
-                               double* __restrict__ r, const double* __restrict__ p,
-                               const double* __restrict__ w) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
-  const double pw = sc[kSPW], pr = sc[kSPR];
-  const double alpha = (pw > 0.0) ? pr / pw : 0.0;
-  u[i] += alpha * p[i];
-  r[i] -= alpha * w[i];
-}
-
 //   beta = -(z, w) / (p, w);  p = z + beta p   (A-orthogonalise against the last direction)
 // (z, w) is re-added from the partials of the finest prolongation kernel.
 // When elog is set, block 0 also forms the error estimate of the iteration
@@ -151,8 +154,14 @@ __global__ void k_outer_update(int len, const double* __restrict__ sc, double* _
 __global__ __launch_bounds__(256) void k_outer_direction(int len, double* __restrict__ sc,
                                                          const double* __restrict__ partz, int nblkz,
                                                          const double* __restrict__ z, double* __restrict__ p,
-                                                         double* __restrict__ elog, int first) {
+                                                         double* __restrict__ elog, int first, size_t zs) {
   __shared__ double sh[16];
+  const size_t zo = blockIdx.z * zs;
+  sc = zsh(sc, zo);
+  partz = zsh(partz, zo);
+  z = zsh(z, zo);
+  p = zsh(p, zo);
+  elog = zsh(elog, zo);
   double beta = 0.0;
   if (!first) {
     const double zw = sum_partials(partz, nblkz, 2, sh);
@@ -184,8 +193,13 @@ __global__ __launch_bounds__(256) void k_outer_direction(int len, double* __rest
 // w = A p fused with the per-block partial sums of (p, w), (p, r), (p, p).
 __global__ __launch_bounds__(256) void k_apply_fine_dots(const double* __restrict__ a, int n,
                                                          const double* __restrict__ p, const double* __restrict__ r,
-                                                         double* __restrict__ w, double* part) {
+                                                         double* __restrict__ w, double* part, size_t zs) {
   __shared__ double sh[3 * 16];
+  const size_t zo = blockIdx.z * zs;
+  p = zsh(p, zo);
+  r = zsh(r, zo);
+  w = zsh(w, zo);
+  part = zsh(part, zo);
   double v[3] = {0.0, 0.0, 0.0};
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id < n * n) {
@@ -215,8 +229,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_outer_update_convert(int len, const double* __restrict__ part, int nblk,
                                                               double* __restrict__ sc, double* __restrict__ u,
                                                               double* __restrict__ r, const double* __restrict__ p,
-                                                              const double* __restrict__ w, T* __restrict__ g) {
+                                                              const double* __restrict__ w, T* __restrict__ g,
+                                                              size_t zs) {
   __shared__ double sh[16];
+  const size_t zo = blockIdx.z * zs;
+  part = zsh(part, zo);
+  sc = zsh(sc, zo);
+  u = zsh(u, zo);
+  r = zsh(r, zo);
+  p = zsh(p, zo);
+  w = zsh(w, zo);
+  g = zsh(g, zo);
   const double pw = sum_partials(part, nblk, 0, sh);
   const double pr = sum_partials(part, nblk, 1, sh);
   if (blockIdx.x == 0) {
@@ -237,7 +260,10 @@ __global__ __launch_bounds__(256) void k_outer_update_convert(int len, const dou
 }
 
 // slot vector -> nodal interior (boundary entries untouched)
-__global__ void k_slots_to_nodal(int n, const double* __restrict__ s, double* __restrict__ u) {
+__global__ void k_slots_to_nodal(int n, const double* __restrict__ s, double* __restrict__ u, size_t zs,
+                                 size_t u_stride) {
+  s = zsh(s, blockIdx.z * zs);
+  u += blockIdx.z * u_stride;
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= n * n) return;
   const int x = id / n, y = id % n;
@@ -245,19 +271,23 @@ __global__ void k_slots_to_nodal(int n, const double* __restrict__ s, double* __
   u[x * (n + 1) + y] = s[id];
 }
 
-__global__ void k_fill(size_t len, double v, double* __restrict__ x) {
+__global__ void k_fill(size_t len, double v, double* __restrict__ x, size_t zs) {
+  x = zsh(x, blockIdx.z * zs);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) x[i] = v;
 }
 
 template <typename T>
-__global__ void k_fill_t(size_t len, T* __restrict__ x) {
+__global__ void k_fill_t(size_t len, T* __restrict__ x, size_t zs) {
+  x = zsh(x, blockIdx.z * zs);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) x[i] = T(0);
 }
 
 template <typename TD, typename TS>
-__global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__ d) {
+__global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__ d, size_t zs) {
+  s = zsh(s, blockIdx.z * zs);
+  d = zsh(d, blockIdx.z * zs);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) d[i] = TD(s[i]);
 }
@@ -292,7 +322,9 @@ __device__ __forceinline__ T restrict_row(const T* __restrict__ R, const T* __re
 
 template <typename T, int RHO>
 __global__ __launch_bounds__(128) void k_restrict(const T* __restrict__ R, const T* __restrict__ gf,
-                                                  T* __restrict__ gc, int nk) {
+                                                  T* __restrict__ gc, int nk, size_t zs) {
+  gf = zsh(gf, blockIdx.z * zs);
+  gc = zsh(gc, blockIdx.z * zs);
   // 64 consecutive coarse slots per workgroup, one per lane, so every load of
   // R reads 64 consecutive words.  The restriction block has 2 (2 RHO + 1)
   // rows: wavefront w sums rows w (2 RHO + 1) ... w (2 RHO + 1) + 2 RHO (a
@@ -313,15 +345,15 @@ __global__ __launch_bounds__(128) void k_restrict(const T* __restrict__ R, const
 }
 
 template <typename T>
-void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st) {
+void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st, Zb zb) {
   const int nc = L.nk / 2;
-  const dim3 grid((nc * nc + 63) / 64), block(128);
+  const dim3 grid((nc * nc + 63) / 64, 1, zb.m), block(128);
   switch (L.rho) {
-    case 1: hipLaunchKernelGGL((k_restrict<T, 1>), grid, block, 0, st, R, gf, gc, L.nk); break;
-    case 2: hipLaunchKernelGGL((k_restrict<T, 2>), grid, block, 0, st, R, gf, gc, L.nk); break;
-    case 3: hipLaunchKernelGGL((k_restrict<T, 3>), grid, block, 0, st, R, gf, gc, L.nk); break;
-    case 4: hipLaunchKernelGGL((k_restrict<T, 4>), grid, block, 0, st, R, gf, gc, L.nk); break;
-    default: hipLaunchKernelGGL((k_restrict<T, 5>), grid, block, 0, st, R, gf, gc, L.nk); break;
+    case 1: hipLaunchKernelGGL((k_restrict<T, 1>), grid, block, 0, st, R, gf, gc, L.nk, zb.zs); break;
+    case 2: hipLaunchKernelGGL((k_restrict<T, 2>), grid, block, 0, st, R, gf, gc, L.nk, zb.zs); break;
+    case 3: hipLaunchKernelGGL((k_restrict<T, 3>), grid, block, 0, st, R, gf, gc, L.nk, zb.zs); break;
+    case 4: hipLaunchKernelGGL((k_restrict<T, 4>), grid, block, 0, st, R, gf, gc, L.nk, zb.zs); break;
+    default: hipLaunchKernelGGL((k_restrict<T, 5>), grid, block, 0, st, R, gf, gc, L.nk, zb.zs); break;
   }
 }
 
@@ -381,7 +413,16 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ R, const T* __rest
 template <typename T>
 __global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, const T* __restrict__ w,
                           T* __restrict__ vf, int nk, int rho, int fine, const T* __restrict__ u,
-                          const T* __restrict__ pdir, const double* __restrict__ scal, double* __restrict__ zout) {
+                          const T* __restrict__ pdir, const double* __restrict__ scal, double* __restrict__ zout,
+                          size_t zs) {
+  const size_t zo = blockIdx.z * zs;
+  vc = zsh(vc, zo);
+  w = zsh(w, zo);
+  vf = zsh(vf, zo);
+  u = zsh(u, zo);
+  pdir = zsh(pdir, zo);
+  scal = zsh(scal, zo);
+  zout = zsh(zout, zo);
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nk * nk) return;
   const int nc = nk / 2;
@@ -409,20 +450,29 @@ __global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, con
 
 template <typename T>
 void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
-                    hipStream_t st) {
+                    hipStream_t st, Zb zb) {
   const int tot = L.nk * L.nk;
-  hipLaunchKernelGGL(k_prolong<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, w, vf, L.nk, L.rho,
-                     fine ? 1 : 0, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL(k_prolong<T>, dim3((tot + 255) / 256, 1, zb.m), dim3(256), 0, st, R, vc, w, vf, L.nk, L.rho,
+                     fine ? 1 : 0, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, (double*)nullptr,
+                     zb.zs);
 }
 
 // Finest level: z = R^T v^(q-1) + W^T (x + alpha (u + beta p)) in FP64,
 // fused with the sums (z, z), (u_out, u_out), (z, w_out) of the outer iteration.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__ R, const T* __restrict__ vc,
-                                                           FineCG<T> F, int nk, int rho, double* __restrict__ z,
+                                                           FineCG<T> F0, int nk, int rho, double* __restrict__ z,
                                                            const double* __restrict__ uo,
-                                                           const double* __restrict__ wo, double* part, int cheb) {
+                                                           const double* __restrict__ wo, double* part, int cheb,
+                                                           size_t zs) {
   __shared__ double sh[3 * 16];
+  const size_t zo = blockIdx.z * zs;
+  const FineCG<T> F = zfine(F0, zo);
+  vc = zsh(vc, zo);
+  z = zsh(z, zo);
+  uo = zsh(uo, zo);
+  wo = zsh(wo, zo);
+  part = zsh(part, zo);
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
   const T alpha = cheb ? T(0) : T(F.scal[kFAlpha]), beta = cheb ? T(0) : T(F.scal[kFBeta]);
@@ -453,33 +503,36 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__
 
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st) {
+                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st, Zb zb) {
   const int tot = L.nk * L.nk;
-  hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3((tot + 255) / 256), dim3(256), 0, st, R, vc, F, L.nk, L.rho, z, uo,
-                     wo, part, cheb);
+  hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3((tot + 255) / 256, 1, zb.m), dim3(256), 0, st, R, vc, F, L.nk,
+                     L.rho, z, uo, wo, part, cheb, zb.zs);
 }
 
 template <typename T>
 void launch_outer_update_convert(int len, const double* part, int nblk, double* sc, double* u, double* r,
-                                 const double* p, const double* w, T* g, hipStream_t st) {
+                                 const double* p, const double* w, T* g, hipStream_t st, Zb zb) {
   int nb = (len + 255) / 256;
   if (nb > kUpdateBlocks) nb = kUpdateBlocks;
-  hipLaunchKernelGGL(k_outer_update_convert<T>, dim3(nb), dim3(256), 0, st, len, part, nblk, sc, u, r, p, w, g);
+  hipLaunchKernelGGL(k_outer_update_convert<T>, dim3(nb, 1, zb.m), dim3(256), 0, st, len, part, nblk, sc, u, r, p, w,
+                     g, zb.zs);
 }
 
 void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_fine_dots, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, p, r, w, part);
+                            hipStream_t st, Zb zb) {
+  hipLaunchKernelGGL(k_apply_fine_dots, dim3((n * n + 255) / 256, 1, zb.m), dim3(256), 0, st, a, n, p, r, w, part,
+                     zb.zs);
 }
 
 // Small levels in one workgroup.  Restriction g^(k-1) = R g^(k) for k = khi..2;
 // then the coarse solve and the prolongations v^(k) for k = 2..khi, with a
 // workgroup barrier between levels.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c) {
+__global__ __launch_bounds__(1024) void k_restrict_chain(ChainArgs<T> c, size_t zs) {
   __shared__ T red[256 * 18];   // (cell, row) partial sums of the largest chain level (16 x 16 cells, rw <= 18)
+  const size_t zo = blockIdx.z * zs;
   for (int j = c.n - 1; j >= 0; --j) {
-    const ChainLevel<T>& L = c.lv[j];
+    const ChainLevel<T> L = zchain(c.lv[j], zo);
     const int nc = L.nk / 2;
     const int rw = 2 * (2 * L.rho + 1);
     // work item (cell i, row bx): partial sum over the row, then rows are added
@@ -527,12 +580,14 @@ __device__ __forceinline__ void prolong_level(const T* __restrict__ R, const T* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_chain(ChainArgs<T> c, const double* __restrict__ L1) {
+__global__ __launch_bounds__(256) void k_prolong_chain(ChainArgs<T> c, const double* __restrict__ L1, size_t zs) {
+  const size_t zo = blockIdx.z * zs;
+  T* g1 = zsh(c.g1, zo);
   if (threadIdx.x == 0) {
     // coarsest system with the FP64 Cholesky factor of A^(1)
     double y[4];
     for (int i = 0; i < 4; ++i) {
-      double v = (double)c.g1[i];
+      double v = (double)g1[i];
       for (int k = 0; k < i; ++k) v -= L1[i * 4 + k] * y[k];
       y[i] = v / L1[i * 4 + i];
     }
@@ -541,11 +596,11 @@ __global__ __launch_bounds__(256) void k_prolong_chain(ChainArgs<T> c, const dou
       for (int k = i + 1; k < 4; ++k) v -= L1[k * 4 + i] * y[k];
       y[i] = v / L1[i * 4 + i];
     }
-    for (int i = 0; i < 4; ++i) c.g1[i] = T(y[i]);
+    for (int i = 0; i < 4; ++i) g1[i] = T(y[i]);
   }
   __syncthreads();
   for (int j = 0; j < c.n; ++j) {
-    const ChainLevel<T>& L = c.lv[j];
+    const ChainLevel<T> L = zchain(c.lv[j], zo);
     switch (L.rho) {
       case 1: prolong_level<T, 1>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
       case 2: prolong_level<T, 2>(L.R, L.gc, L.w, L.gf, L.nk, L.fine); break;
@@ -557,13 +612,13 @@ __global__ __launch_bounds__(256) void k_prolong_chain(ChainArgs<T> c, const dou
 }
 
 template <typename T>
-void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st) {
+void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st, Zb zb) {
   if (c.n == 0) return;
-  hipLaunchKernelGGL(k_restrict_chain<T>, dim3(1), dim3(1024), 0, st, c);
+  hipLaunchKernelGGL(k_restrict_chain<T>, dim3(1, 1, zb.m), dim3(1024), 0, st, c, zb.zs);
 }
 template <typename T>
-void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1), dim3(256), 0, st, c, L1);
+void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st, Zb zb) {
+  hipLaunchKernelGGL(k_prolong_chain<T>, dim3(1, 1, zb.m), dim3(256), 0, st, c, L1, zb.zs);
 }
 
 // Coarsest system A^(1) U^(1) = g^(1) (last solve of Algorithm 2) with the FP64
@@ -613,10 +668,10 @@ __device__ __forceinline__ int find_level_s(const CGArgs<T>& A, int b) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args) {
+__global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args, size_t zs) {
   __shared__ double sh[16];
   const int l = find_level(args, blockIdx.x);
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   const int blk = blockIdx.x - L.blk0;
   const int p = blk * 256 + threadIdx.x;
   const int np = L.np;
@@ -723,12 +778,12 @@ __device__ __forceinline__ void coarse_apply(const CGLev<T>& L, const T* zs, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int blk_begin) {
+__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int blk_begin, size_t zs) {
   __shared__ double sh[16];
   __shared__ T red[3 * 16 * 64];
   const int gb = blk_begin + (int)blockIdx.x;
   const int l = find_level_s(args, gb);
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   if (it >= L.iters) return;
   const int blk = gb - L.blk0s;
   const int np = L.np;
@@ -771,10 +826,10 @@ __global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int bl
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it) {
+__global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it, size_t zs) {
   __shared__ double sh[16];
   const int l = find_level(args, blockIdx.x);
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   if (it >= L.iters) return;
   const int blk = blockIdx.x - L.blk0;
   const int p = blk * 256 + threadIdx.x;
@@ -816,25 +871,26 @@ __global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it) {
 }
 
 template <typename T>
-void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks), dim3(256), 0, st, a);
+void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb) {
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks, 1, zb.m), dim3(256), 0, st, a, zb.zs);
 }
 // The largest coarse level (first in the list) gets its own launch with
 // one wavefront per stencil row; the smaller levels share a second launch.
 template <typename T>
-void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
+void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
   const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
   const int t0 = 2 * a.lv[0].t + 1;
-  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, it, 0);
+  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n0, 1, zb.m), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, it, 0, zb.zs);
   if (nblocks > n0) {
     int tmax = 1;
     for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
-    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks - n0), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, it, n0);
+    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks - n0, 1, zb.m), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, it,
+                       n0, zb.zs);
   }
 }
 template <typename T>
-void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks), dim3(256), 0, st, a, it);
+void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks, 1, zb.m), dim3(256), 0, st, a, it, zb.zs);
 }
 
 // ---------------------------------------------------------------------------
@@ -843,10 +899,10 @@ void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st) {
 // the z (k even) and p (k odd) vectors; x accumulates d_0 + ... + d_k.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs, int blk_begin) {
+__global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs, int blk_begin, size_t zs) {
   const int gb = blk_begin + (int)blockIdx.x;
   const int l = find_level(args, gb);
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   const int p = (gb - L.blk0) * 256 + threadIdx.x;
   const int np = L.np;
   const size_t np2 = (size_t)np * np;
@@ -882,11 +938,11 @@ __global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs, 
 // operator part is that of k_cg_spmv (64 parents per workgroup, one
 // wavefront per stencil row).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs, int k, int blk_begin) {
+__global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs, int k, int blk_begin, size_t zs) {
   __shared__ T red[3 * 16 * 64];
   const int gb = blk_begin + (int)blockIdx.x;
   const int l = find_level_s(args, gb);
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   if (k >= L.iters) return;
   const int blk = gb - L.blk0s;
   const int np = L.np;
@@ -926,17 +982,18 @@ __global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs,
 }
 
 template <typename T>
-void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st) {
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st, Zb zb) {
   const int b0 = a.lv[l0].blk0, b1 = a.lv[l1 - 1].blk0 + a.lv[l1 - 1].nblk;
-  hipLaunchKernelGGL(k_cheb_init<T>, dim3(b1 - b0), dim3(256), 0, st, a, s, b0);
+  hipLaunchKernelGGL(k_cheb_init<T>, dim3(b1 - b0, 1, zb.m), dim3(256), 0, st, a, s, b0, zb.zs);
 }
 // One launch for the levels l0 .. l1-1: one wavefront per stencil row of the
 // largest of them (its blocks dominate); wider stencils loop over their rows.
 template <typename T>
-void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st) {
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st, Zb zb) {
   const int b0 = a.lv[l0].blk0s, b1 = a.lv[l1 - 1].blk0s + a.lv[l1 - 1].nblks;
   const int t0 = 2 * a.lv[l0].t + 1;
-  hipLaunchKernelGGL(k_cheb_step<T>, dim3(b1 - b0), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, b0);
+  hipLaunchKernelGGL(k_cheb_step<T>, dim3(b1 - b0, 1, zb.m), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, b0,
+                     zb.zs);
 }
 
 // ---------------------------------------------------------------------------
@@ -953,7 +1010,8 @@ void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int 
 // their neighbours' values.
 // ---------------------------------------------------------------------------
 template <typename T, int H>
-__global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F, ChebCoef cf, int k0, int nsteps, int rd) {
+__global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F0, ChebCoef cf, int k0, int nsteps, int rd, size_t zs) {
+  const FineCG<T> F = zfine(F0, blockIdx.z * zs);
   constexpr int TPM = 8;
   constexpr int VWM = 2 * (TPM + 2 * H) + 2;
   __shared__ T vl[VWM * VWM];
@@ -1069,11 +1127,12 @@ __global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F, ChebCoef cf, int
 }
 
 template <typename T>
-void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st) {
+void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st,
+                      Zb zb) {
   (void)K;
   const int TP = f.np < 8 ? f.np : 8;
   const int nb = (f.np / TP) * (f.np / TP);
-  hipLaunchKernelGGL((k_fine_cheb<T, 4>), dim3(nb), dim3(256), 0, st, f, c, k0, nsteps, rd);
+  hipLaunchKernelGGL((k_fine_cheb<T, 4>), dim3(nb, 1, zb.m), dim3(256), 0, st, f, c, k0, nsteps, rd, zb.zs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,7 +1147,8 @@ void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int 
 // it == 0 starts from x = 0, r = W g.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F, int it) {
+__global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs) {
+  const FineCG<T> F = zfine(F0, blockIdx.z * zs);
   __shared__ double sh[32];
   __shared__ T lds[3 * 18 * 18 + 36 * 36 + 33 * 33 + 3 * 16 * 16];
   const int np = F.np;
@@ -1248,7 +1308,8 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F, int it) {
 
 // Last update x += a p after the final iteration (no operator application).
 template <typename T>
-__global__ void k_fine_cg_finish(FineCG<T> F, int it) {
+__global__ void k_fine_cg_finish(FineCG<T> F0, int it, size_t zs) {
+  const FineCG<T> F = zfine(F0, blockIdx.z * zs);
   const size_t np2 = (size_t)F.np * F.np;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * np2) return;
@@ -1258,12 +1319,13 @@ __global__ void k_fine_cg_finish(FineCG<T> F, int it) {
 }
 
 template <typename T>
-void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st) {
+void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st, Zb zb) {
   if (it >= 0) {
-    hipLaunchKernelGGL(k_fine_cg<T>, dim3(f.nblk), dim3(256), 0, st, f, it);
+    hipLaunchKernelGGL(k_fine_cg<T>, dim3(f.nblk, 1, zb.m), dim3(256), 0, st, f, it, zb.zs);
   } else {
     const size_t n = 3 * (size_t)f.np * f.np;
-    hipLaunchKernelGGL(k_fine_cg_finish<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, it);
+    hipLaunchKernelGGL(k_fine_cg_finish<T>, dim3((unsigned)((n + 255) / 256), 1, zb.m), dim3(256), 0, st, f, it,
+                       zb.zs);
   }
 }
 
@@ -1307,46 +1369,46 @@ __global__ void k_cell_gradient(const double* __restrict__ a, int n, const doubl
 // Host launch helpers for the non-templated kernels.
 // ---------------------------------------------------------------------------
 void launch_residual(const double* a, int n, int mode, const double* src, const double* u_nodal,
-                     const double* u_slot, double* r, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, mode, src, u_nodal, u_slot,
-                     r);
+                     const double* u_slot, double* r, hipStream_t st, Zb zb, size_t src_stride, size_t u_stride) {
+  hipLaunchKernelGGL(k_residual, dim3((n * n + 255) / 256, 1, zb.m), dim3(256), 0, st, a, n, mode, src, u_nodal,
+                     u_slot, r, zb.zs, src_stride, u_stride);
 }
 void launch_apply_fine(const double* a, int n, const double* p, double* w, hipStream_t st) {
   hipLaunchKernelGGL(k_apply_fine, dim3((n * n + 255) / 256), dim3(256), 0, st, a, n, p, w);
 }
 void launch_dots(int len, int nv, const double* x0, const double* y0, const double* x1, const double* y1,
                  const double* x2, const double* y2, double* part, unsigned* cnt, double* out,
-                 hipStream_t st) {
+                 hipStream_t st, Zb zb) {
   int nb = (len + 255) / 256;
   if (nb > kDotBlocks) nb = kDotBlocks;
-  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(256), 0, st, len, nv, x0, y0, x1, y1, x2, y2, part, cnt, out);
-}
-void launch_outer_update(int len, const double* sc, double* u, double* r, const double* p, const double* w,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_outer_update, dim3((len + 255) / 256), dim3(256), 0, st, len, sc, u, r, p, w);
+  hipLaunchKernelGGL(k_dots, dim3(nb, 1, zb.m), dim3(256), 0, st, len, nv, x0, y0, x1, y1, x2, y2, part, cnt, out,
+                     zb.zs);
 }
 void launch_outer_direction(int len, double* sc, const double* partz, int nblkz, const double* z, double* p,
-                            double* elog, int first, hipStream_t st) {
+                            double* elog, int first, hipStream_t st, Zb zb) {
   int nb = (len + 255) / 256;
   if (nb > kUpdateBlocks) nb = kUpdateBlocks;
-  hipLaunchKernelGGL(k_outer_direction, dim3(nb), dim3(256), 0, st, len, sc, partz, nblkz, z, p, elog, first);
+  hipLaunchKernelGGL(k_outer_direction, dim3(nb, 1, zb.m), dim3(256), 0, st, len, sc, partz, nblkz, z, p, elog, first,
+                     zb.zs);
 }
-void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st) {
-  hipLaunchKernelGGL(k_slots_to_nodal, dim3((n * n + 255) / 256), dim3(256), 0, st, n, s, u);
+void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st, Zb zb, size_t u_stride) {
+  hipLaunchKernelGGL(k_slots_to_nodal, dim3((n * n + 255) / 256, 1, zb.m), dim3(256), 0, st, n, s, u, zb.zs,
+                     u_stride);
 }
-void launch_fill(size_t len, double v, double* x, hipStream_t st) {
+void launch_fill(size_t len, double v, double* x, hipStream_t st, Zb zb) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, v, x);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((len + 255) / 256), 1, zb.m), dim3(256), 0, st, len, v, x, zb.zs);
 }
 template <typename T>
-void launch_zero(size_t len, T* x, hipStream_t st) {
+void launch_zero(size_t len, T* x, hipStream_t st, Zb zb) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_fill_t<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, x);
+  hipLaunchKernelGGL(k_fill_t<T>, dim3((unsigned)((len + 255) / 256), 1, zb.m), dim3(256), 0, st, len, x, zb.zs);
 }
 template <typename TD, typename TS>
-void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st) {
+void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st, Zb zb) {
   if (len == 0) return;
-  hipLaunchKernelGGL((k_convert<TD, TS>), dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, s, d);
+  hipLaunchKernelGGL((k_convert<TD, TS>), dim3((unsigned)((len + 255) / 256), 1, zb.m), dim3(256), 0, st, len, s, d,
+                     zb.zs);
 }
 void launch_cell_gradient(const double* a, int n, const double* u, const double* lam, double* dloga,
                           double* dg, hipStream_t st) {
@@ -1442,29 +1504,29 @@ void launch_mass_nodal_dots(int n, int rho, const double* Y, const T* v, double*
   template void launch_mass_load_slots<T>(int, int, const double*, const double*, T*, hipStream_t);     \
   template void launch_mass_nodal_dots<T>(int, int, const double*, const T*, double*, const double*,    \
                                           const double*, double*, hipStream_t);                         \
-  template void launch_restrict<T>(const LevelGeom&, const T*, const T*, T*, hipStream_t);              \
-  template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t); \
+  template void launch_restrict<T>(const LevelGeom&, const T*, const T*, T*, hipStream_t, Zb);          \
+  template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t, Zb); \
   template void launch_coarse_solve<T>(const double*, const T*, T*, hipStream_t);                       \
-  template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t);                                  \
-  template void launch_cg_spmv<T>(const CGArgs<T>&, int, int, hipStream_t);                             \
-  template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t);                           \
-  template void launch_zero<T>(size_t, T*, hipStream_t);                                                \
-  template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t);                                 \
-  template void launch_fine_cheb<T>(const FineCG<T>&, const ChebCoef&, int, int, int, int, hipStream_t); \
-  template void launch_cheb_init<T>(const CGArgs<T>&, const ChebStep&, int, int, hipStream_t);          \
-  template void launch_cheb_step<T>(const CGArgs<T>&, const ChebStep&, int, int, int, hipStream_t);     \
+  template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t, Zb);                              \
+  template void launch_cg_spmv<T>(const CGArgs<T>&, int, int, hipStream_t, Zb);                         \
+  template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t, Zb);                       \
+  template void launch_zero<T>(size_t, T*, hipStream_t, Zb);                                            \
+  template void launch_fine_cg<T>(const FineCG<T>&, int, hipStream_t, Zb);                             \
+  template void launch_fine_cheb<T>(const FineCG<T>&, const ChebCoef&, int, int, int, int, hipStream_t, Zb); \
+  template void launch_cheb_init<T>(const CGArgs<T>&, const ChebStep&, int, int, hipStream_t, Zb);      \
+  template void launch_cheb_step<T>(const CGArgs<T>&, const ChebStep&, int, int, int, hipStream_t, Zb); \
   template void launch_prolong_fine_dots<T>(const LevelGeom&, const T*, const T*, const FineCG<T>&,      \
                                             double*, const double*, const double*, double*, int,         \
-                                            hipStream_t);                                               \
+                                            hipStream_t, Zb);                                           \
   template void launch_outer_update_convert<T>(int, const double*, int, double*, double*, double*,      \
-                                               const double*, const double*, T*, hipStream_t);          \
-  template void launch_restrict_chain<T>(const ChainArgs<T>&, hipStream_t);                             \
-  template void launch_prolong_chain<T>(const ChainArgs<T>&, const double*, hipStream_t);
+                                               const double*, const double*, T*, hipStream_t, Zb);      \
+  template void launch_restrict_chain<T>(const ChainArgs<T>&, hipStream_t, Zb);                         \
+  template void launch_prolong_chain<T>(const ChainArgs<T>&, const double*, hipStream_t, Zb);
 GBL_INST(float)
 GBL_INST(double)
 #undef GBL_INST
-template void launch_convert<float, double>(size_t, const double*, float*, hipStream_t);
-template void launch_convert<double, float>(size_t, const float*, double*, hipStream_t);
-template void launch_convert<double, double>(size_t, const double*, double*, hipStream_t);
+template void launch_convert<float, double>(size_t, const double*, float*, hipStream_t, Zb);
+template void launch_convert<double, float>(size_t, const float*, double*, hipStream_t, Zb);
+template void launch_convert<double, double>(size_t, const double*, double*, hipStream_t, Zb);
 
 }  // namespace gbl

@@ -150,13 +150,13 @@ void launch_win_build(const LevelGeom& g, const T* B, double tol, int cap, int* 
 // Y_w = B_w^-1 r_w for every kept window of the windowed levels (one
 // wavefront per window; the level of a block from its window range).
 template <typename T>
-__global__ __launch_bounds__(256) void k_win_apply(CGArgs<T> args, int it) {
+__global__ __launch_bounds__(256) void k_win_apply(CGArgs<T> args, int it, size_t zs) {
   __shared__ T rs[4][32];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gw = blockIdx.x * 4 + wv;
   int l = 0;
   while (l + 1 < args.nlev && gw >= args.lv[l + 1].win0) ++l;
-  const CGLev<T>& L = args.lv[l];
+  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
   const int w = gw - L.win0;
   const bool live = (it < L.iters - 1) && w >= 0 && w < L.nwin;
   const int np = L.np;
@@ -182,8 +182,9 @@ __global__ __launch_bounds__(256) void k_win_apply(CGArgs<T> args, int it) {
 // (a fixed order: origins by dx, then dy), and the (r, z) update of the
 // level: (r, z) = (r, D^-1 r) (left in kCRZD by the CG kernel) + (r, sum).
 template <typename T>
-__global__ __launch_bounds__(256) void k_win_gather(CGLev<T> L, int it, int init) {
+__global__ __launch_bounds__(256) void k_win_gather(CGLev<T> L0, int it, int init, size_t zs) {
   __shared__ double sh[16];
+  const CGLev<T> L = zlev(L0, blockIdx.z * zs);
   if (!init && it >= L.iters - 1) return;
   const int blk = blockIdx.x;
   const int p = blk * 256 + threadIdx.x;
@@ -231,14 +232,15 @@ __global__ __launch_bounds__(256) void k_win_gather(CGLev<T> L, int it, int init
 }
 
 template <typename T>
-void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st) {
+void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st, Zb zb) {
   const CGLev<T>& last = a.lv[a.nlev - 1];
   const int total = last.win0 + last.nwin;
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_win_apply<T>, dim3((total + 3) / 4), dim3(256), 0, st, a, init ? -1 : it);
+  hipLaunchKernelGGL(k_win_apply<T>, dim3((total + 3) / 4, 1, zb.m), dim3(256), 0, st, a, init ? -1 : it, zb.zs);
   for (int l = 0; l < a.nlev; ++l) {
     if (a.lv[l].nwin <= 0) continue;
-    hipLaunchKernelGGL(k_win_gather<T>, dim3(a.lv[l].nblk), dim3(256), 0, st, a.lv[l], it, init ? 1 : 0);
+    hipLaunchKernelGGL(k_win_gather<T>, dim3(a.lv[l].nblk, 1, zb.m), dim3(256), 0, st, a.lv[l], it, init ? 1 : 0,
+                       zb.zs);
   }
 }
 
@@ -246,7 +248,7 @@ template void launch_win_build<float>(const LevelGeom&, const float*, double, in
                                       int*, hipStream_t);
 template void launch_win_build<double>(const LevelGeom&, const double*, double, int, int*, int*, double*,
                                        unsigned*, int*, hipStream_t);
-template void launch_win_correct<float>(const CGArgs<float>&, int, bool, hipStream_t);
-template void launch_win_correct<double>(const CGArgs<double>&, int, bool, hipStream_t);
+template void launch_win_correct<float>(const CGArgs<float>&, int, bool, hipStream_t, Zb);
+template void launch_win_correct<double>(const CGArgs<double>&, int, bool, hipStream_t, Zb);
 
 }  // namespace gbl

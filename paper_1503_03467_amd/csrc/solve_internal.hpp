@@ -67,10 +67,42 @@ struct CGArgs {
   int nlev;
 };
 
+// Several right-hand sides solved together.  Right-hand side z of a launch
+// (blockIdx.z, z < m) works on the copy of the per-solve region of the
+// workspace (vectors, scalars, partial sums, tickets) that sits zs bytes
+// after the previous one; the hierarchy (operators, factors, windows) is
+// shared.  Pointers that are null stay null.
+struct Zb {
+  int m = 1;
+  size_t zs = 0;
+};
+template <typename P>
+__device__ __forceinline__ P* zsh(P* p, size_t off) {
+  return p ? reinterpret_cast<P*>(reinterpret_cast<char*>(p) + off) : p;
+}
+template <typename P>
+__device__ __forceinline__ const P* zsh(const P* p, size_t off) {
+  return p ? reinterpret_cast<const P*>(reinterpret_cast<const char*>(p) + off) : p;
+}
+template <typename T>
+__device__ __forceinline__ CGLev<T> zlev(CGLev<T> L, size_t off) {
+  L.g = zsh(L.g, off);
+  L.x = zsh(L.x, off);
+  L.r = zsh(L.r, off);
+  L.z = zsh(L.z, off);
+  L.p = zsh(L.p, off);
+  L.q = zsh(L.q, off);
+  L.scal = zsh(L.scal, off);
+  L.part = zsh(L.part, off);
+  L.cnt = zsh(L.cnt, off);
+  L.Y = zsh(L.Y, off);
+  return L;
+}
+
 // After the CG start (init) or CG iteration it: z += sum_w P_w^T B_w^-1 P_w r
 // on the levels with kept windows, and their (r, z) / beta update.
 template <typename T>
-void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st);
+void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st, Zb zb = Zb());
 
 // Finest subband level, conjugate gradients in the Chronopoulos-Gear form
 // (one reduction and one launch per iteration).  r, w (= B u) and s (= B p)
@@ -97,6 +129,22 @@ struct FineCG {
   int np;
   int nblk;          // tiles
 };
+template <typename T>
+__device__ __forceinline__ FineCG<T> zfine(FineCG<T> F, size_t off) {
+  F.g = zsh(F.g, off);
+  F.x = zsh(F.x, off);
+  F.u = zsh(F.u, off);
+  F.p = zsh(F.p, off);
+  for (int i = 0; i < 2; ++i) {
+    F.r[i] = zsh(F.r[i], off);
+    F.w[i] = zsh(F.w[i], off);
+    F.s[i] = zsh(F.s[i], off);
+  }
+  F.scal = zsh(F.scal, off);
+  F.part = zsh(F.part, off);
+  F.cnt = zsh(F.cnt, off);
+  return F;
+}
 
 // Chebyshev iteration for the subband systems (an alternative to CG with no
 // inner products: the preconditioner it defines is a fixed polynomial in
@@ -121,15 +169,16 @@ struct ChebStep {
 };
 
 template <typename T>
-void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st);
+void launch_fine_cheb(const FineCG<T>& f, const ChebCoef& c, int K, int k0, int nsteps, int rd, hipStream_t st,
+                      Zb zb = Zb());
 // levels l0 .. l1-1 of the coarser subband systems (CGArgs order)
 template <typename T>
-void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st);
+void launch_cheb_init(const CGArgs<T>& a, const ChebStep& s, int l0, int l1, hipStream_t st, Zb zb = Zb());
 template <typename T>
-void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st);
+void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st, Zb zb = Zb());
 
 template <typename T>
-void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st);
+void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st, Zb zb = Zb());
 // Level-q gamblets from the localized mass inverse: g^(q) = Minv^T r, and
 // z = Minv v^(q) with the partial sums of launch_prolong_fine_dots.
 template <typename T>
@@ -139,12 +188,13 @@ void launch_mass_nodal_dots(int n, int rho, const double* Y, const T* v, double*
                             const double* wo, double* part, hipStream_t st);
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
-                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st);
+                              const double* uo, const double* wo, double* part, int cheb, hipStream_t st,
+                              Zb zb = Zb());
 template <typename T>
 void launch_outer_update_convert(int len, const double* part, int nblk, double* sc, double* u, double* r,
-                                 const double* p, const double* w, T* g, hipStream_t st);
+                                 const double* p, const double* w, T* g, hipStream_t st, Zb zb = Zb());
 void launch_apply_fine_dots(const double* a, int n, const double* p, const double* r, double* w, double* part,
-                            hipStream_t st);
+                            hipStream_t st, Zb zb = Zb());
 
 // Small levels handled inside one workgroup (restriction and prolongation
 // chains).  Entry j is level k = kmin + j: R = R^(k-1,k), gf = level-k
@@ -166,35 +216,49 @@ struct ChainArgs {
   int n;   // levels 2 .. 2+n-1, ordered by increasing level for prolongation
   T* g1;   // level-1 vector (coarse solve in place)
 };
+template <typename T>
+__device__ __forceinline__ ChainLevel<T> zchain(ChainLevel<T> L, size_t off) {
+  L.gf = zsh(L.gf, off);
+  L.gc = zsh(L.gc, off);
+  L.w = zsh(L.w, off);
+  return L;
+}
 
 template <typename T>
-void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st);
+void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st, Zb zb = Zb());
 template <typename T>
-void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st);
+void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st, Zb zb = Zb());
 
 template <typename T>
-void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st);
+void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb = Zb());
 template <typename T>
-void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st);
+void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb = Zb());
 template <typename T>
-void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st);
+void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb = Zb());
 template <typename T>
-void launch_zero(size_t len, T* x, hipStream_t st);
+void launch_zero(size_t len, T* x, hipStream_t st, Zb zb = Zb());
 template <typename TD, typename TS>
-void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st);
+void launch_convert(size_t len, const TS* s, TD* d, hipStream_t st, Zb zb = Zb());
 
+template <typename T>
+void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st, Zb zb = Zb());
+template <typename T>
+void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
+                    hipStream_t st, Zb zb = Zb());
+
+// src_stride / u_stride: doubles between the right-hand sides of the
+// caller's source and nodal arrays
 void launch_residual(const double* a, int n, int mode, const double* src, const double* u_nodal,
-                     const double* u_slot, double* r, hipStream_t st);
+                     const double* u_slot, double* r, hipStream_t st, Zb zb = Zb(), size_t src_stride = 0,
+                     size_t u_stride = 0);
 void launch_apply_fine(const double* a, int n, const double* p, double* w, hipStream_t st);
 void launch_dots(int len, int nv, const double* x0, const double* y0, const double* x1, const double* y1,
                  const double* x2, const double* y2, double* part, unsigned* cnt, double* out,
-                 hipStream_t st);
-void launch_outer_update(int len, const double* sc, double* u, double* r, const double* p, const double* w,
-                         hipStream_t st);
+                 hipStream_t st, Zb zb = Zb());
 void launch_outer_direction(int len, double* sc, const double* partz, int nblkz, const double* z, double* p,
-                            double* elog, int first, hipStream_t st);
-void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st);
-void launch_fill(size_t len, double v, double* x, hipStream_t st);
+                            double* elog, int first, hipStream_t st, Zb zb = Zb());
+void launch_slots_to_nodal(int n, const double* s, double* u, hipStream_t st, Zb zb = Zb(), size_t u_stride = 0);
+void launch_fill(size_t len, double v, double* x, hipStream_t st, Zb zb = Zb());
 void launch_cell_gradient(const double* a, int n, const double* u, const double* lam, double* dloga,
                           double* dg, hipStream_t st);
 
