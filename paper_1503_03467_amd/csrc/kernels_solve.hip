@@ -667,6 +667,22 @@ __device__ __forceinline__ int find_level_s(const CGArgs<T>& A, int b) {
   return l;
 }
 
+// Operator kernels of a block of m right-hand sides run as one 1-D grid in
+// which the m workgroups of one stencil group (64 parents) sit on the same
+// XCD and are dispatched next to each other (workgroups go round-robin over
+// the 8 XCDs by linear id): id = (g / 8) 8m + r 8 + g % 8 for group g and
+// right-hand side r.  The group's block of B^(k) is then fetched from HBM
+// once and read from that XCD's L2 by the other m - 1.  Returns false for
+// the padding ids past the last group.
+__device__ __forceinline__ bool xcd_group_rhs(int id, int m, int ngroups, int& grp, int& rhs) {
+  const int per = 8 * m;
+  const int hi = id / per, rem = id - hi * per;
+  rhs = rem >> 3;
+  grp = hi * 8 + (rem & 7);
+  return grp < ngroups;
+}
+inline unsigned xcd_group_grid(int ngroups, int m) { return (unsigned)(((ngroups + 7) / 8) * 8 * m); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args, size_t zs) {
   __shared__ double sh[16];
@@ -778,12 +794,15 @@ __device__ __forceinline__ void coarse_apply(const CGLev<T>& L, const T* zs, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int blk_begin, size_t zs) {
+__global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int blk_begin, int ngroups, int m,
+                                                 size_t zs) {
   __shared__ double sh[16];
   __shared__ T red[3 * 16 * 64];
-  const int gb = blk_begin + (int)blockIdx.x;
+  int grp, rhs;
+  if (!xcd_group_rhs((int)blockIdx.x, m, ngroups, grp, rhs)) return;
+  const int gb = blk_begin + grp;
   const int l = find_level_s(args, gb);
-  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
+  const CGLev<T> L = zlev(args.lv[l], rhs * zs);
   if (it >= L.iters) return;
   const int blk = gb - L.blk0s;
   const int np = L.np;
@@ -870,6 +889,181 @@ __global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it, size_
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same operator steps for a block of right-hand sides with B^(k) read
+// once per chunk of up to MC of them: every B word a lane loads is applied to
+// the chunk's MC vectors (each in its own per-solve copy, zs bytes apart)
+// before the next load.  Per right-hand side the sums run in the order of the
+// single-vector kernels, so results are the same bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T, int TT, int MC>
+__device__ __forceinline__ void coarse_rows_mr(const CGLev<T>& L, const T* __restrict__ zs0, size_t zs, int nr,
+                                               int p, int wv, int nw, T (&acc)[MC][3]) {
+  constexpr int t = TT / 2;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int px = p / np, py = p - (p / np) * np;
+  for (int ox = wv; ox < TT; ox += nw) {
+    const int qx = px + ox - t;
+    if (qx < 0 || qx >= np) continue;
+    const T* Bo = L.B + b_index(ox * TT, 0, p, TT);
+    const int qb = qx * np + py - t;
+#pragma unroll
+    for (int oy = 0; oy < TT; ++oy) {
+      const int qy = min(max(py + oy - t, 0), np - 1);
+      const int qn = qb + t + (qy - py);
+      const T* Bb = Bo + oy * 9 * 64;
+      const T b0 = Bb[0], b1 = Bb[64], b2 = Bb[128], b3 = Bb[192], b4 = Bb[256], b5 = Bb[320];
+      const T b6 = Bb[384], b7 = Bb[448], b8 = Bb[512];
+#pragma unroll
+      for (int r = 0; r < MC; ++r) {
+        if (r < nr) {
+          const T* zr = reinterpret_cast<const T*>(reinterpret_cast<const char*>(zs0) + (size_t)r * zs);
+          const T z0 = zr[qn], z1 = zr[np2 + qn], z2 = zr[2 * np2 + qn];
+          acc[r][0] += b0 * z0 + b1 * z1 + b2 * z2;
+          acc[r][1] += b3 * z0 + b4 * z1 + b5 * z2;
+          acc[r][2] += b6 * z0 + b7 * z1 + b8 * z2;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int MC>
+__device__ __forceinline__ void coarse_apply_mr(const CGLev<T>& L, const T* zs0, size_t zs, int nr, int TT, int p,
+                                                int wv, int nw, T (&acc)[MC][3]) {
+  switch (TT) {
+    case 1: coarse_rows_mr<T, 1, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 3: coarse_rows_mr<T, 3, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 5: coarse_rows_mr<T, 5, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 7: coarse_rows_mr<T, 7, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 9: coarse_rows_mr<T, 9, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 11: coarse_rows_mr<T, 11, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 13: coarse_rows_mr<T, 13, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    case 15: coarse_rows_mr<T, 15, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+    default: coarse_rows_mr<T, 17, MC>(L, zs0, zs, nr, p, wv, nw, acc); break;
+  }
+}
+
+// Right-hand sides per chunk of the shared-B kernels (LDS holds 3 x waves x
+// 64 partial sums per right-hand side).
+template <typename T>
+constexpr int kChunkRhs = sizeof(T) == 4 ? 8 : 4;
+
+template <typename T, int MC>
+__global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int blk_begin, int ngroups, int nchunks,
+                                                   int m, size_t zs) {
+  __shared__ double sh[16];
+  extern __shared__ unsigned char red_raw[];
+  T* red = reinterpret_cast<T*>(red_raw);   // [MC][3][nw][64]
+  int grp, chunk;
+  if (!xcd_group_rhs((int)blockIdx.x, nchunks, ngroups, grp, chunk)) return;
+  const int r0 = chunk * MC;
+  const int nr = min(MC, m - r0);
+  const int gb = blk_begin + grp;
+  const int l = find_level_s(args, gb);
+  const CGLev<T> L0 = zlev(args.lv[l], r0 * zs);
+  if (it >= L0.iters) return;
+  const int blk = gb - L0.blk0s;
+  const int np = L0.np;
+  const size_t np2 = (size_t)np * np;
+  const int TT = 2 * L0.t + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int p = blk * 64 + lane;
+  T acc[MC][3];
+#pragma unroll
+  for (int r = 0; r < MC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = T(0);
+  if (p < np * np) coarse_apply_mr<T, MC>(L0, L0.z, zs, nr, TT, p, wv, nw, acc);
+#pragma unroll
+  for (int r = 0; r < MC; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[((r * 3 + i) * nw + wv) * 64 + lane] = acc[r][i];
+  __syncthreads();
+  for (int r = 0; r < nr; ++r) {
+    const CGLev<T> L = zlev(args.lv[l], (r0 + r) * zs);
+    double v[1] = {0.0};
+    if (threadIdx.x < 64 && p < np * np) {
+      const T beta = T(L.scal[kCBETA]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T sum = T(0);
+        for (int w = 0; w < nw; ++w) sum += red[((r * 3 + i) * nw + w) * 64 + lane];
+        const T qv = sum + beta * L.q[i * np2 + p];
+        const T pv = L.z[i * np2 + p] + beta * L.p[i * np2 + p];
+        L.q[i * np2 + p] = qv;
+        L.p[i * np2 + p] = pv;
+        v[0] += (double)(pv * qv);
+      }
+    }
+    block_sum<1>(v, sh);
+    bool last;
+    double res[1];
+    finish_reduction<1>(v, L.part, L.nblks, blk, L.cnt, res, &last, sh);
+    if (last) {
+      const double pq = res[0];
+      L.scal[kCPQ] = pq;
+      L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
+    }
+  }
+}
+
+template <typename T, int MC>
+__global__ __launch_bounds__(1024) void k_cheb_step_mr(CGArgs<T> args, ChebStep cs, int k, int blk_begin, int ngroups,
+                                                     int nchunks, int m, size_t zs) {
+  extern __shared__ unsigned char red_raw[];
+  T* red = reinterpret_cast<T*>(red_raw);   // [MC][3][nw][64]
+  int grp, chunk;
+  if (!xcd_group_rhs((int)blockIdx.x, nchunks, ngroups, grp, chunk)) return;
+  const int r0 = chunk * MC;
+  const int nr = min(MC, m - r0);
+  const int gb = blk_begin + grp;
+  const int l = find_level_s(args, gb);
+  const CGLev<T> L0 = zlev(args.lv[l], r0 * zs);
+  if (k >= L0.iters) return;
+  const int blk = gb - L0.blk0s;
+  const int np = L0.np;
+  const size_t np2 = (size_t)np * np;
+  const int TT = 2 * L0.t + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int p = blk * 64 + lane;
+  T acc[MC][3];
+#pragma unroll
+  for (int r = 0; r < MC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = T(0);
+  if (p < np * np) coarse_apply_mr<T, MC>(L0, (k & 1) ? L0.z : L0.p, zs, nr, TT, p, wv, nw, acc);
+#pragma unroll
+  for (int r = 0; r < MC; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[((r * 3 + i) * nw + wv) * 64 + lane] = acc[r][i];
+  __syncthreads();
+  if (threadIdx.x < 64 && p < np * np) {
+    const T ca = T(cs.ca[l]), cb = T(cs.cb[l]);
+    for (int r = 0; r < nr; ++r) {
+      const CGLev<T> L = zlev(args.lv[l], (r0 + r) * zs);
+      const T* dold = (k & 1) ? L.z : L.p;
+      T* dnew = (k & 1) ? L.p : L.z;
+      T rr[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T sum = T(0);
+        for (int w = 0; w < nw; ++w) sum += red[((r * 3 + i) * nw + w) * 64 + lane];
+        rr[i] = L.r[i * np2 + p] - sum;
+        L.r[i * np2 + p] = rr[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T acc1 = T(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc1 += L.BJ[(i * 3 + j) * np2 + p] * rr[j];
+        const T dn = ca * dold[i * np2 + p] + cb * acc1;
+        dnew[i * np2 + p] = dn;
+        L.x[i * np2 + p] += dn;
+      }
+    }
+  }
+}
+
 template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks, 1, zb.m), dim3(256), 0, st, a, zb.zs);
@@ -880,13 +1074,23 @@ template <typename T>
 void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
   const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
   const int t0 = 2 * a.lv[0].t + 1;
-  hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n0, 1, zb.m), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, it, 0, zb.zs);
-  if (nblocks > n0) {
-    int tmax = 1;
-    for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
-    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(nblocks - n0, 1, zb.m), dim3(64 * (tmax < 16 ? tmax : 16)), 0, st, a, it,
-                       n0, zb.zs);
+  int tmax = 1;
+  for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
+  const int w0 = t0 < 16 ? t0 : 16, w1 = tmax < 16 ? tmax : 16;
+  if (zb.m == 1) {
+    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(xcd_group_grid(n0, 1)), dim3(64 * w0), 0, st, a, it, 0, n0, 1, zb.zs);
+    if (nblocks > n0)
+      hipLaunchKernelGGL(k_cg_spmv<T>, dim3(xcd_group_grid(nblocks - n0, 1)), dim3(64 * w1), 0, st, a, it, n0,
+                         nblocks - n0, 1, zb.zs);
+    return;
   }
+  constexpr int MC = kChunkRhs<T>;
+  const int nch = (zb.m + MC - 1) / MC;
+  hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(n0, nch)), dim3(64 * w0),
+                     (size_t)MC * 3 * w0 * 64 * sizeof(T), st, a, it, 0, n0, nch, zb.m, zb.zs);
+  if (nblocks > n0)
+    hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(nblocks - n0, nch)), dim3(64 * w1),
+                       (size_t)MC * 3 * w1 * 64 * sizeof(T), st, a, it, n0, nblocks - n0, nch, zb.m, zb.zs);
 }
 template <typename T>
 void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
@@ -938,11 +1142,14 @@ __global__ __launch_bounds__(256) void k_cheb_init(CGArgs<T> args, ChebStep cs, 
 // operator part is that of k_cg_spmv (64 parents per workgroup, one
 // wavefront per stencil row).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs, int k, int blk_begin, size_t zs) {
+__global__ __launch_bounds__(1024) void k_cheb_step(CGArgs<T> args, ChebStep cs, int k, int blk_begin, int ngroups,
+                                                   int m, size_t zs) {
   __shared__ T red[3 * 16 * 64];
-  const int gb = blk_begin + (int)blockIdx.x;
+  int grp, rhs;
+  if (!xcd_group_rhs((int)blockIdx.x, m, ngroups, grp, rhs)) return;
+  const int gb = blk_begin + grp;
   const int l = find_level_s(args, gb);
-  const CGLev<T> L = zlev(args.lv[l], blockIdx.z * zs);
+  const CGLev<T> L = zlev(args.lv[l], rhs * zs);
   if (k >= L.iters) return;
   const int blk = gb - L.blk0s;
   const int np = L.np;
@@ -992,8 +1199,16 @@ template <typename T>
 void launch_cheb_step(const CGArgs<T>& a, const ChebStep& s, int k, int l0, int l1, hipStream_t st, Zb zb) {
   const int b0 = a.lv[l0].blk0s, b1 = a.lv[l1 - 1].blk0s + a.lv[l1 - 1].nblks;
   const int t0 = 2 * a.lv[l0].t + 1;
-  hipLaunchKernelGGL(k_cheb_step<T>, dim3(b1 - b0, 1, zb.m), dim3(64 * (t0 < 16 ? t0 : 16)), 0, st, a, s, k, b0,
-                     zb.zs);
+  const int w0 = t0 < 16 ? t0 : 16;
+  if (zb.m == 1) {
+    hipLaunchKernelGGL(k_cheb_step<T>, dim3(xcd_group_grid(b1 - b0, 1)), dim3(64 * w0), 0, st, a, s, k, b0, b1 - b0,
+                       1, zb.zs);
+    return;
+  }
+  constexpr int MC = kChunkRhs<T>;
+  const int nch = (zb.m + MC - 1) / MC;
+  hipLaunchKernelGGL((k_cheb_step_mr<T, MC>), dim3(xcd_group_grid(b1 - b0, nch)), dim3(64 * w0),
+                     (size_t)MC * 3 * w0 * 64 * sizeof(T), st, a, s, k, b0, b1 - b0, nch, zb.m, zb.zs);
 }
 
 // ---------------------------------------------------------------------------
