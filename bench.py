@@ -9,6 +9,13 @@ restrictions, Galerkin coarsening) and solve to a relative error of 1e-8
 (flexible CG on the FP64 fine residual, subband solves in FP32).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
+The timed line is the rough 512 x 512-cell workload: a step of the
+2048 x 2048-cell inclusion workload (16 right-hand sides, discs of a = 1e6)
+takes minutes (its outer iteration needs over a thousand iterations at patch
+radius 4), so it is measured once, as the extra "inclusion_workload_q11"
+(build, the 16 right-hand sides as one block, the adjoint gradient), next to
+the other workloads.
+
 Besides the timed steps the line carries: the roofline figure of the
 dominant build kernel (HIP events in the timed region, HBM traffic from
 counters taken on the same kernel source), the CPU oracle's direct solve as
@@ -58,6 +65,7 @@ def parse():
     ap.add_argument("--kappa-coarse", type=float, default=None, help="Chebyshev interval ratio, coarser levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
+    ap.add_argument("--no-inclusions", action="store_true", help="skip the 2048 x 2048-cell inclusion workload")
     return ap.parse_args()
 
 
@@ -193,6 +201,64 @@ def cpu_baseline(pr, dof):
            "sample": f"full 512x512-cell problem, {reps} repetitions: Q1 assembly + SuperLU factor/solve + "
                      f"2 FP64 refinement steps (single-threaded); host has {len(os.sched_getaffinity(0))} cores"}
     return cpu, u_ref
+
+
+def inclusion_workload(P, S, torch, dev):
+    """The 2048 x 2048-cell inclusion workload (discs of a = 1e6 on 10% of the
+    cells over the product field, 16 N(0,1) right-hand sides, patch radius 4),
+    one pass: FP64-built hierarchy with window corrections, the 16 right-hand
+    sides as one block (FP32 subband iterations: 16 Chebyshev steps on the
+    finest level, 16 CG iterations below; FP64 outer iteration to 1e-8), and
+    the adjoint gradient of J = |u_0|^2 / 2 (the first right-hand side's
+    solution).  Also the outer iterations of one right-hand side with radius 5
+    at the finest transition.  Error figures against the direct solve are in
+    the GPU tests (the direct solve of this size takes minutes on the host)."""
+    print("# inclusion workload, 2048 x 2048 cells", file=sys.stderr, flush=True)
+    os.environ["GBL_PROGRESS"] = "1"   # the library reports its outer iterations on stderr every 15 s
+    pr = S.inclusion_problem(q=11, nrhs=16, a_incl=1e6)
+    a = torch.as_tensor(pr.a, device=dev)
+    g = torch.as_tensor(pr.g, device=dev)
+    kw = dict(precision="mixed-fp64-build", rtol=1e-8, max_outer=6000, inner="cheb-cg", inner_iters=16,
+              inner_iters_coarse=16, window_tol=1000.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = P.Hierarchy(a, rho=4, max_rhs=16, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print("# inclusion workload: built, solving 16 right-hand sides", file=sys.stderr, flush=True)
+    u = H.solve(g, check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = H.last_info
+    print("# inclusion workload: solved, adjoint", file=sys.stderr, flush=True)
+    u0 = u[:1].contiguous()
+    H.adjoint(u0, u0, check=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ainfo = H.last_info
+    wins = {str(k): H.level(k)["nwin"] for k in range(3, 11)}
+    H.close()
+    del u, u0
+    dof = ((1 << 11) - 1) ** 2
+    out = {"dof": dof, "rhs": 16, "rho": 4, "build_ms": (t1 - t0) * 1e3, "solve_16rhs_ms": (t2 - t1) * 1e3,
+           "adjoint_grad_ms": (t3 - t2) * 1e3, "outer_iters": info.outer_iters, "status": info.status,
+           "rel_update": info.rel_update, "adjoint_outer_iters": ainfo.outer_iters,
+           "build_solve_dof_per_s": dof * 16 / (t2 - t0), "windows_per_level": wins,
+           "settings": {k: v for k, v in kw.items()}}
+    # radius 5 at the finest transition (the paper sizes radii like ln(1/H_k)), one right-hand side
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = P.Hierarchy(a, rho=5, rho_coarse=4, max_rhs=1, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    H.solve(g[0], check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["finest_radius_5_one_rhs"] = {"build_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
+                                      "outer_iters": H.last_info.outer_iters}
+    H.close()
+    os.environ.pop("GBL_PROGRESS", None)
+    return out
 
 
 def main():
@@ -460,29 +526,34 @@ def main():
                                           "adjoint_grad_ms": best[2], "adjoint_outer_iters": it10,
                                           "build_solve_dof_per_s": dof10 / ((best[0] + best[1]) * 1e-3)}
         del a10, g10, uo10, u10
-        # batch workload: independent problems of 64 x 64 to 256 x 256 cells
-        # with 64 right-hand sides each, built and solved concurrently; a
-        # sample of 32 of the 256 problems keeps the run short
-        print("# batch workload sample", file=sys.stderr, flush=True)
-        probs = S.batch_problems(count=32, nrhs=64)
+        # batch workload: 256 independent problems of 64 x 64 to 256 x 256
+        # cells with 64 right-hand sides each, built and solved concurrently
+        # (each problem's right-hand sides in blocks of 16)
+        print("# batch workload", file=sys.stderr, flush=True)
+        probs = S.batch_problems(count=256, nrhs=64)
         coeffs = [torch.as_tensor(pb.a, device=dev) for pb in probs]
         srcs = [torch.as_tensor(pb.g, device=dev) for pb in probs]
-        hs = P.build_batched(coeffs, rho=3, precision=args.precision, rtol=args.rtol, max_rhs=64)
-        P.solve_batched(hs, [x[:1].contiguous() for x in srcs], check=False)   # warm-up: streams, graphs
+        hs = P.build_batched(coeffs[:16], rho=3, precision=args.precision, rtol=args.rtol, max_rhs=16)
+        P.solve_batched(hs, [x[:16].contiguous() for x in srcs[:16]], check=False)   # warm-up: streams, graphs
         for h in hs:
             h.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hs = P.build_batched(coeffs, rho=3, precision=args.precision, rtol=args.rtol, max_rhs=64)
+        hs = P.build_batched(coeffs, rho=3, precision=args.precision, rtol=args.rtol, max_rhs=16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         P.solve_batched(hs, srcs, check=False)
         torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) * 1e3
+        t2 = time.perf_counter()
+        its = [h.last_info.outer_iters for h in hs]
         for h in hs:
             h.close()
         dofs = sum(((1 << pb.q) - 1) ** 2 * 64 for pb in probs)
-        extras["batch_workload_sample"] = {"problems": len(probs), "rhs_per_problem": 64,
-                                           "q_counts": {str(qq): sum(1 for pb in probs if pb.q == qq) for qq in (6, 7, 8)},
-                                           "build_solve_ms": tb, "dof_per_s": dofs / (tb * 1e-3)}
+        extras["batch_workload"] = {"problems": len(probs), "rhs_per_problem": 64, "rhs_block": 16,
+                                    "q_counts": {str(qq): sum(1 for pb in probs if pb.q == qq) for qq in (6, 7, 8)},
+                                    "build_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
+                                    "build_solve_ms": (t2 - t0) * 1e3, "dof_per_s": dofs / (t2 - t0),
+                                    "outer_iters_max": max(its)}
         del coeffs, srcs, hs
         # gamblet transform of a solution, compression by thresholding and the
         # reconstruction (discussion of Example 5.1, Figures 10-11): the smooth
@@ -515,6 +586,9 @@ def main():
         tr["energy_err_vs_kept_fraction"] = errs
         extras["gamblet_transform"] = tr
         H.close()
+
+    if not args.no_inclusions:
+        extras["inclusion_workload_q11"] = inclusion_workload(P, S, torch, dev)
 
     out = {
         "metric": "DOF/s gamblet build+solve at 1e-8 rel err; adjoint grad time; % HBM roof",

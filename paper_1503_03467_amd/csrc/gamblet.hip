@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <thread>
 #include <new>
@@ -1004,6 +1005,10 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, size
   std::vector<int> done_rhs(m, 0), status(m, GBL_ENOCONV);
   std::vector<double> est(m, 1.0), prev(m, INFINITY);
   int done = 0;
+  // GBL_PROGRESS=1: a line on stderr about every 15 s of a long solve
+  const char* pe = getenv("GBL_PROGRESS");
+  const bool progress = pe && pe[0] == '1';
+  auto t_last = std::chrono::steady_clock::now();
   while (done < c->opts.max_outer) {
     int chunk = kMaxChunk;
     for (int j = 0; j < m; ++j)
@@ -1036,6 +1041,18 @@ int fcg_solve(gbl_ctx* c, const CGArgs<T>& cg, int mode, const double* src, size
       open += done_rhs[j] ? 0 : 1;
     }
     if (!open) break;
+    if (progress) {
+      const auto now = std::chrono::steady_clock::now();
+      if (std::chrono::duration<double>(now - t_last).count() >= 15.0) {
+        double worst_est = 0.0;
+        for (int j = 0; j < m; ++j)
+          if (!done_rhs[j]) worst_est = std::max(worst_est, est[j]);
+        std::fprintf(stderr, "gbl: %d right-hand side(s), outer iteration %d, %d open, largest estimate %.3e\n", m,
+                     done, open, worst_est);
+        std::fflush(stderr);
+        t_last = now;
+      }
+    }
   }
   const int it = done;
   launch_slots_to_nodal(n, u, u_nodal, st, zb, u_stride);
