@@ -124,6 +124,17 @@ typedef struct gbl_opts {
                          Schwarz, symmetric positive definite).  1000 keeps the windows whose pencil has an
                          eigenvalue below 0.027 and always those below 0.001.  Costs 27^2 words per window of
                          workspace on every level k in [3, q - 1] */
+  int exact;          /* 1: the exact (unlocalized) hierarchy of Algorithm 1 -- gamblets over the whole level,
+                         dense FP64 level matrices A^(k), B^(k), R^(k-1,k), every subband system solved by a dense
+                         Cholesky factorization; the solve is the subband sum of Theorem 4.15 with two FP64
+                         refinement steps.  Needs precision GBL_FP64 and 2 <= q <= 7 (the memory grows like 4^2q);
+                         gbl_adjoint and the batched calls reject it.  0: the localized hierarchy (default) */
+  int geometry;       /* 0: 2^q x 2^q cells, (2^q - 1)^2 interior nodes (the default).  1 (exact only): the mesh of
+                         Example 5.1 (Section 5.1), (2^q + 1)^2 cells of side 1 / (2^q + 1), 2^q x 2^q interior nodes,
+                         node (i, j) in level-(q-1) cell ((i-1)/2, (j-1)/2): a_dev is [2^q + 1][2^q + 1] */
+  int source;         /* 0: g_dev holds one value per cell (b_i = (h^2/4) sum of the four cells); 1 (exact only):
+                         g_dev holds the values at the interior nodes, [m][m] with m nodes per side, and b = M g
+                         with the Q1 mass matrix (Example 5.1's source) */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -155,6 +166,12 @@ typedef struct gbl_level_desc {
   int nwin;           /* kept windows of the preconditioner (window_tol > 0, 3 <= k < q), else 0 */
   const int* wlist;   /* [nwin] window origins x0 * (nk/2) + y0 (parents x0..x0+2, y0..y0+2), any order */
   const void* winv;   /* [nwin][27][27] B_w^-1, unknown (3 dx + dy) * 3 + t of parent (x0 + dx, y0 + dy) */
+  int dense;          /* 1 for the exact hierarchy: A is [n][n], B [nsub][nsub] (subband row t * (n_{k-1}) + parent,
+                         identity rows where a parent has fewer children), R [n_{k-1}][n], row-major FP64; level-q
+                         unknowns are the interior nodes (i - 1) m + (j - 1), level-k < q unknowns the cells
+                         x 2^k + y.  0 for the localized hierarchy (the stencil layouts above) */
+  int n;              /* unknowns of level k (dense only) */
+  int nsub;           /* subband rows of level k, three per parent (dense only) */
 } gbl_level_desc;
 
 typedef struct gbl_ctx gbl_ctx;
@@ -164,7 +181,8 @@ int gbl_version(void);
 
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
- * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0. */
+ * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0, exact 0, geometry 0,
+ * source 0. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
@@ -172,7 +190,10 @@ int gbl_default_opts(gbl_opts* opts);
  * Pure host computation.  EINVAL on a bad q or options. */
 int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
 
-/* Build the localized hierarchy for the cell coefficient a_dev [n][n] (n = 2^q).
+/* Build the localized hierarchy for the cell coefficient a_dev [n][n] (n = 2^q;
+ * n = 2^q + 1 for the exact hierarchy with geometry 1), or with opts->exact
+ * the exact hierarchy of Algorithm 1 (dense FP64 level matrices, Cholesky
+ * factors of every B^(k) and of A^(1)).
  * The hierarchy is stored in ws_dev (ws_bytes >= gbl_workspace_bytes); the
  * caller must keep ws_dev alive and untouched until gbl_destroy.  On success
  * *out receives a new context.  EINVAL if any a <= 0 or non-finite (checked on
@@ -183,13 +204,17 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts,
 
 /* Solve for nrhs >= 1 right-hand sides (in blocks of min(opts->max_rhs, 16); a block
  * iterates until all its right-hand sides meet rtol).
- * g_dev : [nrhs][n][n] cell source.
+ * g_dev : [nrhs][n][n] cell source ([nrhs][n-1][n-1] interior nodal values when
+ *         opts->source = 1).
  * u_dev : [nrhs][n+1][n+1] nodal; on entry its boundary entries hold the
  *         Dirichlet data (interior entries are ignored), on exit the interior
  *         holds the solution.
  * info  : optional (may be NULL).
  * ENOCONV if rtol was not reached within max_outer iterations (u holds the
- * last iterate).  Synchronises the stream. */
+ * last iterate).  The exact hierarchy applies the subband solve of Theorem
+ * 4.15 (every subband system solved by its Cholesky factor) and two FP64
+ * refinement steps with A^(q); its info reports no iterations.
+ * Synchronises the stream. */
 int gbl_solve(gbl_ctx* ctx, int nrhs, const double* g_dev, double* u_dev,
               gbl_solve_info* info, void* stream);
 

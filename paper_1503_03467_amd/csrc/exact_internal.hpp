@@ -1,0 +1,43 @@
+// Exact (unlocalized) hierarchy: dense level matrices in FP64 (Algorithm 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+
+#include "gamblet_internal.hpp"
+
+namespace gbl {
+
+// Tree tables of the transition from level k to level k - 1 (device pointers).
+struct ExLevelTables {
+  int np2 = 0;                  // parents (level k-1 unknowns)
+  const int* nch = nullptr;     // [np2] child counts m_p
+  const int* child = nullptr;   // [np2][4] level-k index of the child at position d (by t), -1 past m_p
+  const double* wc = nullptr;   // [np2][3][4] Helmert row t of parent p over its child positions
+  const int* parent = nullptr;  // [N_k] parent of a level-k unknown
+  const int* pos = nullptr;     // [N_k] its position among the parent's children
+};
+
+void ex_gemm(int M, int N, int K, double alpha, const double* A, long as0, long as1, const double* B, long bs0,
+             long bs1, double beta, double* C, long ldc, hipStream_t st);
+void ex_cholesky(double* A, int n, long lda, int* status, hipStream_t st);
+void ex_chol_solve(const double* A, int n, long lda, double* X, long ldx, int nrhs, hipStream_t st);
+void ex_fill(long len, double v, double* x, hipStream_t st);
+void ex_level_operators(const double* A, long N, const ExLevelTables& t, double* B, double* C, hipStream_t st);
+void ex_restriction(const double* D, const ExLevelTables& t, long N, double* R, hipStream_t st);
+void ex_load(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
+             hipStream_t st);
+void ex_wapply(const ExLevelTables& t, const double* g, int nrhs, double* y, hipStream_t st);
+void ex_wtadd(const ExLevelTables& t, long N, const double* w, int nrhs, double* v, hipStream_t st);
+void ex_to_nodal(int nc, const double* x, int nrhs, double* u, hipStream_t st);
+void ex_from_nodal(int nc, const double* u, int nrhs, double* x, hipStream_t st);
+void ex_axpy(long n, double alpha, const double* x, double* y, hipStream_t st);
+void ex_diag(const double* M, long n, double* d, hipStream_t st);
+void ex_diag_scale(const double* M, long n, long ld, const double* in, double* out, bool inverse,
+                   const ExLevelTables* t, hipStream_t st);
+void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStream_t st);
+void launch_ex_assemble(const double* a, int nc, double* A, int* status, hipStream_t st);
+
+}  // namespace gbl

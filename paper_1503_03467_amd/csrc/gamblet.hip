@@ -26,6 +26,7 @@
 #include "../../include/gamblet.h"
 #include "gamblet_internal.hpp"
 #include "solve_internal.hpp"
+#include "exact_host.hpp"
 
 using namespace gbl;
 
@@ -177,6 +178,14 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
     msg = "unknown inner_kind";
     return GBL_EINVAL;
   }
+  if (o->exact != 0 && o->exact != 1) { msg = "exact must be 0 or 1"; return GBL_EINVAL; }
+  if (o->geometry != 0 && o->geometry != 1) { msg = "geometry must be 0 or 1"; return GBL_EINVAL; }
+  if (o->source != 0 && o->source != 1) { msg = "source must be 0 or 1"; return GBL_EINVAL; }
+  if (!o->exact && (o->geometry != 0 || o->source != 0)) {
+    msg = "geometry 1 and nodal sources need the exact hierarchy (exact = 1)";
+    return GBL_EINVAL;
+  }
+  if (o->exact && o->precision != GBL_FP64) { msg = "the exact hierarchy is FP64"; return GBL_EINVAL; }
   if (!(o->window_tol >= 0.0) || !(o->window_tol < 1e300)) {
     msg = "window_tol must be finite and >= 0";
     return GBL_EINVAL;
@@ -376,6 +385,7 @@ struct gbl_ctx {
   ChebStep cheb_q[kMaxCheb]{};          // the same for the stored finest level (slot 0)
   bool diverged = false;                // the last solve produced a non-finite estimate or residual
   int nwin[kMaxLevels] = {};            // kept windows of the preconditioner per level
+  ExactHier* ex = nullptr;              // the exact (dense) hierarchy when opts.exact
 
   // The arena in the scalar T: the build's own (FP64 or FP32), or with
   // MIXED_FP64_BUILD the FP32 copy the solve reads.
@@ -480,6 +490,7 @@ void release(gbl_ctx* c) {
     }
   }
   destroy_resources(r);
+  delete c->ex;
   delete c;
 }
 
@@ -1157,13 +1168,24 @@ int gbl_default_opts(gbl_opts* o) {
   o->level_q_mass = 0;
   o->rho_coarse = 0;
   o->window_tol = 0.0;
+  o->exact = 0;
+  o->geometry = 0;
+  o->source = 0;
   return GBL_OK;
 }
 
 int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes) {
   if (!bytes) return fail(nullptr, GBL_EINVAL, "bytes is NULL");
-  Layout L;
   std::string msg;
+  if (opts && opts->exact) {
+    int st = validate_opts(opts, msg);
+    ExactHier E;
+    if (!st) st = exact_layout(E, q, opts->geometry, opts->max_rhs, msg);
+    if (st) return fail(nullptr, st, msg);
+    *bytes = E.total;
+    return GBL_OK;
+  }
+  Layout L;
   const int st = make_layout(q, opts, L, msg);
   if (st) return fail(nullptr, st, msg);
   *bytes = L.total;
@@ -1176,8 +1198,38 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   *out = nullptr;
   if (!a_dev) return fail(nullptr, GBL_EINVAL, "a_dev is NULL");
   if (!ws_dev) return fail(nullptr, GBL_EINVAL, "ws_dev is NULL");
-  Layout L;
   std::string msg;
+  if (opts && opts->exact) {
+    int st = validate_opts(opts, msg);
+    ExactHier E;
+    if (!st) st = exact_layout(E, q, opts->geometry, opts->max_rhs, msg);
+    if (st) return fail(nullptr, st, msg);
+    if (ws_bytes < E.total)
+      return fail(nullptr, GBL_ENOMEM, "workspace too small: need " + std::to_string(E.total) + " bytes");
+    gbl_ctx* c = new (std::nothrow) gbl_ctx();
+    if (c) c->ex = new (std::nothrow) ExactHier(E);
+    if (!c || !c->ex) {
+      delete c;
+      return fail(nullptr, GBL_ENOMEM, "host allocation failed");
+    }
+    c->opts = *opts;
+    c->L.q = q;
+    c->L.n = E.nc;
+    c->L.prec = GBL_FP64;
+    c->L.elem = c->L.selem = 8;
+    c->ws = static_cast<char*>(ws_dev);
+    c->ws_bytes = ws_bytes;
+    c->ex->ws = c->ws;
+    st = exact_build(*c->ex, a_dev, static_cast<hipStream_t>(stream), msg);
+    if (st) {
+      g_last_error = msg;
+      release(c);
+      return st;
+    }
+    *out = c;
+    return GBL_OK;
+  }
+  Layout L;
   int st = make_layout(q, opts, L, msg);
   if (st) return fail(nullptr, st, msg);
   if (ws_bytes < L.total)
@@ -1289,6 +1341,12 @@ int gbl_solve(gbl_ctx* c, int nrhs, const double* g_dev, double* u_dev, gbl_solv
   if (info) std::memset(info, 0, sizeof(*info));
   c->diverged = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->ex) {
+    std::string msg;
+    const int st = exact_solve(*c->ex, nrhs, c->opts.source, g_dev, u_dev, 2, s, msg);
+    if (info) info->status = st;
+    return st ? fail(c, st, msg) : GBL_OK;
+  }
   const size_t n2 = (size_t)c->L.n * c->L.n;
   const int st = (c->L.selem == 8) ? solve_many<double>(c, nrhs, 0, g_dev, n2, u_dev, info, s)
                                          : solve_many<float>(c, nrhs, 0, g_dev, n2, u_dev, info, s);
@@ -1303,6 +1361,7 @@ int gbl_adjoint(gbl_ctx* c, int nrhs, const double* u_dev, const double* dJdu_de
                 double* dJdg_dev, double* lambda_dev, gbl_solve_info* info, void* stream) {
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!u_dev || !dJdu_dev || !dJdloga_dev) return fail(c, GBL_EINVAL, "u, dJdu and dJdloga must not be NULL");
+  if (c->ex) return fail(c, GBL_EINVAL, "the exact hierarchy has no adjoint call");
   if (nrhs < 1) return fail(c, GBL_EINVAL, "nrhs must be at least 1");
   if (info) std::memset(info, 0, sizeof(*info));
   c->diverged = false;
@@ -1435,6 +1494,7 @@ int gbl_build_batched(int nprob, const int* q, const double* const* a_dev, const
                       void* const* ws_dev, const size_t* ws_bytes, gbl_ctx** ctx_out, int* status, void* stream) {
   if (nprob < 1 || !q || !a_dev || !opts || !ws_dev || !ws_bytes || !ctx_out || !status)
     return fail(nullptr, GBL_EINVAL, "batched build: null argument or nprob < 1");
+  if (opts->exact) return fail(nullptr, GBL_EINVAL, "batched build: the exact hierarchy is built one problem at a time");
   std::vector<double> work(nprob);
   for (int i = 0; i < nprob; ++i) {
     ctx_out[i] = nullptr;
@@ -1483,6 +1543,20 @@ int gbl_build_flags(const gbl_ctx* c, unsigned* flags) {
 int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
   if (!c || !d) return fail(nullptr, GBL_EINVAL, "ctx and desc must not be NULL");
   if (k < 1 || k > c->L.q) return fail(const_cast<gbl_ctx*>(c), GBL_EINVAL, "level out of range");
+  if (c->ex) {
+    const ExactHier& E = *c->ex;
+    std::memset(d, 0, sizeof(*d));
+    d->k = k;
+    d->dense = 1;
+    d->n = (int)E.N[k];
+    d->nsub = k >= 2 ? 3 * E.np2[k] : 0;
+    d->nk = k == c->L.q ? E.m : (1 << k);
+    d->elem_bytes = 8;
+    d->A = E.A(k);
+    d->B = k >= 2 ? E.B(k) : nullptr;
+    d->R = k >= 2 ? E.R(k) : nullptr;
+    return GBL_OK;
+  }
   const LevelGeom& g = c->L.lv[k];
   d->k = k;
   d->nk = g.nk;
@@ -1498,6 +1572,9 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
   d->nwin = (k >= 2 && k < c->L.q) ? c->nwin[k] : 0;
   d->wlist = d->nwin > 0 ? reinterpret_cast<const int*>(c->ws + c->L.win_list_off[k]) : nullptr;
   d->winv = d->nwin > 0 ? c->ws + c->L.win_inv_off[k] : nullptr;
+  d->dense = 0;
+  d->n = 0;
+  d->nsub = 0;
   return GBL_OK;
 }
 
@@ -1538,6 +1615,7 @@ int gbl_transform(gbl_ctx* c, const double* u_dev, double* coef_dev, void* strea
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
   if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->ex) return exact_transform(*c->ex, u_dev, coef_dev, s) ? fail(c, GBL_EHIP, "launch failed") : GBL_OK;
   if (c->L.elem == 8) launch_transform<double>(transform_args<double>(c), u_dev, coef_dev, s);
   else launch_transform<float>(transform_args<float>(c), u_dev, coef_dev, s);
   HIPCHK(c, hipGetLastError());
@@ -1549,6 +1627,8 @@ int gbl_inverse_transform(gbl_ctx* c, const double* coef_dev, double* u_dev, voi
   if (!u_dev || !coef_dev) return fail(c, GBL_EINVAL, "u and coef must not be NULL");
   if (c->L.mass > 0) return fail(c, GBL_EINVAL, "the transform needs the nodal-basis level-q gamblets");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->ex)
+    return exact_inverse_transform(*c->ex, coef_dev, u_dev, s) ? fail(c, GBL_EHIP, "launch failed") : GBL_OK;
   if (c->L.elem == 8) launch_inverse_transform<double>(transform_args<double>(c), coef_dev, u_dev, s);
   else launch_inverse_transform<float>(transform_args<float>(c), coef_dev, u_dev, s);
   HIPCHK(c, hipGetLastError());
@@ -1560,20 +1640,19 @@ int gbl_compress(gbl_ctx* c, double* coef_dev, long keep, double* threshold, voi
   if (!coef_dev) return fail(c, GBL_EINVAL, "coef must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long n = (long)1 << (2 * c->L.q);
-  double* thr = c->oscal() + kSSpare;   // device scalar
+  double* thr = c->ex ? c->ex->at(c->ex->offThr) : c->oscal() + kSSpare;   // device scalar
   if (keep <= 0) {
     launch_fill((size_t)n, 0.0, coef_dev, s);
     if (threshold) *threshold = HUGE_VAL;
   } else if (keep >= n) {
     if (threshold) *threshold = 0.0;
   } else {
-    auto* sel = reinterpret_cast<unsigned long long*>(c->ws + c->L.sel_off);
+    auto* sel = reinterpret_cast<unsigned long long*>(c->ws + (c->ex ? c->ex->offSel : c->L.sel_off));
     launch_select_threshold(coef_dev, n, keep, sel, reinterpret_cast<unsigned*>(sel + 4), thr, s);
     launch_zero_below(thr, n, coef_dev, s);
     if (threshold) {
-      HIPCHK(c, hipMemcpyAsync(c->host, thr, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(threshold, thr, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
-      *threshold = c->host[0];
     }
   }
   HIPCHK(c, hipGetLastError());
@@ -1659,6 +1738,7 @@ int gbl_energy_norm(gbl_ctx* c, const double* u_dev, double* norm, void* stream)
   if (!c || !norm) return fail(c, GBL_EINVAL, "ctx and norm must not be NULL");
   if (!u_dev) return fail(c, GBL_EINVAL, "u must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->ex) return exact_energy_norm(*c->ex, u_dev, norm, s) ? fail(c, GBL_EHIP, "energy norm failed") : GBL_OK;
   const Layout& L = c->L;
   const int n = L.n;
   double* sl = c->fine(0);

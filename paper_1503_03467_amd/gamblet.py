@@ -27,7 +27,8 @@ class GblOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int), ("inner_iters", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
-                ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double)]
+                ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double), ("exact", ctypes.c_int),
+                ("geometry", ctypes.c_int), ("source", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -39,7 +40,8 @@ class GblLevelDesc(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("nk", ctypes.c_int), ("s", ctypes.c_int), ("t", ctypes.c_int),
                 ("rw", ctypes.c_int), ("rho", ctypes.c_int), ("elem_bytes", ctypes.c_int),
                 ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("R", ctypes.c_void_p),
-                ("nwin", ctypes.c_int), ("wlist", ctypes.c_void_p), ("winv", ctypes.c_void_p)]
+                ("nwin", ctypes.c_int), ("wlist", ctypes.c_void_p), ("winv", ctypes.c_void_p),
+                ("dense", ctypes.c_int), ("n", ctypes.c_int), ("nsub", ctypes.c_int)]
 
 
 class GambletError(RuntimeError):
@@ -107,12 +109,14 @@ def _check(code: int, ctx=None):
 
 
 INNER_KINDS = {"chebyshev": 0, "cg": 1, "cheb-cg": 2}
+SOURCES = {"cell": 0, "nodal": 1}
 
 
 def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_outer: int = 100,
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
-              level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0) -> GblOpts:
+              level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0, exact: bool = False,
+              geometry: int = 0, source: str = "cell") -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -133,6 +137,9 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.level_q_mass = int(level_q_mass)
     o.rho_coarse = int(rho_coarse)
     o.window_tol = float(window_tol)
+    o.exact = 1 if exact else 0
+    o.geometry = int(geometry)
+    o.source = SOURCES[source]
     return o
 
 
@@ -162,21 +169,28 @@ class SolveInfo:
 
 
 class Hierarchy:
-    """Localized gamblet hierarchy of one coefficient field, built on the GPU."""
+    """Gamblet hierarchy of one coefficient field, built on the GPU: localized
+    (the default) or, with ``exact=True``, the dense FP64 hierarchy of
+    Algorithm 1 (``geometry=1``: the mesh of Example 5.1, a of shape
+    [2^q + 1][2^q + 1]; ``source="nodal"``: sources given at the interior
+    nodes and loaded with the mass matrix)."""
 
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
                  kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0,
-                 window_tol: float = 0.0):
+                 window_tol: float = 0.0, exact: bool = False, geometry: int = 0, source: str = "cell"):
         n = a.shape[0]
-        q = n.bit_length() - 1
-        if n != (1 << q) or q < 2:
-            raise ValueError("a must be [2^q][2^q] with q >= 2")
+        q = (n - geometry).bit_length() - 1
+        if n - geometry != (1 << q) or q < 2:
+            raise ValueError("a must be [2^q][2^q] (geometry 0) or [2^q + 1][2^q + 1] (geometry 1) with q >= 2")
         _require(a, (n, n), "a")
         self.q, self.n, self.device = q, n, a.device
-        self.opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
-                              kappa_coarse, level_q_mass, rho_coarse, window_tol)
+        self.exact = bool(exact)
+        self.source = source
+        self.opts = make_opts(rho, "fp64" if exact else precision, rtol, max_outer, inner_iters, max_rhs,
+                              inner_iters_coarse, inner, kappa, kappa_coarse, level_q_mass, rho_coarse, window_tol,
+                              exact, geometry, source)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -197,11 +211,13 @@ class Hierarchy:
             pass
 
     def solve(self, g: torch.Tensor, u_boundary: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
-        """Solve for cell sources ``g`` ([n][n] or [nrhs][n][n]); returns nodal u ([.., n+1, n+1])."""
+        """Solve for cell sources ``g`` ([n][n] or [nrhs][n][n]; nodal sources [n-1][n-1] when the
+        hierarchy was built with ``source="nodal"``); returns nodal u ([.., n+1, n+1])."""
         single = g.dim() == 2
         gg = g.unsqueeze(0) if single else g
         nrhs = gg.shape[0]
-        _require(gg, (nrhs, self.n, self.n), "g")
+        gs = self.n - 1 if self.source == "nodal" else self.n
+        _require(gg, (nrhs, gs, gs), "g")
         m = self.n + 1
         if u_boundary is None:
             u = torch.zeros((nrhs, m, m), dtype=torch.float64, device=self.device)
@@ -294,7 +310,8 @@ class Hierarchy:
 
     def level(self, k: int) -> dict:
         """A^(k) [S,S,nk,nk] and R^(k-1,k) [rw,rw,nc,nc] as device views, B^(k) as a
-        [T,T,3,3,np,np] copy (the library stores it block-interleaved, see ``gamblet.h``)."""
+        [T,T,3,3,np,np] copy (the library stores it block-interleaved, see ``gamblet.h``).
+        For the exact hierarchy: dense views A [n][n], B [nsub][nsub], R [n_{k-1}][n]."""
         d = GblLevelDesc()
         _check(lib().gbl_level_layout(self.ctx, int(k), ctypes.byref(d)), self.ctx)
         dt = torch.float64 if d.elem_bytes == 8 else torch.float32
@@ -303,6 +320,14 @@ class Hierarchy:
         def view(ptr, count):
             off = ptr - base
             return self.ws[off: off + count * d.elem_bytes].view(dt)
+
+        if d.dense:
+            out = {"k": d.k, "n": d.n, "nsub": d.nsub, "A": view(d.A, d.n * d.n).view(d.n, d.n)}
+            if k >= 2:
+                npar = d.nsub // 3
+                out["B"] = view(d.B, d.nsub * d.nsub).view(d.nsub, d.nsub)
+                out["R"] = view(d.R, npar * d.n).view(npar, d.n)
+            return out
 
         nk = d.nk
         S = 2 * d.s + 1
@@ -443,8 +468,9 @@ class GambletSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         (u,) = ctx.saved_tensors
+        # The hierarchy stays open: a graph kept with retain_graph may run
+        # backward again; it is released with the autograd context.
         dloga, dg, _ = ctx.H.adjoint(u, grad_u.contiguous())
-        ctx.H.close()
         return dloga, dg, None, None, None
 
 
@@ -453,6 +479,7 @@ def _adopt(ctx_value: int, q: int, ws: torch.Tensor, opts: GblOpts) -> Hierarchy
     h = Hierarchy.__new__(Hierarchy)
     h.q, h.n, h.device = q, 1 << q, ws.device
     h.opts, h.ws = opts, ws
+    h.exact, h.source = False, "cell"
     h.ctx = ctypes.c_void_p(ctx_value)
     h.last_info = None
     return h

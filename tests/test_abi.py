@@ -154,3 +154,25 @@ def test_noalloc_compression_rejects_bad_sizes():
     assert L.gbl_compress_noalloc(dummy, 0, 1, ctypes.byref(thr), None) == -1
     assert L.gbl_compress_noalloc(dummy, 1 << 32, 1, ctypes.byref(thr), None) == -1
     assert b"count" in L.gbl_last_error(None)
+
+
+def test_exact_options_validated():
+    """The exact hierarchy needs FP64 and 2 <= q <= 7; the Example 5.1 mesh and
+    nodal sources exist only with it."""
+    P, L = _lib()
+    sz = ctypes.c_size_t()
+    bad = [P.make_opts(precision="mixed", exact=True), P.make_opts(precision="fp64", geometry=1),
+           P.make_opts(precision="fp64", source="nodal")]
+    for o in bad:
+        assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(sz)) == -1
+    o = P.make_opts(precision="fp64", exact=True)
+    assert L.gbl_workspace_bytes(8, ctypes.byref(o), ctypes.byref(sz)) == -1
+    assert b"q <= 7" in L.gbl_last_error(None)
+    for field, value in (("exact", 2), ("geometry", 2), ("source", 2)):
+        o = P.make_opts(precision="fp64", exact=True)
+        setattr(o, field, value)
+        assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(sz)) == -1
+    g0 = P.workspace_bytes(6, P.make_opts(precision="fp64", exact=True))
+    g1 = P.workspace_bytes(6, P.make_opts(precision="fp64", exact=True, geometry=1))
+    # the dense level-6 stiffness matrix alone: 3969^2 (geometry 0) and 4096^2 (geometry 1) doubles
+    assert g0 > 3969 ** 2 * 8 and g1 > 4096 ** 2 * 8 and g1 > g0
