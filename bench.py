@@ -181,6 +181,114 @@ def kernel_work(name, geo, q, elem, inner="chebyshev"):
     return "bytes", 0.0
 
 
+def host_info():
+    """CPU model, usable cores and BLAS threads of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"), default=None)
+    except Exception:
+        pass
+    return {"cpu_model": model, "cores_usable": len(os.sched_getaffinity(0)), "blas_threads": blas}
+
+
+def superlu_leg(a, g):
+    """The oracle's direct solve (Q1 assembly, SuperLU factor, solves with two
+    FP64 refinement steps; single-threaded) of one problem and its right-hand
+    sides ([nrhs][n][n]), timed on the host.  Returns the record and the solutions."""
+    from oracle import fem
+    t0 = time.perf_counter()
+    fe = fem.assemble(a)
+    b = fem.load_cellwise(g, fe.h)
+    ds = fem.DirectSolver(fe.A)
+    t1 = time.perf_counter()
+    u = ds.solve(b)
+    t2 = time.perf_counter()
+    nrhs = g.shape[0] if g.ndim == 3 else 1
+    dof = fe.A.shape[0]
+    return {"dof": dof, "rhs": nrhs, "factor_s": t1 - t0, "solve_s": t2 - t1,
+            "dof_per_s": dof * nrhs / (t2 - t0), "threads": 1, "kind": "oracle (SuperLU)"}, u
+
+
+def oracle_localized_leg(S):
+    """The oracle's localized hierarchy (Algorithm 2, patch radius 3) and its
+    solve with refinement to 1e-10, numpy/scipy with BLAS on every core, on a
+    bounded sample: the 128 x 128-cell problem of the rough recipe (sigma = 2)."""
+    from oracle import fem
+    from oracle import gamblets as G
+    pr = S.rough_problem(7, 2.0, S.TAG_Q9_ROUGH)
+    t0 = time.perf_counter()
+    fe = fem.assemble(pr.a)
+    h = G.localized_hierarchy(fe.A, G.Tree(7), 3)
+    t1 = time.perf_counter()
+    _, sweeps, _ = G.refine_solve(h, fe.A, fem.load_cellwise(pr.g[0], fe.h), tol=1e-10)
+    t2 = time.perf_counter()
+    return {"sample": "128x128-cell rough problem (sigma=2), radius 3", "dof": pr.dof, "build_s": t1 - t0,
+            "solve_s": t2 - t1, "refinement_sweeps": sweeps, "dof_per_s": pr.dof / (t2 - t0),
+            "kind": "oracle (numpy, localized build + refined solve)", **host_info()}
+
+
+def exact_workloads(P, S, torch, dev):
+    """The exact hierarchy (Algorithm 1, dense FP64) on its two 64 x 64-scale
+    workloads: the 64 x 64-cell lognormal product field (sigma = 1) with g = 1,
+    and Example 5.1 (65 x 65 cells, K = 6, nodal source).  Build and solve
+    timed apart (minimum of three), error against the oracle's direct solve,
+    and the energy error of the solution compressed in the normalized exact
+    basis; the oracle's own dense exact hierarchy timed beside it."""
+    import numpy as np
+    from oracle import fem
+    from oracle import gamblets as G
+    print("# exact hierarchy workloads", file=sys.stderr, flush=True)
+    out = {}
+    pr = S.q6_exact_problem()
+    cases = {"q6_lognormal_g1": (pr.a, pr.g[0], 0, "cell"),
+             "example_5_1": (S.example51_coefficient(), S.example51_nodal_source(), 1, "nodal")}
+    for name, (a_np, g_np, geometry, source) in cases.items():
+        a = torch.as_tensor(a_np, device=dev)
+        g = torch.as_tensor(g_np, device=dev)
+        fe = fem.assemble(a_np)
+        b = fem.load_nodal(g_np, fe.h) if source == "nodal" else fem.load_cellwise(g_np, fe.h)
+        u_ref = fem.DirectSolver(fe.A).solve(b)
+        best_b, best_s = float("inf"), float("inf")
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = P.Hierarchy(a, exact=True, geometry=geometry, source=source)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            u = H.solve(g)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            best_b, best_s = min(best_b, (t1 - t0) * 1e3), min(best_s, (t2 - t1) * 1e3)
+            if _ < 2:
+                H.close()
+        err = float(np.linalg.norm(u.cpu().numpy().ravel()[fe.interior] - u_ref) / np.linalg.norm(u_ref))
+        nrm = H.energy_norm(u)
+        total = H.transform_size()
+        comp = {}
+        for frac in (0.01, 0.05, 0.25):
+            c = H.transform(u)
+            H.compress(c, int(round(frac * total)))
+            comp[f"{frac:g}"] = H.energy_norm(u - H.inverse_transform(c)) / nrm
+        H.close()
+        tc = time.perf_counter()
+        G.exact_hierarchy(fe.A, G.Tree(6, offset=geometry))
+        cpu_s = time.perf_counter() - tc
+        out[name] = {"dof": fe.A.shape[0], "build_ms": best_b, "solve_ms": best_s,
+                     "rel_err_vs_direct": err, "energy_err_vs_kept_fraction": comp,
+                     "oracle_exact_hierarchy_s": cpu_s, **host_info()}
+    return out
+
+
 def cpu_baseline(pr, dof):
     """The oracle (Q1 assembly, SuperLU factor and solve, two FP64 refinement
     steps; single-threaded) on the full benchmark problem, repeated for about
@@ -197,13 +305,15 @@ def cpu_baseline(pr, dof):
         t_sum += d
         spent += d
         reps += 1
+    hi = host_info()
     cpu = {"value": dof / (t_sum / reps), "unit": "DOF/s", "cores": 1, "kind": "oracle",
            "sample": f"full 512x512-cell problem, {reps} repetitions: Q1 assembly + SuperLU factor/solve + "
-                     f"2 FP64 refinement steps (single-threaded); host has {len(os.sched_getaffinity(0))} cores"}
+                     f"2 FP64 refinement steps (single-threaded); host has {hi['cores_usable']} cores",
+           "cpu_model": hi["cpu_model"]}
     return cpu, u_ref
 
 
-def inclusion_workload(P, S, torch, dev):
+def inclusion_workload(P, S, torch, dev, cpu_leg=True):
     """The 2048 x 2048-cell inclusion workload (discs of a = 1e6 on 10% of the
     cells over the product field, 16 N(0,1) right-hand sides, patch radius 4),
     one pass: FP64-built hierarchy with window corrections, the 16 right-hand
@@ -258,6 +368,10 @@ def inclusion_workload(P, S, torch, dev):
                                       "outer_iters": H.last_info.outer_iters}
     H.close()
     os.environ.pop("GBL_PROGRESS", None)
+    if cpu_leg:
+        print("# inclusion workload: oracle direct solve of the 16 right-hand sides on the host", file=sys.stderr,
+              flush=True)
+        out["cpu_superlu"], _ = superlu_leg(pr.a, pr.g)
     return out
 
 
@@ -325,6 +439,10 @@ def main():
     print("# step wall times (ms, host clock; a solve ends with a host read of its status): "
           + " ".join("%.3f" % ((b - a) * 1e3) for a, b in zip(marks, marks[1:])), file=sys.stderr, flush=True)
     P.profile_enable(None)
+    bad = [(i, inf.status) for i, inf in enumerate(infos) if inf.status != 0]
+    if bad:
+        print(f"timed steps did not converge (step, status): {bad}", file=sys.stderr, flush=True)
+        sys.exit(1)
     dom_ms, dom_launches = P.profile_read()[dominant]
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = dof / (ms_per_step * 1e-3)
@@ -525,6 +643,13 @@ def main():
         extras["adjoint_workload_q10"] = {"dof": dof10, "build_ms": best[0], "solve_ms": best[1],
                                           "adjoint_grad_ms": best[2], "adjoint_outer_iters": it10,
                                           "build_solve_dof_per_s": dof10 / ((best[0] + best[1]) * 1e-3)}
+        if not args.no_cpu_baseline:
+            print("# adjoint workload: oracle direct solve on the host", file=sys.stderr, flush=True)
+            leg, u10_ref = superlu_leg(pa.a, pa.g[:1])
+            u10_np = u10.cpu().numpy()[1:-1, 1:-1].ravel()
+            extras["adjoint_workload_q10"]["cpu_superlu"] = leg
+            extras["adjoint_workload_q10"]["rel_err_vs_direct"] = float(
+                np.linalg.norm(u10_np - u10_ref) / np.linalg.norm(u10_ref))
         del a10, g10, uo10, u10
         # batch workload: 256 independent problems of 64 x 64 to 256 x 256
         # cells with 64 right-hand sides each, built and solved concurrently
@@ -587,8 +712,13 @@ def main():
         extras["gamblet_transform"] = tr
         H.close()
 
+        extras["exact_workloads"] = exact_workloads(P, S, torch, dev)
+        if not args.no_cpu_baseline:
+            print("# oracle localized build + solve on the host", file=sys.stderr, flush=True)
+            extras["cpu_oracle_localized"] = oracle_localized_leg(S)
+
     if not args.no_inclusions:
-        extras["inclusion_workload_q11"] = inclusion_workload(P, S, torch, dev)
+        extras["inclusion_workload_q11"] = inclusion_workload(P, S, torch, dev, not args.no_cpu_baseline)
 
     out = {
         "metric": "DOF/s gamblet build+solve at 1e-8 rel err; adjoint grad time; % HBM roof",

@@ -16,8 +16,16 @@ Modules
               4.11/4.13), the exact gamblet transform (Algorithm 1 with the
               level-q initialisation psi = nodal basis allowed in Section
               5.2), the localized transform (Algorithm 2, Definition 5.3) and
-              the subband solve (Theorem 4.15).
+              the subband solve (Theorem 4.15), the gamblet transform and
+              compression of the discussion of Example 5.1.
+``mass_inverse`` Level-q gamblets from the localized mass inverse
+              (Algorithms 1-2, Definition 5.2).
 
-Parity status of each function is stated in its docstring; the only
-function without an outside pin is marked "parity unpinned".
+Every function is pinned by a test in ``tests/test_oracle_*.py`` against
+something other than itself: closed forms (sine-transform solution of the
+constant-coefficient problem, the identities of Theorem 4.8), brute force on
+tiny inputs (quadrature of the element integrals, KKT systems of the
+constrained energy minimisation, dense exact gamblets), the patch box sizes of
+Definition 5.3, and special cases that reduce to the exact hierarchy or to a
+direct solve.  No function is left unpinned.
 """

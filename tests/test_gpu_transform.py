@@ -88,6 +88,75 @@ def test_transform_matches_oracle(prec, tol):
     H.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_transform_per_level_matches_oracle_q7(prec):
+    """Level by level and element by element at q = 7 (16,129 unknowns, 16,384
+    coefficients over seven levels).  FP64: every level's coefficient vector
+    within 1e-10 of the oracle's (relative Euclidean) and every coefficient
+    within 1e-10 of that level's largest one.  Mixed: a level-k coefficient is
+    W (U^(k) - R^T U^(k-1)) and the FP32 patch solves move entries of R by up
+    to ~2e-4, acting on U^(k-1), whose size is that of the whole solution, not
+    of the level's detail; so each level's error is bounded against the whole
+    normalized coefficient vector: 1e-3 of its norm (the mixed-path bound of
+    the other coefficient tests)."""
+    q, rho = 7, 3
+    _case(test="transform_per_level", q=q, rho=rho, prec=prec)
+    pr = S.rough_problem(q, 2.0, 37)
+    fe = fem.assemble(pr.a)
+    tree = G.Tree(q)
+    h = G.localized_hierarchy(fe.A, tree, rho)
+    u = fem.DirectSolver(fe.A).solve(fem.load_cellwise(pr.g[0], fe.h))
+    c1_ref, ck_ref = G.normalized_coefficients(h, u)
+    H = _P().Hierarchy(_dev(pr.a), rho=rho, precision=prec)
+    c = H.transform(_dev(_nodal(fe, u))).cpu().numpy()
+    c1, ck, pads = _gpu_to_oracle(c, tree, q)
+    assert not np.any(pads)
+    got, ref = {1: c1, **ck}, {1: c1_ref, **ck_ref}
+    whole = float(np.sqrt(sum(float(np.sum(v * v)) for v in ref.values())))
+    errs = {k: _rel(got[k], ref[k]) for k in ref}
+    emax = {k: float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in ref}
+    ewhole = {k: float(np.linalg.norm(got[k] - ref[k])) / whole for k in ref}
+    print("per-level rel err", {k: f"{e:.2e}" for k, e in errs.items()})
+    print("per-level max entry err", {k: f"{e:.2e}" for k, e in emax.items()})
+    print("per-level err / whole vector", {k: f"{e:.2e}" for k, e in ewhole.items()})
+    if prec == "fp64":
+        assert all(e < 1e-10 for e in errs.values()), errs
+        assert all(e < 1e-10 for e in emax.values()), emax
+    else:
+        assert all(e < 1e-3 for e in ewhole.values()), ewhole
+    H.close()
+
+
+@pytest.mark.parametrize("q", [8, 10])
+def test_compression_kept_set_is_exact_at_many_workgroups(q):
+    """The selection runs min(1024, 4^q / 1024) histogram workgroups: 64 at
+    q = 8, 1024 grid-striding ones at q = 10.  The kept set must equal the
+    oracle's rule (every |c| >= the keep-th largest) on the transform of a
+    solution, with ties planted at the threshold."""
+    _case(test="compression_kept_set", q=q)
+    pr = S.rough_problem(q, 1.0, 38)
+    H = _P().Hierarchy(_dev(pr.a), rho=3, precision="fp64")
+    u = H.solve(_dev(pr.g[0]))
+    base = H.transform(u)
+    total = H.transform_size()
+    for frac in (0.01, 0.05, 0.25):
+        keep = int(round(frac * total))
+        c = base.clone()
+        cc = c.cpu().numpy()
+        order = np.argsort(-np.abs(cc), kind="stable")
+        tie = cc[order[keep - 1]]
+        rng = np.random.default_rng(q * 100 + int(frac * 100))
+        cc[rng.integers(0, total, 7)] = -tie        # entries equal in magnitude to the threshold
+        c.copy_(torch.as_tensor(cc))
+        thr = H.compress(c, keep)
+        a1, _ = G.compress(cc, {}, keep)
+        got = c.cpu().numpy()
+        assert np.array_equal(got != 0, a1 != 0), frac
+        assert np.array_equal(got, a1)
+        assert thr == np.min(np.abs(cc[a1 != 0]))
+    H.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
 @pytest.mark.parametrize("q", [6, 9])
 def test_inverse_undoes_transform(q, prec, tol):

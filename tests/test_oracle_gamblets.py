@@ -202,6 +202,29 @@ def test_paper_geometry_tree_is_uniform():
     assert counts.count(1) == 1 and counts.count(2) == 6 and counts.count(4) == 9
 
 
+@pytest.mark.parametrize("rho", [1, 2, 3])
+def test_tree_box_sizes(rho):
+    """Definition 5.3's patch as read here (the box of coarse cells within rho
+    in each coordinate, clipped to the domain): an interior box holds
+    (2 rho + 1)^2 cells, a corner box (rho + 1)^2, an edge box
+    (rho + 1)(2 rho + 1); level-q boxes are clipped to the interior nodes."""
+    tree = G.Tree(6)
+    k = 5
+    side = 1 << k
+    idx = lambda x, y: x * side + y
+    assert tree.box(k, idx(10, 12), rho).size == (2 * rho + 1) ** 2
+    assert tree.box(k, idx(0, 0), rho).size == (rho + 1) ** 2
+    assert tree.box(k, idx(side - 1, side - 1), rho).size == (rho + 1) ** 2
+    assert tree.box(k, idx(0, 12), rho).size == (rho + 1) * (2 * rho + 1)
+    # the members are exactly the cells within rho in both coordinates
+    members = {tuple(c) for c in tree.coords[k][tree.box(k, idx(10, 12), rho)]}
+    assert members == {(x, y) for x in range(10 - rho, 11 + rho) for y in range(12 - rho, 13 + rho)}
+    # level q: node (1, 1) is the first interior node; its box stops at the boundary
+    m = (1 << 6) - 1
+    assert tree.box(6, 0, rho).size == (rho + 1) ** 2
+    assert tree.box(6, (m // 2) * m + m // 2, rho).size == (2 * rho + 1) ** 2
+
+
 def test_example51_exact_transform():
     """Example 5.1 end to end: exact transform on the paper's own mesh reproduces the FE solve."""
     a = S.example51_coefficient()
