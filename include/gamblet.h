@@ -135,6 +135,10 @@ typedef struct gbl_opts {
   int source;         /* 0: g_dev holds one value per cell (b_i = (h^2/4) sum of the four cells); 1 (exact only):
                          g_dev holds the values at the interior nodes, [m][m] with m nodes per side, and b = M g
                          with the Q1 mass matrix (Example 5.1's source) */
+  int w_kind;         /* rows of W^(k) over a parent's m children: 0 (default) the normalised Helmert rows of
+                         Construction 4.13; 1 (exact only) the differences e_t - e_{t+1} of Construction 4.11.
+                         A^(k), R and the solve do not depend on it; B^(k) and the transform coefficients do
+                         (the transform then applies (W W^T)^-1 per parent) */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -182,7 +186,7 @@ int gbl_version(void);
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
  * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0, exact 0, geometry 0,
- * source 0. */
+ * source 0, w_kind 0. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

@@ -24,10 +24,13 @@ namespace {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Normalised Helmert rows over m children (Construction 4.13): row t < m - 1
-// is (1, ..., 1, -(t + 1), 0, ...) / sqrt((t + 1)(t + 2)) with t + 1 ones.
-double helmert(int m, int t, int d) {
+// Row t (< m - 1) of W over a parent's m children.  kind 0, Construction
+// 4.13: the normalised Helmert row (1, ..., 1, -(t + 1), 0, ...) /
+// sqrt((t + 1)(t + 2)) with t + 1 ones.  kind 1, Construction 4.11: the
+// difference e_t - e_{t+1}.
+double wrow(int kind, int m, int t, int d) {
   if (t >= m - 1 || d >= m) return 0.0;
+  if (kind == 1) return d == t ? 1.0 : (d == t + 1 ? -1.0 : 0.0);
   const double s = 1.0 / std::sqrt((double)(t + 1) * (double)(t + 2));
   if (d <= t) return s;
   if (d == t + 1) return -(double)(t + 1) * s;
@@ -36,12 +39,13 @@ double helmert(int m, int t, int d) {
 
 }  // namespace
 
-int exact_layout(ExactHier& E, int q, int geom, int max_rhs, std::string& msg) {
+int exact_layout(ExactHier& E, int q, int geom, int wkind, int max_rhs, std::string& msg) {
   if (q < 2 || q > 7) { msg = "the exact hierarchy is built for 2 <= q <= 7"; return GBL_EINVAL; }
   if (geom != 0 && geom != 1) { msg = "geometry must be 0 or 1"; return GBL_EINVAL; }
   E = ExactHier{};
   E.q = q;
   E.geom = geom;
+  E.wkind = wkind;
   E.nc = geom == 0 ? (1 << q) : (1 << q) + 1;
   E.m = E.nc - 1;
   E.nr = std::max(1, std::min(max_rhs, 64));
@@ -63,6 +67,7 @@ int exact_layout(ExactHier& E, int q, int geom, int max_rhs, std::string& msg) {
       E.offWc[k] = b; b = al(b + (size_t)np2 * 12 * 8);
       E.offParent[k] = b; b = al(b + (size_t)N * 4);
       E.offPos[k] = b; b = al(b + (size_t)N * 4);
+      E.offGinv[k] = b; b = al(b + (size_t)np2 * 9 * 8);
       most = std::max(most, np2 * N);
       E.offW[k] = b; b = al(b + (size_t)nj * E.nr * 8);
     }
@@ -119,7 +124,7 @@ static int upload_tables(ExactHier& E, std::string& msg) {
       parent[b] = p;
       kids[p].push_back({2 * (sx & 1) + (sy & 1), (int)b});
     }
-    std::vector<double> wc(12 * (size_t)np2, 0.0);
+    std::vector<double> wc(12 * (size_t)np2, 0.0), gram_inv(9 * (size_t)np2, 0.0);
     for (int p = 0; p < np2; ++p) {
       auto& v = kids[p];
       std::sort(v.begin(), v.end());
@@ -130,13 +135,39 @@ static int upload_tables(ExactHier& E, std::string& msg) {
         pos[v[d].second] = (int)d;
       }
       for (int t = 0; t < 3; ++t)
-        for (int d = 0; d < 4; ++d) wc[(p * 3 + t) * 4 + d] = helmert(nch[p], t, d);
+        for (int d = 0; d < 4; ++d) wc[(p * 3 + t) * 4 + d] = wrow(E.wkind, nch[p], t, d);
+      // (W_p W_p^T)^-1 over the parent's real rows (identity on the rows it lacks)
+      const int nr = nch[p] - 1;
+      double g[3][3] = {};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          if (a < nr && b < nr)
+            for (int d = 0; d < 4; ++d) g[a][b] += wc[(p * 3 + a) * 4 + d] * wc[(p * 3 + b) * 4 + d];
+          else
+            g[a][b] = a == b ? 1.0 : 0.0;
+        }
+      // Gauss-Jordan on the 3 x 3 SPD Gram matrix
+      double m3[3][6];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 6; ++b) m3[a][b] = b < 3 ? g[a][b] : (b - 3 == a ? 1.0 : 0.0);
+      for (int c = 0; c < 3; ++c) {
+        const double piv = m3[c][c];
+        for (int b = 0; b < 6; ++b) m3[c][b] /= piv;
+        for (int a = 0; a < 3; ++a)
+          if (a != c) {
+            const double f = m3[a][c];
+            for (int b = 0; b < 6; ++b) m3[a][b] -= f * m3[c][b];
+          }
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gram_inv[(size_t)p * 9 + a * 3 + b] = m3[a][b + 3];
     }
     if (hipMemcpy(E.ws + E.offNch[k], nch.data(), nch.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(E.ws + E.offChild[k], child.data(), child.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(E.ws + E.offWc[k], wc.data(), wc.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(E.ws + E.offParent[k], parent.data(), parent.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(E.ws + E.offPos[k], pos.data(), pos.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(E.ws + E.offPos[k], pos.data(), pos.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(E.ws + E.offGinv[k], gram_inv.data(), gram_inv.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
       msg = "copy of the tree tables failed";
       return GBL_EHIP;
     }
@@ -256,8 +287,9 @@ int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u
 }
 
 // Coefficients of a nodal u on psi^(1)/||psi^(1)||_a and chi^(k)/||chi^(k)||_a:
-// U^(k-1) = pi U^(k), w^(k) = W (U^(k) - R^T U^(k-1)), scaled by sqrt(A^(1)_ii),
-// sqrt(B^(k)_jj) (W has orthonormal rows).
+// U^(k-1) = pi U^(k), w^(k) = (W W^T)^-1 W (U^(k) - R^T U^(k-1)) (the Gram
+// factor is the identity for the orthonormal rows of Construction 4.13),
+// scaled by sqrt(A^(1)_ii), sqrt(B^(k)_jj).
 int exact_transform(ExactHier& E, const double* u_nodal, double* coef, hipStream_t st) {
   const int q = E.q;
   ex_from_nodal(E.nc, u_nodal, 1, E.U(q), st);
@@ -268,6 +300,7 @@ int exact_transform(ExactHier& E, const double* u_nodal, double* coef, hipStream
     if (hipMemcpyAsync(d, E.U(k), (size_t)E.N[k] * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return GBL_EHIP;
     ex_gemm((int)E.N[k], 1, E.np2[k], -1.0, E.R(k), 1, E.N[k], E.U(k - 1), 1, 1, 1.0, d, 1, st);   // d -= R^T U^(k-1)
     ex_wapply(t, d, 1, E.W(k), st);
+    if (E.wkind != 0) ex_gram_solve(t, E.at(E.offGinv[k]), E.W(k), st);   // w = (W W^T)^-1 W d
     const int nj = 3 * E.np2[k];
     ex_diag_scale(E.B(k), nj, nj, E.W(k), coef + E.np2[k], false, &t, st);
   }

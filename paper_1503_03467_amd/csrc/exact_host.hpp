@@ -13,6 +13,7 @@ namespace gbl {
 // Workspace offsets (bytes) of the exact hierarchy of depth q.
 struct ExactHier {
   int q = 0, geom = 0;
+  int wkind = 0;   // 0: Construction 4.13 (Helmert), 1: Construction 4.11 (differences)
   int nc = 0;   // cells per side
   int m = 0;    // interior nodes per side
   int nr = 1;   // right-hand sides per solve pass
@@ -21,7 +22,7 @@ struct ExactHier {
   size_t offA[kMaxLevels] = {}, offB[kMaxLevels] = {}, offBL[kMaxLevels] = {}, offD[kMaxLevels] = {},
          offR[kMaxLevels] = {};
   size_t offNch[kMaxLevels] = {}, offChild[kMaxLevels] = {}, offWc[kMaxLevels] = {}, offParent[kMaxLevels] = {},
-         offPos[kMaxLevels] = {};
+         offPos[kMaxLevels] = {}, offGinv[kMaxLevels] = {};
   size_t offG[kMaxLevels] = {}, offW[kMaxLevels] = {}, offU[kMaxLevels] = {};
   size_t offT = 0, offB0 = 0, offX = 0, offRes = 0, offDx = 0, offL1 = 0, offStatus = 0, offSel = 0, offThr = 0;
   size_t offDot = 0, offCoef = 0;   // offCoef: a copy of the cell coefficient [nc][nc]
@@ -39,7 +40,7 @@ struct ExactHier {
   double* U(int k) const { return at(offU[k]); }    // transform vectors [N_k]
 };
 
-int exact_layout(ExactHier& E, int q, int geom, int max_rhs, std::string& msg);
+int exact_layout(ExactHier& E, int q, int geom, int wkind, int max_rhs, std::string& msg);
 int exact_build(ExactHier& E, const double* a_dev, hipStream_t st, std::string& msg);
 int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u_nodal, int refine, hipStream_t st,
                 std::string& msg);

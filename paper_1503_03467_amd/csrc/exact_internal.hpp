@@ -38,6 +38,7 @@ void ex_diag(const double* M, long n, double* d, hipStream_t st);
 void ex_diag_scale(const double* M, long n, long ld, const double* in, double* out, bool inverse,
                    const ExLevelTables* t, hipStream_t st);
 void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStream_t st);
+void ex_gram_solve(const ExLevelTables& t, const double* gram_inv, double* w, hipStream_t st);
 void launch_ex_assemble(const double* a, int nc, double* A, int* status, hipStream_t st);
 
 }  // namespace gbl

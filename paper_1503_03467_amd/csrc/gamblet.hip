@@ -186,6 +186,11 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
     return GBL_EINVAL;
   }
   if (o->exact && o->precision != GBL_FP64) { msg = "the exact hierarchy is FP64"; return GBL_EINVAL; }
+  if (o->w_kind != 0 && o->w_kind != 1) { msg = "w_kind must be 0 or 1"; return GBL_EINVAL; }
+  if (o->w_kind == 1 && !o->exact) {
+    msg = "w_kind 1 (Construction 4.11) needs the exact hierarchy: the localized kernels use the orthonormal rows";
+    return GBL_EINVAL;
+  }
   if (!(o->window_tol >= 0.0) || !(o->window_tol < 1e300)) {
     msg = "window_tol must be finite and >= 0";
     return GBL_EINVAL;
@@ -1171,6 +1176,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->exact = 0;
   o->geometry = 0;
   o->source = 0;
+  o->w_kind = 0;
   return GBL_OK;
 }
 
@@ -1180,7 +1186,7 @@ int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes) {
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->geometry, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->geometry, opts->w_kind, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     *bytes = E.total;
     return GBL_OK;
@@ -1202,7 +1208,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->geometry, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->geometry, opts->w_kind, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     if (ws_bytes < E.total)
       return fail(nullptr, GBL_ENOMEM, "workspace too small: need " + std::to_string(E.total) + " bytes");

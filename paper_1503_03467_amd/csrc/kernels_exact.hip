@@ -499,6 +499,21 @@ void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStre
   hipLaunchKernelGGL(k_ex_child_sum, dim3((t.np2 + 255) / 256), dim3(256), 0, st, t, in, out);
 }
 
+// w[t][p] <- sum_u G_p^-1[t][u] w[u][p], G_p = W_p W_p^T per parent (3 x 3)
+__global__ void k_ex_gram_solve(int np2, const double* __restrict__ gi, double* __restrict__ w) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np2) return;
+  const double a = w[p], b = w[np2 + p], c = w[2 * (size_t)np2 + p];
+  const double* g = gi + (size_t)p * 9;
+  w[p] = g[0] * a + g[1] * b + g[2] * c;
+  w[np2 + p] = g[3] * a + g[4] * b + g[5] * c;
+  w[2 * (size_t)np2 + p] = g[6] * a + g[7] * b + g[8] * c;
+}
+
+void ex_gram_solve(const ExLevelTables& t, const double* gram_inv, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_ex_gram_solve, dim3((t.np2 + 255) / 256), dim3(256), 0, st, t.np2, gram_inv, w);
+}
+
 }  // namespace gbl
 
 namespace gbl {

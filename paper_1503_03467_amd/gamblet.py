@@ -28,7 +28,7 @@ class GblOpts(ctypes.Structure):
                 ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
                 ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double), ("exact", ctypes.c_int),
-                ("geometry", ctypes.c_int), ("source", ctypes.c_int)]
+                ("geometry", ctypes.c_int), ("source", ctypes.c_int), ("w_kind", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -116,7 +116,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
               level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0, exact: bool = False,
-              geometry: int = 0, source: str = "cell") -> GblOpts:
+              geometry: int = 0, source: str = "cell", w_kind: int = 0) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -140,6 +140,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.exact = 1 if exact else 0
     o.geometry = int(geometry)
     o.source = SOURCES[source]
+    o.w_kind = int(w_kind)
     return o
 
 
@@ -179,7 +180,8 @@ class Hierarchy:
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
                  kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0,
-                 window_tol: float = 0.0, exact: bool = False, geometry: int = 0, source: str = "cell"):
+                 window_tol: float = 0.0, exact: bool = False, geometry: int = 0, source: str = "cell",
+                 w_kind: int = 0):
         n = a.shape[0]
         q = (n - geometry).bit_length() - 1
         if n - geometry != (1 << q) or q < 2:
@@ -190,7 +192,7 @@ class Hierarchy:
         self.source = source
         self.opts = make_opts(rho, "fp64" if exact else precision, rtol, max_outer, inner_iters, max_rhs,
                               inner_iters_coarse, inner, kappa, kappa_coarse, level_q_mass, rho_coarse, window_tol,
-                              exact, geometry, source)
+                              exact, geometry, source, w_kind)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):

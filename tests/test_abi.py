@@ -168,7 +168,10 @@ def test_exact_options_validated():
     o = P.make_opts(precision="fp64", exact=True)
     assert L.gbl_workspace_bytes(8, ctypes.byref(o), ctypes.byref(sz)) == -1
     assert b"q <= 7" in L.gbl_last_error(None)
-    for field, value in (("exact", 2), ("geometry", 2), ("source", 2)):
+    assert L.gbl_workspace_bytes(6, ctypes.byref(P.make_opts(precision="fp64", w_kind=1)), ctypes.byref(sz)) == -1
+    assert b"Construction 4.11" in L.gbl_last_error(None)
+    assert P.workspace_bytes(6, P.make_opts(precision="fp64", exact=True, w_kind=1)) > 0
+    for field, value in (("exact", 2), ("geometry", 2), ("source", 2), ("w_kind", 2)):
         o = P.make_opts(precision="fp64", exact=True)
         setattr(o, field, value)
         assert L.gbl_workspace_bytes(6, ctypes.byref(o), ctypes.byref(sz)) == -1

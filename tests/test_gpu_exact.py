@@ -107,6 +107,48 @@ def test_exact_level_matrices_match_oracle(q, geometry):
     H.close()
 
 
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_exact_construction_4_11(geometry):
+    """W from the differences of Construction 4.11: B^(k) and the transform
+    coefficients follow the oracle built with that construction (1e-10), while
+    A^(k), R and the solve equal those of Construction 4.13 (they do not
+    depend on the choice of W)."""
+    q = 4
+    _case(test="exact_construction_4_11", q=q, geometry=geometry)
+    a = _coefficient(q, geometry, 801)
+    fe = fem.assemble(a)
+    tree = G.Tree(q, offset=geometry)
+    h1 = G.exact_hierarchy(fe.A, tree, construction=1)
+    H1 = _P().Hierarchy(_dev(a), exact=True, geometry=geometry, w_kind=1)
+    H2 = _P().Hierarchy(_dev(a), exact=True, geometry=geometry)
+    for k in range(q, 1, -1):
+        l1, l2 = H1.level(k), H2.level(k)
+        assert _maxrel(l1["A"].cpu().numpy(), h1.levels[k].A) < 1e-10
+        assert _maxrel(l1["R"].cpu().numpy(), l2["R"].cpu().numpy()) < 1e-10
+        B = l1["B"].cpu().numpy()
+        m = subband_map(tree, k)
+        real = np.flatnonzero(m >= 0)
+        Bo = np.zeros_like(h1.levels[k].B)
+        Bo[np.ix_(m[real], m[real])] = B[np.ix_(real, real)]
+        assert _maxrel(Bo, h1.levels[k].B) < 1e-10, k
+    n = (1 << q) + geometry
+    g = S.rng(802).standard_normal((n, n))
+    u1, u2 = H1.solve(_dev(g)), H2.solve(_dev(g))
+    assert _rel(u1.cpu().numpy(), u2.cpu().numpy()) < 1e-12
+    uref = fem.DirectSolver(fe.A).solve(fem.load_cellwise(g, fe.h))
+    c1_ref, ck_ref = G.normalized_coefficients(h1, uref)
+    c = H1.transform(_dev(_nodal(fe, uref)))
+    c1, ck, pads = _gpu_to_oracle(c.cpu().numpy(), tree, q)
+    assert not np.any(pads)
+    allg = np.concatenate([c1] + [ck[k] for k in sorted(ck)])
+    allr = np.concatenate([c1_ref] + [ck_ref[k] for k in sorted(ck_ref)])
+    assert _rel(allg, allr) < 1e-10
+    back = H1.inverse_transform(c).cpu().numpy().ravel()[fe.interior]
+    assert _rel(back, uref) < 1e-12
+    H1.close()
+    H2.close()
+
+
 @pytest.mark.parametrize("q,geometry,source", [(4, 0, "cell"), (6, 0, "cell"), (5, 1, "cell"), (6, 1, "nodal"),
                                                  (7, 0, "cell")])
 def test_exact_solve_matches_direct(q, geometry, source):
@@ -208,6 +250,21 @@ def test_exact_transform_and_compression_match_oracle(geometry):
         assert abs(e - e_ref) <= 1e-8 * max(e_ref, 1e-3)
         errs.append(e)
     assert errs[0] > errs[1] > errs[2]
+    H.close()
+
+
+def test_exact_source_constant_on_level_one_cells_lives_in_psi1():
+    """g = 1 on the 64 x 64 exact workload: the load b = h^2 (1, ..., 1) is a sum
+    of level-1 measurement functions, so the solution is the level-1 gamblet
+    part alone (Theorem 4.6 / the conditional-expectation reading of Section
+    3: u^(1) = u when b lies in the range of the level-1 aggregation): every
+    subband coefficient of levels 2..q vanishes to rounding."""
+    _case(test="exact_level1_source")
+    pr = S.q6_exact_problem()
+    H = _P().Hierarchy(_dev(pr.a), exact=True)
+    u = H.solve(_dev(pr.g[0]))
+    c = H.transform(u).cpu().numpy()
+    assert np.linalg.norm(c[4:]) <= 1e-12 * np.linalg.norm(c[:4])
     H.close()
 
 
