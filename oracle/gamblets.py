@@ -145,6 +145,43 @@ class Tree:
         return np.flatnonzero((d[:, 0] <= rho) & (d[:, 1] <= rho))
 
 
+@dataclass
+class Tree3(Tree):
+    """The same index tree on the unit cube (the problem of Section 1 in d = 3):
+    level q indexes the interior nodes (order of ``oracle.fem3d``), levels
+    k < q the dyadic cubes (index (cx 2^k + cy) 2^k + cz); node (i, j, l)
+    belongs to level-(q-1) cube ((i - offset) // 2, ...), a cube to its
+    parent by halving every coordinate.  A parent has up to eight children,
+    ordered by t = 4 dx + 2 dy + dz."""
+
+    def __post_init__(self):
+        q = self.q
+        n = (1 << q) + self.offset
+        self.n_cells = n
+        i = np.arange(1, n)
+        I, J, L = np.meshgrid(i, i, i, indexing="ij")
+        self.coords[q] = np.stack([I.ravel(), J.ravel(), L.ravel()], axis=1) - self.offset
+        for k in range(q - 1, 0, -1):
+            c = np.arange(1 << k)
+            X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+            self.coords[k] = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+        for k in range(q, 1, -1):
+            c = self.coords[k]
+            side = 1 << (k - 1)
+            par = ((c[:, 0] // 2) * side + (c[:, 1] // 2)) * side + (c[:, 2] // 2)
+            self.parent[k] = par
+            t = 4 * (c[:, 0] % 2) + 2 * (c[:, 1] % 2) + (c[:, 2] % 2)
+            kids = [[] for _ in range(side ** 3)]
+            for idx in np.lexsort((t, par)):
+                kids[par[idx]].append(int(idx))
+            self.children[k] = kids
+
+    def box(self, k: int, i: int, rho: int) -> np.ndarray:
+        c = self.coords[k]
+        d = np.abs(c - c[i])
+        return np.flatnonzero((d[:, 0] <= rho) & (d[:, 1] <= rho) & (d[:, 2] <= rho))
+
+
 # ----------------------------------------------------------------------------
 # Exact gamblet transform (Algorithm 1 with psi^(q) = nodal basis).
 # ----------------------------------------------------------------------------
