@@ -139,6 +139,12 @@ typedef struct gbl_opts {
                          Construction 4.13; 1 (exact only) the differences e_t - e_{t+1} of Construction 4.11.
                          A^(k), R and the solve do not depend on it; B^(k) and the transform coefficients do
                          (the transform then applies (W W^T)^-1 per parent) */
+  int dim;            /* space dimension: 2 (default) or 3 (exact only, 2 <= q <= 4: the problem on the unit cube
+                         with trilinear elements, 2^q (geometry 0) or 2^q + 1 (geometry 1) cells per side, eight
+                         children per parent and seven subband rows).  In 3-D every array gains a third index
+                         of the same extent: a_dev [n][n][n], g_dev [nrhs][n][n][n] (nodal: [n-1]^3), u_dev
+                         [nrhs][n+1]^3, node (i, j, l) -> ((i-1) m + (j-1)) m + (l-1) on level q, 8^q
+                         transform coefficients */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -175,7 +181,7 @@ typedef struct gbl_level_desc {
                          unknowns are the interior nodes (i - 1) m + (j - 1), level-k < q unknowns the cells
                          x 2^k + y.  0 for the localized hierarchy (the stencil layouts above) */
   int n;              /* unknowns of level k (dense only) */
-  int nsub;           /* subband rows of level k, three per parent (dense only) */
+  int nsub;           /* subband rows of level k, 2^dim - 1 per parent (dense only) */
 } gbl_level_desc;
 
 typedef struct gbl_ctx gbl_ctx;
@@ -186,7 +192,7 @@ int gbl_version(void);
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
  * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0, exact 0, geometry 0,
- * source 0, w_kind 0. */
+ * source 0, w_kind 0, dim 2. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

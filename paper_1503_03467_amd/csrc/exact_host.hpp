@@ -13,6 +13,12 @@ namespace gbl {
 // Workspace offsets (bytes) of the exact hierarchy of depth q.
 struct ExactHier {
   int q = 0, geom = 0;
+  int dim = 2;     // 2 or 3
+  int cp = 4;      // child slots per parent, 2^dim
+  int rp = 3;      // subband rows per parent, 2^dim - 1
+  long ncells = 0; // nc^dim
+  long nnodes = 0; // (nc + 1)^dim
+  long ncoef = 0;  // coefficients of the transform, 2^(dim q)
   int wkind = 0;   // 0: Construction 4.13 (Helmert), 1: Construction 4.11 (differences)
   int nc = 0;   // cells per side
   int m = 0;    // interior nodes per side
@@ -31,16 +37,16 @@ struct ExactHier {
 
   double* at(size_t off) const { return reinterpret_cast<double*>(ws + off); }
   double* A(int k) const { return at(offA[k]); }    // A^(k), N_k x N_k
-  double* B(int k) const { return at(offB[k]); }    // B^(k) = W A^(k) W^T, 3 np2 x 3 np2
+  double* B(int k) const { return at(offB[k]); }    // B^(k) = W A^(k) W^T, rp np2 x rp np2
   double* BL(int k) const { return at(offBL[k]); }  // its Cholesky factor (lower)
-  double* D(int k) const { return at(offD[k]); }    // D^(k,k-1), 3 np2 x np2
+  double* D(int k) const { return at(offD[k]); }    // D^(k,k-1), rp np2 x np2
   double* R(int k) const { return at(offR[k]); }    // R^(k-1,k), np2 x N_k
   double* G(int k) const { return at(offG[k]); }    // level-k solve vectors [N_k][nr]
-  double* W(int k) const { return at(offW[k]); }    // subband vectors [3 np2][nr]
+  double* W(int k) const { return at(offW[k]); }    // subband vectors [rp np2][nr]
   double* U(int k) const { return at(offU[k]); }    // transform vectors [N_k]
 };
 
-int exact_layout(ExactHier& E, int q, int geom, int wkind, int max_rhs, std::string& msg);
+int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs, std::string& msg);
 int exact_build(ExactHier& E, const double* a_dev, hipStream_t st, std::string& msg);
 int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u_nodal, int refine, hipStream_t st,
                 std::string& msg);

@@ -13,9 +13,11 @@ namespace gbl {
 // Tree tables of the transition from level k to level k - 1 (device pointers).
 struct ExLevelTables {
   int np2 = 0;                  // parents (level k-1 unknowns)
+  int cp = 4;                   // child slots per parent: 2^d
+  int rp = 3;                   // subband rows per parent: 2^d - 1
   const int* nch = nullptr;     // [np2] child counts m_p
-  const int* child = nullptr;   // [np2][4] level-k index of the child at position d (by t), -1 past m_p
-  const double* wc = nullptr;   // [np2][3][4] Helmert row t of parent p over its child positions
+  const int* child = nullptr;   // [np2][cp] level-k index of the child at position d (by t), -1 past m_p
+  const double* wc = nullptr;   // [np2][rp][cp] row t of W over parent p's child positions
   const int* parent = nullptr;  // [N_k] parent of a level-k unknown
   const int* pos = nullptr;     // [N_k] its position among the parent's children
 };
@@ -40,5 +42,9 @@ void ex_diag_scale(const double* M, long n, long ld, const double* in, double* o
 void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStream_t st);
 void ex_gram_solve(const ExLevelTables& t, const double* gram_inv, double* w, hipStream_t st);
 void launch_ex_assemble(const double* a, int nc, double* A, int* status, hipStream_t st);
+void launch_ex_assemble3(const double* a, int nc, double* A, int* status, hipStream_t st);
+void ex_load3(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
+              hipStream_t st);
+void ex_to_nodal3(int nc, const double* x, int nrhs, double* u, bool back, hipStream_t st);
 
 }  // namespace gbl

@@ -187,6 +187,8 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   }
   if (o->exact && o->precision != GBL_FP64) { msg = "the exact hierarchy is FP64"; return GBL_EINVAL; }
   if (o->w_kind != 0 && o->w_kind != 1) { msg = "w_kind must be 0 or 1"; return GBL_EINVAL; }
+  if (o->dim != 2 && o->dim != 3) { msg = "dim must be 2 or 3"; return GBL_EINVAL; }
+  if (o->dim == 3 && !o->exact) { msg = "dim 3 needs the exact hierarchy (exact = 1)"; return GBL_EINVAL; }
   if (o->w_kind == 1 && !o->exact) {
     msg = "w_kind 1 (Construction 4.11) needs the exact hierarchy: the localized kernels use the orthonormal rows";
     return GBL_EINVAL;
@@ -1177,6 +1179,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->geometry = 0;
   o->source = 0;
   o->w_kind = 0;
+  o->dim = 2;
   return GBL_OK;
 }
 
@@ -1186,7 +1189,7 @@ int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes) {
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->geometry, opts->w_kind, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     *bytes = E.total;
     return GBL_OK;
@@ -1208,7 +1211,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->geometry, opts->w_kind, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     if (ws_bytes < E.total)
       return fail(nullptr, GBL_ENOMEM, "workspace too small: need " + std::to_string(E.total) + " bytes");
@@ -1555,7 +1558,7 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
     d->k = k;
     d->dense = 1;
     d->n = (int)E.N[k];
-    d->nsub = k >= 2 ? 3 * E.np2[k] : 0;
+    d->nsub = k >= 2 ? E.rp * E.np2[k] : 0;
     d->nk = k == c->L.q ? E.m : (1 << k);
     d->elem_bytes = 8;
     d->A = E.A(k);
@@ -1612,7 +1615,7 @@ int gbl_profile_read(int kernel, double* total_ms, long* launches) {
 
 int gbl_transform_size(const gbl_ctx* c, size_t* count) {
   if (!c || !count) return fail(nullptr, GBL_EINVAL, "ctx or count is NULL");
-  *count = (size_t)1 << (2 * c->L.q);
+  *count = c->ex ? (size_t)c->ex->ncoef : (size_t)1 << (2 * c->L.q);
   return GBL_OK;
 }
 
@@ -1645,7 +1648,7 @@ int gbl_compress(gbl_ctx* c, double* coef_dev, long keep, double* threshold, voi
   if (!c) return fail(nullptr, GBL_EINVAL, "ctx is NULL");
   if (!coef_dev) return fail(c, GBL_EINVAL, "coef must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const long n = (long)1 << (2 * c->L.q);
+  const long n = c->ex ? c->ex->ncoef : (long)1 << (2 * c->L.q);
   double* thr = c->ex ? c->ex->at(c->ex->offThr) : c->oscal() + kSSpare;   // device scalar
   if (keep <= 0) {
     launch_fill((size_t)n, 0.0, coef_dev, s);

@@ -243,11 +243,12 @@ __global__ void k_ex_assemble(const double* __restrict__ a, int nc, double* __re
   put(-1, 1, -a01 / 3.0);
 }
 
-// B = W A W^T over the 3 np2 subband rows (identity rows for rows a parent
-// lacks) and C = -W A pibar^T (3 np2 x np2), one thread per entry.
+// B = W A W^T over the rp np2 subband rows (identity rows for rows a parent
+// lacks) and C = -W A pibar^T (rp np2 x np2), one thread per entry.
 __global__ void k_ex_subband(const double* __restrict__ A, long N, ExLevelTables t, double* __restrict__ B,
                              double* __restrict__ C) {
-  const long nj = 3L * t.np2;
+  const int cp = t.cp, rp = t.rp;
+  const long nj = (long)rp * t.np2;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nB = nj * nj;
   if (id < nB) {
@@ -258,14 +259,14 @@ __global__ void k_ex_subband(const double* __restrict__ A, long N, ExLevelTables
     if (!rr || !rs) {
       v = (r == s) ? 1.0 : 0.0;
     } else {
-      for (int d = 0; d < 4; ++d) {
-        const double wr = t.wc[(pr * 3 + tr) * 4 + d];
+      for (int d = 0; d < cp; ++d) {
+        const double wr = t.wc[((long)pr * rp + tr) * cp + d];
         if (wr == 0.0) continue;
-        const long cr = t.child[pr * 4 + d];
-        for (int e = 0; e < 4; ++e) {
-          const double ws = t.wc[(ps * 3 + ts) * 4 + e];
+        const long cr = t.child[(long)pr * cp + d];
+        for (int e = 0; e < cp; ++e) {
+          const double ws = t.wc[((long)ps * rp + ts) * cp + e];
           if (ws == 0.0) continue;
-          v += wr * ws * A[cr * N + t.child[ps * 4 + e]];
+          v += wr * ws * A[cr * N + t.child[(long)ps * cp + e]];
         }
       }
     }
@@ -278,12 +279,12 @@ __global__ void k_ex_subband(const double* __restrict__ A, long N, ExLevelTables
   const int tr = r / t.np2, pr = r % t.np2;
   double v = 0.0;
   if (tr < t.nch[pr] - 1) {
-    for (int d = 0; d < 4; ++d) {
-      const double wr = t.wc[(pr * 3 + tr) * 4 + d];
+    for (int d = 0; d < cp; ++d) {
+      const double wr = t.wc[((long)pr * rp + tr) * cp + d];
       if (wr == 0.0) continue;
-      const long cr = t.child[pr * 4 + d];
-      for (int e = 0; e < 4; ++e) {
-        const int ce = t.child[c * 4 + e];
+      const long cr = t.child[(long)pr * cp + d];
+      for (int e = 0; e < cp; ++e) {
+        const int ce = t.child[(long)c * cp + e];
         if (ce < 0) continue;
         v += wr * A[cr * N + ce] / (double)t.nch[c];
       }
@@ -300,21 +301,143 @@ __global__ void k_ex_restriction(const double* __restrict__ D, ExLevelTables t, 
   const int b = (int)(id % N);
   const int pb = t.parent[b], db = t.pos[b];
   double v = (pb == c) ? 1.0 / (double)t.nch[c] : 0.0;
-  for (int tt = 0; tt < 3; ++tt) {
-    const double w = t.wc[(pb * 3 + tt) * 4 + db];
-    if (w != 0.0) v += D[(long)(tt * t.np2 + pb) * t.np2 + c] * w;
+  for (int tt = 0; tt < t.rp; ++tt) {
+    const double w = t.wc[((long)pb * t.rp + tt) * t.cp + db];
+    if (w != 0.0) v += D[((long)tt * t.np2 + pb) * t.np2 + c] * w;
   }
   R[id] = v;
 }
 
 void ex_level_operators(const double* A, long N, const ExLevelTables& t, double* B, double* C, hipStream_t st) {
-  const long tot = 9L * t.np2 * t.np2 + 3L * t.np2 * t.np2;
+  const long tot = ((long)t.rp * t.rp + t.rp) * t.np2 * t.np2;
   hipLaunchKernelGGL(k_ex_subband, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, N, t, B, C);
 }
 
 void ex_restriction(const double* D, const ExLevelTables& t, long N, double* R, hipStream_t st) {
   const long tot = (long)t.np2 * N;
   hipLaunchKernelGGL(k_ex_restriction, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, t, N, R);
+}
+
+// Entry (li, lj) of the trilinear element stiffness of a unit cube, local
+// node index 4 dx + 2 dy + dz: the gradient of a product of 1-D hats splits
+// into three products of 1-D stiffness (k: 1 on, -1 off the diagonal) and
+// mass (m: 2/6 on, 1/6 off) entries.
+__device__ __forceinline__ double k_unit3(int li, int lj) {
+  const int dx = li >> 2, dy = (li >> 1) & 1, dz = li & 1;
+  const int ex = lj >> 2, ey = (lj >> 1) & 1, ez = lj & 1;
+  const double kx = dx == ex ? 1.0 : -1.0, ky = dy == ey ? 1.0 : -1.0, kz = dz == ez ? 1.0 : -1.0;
+  const double mx = (dx == ex ? 2.0 : 1.0) / 6.0, my = (dy == ey ? 2.0 : 1.0) / 6.0, mz = (dz == ez ? 2.0 : 1.0) / 6.0;
+  return kx * my * mz + mx * ky * mz + mx * my * kz;
+}
+
+// Dense trilinear stiffness over the interior nodes of an nc^3 cell grid
+// (m = nc - 1 nodes per side, node (i, j, l) -> ((i-1) m + (j-1)) m + (l-1)),
+// one thread per node row: the eight cells around the node, each adding
+// h a_e K_unit3 to the entries of its interior corners.
+__global__ void k_ex_assemble3(const double* __restrict__ a, int nc, double* __restrict__ A,
+                               int* __restrict__ status) {
+  const int m = nc - 1;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = (long)m * m * m;
+  if (id >= N) return;
+  const int i = (int)(id / ((long)m * m)) + 1, j = (int)((id / m) % m) + 1, l = (int)(id % m) + 1;
+  const double h = 1.0 / nc;
+  double* row = A + id * N;
+  for (int c = 0; c < 8; ++c) {
+    const int cx = i - 1 + (c >> 2), cy = j - 1 + ((c >> 1) & 1), cz = l - 1 + (c & 1);   // cell
+    const double ae = a[((long)cx * nc + cy) * nc + cz];
+    if (!(ae > 0.0) || !isfinite(ae)) atomicOr(status, kBadCoefficient);
+    const int li = ((i - cx) << 2) | ((j - cy) << 1) | (l - cz);   // the node inside the cell
+    for (int lj = 0; lj < 8; ++lj) {
+      const int ii = cx + (lj >> 2), jj = cy + ((lj >> 1) & 1), ll = cz + (lj & 1);
+      if (ii < 1 || jj < 1 || ll < 1 || ii > m || jj > m || ll > m) continue;
+      row[((long)(ii - 1) * m + (jj - 1)) * m + (ll - 1)] += h * ae * k_unit3(li, lj);
+    }
+  }
+}
+
+// 3-D load: mode 0 cell source ((h^3 / 8) sum of the eight cells), mode 1
+// nodal source on the interior nodes (trilinear mass M g: (h/6)^3 times the
+// product of the 1-D weights 4 (same) and 1 (neighbour)); then the Dirichlet
+// values of u (boundary entries of [nrhs][nc+1]^3) moved to the right-hand side.
+__global__ void k_ex_load3(int nc, int mode, const double* __restrict__ src, const double* __restrict__ a,
+                           const double* __restrict__ u, int nrhs, double* __restrict__ b) {
+  const int m = nc - 1;
+  const long M3 = (long)m * m * m;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= M3 * nrhs) return;
+  const long node = id / nrhs;
+  const int c = (int)(id % nrhs);
+  const int i = (int)(node / ((long)m * m)) + 1, j = (int)((node / m) % m) + 1, l = (int)(node % m) + 1;
+  const double h = 1.0 / nc;
+  double v = 0.0;
+  if (mode == 0) {
+    const double* g = src + (long)c * nc * nc * nc;
+    for (int e = 0; e < 8; ++e) {
+      const int cx = i - 1 + (e >> 2), cy = j - 1 + ((e >> 1) & 1), cz = l - 1 + (e & 1);
+      v += g[((long)cx * nc + cy) * nc + cz];
+    }
+    v *= h * h * h / 8.0;
+  } else {
+    const double* g = src + (long)c * M3;
+    for (int di = -1; di <= 1; ++di)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int dl = -1; dl <= 1; ++dl) {
+          const int ii = i + di, jj = j + dj, ll = l + dl;
+          if (ii < 1 || jj < 1 || ll < 1 || ii > m || jj > m || ll > m) continue;
+          const double w = (di == 0 ? 4.0 : 1.0) * (dj == 0 ? 4.0 : 1.0) * (dl == 0 ? 4.0 : 1.0);
+          v += w * g[((long)(ii - 1) * m + (jj - 1)) * m + (ll - 1)];
+        }
+    v *= h * h * h / 216.0;
+  }
+  if (i == 1 || j == 1 || l == 1 || i == m || j == m || l == m) {
+    const double* uc = u + (long)c * (nc + 1) * (nc + 1) * (nc + 1);
+    for (int e = 0; e < 8; ++e) {
+      const int cx = i - 1 + (e >> 2), cy = j - 1 + ((e >> 1) & 1), cz = l - 1 + (e & 1);
+      const double ae = a[((long)cx * nc + cy) * nc + cz];
+      const int li = ((i - cx) << 2) | ((j - cy) << 1) | (l - cz);
+      for (int lj = 0; lj < 8; ++lj) {
+        const int ii = cx + (lj >> 2), jj = cy + ((lj >> 1) & 1), ll = cz + (lj & 1);
+        if (!(ii == 0 || jj == 0 || ll == 0 || ii == nc || jj == nc || ll == nc)) continue;
+        v -= h * ae * k_unit3(li, lj) * uc[((long)ii * (nc + 1) + jj) * (nc + 1) + ll];
+      }
+    }
+  }
+  b[id] = v;
+}
+
+// nodal [nrhs][(nc+1)^3] arrays and interior vectors x [N][nrhs]
+__global__ void k_ex_to_nodal3(int nc, double* __restrict__ x, int nrhs, double* __restrict__ u, int back) {
+  const int m = nc - 1;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long)m * m * m * nrhs) return;
+  const long node = id / nrhs;
+  const int c = (int)(id % nrhs);
+  const int i = (int)(node / ((long)m * m)) + 1, j = (int)((node / m) % m) + 1, l = (int)(node % m) + 1;
+  const long s = nc + 1;
+  double* uu = u + (long)c * s * s * s + ((long)i * s + j) * s + l;
+  if (back) x[id] = *uu;
+  else *uu = x[id];
+}
+
+void launch_ex_assemble3(const double* a, int nc, double* A, int* status, hipStream_t st) {
+  const long m = nc - 1;
+  hipLaunchKernelGGL(k_ex_assemble3, dim3((unsigned)((m * m * m + 255) / 256)), dim3(256), 0, st, a, nc, A, status);
+}
+
+void ex_load3(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
+              hipStream_t st) {
+  const long m = nc - 1;
+  const long tot = m * m * m * nrhs;
+  hipLaunchKernelGGL(k_ex_load3, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nc, mode, src, a, u, nrhs,
+                     b);
+}
+
+void ex_to_nodal3(int nc, const double* x, int nrhs, double* u, bool back, hipStream_t st) {
+  const long m = nc - 1;
+  const long tot = m * m * m * nrhs;
+  hipLaunchKernelGGL(k_ex_to_nodal3, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nc,
+                     const_cast<double*>(x), nrhs, u, back ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,20 +500,20 @@ void ex_load(int nc, int mode, const double* src, const double* a, const double*
 // y[J][c] = (W g)[J][c] (zero on the rows a parent lacks); g is level-k [N][nrhs]
 __global__ void k_ex_wapply(ExLevelTables t, const double* __restrict__ g, int nrhs, double* __restrict__ y) {
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 3L * t.np2 * nrhs) return;
+  if (id >= (long)t.rp * t.np2 * nrhs) return;
   const int r = (int)(id / nrhs), c = (int)(id % nrhs);
   const int tr = r / t.np2, pr = r % t.np2;
   double v = 0.0;
   if (tr < t.nch[pr] - 1)
-    for (int d = 0; d < 4; ++d) {
-      const double w = t.wc[(pr * 3 + tr) * 4 + d];
-      if (w != 0.0) v += w * g[(long)t.child[pr * 4 + d] * nrhs + c];
+    for (int d = 0; d < t.cp; ++d) {
+      const double w = t.wc[((long)pr * t.rp + tr) * t.cp + d];
+      if (w != 0.0) v += w * g[(long)t.child[(long)pr * t.cp + d] * nrhs + c];
     }
   y[id] = v;
 }
 
 void ex_wapply(const ExLevelTables& t, const double* g, int nrhs, double* y, hipStream_t st) {
-  const long tot = 3L * t.np2 * nrhs;
+  const long tot = (long)t.rp * t.np2 * nrhs;
   hipLaunchKernelGGL(k_ex_wapply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, t, g, nrhs, y);
 }
 
@@ -401,9 +524,9 @@ __global__ void k_ex_wtadd(ExLevelTables t, long N, const double* __restrict__ w
   const int b = (int)(id / nrhs), c = (int)(id % nrhs);
   const int pb = t.parent[b], db = t.pos[b];
   double acc = 0.0;
-  for (int tt = 0; tt < 3; ++tt) {
-    const double wc = t.wc[(pb * 3 + tt) * 4 + db];
-    if (wc != 0.0) acc += wc * w[(long)(tt * t.np2 + pb) * nrhs + c];
+  for (int tt = 0; tt < t.rp; ++tt) {
+    const double wc = t.wc[((long)pb * t.rp + tt) * t.cp + db];
+    if (wc != 0.0) acc += wc * w[((long)tt * t.np2 + pb) * nrhs + c];
   }
   v[id] += acc;
 }
@@ -488,8 +611,8 @@ __global__ void k_ex_child_sum(ExLevelTables t, const double* __restrict__ in, d
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= t.np2) return;
   double v = 0.0;
-  for (int d = 0; d < 4; ++d) {
-    const int ch = t.child[c * 4 + d];
+  for (int d = 0; d < t.cp; ++d) {
+    const int ch = t.child[(long)c * t.cp + d];
     if (ch >= 0) v += in[ch];
   }
   out[c] = v;
@@ -499,19 +622,22 @@ void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStre
   hipLaunchKernelGGL(k_ex_child_sum, dim3((t.np2 + 255) / 256), dim3(256), 0, st, t, in, out);
 }
 
-// w[t][p] <- sum_u G_p^-1[t][u] w[u][p], G_p = W_p W_p^T per parent (3 x 3)
-__global__ void k_ex_gram_solve(int np2, const double* __restrict__ gi, double* __restrict__ w) {
+// w[t][p] <- sum_u G_p^-1[t][u] w[u][p], G_p = W_p W_p^T per parent (rp x rp, rp <= 7)
+__global__ void k_ex_gram_solve(int np2, int rp, const double* __restrict__ gi, double* __restrict__ w) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np2) return;
-  const double a = w[p], b = w[np2 + p], c = w[2 * (size_t)np2 + p];
-  const double* g = gi + (size_t)p * 9;
-  w[p] = g[0] * a + g[1] * b + g[2] * c;
-  w[np2 + p] = g[3] * a + g[4] * b + g[5] * c;
-  w[2 * (size_t)np2 + p] = g[6] * a + g[7] * b + g[8] * c;
+  double x[7];
+  for (int a = 0; a < rp; ++a) x[a] = w[(size_t)a * np2 + p];
+  const double* g = gi + (size_t)p * rp * rp;
+  for (int a = 0; a < rp; ++a) {
+    double v = 0.0;
+    for (int b = 0; b < rp; ++b) v += g[a * rp + b] * x[b];
+    w[(size_t)a * np2 + p] = v;
+  }
 }
 
 void ex_gram_solve(const ExLevelTables& t, const double* gram_inv, double* w, hipStream_t st) {
-  hipLaunchKernelGGL(k_ex_gram_solve, dim3((t.np2 + 255) / 256), dim3(256), 0, st, t.np2, gram_inv, w);
+  hipLaunchKernelGGL(k_ex_gram_solve, dim3((t.np2 + 255) / 256), dim3(256), 0, st, t.np2, t.rp, gram_inv, w);
 }
 
 }  // namespace gbl

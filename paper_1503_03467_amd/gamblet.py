@@ -28,7 +28,8 @@ class GblOpts(ctypes.Structure):
                 ("inner_iters_coarse", ctypes.c_int), ("inner_kind", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
                 ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double), ("exact", ctypes.c_int),
-                ("geometry", ctypes.c_int), ("source", ctypes.c_int), ("w_kind", ctypes.c_int)]
+                ("geometry", ctypes.c_int), ("source", ctypes.c_int), ("w_kind", ctypes.c_int),
+                ("dim", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -116,7 +117,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
               level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0, exact: bool = False,
-              geometry: int = 0, source: str = "cell", w_kind: int = 0) -> GblOpts:
+              geometry: int = 0, source: str = "cell", w_kind: int = 0, dim: int = 2) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -141,6 +142,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.geometry = int(geometry)
     o.source = SOURCES[source]
     o.w_kind = int(w_kind)
+    o.dim = int(dim)
     return o
 
 
@@ -174,7 +176,8 @@ class Hierarchy:
     (the default) or, with ``exact=True``, the dense FP64 hierarchy of
     Algorithm 1 (``geometry=1``: the mesh of Example 5.1, a of shape
     [2^q + 1][2^q + 1]; ``source="nodal"``: sources given at the interior
-    nodes and loaded with the mass matrix)."""
+    nodes and loaded with the mass matrix).  A three-dimensional ``a``
+    ([n][n][n]) selects the problem on the unit cube (exact hierarchy only)."""
 
     def __init__(self, a: torch.Tensor, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                  max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
@@ -184,15 +187,16 @@ class Hierarchy:
                  w_kind: int = 0):
         n = a.shape[0]
         q = (n - geometry).bit_length() - 1
-        if n - geometry != (1 << q) or q < 2:
-            raise ValueError("a must be [2^q][2^q] (geometry 0) or [2^q + 1][2^q + 1] (geometry 1) with q >= 2")
-        _require(a, (n, n), "a")
+        if n - geometry != (1 << q) or q < 2 or a.dim() not in (2, 3):
+            raise ValueError("a must be [2^q]^d (geometry 0) or [2^q + 1]^d (geometry 1), d = 2 or 3, q >= 2")
+        self.dim = a.dim()
+        _require(a, (n,) * self.dim, "a")
         self.q, self.n, self.device = q, n, a.device
         self.exact = bool(exact)
         self.source = source
         self.opts = make_opts(rho, "fp64" if exact else precision, rtol, max_outer, inner_iters, max_rhs,
                               inner_iters_coarse, inner, kappa, kappa_coarse, level_q_mass, rho_coarse, window_tol,
-                              exact, geometry, source, w_kind)
+                              exact, geometry, source, w_kind, self.dim)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -215,16 +219,17 @@ class Hierarchy:
     def solve(self, g: torch.Tensor, u_boundary: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
         """Solve for cell sources ``g`` ([n][n] or [nrhs][n][n]; nodal sources [n-1][n-1] when the
         hierarchy was built with ``source="nodal"``); returns nodal u ([.., n+1, n+1])."""
-        single = g.dim() == 2
+        d = self.dim
+        single = g.dim() == d
         gg = g.unsqueeze(0) if single else g
         nrhs = gg.shape[0]
         gs = self.n - 1 if self.source == "nodal" else self.n
-        _require(gg, (nrhs, gs, gs), "g")
+        _require(gg, (nrhs,) + (gs,) * d, "g")
         m = self.n + 1
         if u_boundary is None:
-            u = torch.zeros((nrhs, m, m), dtype=torch.float64, device=self.device)
+            u = torch.zeros((nrhs,) + (m,) * d, dtype=torch.float64, device=self.device)
         else:
-            u = u_boundary.reshape(-1, m, m).expand(nrhs, m, m).clone().contiguous()
+            u = u_boundary.reshape((-1,) + (m,) * d).expand((nrhs,) + (m,) * d).clone().contiguous()
         info = GblSolveInfo()
         with torch.cuda.device(self.device):
             code = lib().gbl_solve(self.ctx, nrhs, ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(u.data_ptr()),
@@ -272,9 +277,9 @@ class Hierarchy:
         return int(c.value)
 
     def transform(self, u: torch.Tensor) -> torch.Tensor:
-        """Normalized gamblet coefficients of a nodal u ([n+1, n+1] FP64; layout in ``gamblet.h``)."""
+        """Normalized gamblet coefficients of a nodal u ([n+1]^d FP64; layout in ``gamblet.h``)."""
         m = self.n + 1
-        _require(u, (m, m), "u")
+        _require(u, (m,) * self.dim, "u")
         c = torch.empty(self.transform_size(), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             _check(lib().gbl_transform(self.ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(c.data_ptr()),
@@ -282,10 +287,10 @@ class Hierarchy:
         return c
 
     def inverse_transform(self, c: torch.Tensor) -> torch.Tensor:
-        """Nodal u ([n+1, n+1], zero boundary) from normalized gamblet coefficients."""
+        """Nodal u ([n+1]^d, zero boundary) from normalized gamblet coefficients."""
         _require(c, (self.transform_size(),), "coefficients")
         m = self.n + 1
-        u = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        u = torch.empty((m,) * self.dim, dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             _check(lib().gbl_inverse_transform(self.ctx, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                                _stream_ptr(self.device)), self.ctx)
@@ -303,7 +308,7 @@ class Hierarchy:
     def energy_norm(self, u: torch.Tensor) -> float:
         """sqrt(u^T A u) of a nodal u with the FP64 fine stiffness matrix."""
         m = self.n + 1
-        _require(u, (m, m), "u")
+        _require(u, (m,) * self.dim, "u")
         out = ctypes.c_double(0.0)
         with torch.cuda.device(self.device):
             _check(lib().gbl_energy_norm(self.ctx, ctypes.c_void_p(u.data_ptr()), ctypes.byref(out),
@@ -326,7 +331,7 @@ class Hierarchy:
         if d.dense:
             out = {"k": d.k, "n": d.n, "nsub": d.nsub, "A": view(d.A, d.n * d.n).view(d.n, d.n)}
             if k >= 2:
-                npar = d.nsub // 3
+                npar = d.nsub // ((1 << self.dim) - 1)
                 out["B"] = view(d.B, d.nsub * d.nsub).view(d.nsub, d.nsub)
                 out["R"] = view(d.R, npar * d.n).view(npar, d.n)
             return out
@@ -481,7 +486,7 @@ def _adopt(ctx_value: int, q: int, ws: torch.Tensor, opts: GblOpts) -> Hierarchy
     h = Hierarchy.__new__(Hierarchy)
     h.q, h.n, h.device = q, 1 << q, ws.device
     h.opts, h.ws = opts, ws
-    h.exact, h.source = False, "cell"
+    h.exact, h.source, h.dim = False, "cell", 2
     h.ctx = ctypes.c_void_p(ctx_value)
     h.last_info = None
     return h

@@ -179,3 +179,17 @@ def test_exact_options_validated():
     g1 = P.workspace_bytes(6, P.make_opts(precision="fp64", exact=True, geometry=1))
     # the dense level-6 stiffness matrix alone: 3969^2 (geometry 0) and 4096^2 (geometry 1) doubles
     assert g0 > 3969 ** 2 * 8 and g1 > 4096 ** 2 * 8 and g1 > g0
+
+
+def test_three_dimensional_options_validated():
+    """dim 3 exists for the exact hierarchy only, up to q = 4 (16^3 cells)."""
+    P, L = _lib()
+    sz = ctypes.c_size_t()
+    assert L.gbl_workspace_bytes(3, ctypes.byref(P.make_opts(precision="fp64", dim=3)), ctypes.byref(sz)) == -1
+    assert L.gbl_workspace_bytes(3, ctypes.byref(P.make_opts(precision="fp64", exact=True, dim=4)),
+                                 ctypes.byref(sz)) == -1
+    assert L.gbl_workspace_bytes(5, ctypes.byref(P.make_opts(precision="fp64", exact=True, dim=3)),
+                                 ctypes.byref(sz)) == -1
+    assert b"q <= 4" in L.gbl_last_error(None)
+    # q = 4: the dense level-4 stiffness alone is 3375^2 doubles
+    assert P.workspace_bytes(4, P.make_opts(precision="fp64", exact=True, dim=3)) > 3375 ** 2 * 8
