@@ -712,6 +712,29 @@ def main():
         extras["gamblet_transform"] = tr
         H.close()
 
+        # the build kernels picked per level by timing (autotune), mixed and FP64:
+        # one build fills the table, then build + solve steps as above
+        print("# autotuned build kernels", file=sys.stderr, flush=True)
+        tuned = {}
+        for prec in ("mixed", "fp64"):
+            rt = args.rtol if prec == "mixed" else 1e-10
+            Ht = P.Hierarchy(a, rho=pr.rho, precision=prec, rtol=rt, autotune=True)
+            choices = {str(k): [Ht.level(k)["patch_kernel"], Ht.level(k)["galerkin_kernel"]] for k in range(2, q + 1)}
+            Ht.close()
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            nt = 5
+            for _ in range(nt):
+                Ht = P.Hierarchy(a, rho=pr.rho, precision=prec, rtol=rt, autotune=True)
+                ut = Ht.solve(g, check=False)
+                st_t = Ht.last_info.status
+                Ht.close()
+            torch.cuda.synchronize()
+            tuned[prec] = {"ms_per_step": (time.perf_counter() - tt) * 1e3 / nt, "status": st_t,
+                           "rel_err_vs_oracle": rel_err(ut),
+                           "choices_per_level_patch_galerkin": choices}
+        tuned["default_ms_per_step"] = {"mixed": ms_per_step, "fp64": extras.get("fp64_ms_per_step")}
+        extras["autotuned_build"] = tuned
         extras["exact_workloads"] = exact_workloads(P, S, torch, dev)
         if not args.no_cpu_baseline:
             print("# oracle localized build + solve on the host", file=sys.stderr, flush=True)

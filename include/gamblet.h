@@ -145,6 +145,16 @@ typedef struct gbl_opts {
                          of the same extent: a_dev [n][n][n], g_dev [nrhs][n][n][n] (nodal: [n-1]^3), u_dev
                          [nrhs][n+1]^3, node (i, j, l) -> ((i-1) m + (j-1)) m + (l-1) on level q, 8^q
                          transform coefficients */
+  int autotune;       /* 1: pick each level's build kernels by timing (dense patch solves on the vector units or
+                         the matrix cores; band patch solves of the finest level in LDS or in registers; Galerkin
+                         product per coarse row or on strips): the first build of a level shape times every
+                         applicable candidate (one warm-up and two timed launches each) and keeps the fastest per
+                         (device, precision, shape); later builds reuse it.  The build's result is the chosen
+                         kernel's, so two devices may pick differently and round differently.  0: the built-in
+                         rule (default) */
+  const char* autotune_path; /* autotune: file that keeps the choices across processes (read when first used,
+                         appended to; one line per choice with both candidates' times), or NULL for this
+                         process only.  The string must stay valid for the duration of gbl_build */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -182,6 +192,9 @@ typedef struct gbl_level_desc {
                          x 2^k + y.  0 for the localized hierarchy (the stencil layouts above) */
   int n;              /* unknowns of level k (dense only) */
   int nsub;           /* subband rows of level k, 2^dim - 1 per parent (dense only) */
+  int patch_kernel;   /* autotune: the variant that built level k's patch solves (dense: 0 vector units, 1 matrix
+                         cores; finest-level band: 0 LDS, 1 registers), else -1 (the built-in rule) */
+  int galerkin_kernel;/* autotune: the variant of A^(k-1) = R A^(k) R^T (0 per coarse row, 1 strips), else -1 */
 } gbl_level_desc;
 
 typedef struct gbl_ctx gbl_ctx;
@@ -192,7 +205,7 @@ int gbl_version(void);
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
  * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0, exact 0, geometry 0,
- * source 0, w_kind 0, dim 2. */
+ * source 0, w_kind 0, dim 2, autotune 0, autotune_path NULL. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgamblet.so")
 SOURCES = ["gamblet.hip", "kernels_build.hip", "kernels_solve.hip", "kernels_transform.hip",
            "kernels_level_q.hip",
-           "kernels_window.hip", "kernels_exact.hip", "exact.hip"]
+           "kernels_window.hip", "kernels_exact.hip", "exact.hip", "autotune.hip"]
 ARCH = os.environ.get("GBL_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -26,6 +26,7 @@
 #include "../../include/gamblet.h"
 #include "gamblet_internal.hpp"
 #include "solve_internal.hpp"
+#include "autotune.hpp"
 #include "exact_host.hpp"
 
 using namespace gbl;
@@ -189,6 +190,7 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   if (o->w_kind != 0 && o->w_kind != 1) { msg = "w_kind must be 0 or 1"; return GBL_EINVAL; }
   if (o->dim != 2 && o->dim != 3) { msg = "dim must be 2 or 3"; return GBL_EINVAL; }
   if (o->dim == 3 && !o->exact) { msg = "dim 3 needs the exact hierarchy (exact = 1)"; return GBL_EINVAL; }
+  if (o->autotune != 0 && o->autotune != 1) { msg = "autotune must be 0 or 1"; return GBL_EINVAL; }
   if (o->w_kind == 1 && !o->exact) {
     msg = "w_kind 1 (Construction 4.11) needs the exact hierarchy: the localized kernels use the orthonormal rows";
     return GBL_EINVAL;
@@ -393,6 +395,7 @@ struct gbl_ctx {
   bool diverged = false;                // the last solve produced a non-finite estimate or residual
   int nwin[kMaxLevels] = {};            // kept windows of the preconditioner per level
   ExactHier* ex = nullptr;              // the exact (dense) hierarchy when opts.exact
+  int tuned[kMaxLevels][2] = {};        // autotuned variants of the level's patch and Galerkin kernels
 
   // The arena in the scalar T: the build's own (FP64 or FP32), or with
   // MIXED_FP64_BUILD the FP32 copy the solve reads.
@@ -661,6 +664,54 @@ void make_cheb_tables(gbl_ctx* c) {
   }
 }
 
+// The variant of a build step to launch: kVariantDefault without autotuning;
+// with it, the recorded choice for this device, precision and level shape,
+// or (first time) the faster of the applicable candidates, each launched once
+// to warm up and twice under events on the build stream.  Every candidate
+// rewrites the same outputs from the same inputs, and the chosen one runs
+// again afterwards, so the build's result is the chosen kernel's; the status
+// word is restored around the trials.
+template <typename T, typename Launch, typename Ok>
+int tuned_variant(gbl_ctx* c, const std::string& key, Ok ok, Launch launch, hipStream_t st) {
+  if (!c->opts.autotune) return kVariantDefault;
+  const std::string path = c->opts.autotune_path ? c->opts.autotune_path : "";
+  const std::string full = tune_device_name() + (sizeof(T) == 8 ? ":f64:" : ":f32:") + key;
+  const int known = tune_lookup(path, full);
+  if (known >= 0 && ok(known)) return known;
+  double us[2] = {-1.0, -1.0};
+  int best = -1;
+  int saved = 0;
+  if (hipMemcpyAsync(&saved, c->status(), sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return kVariantDefault;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return kVariantDefault;
+  }
+  for (int v = 0; v < 2; ++v) {
+    if (!ok(v)) continue;
+    launch(v);
+    hipEventRecord(e0, st);
+    launch(v);
+    launch(v);
+    hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+    us[v] = 500.0 * ms;   // per launch
+    if (best < 0 || us[v] < us[best]) best = v;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  (void)hipGetLastError();
+  if (hipMemcpyAsync(c->status(), &saved, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return kVariantDefault;
+  if (best < 0) return kVariantDefault;
+  tune_store(path, full, best, us, 2);
+  return best;
+}
+
 template <typename T>
 int build_impl(gbl_ctx* c, hipStream_t st) {
   const Layout& L = c->L;
@@ -695,14 +746,31 @@ int build_impl(gbl_ctx* c, hipStream_t st) {
                             reinterpret_cast<unsigned*>(c->ws + L.wcnt_off) + k, c->status(), st);
     }
     {
-      ProfScope ps(fine && g.t == 1 && g.nk / 2 > 2 * g.rho + 1 ? GBL_PROF_PATCH_BAND : GBL_PROF_PATCH_SOLVE, st);
-      launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR),
-                            reinterpret_cast<T*>(c->ws + L.bp_off), fine, c->status(), st);
+      const int cls = patch_class(g, fine);
+      auto patch = [&](int v) {
+        launch_patch_solve<T>(g, c->hier<T>(g.offA), c->hier<T>(g.offB), c->hier<T>(g.offR),
+                              reinterpret_cast<T*>(c->ws + L.bp_off), fine, c->status(), st, v);
+      };
+      char key[160];
+      std::snprintf(key, sizeof key, "%s:nk%d:rho%d:s%d:t%d:fine%d:mass%d", cls == kKernelBand ? "band" : "patch",
+                    g.nk, g.rho, g.s, g.t, fine ? 1 : 0, L.mass);
+      const int pv = tuned_variant<T>(c, key, [&](int v) { return patch_variant_ok<T>(g, fine, v); }, patch, st);
+      if (c->opts.autotune) c->tuned[k][0] = pv;
+      ProfScope ps(cls == kKernelBand ? GBL_PROF_PATCH_BAND : GBL_PROF_PATCH_SOLVE, st);
+      patch(pv);
     }
     {
+      const LevelGeom& gc = L.lv[k - 1];
+      auto galerkin = [&](int v) {
+        launch_galerkin<T>(g, gc, c->hier<T>(g.offA), c->hier<T>(g.offR), c->hier<T>(gc.offA), st, v);
+      };
+      char key[160];
+      std::snprintf(key, sizeof key, "galerkin:nk%d:rho%d:s%d:sc%d", g.nk, g.rho, g.s, gc.s);
+      const int gv =
+          tuned_variant<T>(c, key, [&](int v) { return galerkin_variant_ok<T>(g, gc, v); }, galerkin, st);
+      if (c->opts.autotune) c->tuned[k][1] = gv;
       ProfScope ps(GBL_PROF_GALERKIN, st);
-      launch_galerkin<T>(g, L.lv[k - 1], c->hier<T>(g.offA), c->hier<T>(g.offR),
-                         c->hier<T>(L.lv[k - 1].offA), st);
+      galerkin(gv);
     }
   }
   launch_coarse_factor<T>(c->hier<T>(L.lv[1].offA), L.lv[1].s, c->L1(), c->status(), st);
@@ -1180,6 +1248,8 @@ int gbl_default_opts(gbl_opts* o) {
   o->source = 0;
   o->w_kind = 0;
   o->dim = 2;
+  o->autotune = 0;
+  o->autotune_path = nullptr;
   return GBL_OK;
 }
 
@@ -1564,6 +1634,8 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
     d->A = E.A(k);
     d->B = k >= 2 ? E.B(k) : nullptr;
     d->R = k >= 2 ? E.R(k) : nullptr;
+    d->patch_kernel = kVariantDefault;
+    d->galerkin_kernel = kVariantDefault;
     return GBL_OK;
   }
   const LevelGeom& g = c->L.lv[k];
@@ -1584,6 +1656,8 @@ int gbl_level_layout(const gbl_ctx* c, int k, gbl_level_desc* d) {
   d->dense = 0;
   d->n = 0;
   d->nsub = 0;
+  d->patch_kernel = (c->opts.autotune && k >= 2) ? c->tuned[k][0] : kVariantDefault;
+  d->galerkin_kernel = (c->opts.autotune && k >= 2) ? c->tuned[k][1] : kVariantDefault;
   return GBL_OK;
 }
 

@@ -60,13 +60,26 @@ void launch_subband_operator(const LevelGeom& L, const T* A, T* B, T* BJ, bool f
 template <typename T>
 void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out, hipStream_t st);
 // Bp: scratch of TT^2 * 9 * (nk/2)^2 T values for a parent-major copy of B^(k)
-// (read by the matrix-core kernel's patch gather)
+// (read by the matrix-core kernel's patch gather).
+// variant (a build-kernel choice, kVariantDefault: the built-in rule): for
+// the dense patch solves 0 = register-tiled, 1 = matrix cores; for the band
+// patch solves of level q 0 = LDS band, 1 = register band (two patches per
+// wavefront); for the Galerkin product 0 = one workgroup per coarse row,
+// 1 = strips of coarse rows.
+constexpr int kVariantDefault = -1;
+enum BuildKernelClass { kKernelPatch = 0, kKernelBand = 1, kKernelGalerkin = 2 };
+// candidates of a class at this level (0 when the class does not run here)
+int patch_class(const LevelGeom& L, bool fine);   // kKernelPatch or kKernelBand
+template <typename T>
+bool patch_variant_ok(const LevelGeom& L, bool fine, int variant);
+template <typename T>
+bool galerkin_variant_ok(const LevelGeom& L, const LevelGeom& C, int variant);
 template <typename T>
 void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, T* Bp, bool fine, int* status,
-                        hipStream_t st);
+                        hipStream_t st, int variant = kVariantDefault);
 template <typename T>
 void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
-                     hipStream_t st);
+                     hipStream_t st, int variant = kVariantDefault);
 // Window corrections of the subband preconditioner (kernels_window.hip):
 // for every 3 x 3 group of parents of level k < q, B_w^-1 is kept when
 // tr(D_w B_w^-1) > tol (D_w the 3 x 3 parent blocks of B_w).  cap windows fit

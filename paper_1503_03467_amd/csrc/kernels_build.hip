@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void k_patch_solve(const T* __restrict__ A, co
 }
 
 template <typename T>
-void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st);
+void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st,
+                             int variant);
 template <typename T, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_patch_chol_mfma(const T* __restrict__ A, const T* __restrict__ B,
                                                          const T* __restrict__ Bp, T* __restrict__ R, int nk,
@@ -452,19 +453,32 @@ static bool patch_mfma_enabled() {
   return sizeof(T) == 4;
 }
 
+int patch_class(const LevelGeom& L, bool fine) {
+  return (fine && L.t == 1 && L.nk / 2 > 2 * L.rho + 1) ? kKernelBand : kKernelPatch;
+}
+
+template <typename T>
+bool patch_variant_ok(const LevelGeom& L, bool fine, int variant) {
+  const int nc = L.nk / 2;
+  if (patch_class(L, fine) == kKernelBand) return variant == 0 || (variant == 1 && L.rho <= 3);
+  const int wmax = (2 * L.rho + 1) < nc ? (2 * L.rho + 1) : nc;
+  return variant == 0 || (variant == 1 && 3 * wmax * wmax + 1 <= 160);
+}
+
 template <typename T>
 void launch_patch_solve(const LevelGeom& L, const T* A, const T* B, T* R, T* Bp, bool fine, int* status,
-                        hipStream_t st) {
+                        hipStream_t st, int variant) {
   const int nc = L.nk / 2;
-  if (fine && L.t == 1 && nc > 2 * L.rho + 1) {
-    launch_patch_solve_band<T>(L, A, B, R, status, st);
+  if (patch_class(L, fine) == kKernelBand) {
+    launch_patch_solve_band<T>(L, A, B, R, status, st, variant);
     return;
   }
   const int wmax = (2 * L.rho + 1) < nc ? (2 * L.rho + 1) : nc;
   const int need = 3 * wmax * wmax + 1;
   const dim3 grid(nc * nc), block(256);
   const int f = fine ? 1 : 0;
-  if (patch_mfma_enabled<T>() && need <= 160) {
+  const bool mfma = variant == kVariantDefault ? patch_mfma_enabled<T>() : variant == 1;
+  if (mfma && need <= 160) {
     const int np2 = nc * nc, TT = 2 * L.t + 1, per = TT * TT * 9;
     hipLaunchKernelGGL(k_b_parent_major<T>, dim3((np2 + 63) / 64, (per + 31) / 32), dim3(256), 0, st, B, Bp, np2, per);
     hipLaunchKernelGGL((k_patch_chol_mfma<T, 10>), grid, block, 0, st, A, B, Bp, R, L.nk, L.s, L.t, L.rho, f,
@@ -1217,9 +1231,11 @@ __global__ __launch_bounds__(64) void k_patch_solve_band(const T* __restrict__ A
 }
 
 template <typename T>
-void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st) {
+void launch_patch_solve_band(const LevelGeom& L, const T* A, const T* B, T* R, int* status, hipStream_t st,
+                             int variant) {
   const int nc = L.nk / 2;
-  if (band_reg_enabled() && L.rho <= 3) {
+  const bool reg = variant == kVariantDefault ? band_reg_enabled() : variant == 1;
+  if (reg && L.rho <= 3) {
     // two patches per wavefront (nc * nc is even)
     const dim3 grid(nc * nc / 2), block(64);
     if (L.rho == 3) hipLaunchKernelGGL((k_patch_band_pair<T, 3>), grid, block, 0, st, A, B, R, L.nk, L.s, status);
@@ -1475,17 +1491,30 @@ static size_t strip_lds(const LevelGeom& L, const LevelGeom& C, int NS, size_t e
   return ((size_t)NS * (L.rw * ry + zw * uy) + (size_t)P * (Sc * Sc - (Sc * Sc - 1) / 2) * NS) * elem;
 }
 
+// strip height: the largest of 8, 4, 2 whose LDS staging fits 80 KB (two
+// workgroups of 512 threads per compute unit) and that still gives 512
+// workgroups (strips pay off only when they fill the GPU); 1 = no strips
 template <typename T>
-void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
-                     hipStream_t st) {
+static int strip_height(const LevelGeom& L, const LevelGeom& C) {
   const int nc = L.nk / 2;
-  const int zw = L.rw + 2 * L.s;
-  // strip height: the largest of 8, 4, 2 whose LDS staging fits 80 KB (two
-  // workgroups of 512 threads per compute unit)
-  // and that still gives 512 workgroups (strips pay off only when they fill the GPU)
   int NS = 8;
   while (NS > 1 && (NS > nc || strip_lds(L, C, NS, sizeof(T)) > 80 * 1024 || nc * (nc / NS) < 512)) NS /= 2;
-  if (galerkin_strip_enabled() && NS >= 2) {
+  return NS;
+}
+
+template <typename T>
+bool galerkin_variant_ok(const LevelGeom& L, const LevelGeom& C, int variant) {
+  return variant == 0 || (variant == 1 && strip_height<T>(L, C) >= 2);
+}
+
+template <typename T>
+void launch_galerkin(const LevelGeom& L, const LevelGeom& C, const T* A, const T* R, T* Ac,
+                     hipStream_t st, int variant) {
+  const int nc = L.nk / 2;
+  const int zw = L.rw + 2 * L.s;
+  const int NS = strip_height<T>(L, C);
+  const bool strips = variant == kVariantDefault ? galerkin_strip_enabled() : variant == 1;
+  if (strips && NS >= 2) {
     const size_t shm = strip_lds(L, C, NS, sizeof(T));
     const dim3 grid(nc * (nc / NS)), block(kStripThreads);
     if (NS == 8)
@@ -1670,9 +1699,11 @@ void launch_gershgorin(const LevelGeom& L, const T* B, T* scratch, unsigned* out
   template void launch_gershgorin<T>(const LevelGeom&, const T*, T*, unsigned*, hipStream_t);        \
   template void launch_subband_operator<T>(const LevelGeom&, const T*, T*, T*, bool, hipStream_t);   \
   template void launch_patch_solve<T>(const LevelGeom&, const T*, const T*, T*, T*, bool, int*,      \
-                                      hipStream_t);                                                  \
+                                      hipStream_t, int);                                             \
   template void launch_galerkin<T>(const LevelGeom&, const LevelGeom&, const T*, const T*, T*,      \
-                                   hipStream_t);                                                     \
+                                   hipStream_t, int);                                                \
+  template bool patch_variant_ok<T>(const LevelGeom&, bool, int);                                     \
+  template bool galerkin_variant_ok<T>(const LevelGeom&, const LevelGeom&, int);                      \
   template void launch_coarse_factor<T>(const T*, int, double*, int*, hipStream_t);
 GBL_INST(float)
 GBL_INST(double)

@@ -1247,6 +1247,12 @@ __global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F0, ChebCoef cf, in
   const bool interior = act && rx >= H && rx < H + TP && ry >= H && ry < H + TP;
   const int q = in ? px * np + py : 0;
   const int tp = in ? parent_type(true, px, py) : 3;
+  // buffers picked by selects, not by an index into F's arrays (an index
+  // that is not a compile-time constant moves F to scratch memory)
+  const T* const r_in = rd ? F.r[1] : F.r[0];
+  const T* const d_in = rd ? F.w[1] : F.w[0];
+  T* const r_out = rd ? F.r[0] : F.r[1];
+  T* const d_out = rd ? F.w[0] : F.w[1];
   for (int e = tid; e < VW * VW; e += blockDim.x) vl[e] = T(0);
 
   T bj[9], ac[3][3], r[3], d[3], x[3];
@@ -1277,8 +1283,8 @@ __global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F0, ChebCoef cf, in
   } else {
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      r[t] = in ? F.r[rd][t * np2 + q] : T(0);
-      d[t] = in ? F.w[rd][t * np2 + q] : T(0);
+      r[t] = in ? r_in[t * np2 + q] : T(0);
+      d[t] = in ? d_in[t * np2 + q] : T(0);
       x[t] = interior ? F.x[t * np2 + q] : T(0);
     }
   }
@@ -1334,8 +1340,8 @@ __global__ __launch_bounds__(256) void k_fine_cheb(FineCG<T> F0, ChebCoef cf, in
   if (interior) {
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      F.r[rd ^ 1][t * np2 + q] = r[t];
-      F.w[rd ^ 1][t * np2 + q] = d[t];
+      r_out[t * np2 + q] = r[t];
+      d_out[t * np2 + q] = d[t];
       F.x[t * np2 + q] = x[t];
     }
   }
@@ -1389,6 +1395,13 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs
     al[e] = (cx >= 0 && cy >= 0 && cx < nk && cy < nk) ? F.acell[(size_t)cx * nk + cy] : T(0);
   }
   const int rd = (it + 1) & 1, wr = it & 1;   // buffers read / written by this iteration
+  // picked by selects (a run-time index into F's arrays would move F to scratch memory)
+  const T* const w_rd = rd ? F.w[1] : F.w[0];
+  const T* const s_rd = rd ? F.s[1] : F.s[0];
+  const T* const r_rd = rd ? F.r[1] : F.r[0];
+  T* const r_wr = wr ? F.r[1] : F.r[0];
+  T* const s_wr = wr ? F.s[1] : F.s[0];
+  T* const w_wr = wr ? F.w[1] : F.w[0];
   const T alpha = it ? T(F.scal[kFAlpha]) : T(0);
   const T beta = it ? T(F.scal[kFBeta]) : T(0);
 
@@ -1413,8 +1426,8 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs
       } else {
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-          s3[t] = F.w[rd][t * np2 + q] + beta * F.s[rd][t * np2 + q];
-          r3[t] = F.r[rd][t * np2 + q] - alpha * s3[t];
+          s3[t] = w_rd[t * np2 + q] + beta * s_rd[t * np2 + q];
+          r3[t] = r_rd[t * np2 + q] - alpha * s3[t];
         }
       }
 #pragma unroll
@@ -1434,8 +1447,8 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs
             F.x[o] += alpha * pn;
           }
           F.u[o] = u3[t];
-          F.r[wr][o] = r3[t];
-          F.s[wr][o] = s3[t];
+          r_wr[o] = r3[t];
+          s_wr[o] = s3[t];
           rl[(t * TP + hx - 1) * TP + hy - 1] = r3[t];
         }
       }
@@ -1498,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs
         wt = T(wcoef(tp, t, 0)) * Av[0] + T(wcoef(tp, t, 1)) * Av[1] + T(wcoef(tp, t, 2)) * Av[2] +
              T(wcoef(tp, t, 3)) * Av[3];
       }
-      F.w[wr][t * np2 + q] = wt;
+      w_wr[t * np2 + q] = wt;
       v[0] += (double)(rl[(t * TP + lx) * TP + ly] * ut);
       v[1] += (double)(wt * ut);
     }

@@ -29,7 +29,7 @@ class GblOpts(ctypes.Structure):
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
                 ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double), ("exact", ctypes.c_int),
                 ("geometry", ctypes.c_int), ("source", ctypes.c_int), ("w_kind", ctypes.c_int),
-                ("dim", ctypes.c_int)]
+                ("dim", ctypes.c_int), ("autotune", ctypes.c_int), ("autotune_path", ctypes.c_char_p)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -42,7 +42,8 @@ class GblLevelDesc(ctypes.Structure):
                 ("rw", ctypes.c_int), ("rho", ctypes.c_int), ("elem_bytes", ctypes.c_int),
                 ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("R", ctypes.c_void_p),
                 ("nwin", ctypes.c_int), ("wlist", ctypes.c_void_p), ("winv", ctypes.c_void_p),
-                ("dense", ctypes.c_int), ("n", ctypes.c_int), ("nsub", ctypes.c_int)]
+                ("dense", ctypes.c_int), ("n", ctypes.c_int), ("nsub", ctypes.c_int),
+                ("patch_kernel", ctypes.c_int), ("galerkin_kernel", ctypes.c_int)]
 
 
 class GambletError(RuntimeError):
@@ -117,7 +118,8 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
               inner_iters: int | None = None, max_rhs: int = 1, inner_iters_coarse: int | None = None,
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
               level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0, exact: bool = False,
-              geometry: int = 0, source: str = "cell", w_kind: int = 0, dim: int = 2) -> GblOpts:
+              geometry: int = 0, source: str = "cell", w_kind: int = 0, dim: int = 2, autotune: bool = False,
+              autotune_path: str | None = None) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -143,6 +145,8 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.source = SOURCES[source]
     o.w_kind = int(w_kind)
     o.dim = int(dim)
+    o.autotune = 1 if autotune else 0
+    o.autotune_path = autotune_path.encode() if autotune_path else None
     return o
 
 
@@ -184,7 +188,7 @@ class Hierarchy:
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
                  kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0,
                  window_tol: float = 0.0, exact: bool = False, geometry: int = 0, source: str = "cell",
-                 w_kind: int = 0):
+                 w_kind: int = 0, autotune: bool = False, autotune_path: str | None = None):
         n = a.shape[0]
         q = (n - geometry).bit_length() - 1
         if n - geometry != (1 << q) or q < 2 or a.dim() not in (2, 3):
@@ -196,7 +200,7 @@ class Hierarchy:
         self.source = source
         self.opts = make_opts(rho, "fp64" if exact else precision, rtol, max_outer, inner_iters, max_rhs,
                               inner_iters_coarse, inner, kappa, kappa_coarse, level_q_mass, rho_coarse, window_tol,
-                              exact, geometry, source, w_kind, self.dim)
+                              exact, geometry, source, w_kind, self.dim, autotune, autotune_path)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):
@@ -339,6 +343,7 @@ class Hierarchy:
         nk = d.nk
         S = 2 * d.s + 1
         out = {"k": d.k, "nk": nk, "s": d.s, "t": d.t, "rw": d.rw, "rho": d.rho,
+               "patch_kernel": d.patch_kernel, "galerkin_kernel": d.galerkin_kernel,
                "A": view(d.A, S * S * nk * nk).view(S, S, nk, nk)}
         if k >= 2:
             np_ = nk // 2
@@ -495,14 +500,15 @@ def _adopt(ctx_value: int, q: int, ws: torch.Tensor, opts: GblOpts) -> Hierarchy
 def build_batched(coeffs: list, rho: int = 3, precision: str = "mixed", rtol: float = 1e-8,
                   max_outer: int = 100, inner_iters: int | None = None, max_rhs: int = 1,
                   inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
-                  kappa_coarse: float | None = None) -> list:
+                  kappa_coarse: float | None = None, autotune: bool = False,
+                  autotune_path: str | None = None) -> list:
     """Build the hierarchies of independent problems of uneven depth concurrently
     (``gbl_build_batched``); ``coeffs`` holds [2^q][2^q] float64 CUDA tensors."""
     P = len(coeffs)
     if P == 0:
         return []
     opts = make_opts(rho, precision, rtol, max_outer, inner_iters, max_rhs, inner_iters_coarse, inner, kappa,
-                     kappa_coarse)
+                     kappa_coarse, autotune=autotune, autotune_path=autotune_path)
     qs, wss = [], []
     for a in coeffs:
         n = a.shape[0]
