@@ -78,6 +78,7 @@ int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs,
       const long np2 = E.np2[k], nj = (long)rp * np2;
       E.offB[k] = b; b = al(b + (size_t)nj * nj * 8);
       E.offBL[k] = b; b = al(b + (size_t)nj * nj * 8);
+      E.offBinv[k] = b; b = al(b + (size_t)nj * nj * 8);
       E.offD[k] = b; b = al(b + (size_t)nj * np2 * 8);
       E.offR[k] = b; b = al(b + (size_t)np2 * N * 8);
       E.offNch[k] = b; b = al(b + (size_t)np2 * 4);
@@ -88,6 +89,7 @@ int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs,
       E.offGinv[k] = b; b = al(b + (size_t)np2 * rp * rp * 8);
       most = std::max(most, np2 * N);
       E.offW[k] = b; b = al(b + (size_t)nj * E.nr * 8);
+      E.offWt[k] = b; b = al(b + (size_t)nj * E.nr * 8);
     }
     E.offG[k] = b; b = al(b + (size_t)N * E.nr * 8);
     E.offU[k] = b; b = al(b + (size_t)N * 8);
@@ -254,6 +256,11 @@ int exact_build(ExactHier& E, const double* a_dev, hipStream_t st, std::string& 
     }
     ex_cholesky(E.BL(k), nj, nj, status, st);
     ex_chol_solve(E.BL(k), nj, nj, D, np2, np2, st);    // D = B^-1 C
+    // B^-1 itself, for the solves: each subband system is then one
+    // bandwidth-bound matrix-vector product instead of two chains of
+    // dependent triangular blocks
+    ex_identity(nj, E.Binv(k), st);
+    ex_chol_solve(E.BL(k), nj, nj, E.Binv(k), nj, nj, st);
     ex_restriction(D, t, N, R, st);
     // A^(k-1) = R A R^T: T = R A, then T R^T
     double* T = reinterpret_cast<double*>(E.ws + E.offT);
@@ -284,19 +291,19 @@ static void subband_solve(ExactHier& E, const double* y, double* x, int nr, hipS
   const int q = E.q;
   // g^(q) = y, g^(k-1) = R g^(k)
   if (hipMemcpyAsync(E.G(q), y, (size_t)E.N[q] * nr * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return;
-  for (int k = q; k >= 2; --k)
-    ex_gemm(E.np2[k], nr, (int)E.N[k], 1.0, E.R(k), E.N[k], 1, E.G(k), nr, 1, 0.0, E.G(k - 1), nr, st);
-  // subband systems B^(k) w = W g^(k) and A^(1) U = g^(1)
+  for (int k = q; k >= 2; --k) ex_gemv(E.np2[k], (int)E.N[k], nr, 1.0, E.R(k), E.N[k], E.G(k), 0.0, E.G(k - 1), st);
+  // subband systems B^(k) w = W g^(k) (w = B^-1 W g) and A^(1) U = g^(1)
   for (int k = q; k >= 2; --k) {
     const ExLevelTables t = exact_tables(E, k);
-    ex_wapply(t, E.G(k), nr, E.W(k), st);
-    ex_chol_solve(E.BL(k), E.rp * E.np2[k], E.rp * E.np2[k], E.W(k), nr, nr, st);
+    const int nj = E.rp * E.np2[k];
+    ex_wapply(t, E.G(k), nr, E.Wt(k), st);
+    ex_gemv(nj, nj, nr, 1.0, E.Binv(k), nj, E.Wt(k), 0.0, E.W(k), st);
   }
   ex_chol_solve(reinterpret_cast<const double*>(E.ws + E.offL1), E.cp, E.cp, E.G(1), nr, nr, st);
   // v^(1) = U, v^(k) = R^T v^(k-1) + W^T w^(k)   (Theorem 4.15)
   for (int k = 2; k <= q; ++k) {
     double* vk = (k == q) ? x : E.G(k);
-    ex_gemm((int)E.N[k], nr, E.np2[k], 1.0, E.R(k), 1, E.N[k], E.G(k - 1), nr, 1, 0.0, vk, nr, st);
+    ex_gemv_t(E.np2[k], (int)E.N[k], nr, 1.0, E.R(k), E.N[k], E.G(k - 1), 0.0, vk, st);
     ex_wtadd(exact_tables(E, k), E.N[k], E.W(k), nr, vk, st);
   }
 }
@@ -324,7 +331,7 @@ int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u
         msg = "copy failed";
         return GBL_EHIP;
       }
-      ex_gemm((int)Nq, nr, (int)Nq, -1.0, E.A(E.q), Nq, 1, x, nr, 1, 1.0, r, nr, st);
+      ex_gemv((int)Nq, (int)Nq, nr, -1.0, E.A(E.q), Nq, x, 1.0, r, st);
       subband_solve(E, r, dx, nr, st);
       ex_axpy((long)len, 1.0, dx, x, st);
     }
@@ -347,7 +354,7 @@ int exact_transform(ExactHier& E, const double* u_nodal, double* coef, hipStream
     const ExLevelTables t = exact_tables(E, k);
     ex_child_sum(t, E.U(k), E.U(k - 1), st);
     if (hipMemcpyAsync(d, E.U(k), (size_t)E.N[k] * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return GBL_EHIP;
-    ex_gemm((int)E.N[k], 1, E.np2[k], -1.0, E.R(k), 1, E.N[k], E.U(k - 1), 1, 1, 1.0, d, 1, st);   // d -= R^T U^(k-1)
+    ex_gemv_t(E.np2[k], (int)E.N[k], 1, -1.0, E.R(k), E.N[k], E.U(k - 1), 1.0, d, st);   // d -= R^T U^(k-1)
     ex_wapply(t, d, 1, E.W(k), st);
     if (E.wkind != 0) ex_gram_solve(t, E.at(E.offGinv[k]), E.W(k), st);   // w = (W W^T)^-1 W d
     const int nj = E.rp * E.np2[k];
@@ -365,7 +372,7 @@ int exact_inverse_transform(ExactHier& E, const double* coef, double* u_nodal, h
     const ExLevelTables t = exact_tables(E, k);
     const int nj = E.rp * E.np2[k];
     ex_diag_scale(E.B(k), nj, nj, coef + E.np2[k], E.W(k), true, &t, st);
-    ex_gemm((int)E.N[k], 1, E.np2[k], 1.0, E.R(k), 1, E.N[k], E.U(k - 1), 1, 1, 0.0, E.U(k), 1, st);
+    ex_gemv_t(E.np2[k], (int)E.N[k], 1, 1.0, E.R(k), E.N[k], E.U(k - 1), 0.0, E.U(k), st);
     ex_wtadd(t, E.N[k], E.W(k), 1, E.U(k), st);
   }
   ex_fill(E.nnodes, 0.0, u_nodal, st);
@@ -380,8 +387,8 @@ int exact_energy_norm(ExactHier& E, const double* u_nodal, double* norm, hipStre
   double* y = E.at(E.offRes);
   double* out = E.at(E.offDot);
   from_nodal(E, u_nodal, x, st);
-  ex_gemm((int)Nq, 1, (int)Nq, 1.0, E.A(E.q), Nq, 1, x, 1, 1, 0.0, y, 1, st);   // y = A x
-  ex_gemm(1, 1, (int)Nq, 1.0, x, 1, 1, y, 1, 1, 0.0, out, 1, st);              // x . y
+  ex_gemv((int)Nq, (int)Nq, 1, 1.0, E.A(E.q), Nq, x, 0.0, y, st);   // y = A x
+  ex_gemv(1, (int)Nq, 1, 1.0, x, Nq, y, 0.0, out, st);               // x . y
   double h = 0.0;
   if (hipMemcpyAsync(&h, out, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return GBL_EHIP;

@@ -30,6 +30,7 @@ struct ExactHier {
   size_t offNch[kMaxLevels] = {}, offChild[kMaxLevels] = {}, offWc[kMaxLevels] = {}, offParent[kMaxLevels] = {},
          offPos[kMaxLevels] = {}, offGinv[kMaxLevels] = {};
   size_t offG[kMaxLevels] = {}, offW[kMaxLevels] = {}, offU[kMaxLevels] = {};
+  size_t offBinv[kMaxLevels] = {}, offWt[kMaxLevels] = {};
   size_t offT = 0, offB0 = 0, offX = 0, offRes = 0, offDx = 0, offL1 = 0, offStatus = 0, offSel = 0, offThr = 0;
   size_t offDot = 0, offCoef = 0;   // offCoef: a copy of the cell coefficient [nc][nc]
   size_t total = 0;
@@ -39,6 +40,8 @@ struct ExactHier {
   double* A(int k) const { return at(offA[k]); }    // A^(k), N_k x N_k
   double* B(int k) const { return at(offB[k]); }    // B^(k) = W A^(k) W^T, rp np2 x rp np2
   double* BL(int k) const { return at(offBL[k]); }  // its Cholesky factor (lower)
+  double* Binv(int k) const { return at(offBinv[k]); }   // B^(k)^-1 (from the factor)
+  double* Wt(int k) const { return at(offWt[k]); }       // W g^(k) before the subband solve
   double* D(int k) const { return at(offD[k]); }    // D^(k,k-1), rp np2 x np2
   double* R(int k) const { return at(offR[k]); }    // R^(k-1,k), np2 x N_k
   double* G(int k) const { return at(offG[k]); }    // level-k solve vectors [N_k][nr]

@@ -25,8 +25,14 @@ struct ExLevelTables {
 void ex_gemm(int M, int N, int K, double alpha, const double* A, long as0, long as1, const double* B, long bs0,
              long bs1, double beta, double* C, long ldc, hipStream_t st);
 void ex_cholesky(double* A, int n, long lda, int* status, hipStream_t st);
+// y = alpha A x + beta y (A row-major M x N, x [N][nr], y [M][nr]) and its transposed form
+void ex_gemv(int M, int N, int nr, double alpha, const double* A, long lda, const double* x, double beta, double* y,
+             hipStream_t st);
+void ex_gemv_t(int M, int N, int nr, double alpha, const double* A, long lda, const double* x, double beta, double* y,
+               hipStream_t st);
 void ex_chol_solve(const double* A, int n, long lda, double* X, long ldx, int nrhs, hipStream_t st);
 void ex_fill(long len, double v, double* x, hipStream_t st);
+void ex_identity(long n, double* X, hipStream_t st);
 void ex_level_operators(const double* A, long N, const ExLevelTables& t, double* B, double* C, hipStream_t st);
 void ex_restriction(const double* D, const ExLevelTables& t, long N, double* R, hipStream_t st);
 void ex_load(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,

@@ -201,11 +201,91 @@ void ex_chol_solve(const double* A, int n, long lda, double* X, long ldx, int nr
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-vector products for up to kGvRhs right-hand sides at a time.
+// y = alpha A x + beta y with A row-major (lda), x [N][nr], y [M][nr]: one
+// wavefront per row, lanes striding over the row (coalesced), a wavefront
+// reduction per right-hand side.  y = alpha A^T x + beta y: one lane per
+// output column, looping over the rows of A (neighbouring lanes read
+// neighbouring entries of a row).
+// ---------------------------------------------------------------------------
+constexpr int kGvRhs = 8;
+
+__global__ __launch_bounds__(256) void k_ex_gemv(int M, int N, int nr, double alpha, const double* __restrict__ A,
+                                                 long lda, const double* __restrict__ x, double beta,
+                                                 double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= M) return;
+  const double* a = A + row * lda;
+  for (int c0 = 0; c0 < nr; c0 += kGvRhs) {
+    const int nc = min(kGvRhs, nr - c0);
+    double acc[kGvRhs];
+#pragma unroll
+    for (int c = 0; c < kGvRhs; ++c) acc[c] = 0.0;
+    for (int j = lane; j < N; j += 64) {
+      const double av = a[j];
+#pragma unroll
+      for (int c = 0; c < kGvRhs; ++c)
+        if (c < nc) acc[c] += av * x[(long)j * nr + c0 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kGvRhs; ++c) {
+      double v = acc[c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[c] = v;
+    }
+    if (lane < nc) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < kGvRhs; ++c)
+        if (c == lane) v = acc[c];
+      double* yy = y + row * nr + c0 + lane;
+      *yy = alpha * v + (beta == 0.0 ? 0.0 : beta * *yy);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ex_gemv_t(int M, int N, int nr, double alpha, const double* __restrict__ A,
+                                                   long lda, const double* __restrict__ x, double beta,
+                                                   double* __restrict__ y) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;   // output column j, right-hand side c
+  if (id >= (long)N * nr) return;
+  const long j = id / nr;
+  const int c = (int)(id % nr);
+  double acc = 0.0;
+  for (long i = 0; i < M; ++i) acc += A[i * lda + j] * x[i * nr + c];
+  y[id] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[id]);
+}
+
+void ex_gemv(int M, int N, int nr, double alpha, const double* A, long lda, const double* x, double beta, double* y,
+             hipStream_t st) {
+  if (M <= 0 || nr <= 0) return;
+  hipLaunchKernelGGL(k_ex_gemv, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, N, nr, alpha, A, lda, x, beta, y);
+}
+
+void ex_gemv_t(int M, int N, int nr, double alpha, const double* A, long lda, const double* x, double beta, double* y,
+               hipStream_t st) {
+  const long tot = (long)N * nr;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_ex_gemv_t, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N, nr, alpha, A, lda, x,
+                     beta, y);
+}
+
+// ---------------------------------------------------------------------------
 // Level operators.
 // ---------------------------------------------------------------------------
 __global__ void k_ex_fill(long len, double v, double* __restrict__ x) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) x[i] = v;
+}
+
+__global__ void k_ex_identity(long n, double* __restrict__ X) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n * n) X[id] = (id / n == id % n) ? 1.0 : 0.0;
+}
+
+void ex_identity(long n, double* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_ex_identity, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, n, X);
 }
 
 void ex_fill(long len, double v, double* x, hipStream_t st) {
