@@ -41,7 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64 or unpacked FP32 FMA)
+VALU_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64 or unpacked FP32 FMA); FP64 matrix cores too
 MFMA_F32_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak
 # single-kernel build classes (one launch per level, a definite algorithmic
 # amount of work); the solve-phase classes are mixtures of small launches, and
@@ -481,9 +481,10 @@ def main():
     avg_launch_ms = dom_ms / max(dom_launches, 1)
     if kind == "flops":
         achieved = per_launch_work / (avg_launch_ms * 1e-3) / 1e12
-        # the mixed-precision patch solves below the finest level run on FP32 matrix cores
-        mfma = dominant == "patch_solve" and args.precision == "mixed" and os.environ.get("GBL_PATCH_MFMA", "1") != "0"
-        peak = MFMA_F32_PEAK_TFLOPS if mfma else VALU_FMA_PEAK_TFLOPS
+        # the patch solves below the finest level run on the matrix cores (FP32 in the mixed
+        # path, FP64 in the FP64 path, whose dense peak equals the FP64 vector peak)
+        mfma = dominant == "patch_solve" and os.environ.get("GBL_PATCH_MFMA", "1") != "0"
+        peak = MFMA_F32_PEAK_TFLOPS if (mfma and args.precision == "mixed") else VALU_FMA_PEAK_TFLOPS
         roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
     else:
