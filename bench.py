@@ -79,12 +79,12 @@ def level_geometry(H):
 # measured on: the entry records the SHA-256 of that source file, and a mismatch reports None.
 MEASURED_TRAFFIC = {
     # matrix-core patch solves, levels 8..2 of the 512x512-cell benchmark (parent-major copy of B^(k),
-    # then the patch kernel): 107,953 KiB fetched and 118,215 KiB written per build over 7 launches
-    # (FETCH x 2.0 + WRITE x 1.0)
+    # then the patch kernel): 108,061 KiB fetched and 118,707 KiB written per build over 7 launches
+    # (FETCH x 2.0 + WRITE x 1.0); profiles/q9_kernels_hbm_fraction_and_mfma.md
     ("patch_solve", 9, "mixed"): {
-        "bytes_per_launch": 48877129,
+        "bytes_per_launch": 48980622,
         "source": "kernels_build.hip",
-        "sha256": "1f792bf7e55d8ceda8952f3b13cddcf49bb02f298851d232b8ac3a2db4a0c3ac",
+        "sha256": "f354d1700ef05376fa7e98cd24d0e535f3ef395fb0e5ed777b249754c82c544f",
     },
 }
 
