@@ -125,14 +125,22 @@ __global__ __launch_bounds__(256) void k_ex_trsm_panel(double* __restrict__ A, l
   __syncthreads();
   const int r = r0 + blockIdx.x * 256 + tid;
   if (r >= n) return;
+  // fully unrolled over the 64 panel columns (guarded by nb) so that x stays
+  // in registers: a run-time index would put it in scratch memory
   double x[kCB];
   double* row = A + (long)r * lda + j0;
-  for (int c = 0; c < nb; ++c) {
-    double v = row[c];
-    for (int k = 0; k < c; ++k) v -= x[k] * L[c][k];
-    x[c] = v / L[c][c];
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) {
+    if (c < nb) {
+      double v = row[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) v -= x[k] * L[c][k];
+      x[c] = v / L[c][c];
+    }
   }
-  for (int c = 0; c < nb; ++c) row[c] = x[c];
+#pragma unroll
+  for (int c = 0; c < kCB; ++c)
+    if (c < nb) row[c] = x[c];
 }
 
 void ex_cholesky(double* A, int n, long lda, int* status, hipStream_t st) {
@@ -163,22 +171,35 @@ __global__ __launch_bounds__(256) void k_ex_trsv_block(const double* __restrict_
   __syncthreads();
   const int c = blockIdx.x * 256 + tid;
   if (c >= nrhs) return;
+  // unrolled over the 64 block rows (guarded by nb): x stays in registers
   double x[kCB];
-  for (int i = 0; i < nb; ++i) x[i] = X[(long)(i0 + i) * ldx + c];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i) x[i] = i < nb ? X[(long)(i0 + i) * ldx + c] : 0.0;
   if (!upper) {
-    for (int i = 0; i < nb; ++i) {
-      double v = x[i];
-      for (int k = 0; k < i; ++k) v -= L[i][k] * x[k];
-      x[i] = v / L[i][i];
+#pragma unroll
+    for (int i = 0; i < kCB; ++i) {
+      if (i < nb) {
+        double v = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= L[i][k] * x[k];
+        x[i] = v / L[i][i];
+      }
     }
   } else {
-    for (int i = nb - 1; i >= 0; --i) {
-      double v = x[i];
-      for (int k = i + 1; k < nb; ++k) v -= L[k][i] * x[k];
-      x[i] = v / L[i][i];
+#pragma unroll
+    for (int i = kCB - 1; i >= 0; --i) {
+      if (i < nb) {
+        double v = x[i];
+#pragma unroll
+        for (int k = i + 1; k < kCB; ++k)
+          if (k < nb) v -= L[k][i] * x[k];
+        x[i] = v / L[i][i];
+      }
     }
   }
-  for (int i = 0; i < nb; ++i) X[(long)(i0 + i) * ldx + c] = x[i];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i)
+    if (i < nb) X[(long)(i0 + i) * ldx + c] = x[i];
 }
 
 void ex_chol_solve(const double* A, int n, long lda, double* X, long ldx, int nrhs, hipStream_t st) {
