@@ -91,6 +91,48 @@ def assemble(a: np.ndarray, h: float | None = None) -> FEProblem:
     return FEProblem(n=n, h=h, A_full=A_full, A=A, A_IB=A_IB, interior=inner, boundary=bnd)
 
 
+# Tensor-valued coefficients (the symmetric matrix a(x) of Section 1): per
+# cell a constant SPD matrix [[a11, a12], [a12, a22]].  On a cell the local
+# basis is hat_dx(x) hat_dy(y) (local index dx + 2 dy), so
+#   int dx phi_i dx phi_j = k1[dx_i][dx_j] m1[dy_i][dy_j],
+#   int dy phi_i dy phi_j = m1[dx_i][dx_j] k1[dy_i][dy_j],
+#   int dx phi_i dy phi_j = c1[dx_i][dx_j] c1[dy_j][dy_i],
+# with the unit-interval matrices k1 (stiffness), m1 (mass) and
+# c1[a][b] = int hat_a' hat_b = (+1/2 for a = 1, -1/2 for a = 0); the cell
+# side cancels in two dimensions.
+K1_1D = np.array([[1.0, -1.0], [-1.0, 1.0]])
+M1_1D = np.array([[2.0, 1.0], [1.0, 2.0]]) / 6.0
+C1_1D = np.array([[-0.5, -0.5], [0.5, 0.5]])
+
+
+def tensor_element_parts():
+    """(Kxx, Kyy, Kxy + Kyx) over the local nodes (0,0), (1,0), (0,1), (1,1)."""
+    loc = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    Kxx = np.array([[K1_1D[a[0], b[0]] * M1_1D[a[1], b[1]] for b in loc] for a in loc])
+    Kyy = np.array([[M1_1D[a[0], b[0]] * K1_1D[a[1], b[1]] for b in loc] for a in loc])
+    Kxy = np.array([[C1_1D[a[0], b[0]] * C1_1D[b[1], a[1]] for b in loc] for a in loc])
+    return Kxx, Kyy, Kxy + Kxy.T
+
+
+def assemble_tensor(a3: np.ndarray) -> FEProblem:
+    """Stiffness of -div(a grad u) with a per-cell symmetric tensor a3[ex][ey] = (a11, a12, a22)."""
+    a3 = np.asarray(a3, dtype=np.float64)
+    n = a3.shape[0]
+    assert a3.shape == (n, n, 3)
+    Kxx, Kyy, Ks = tensor_element_parts()
+    cn = cell_nodes(n)
+    rows = np.repeat(cn, 4, axis=1).ravel()
+    cols = np.tile(cn, (1, 4)).ravel()
+    a11, a12, a22 = (a3[..., i].ravel()[:, None, None] for i in range(3))
+    vals = (a11 * Kxx[None] + a22 * Kyy[None] + a12 * Ks[None]).ravel()
+    nn = (n + 1) ** 2
+    A_full = sp.coo_matrix((vals, (rows, cols)), shape=(nn, nn)).tocsr()
+    inner = interior_ids(n)
+    bnd = np.flatnonzero(boundary_mask(n))
+    return FEProblem(n=n, h=1.0 / n, A_full=A_full, A=A_full[inner][:, inner].tocsc(),
+                     A_IB=A_full[inner][:, bnd].tocsr(), interior=inner, boundary=bnd)
+
+
 def load_cellwise(g: np.ndarray, h: float) -> np.ndarray:
     """Load of a source constant on every cell: b_i = int phi_i g = (h^2/4) sum_{e ni i} g_e.
 
