@@ -155,6 +155,9 @@ typedef struct gbl_opts {
   const char* autotune_path; /* autotune: file that keeps the choices across processes (read when first used,
                          appended to; one line per choice with both candidates' times), or NULL for this
                          process only.  The string must stay valid for the duration of gbl_build */
+  int tensor;         /* 1 (exact only, dim 2): the coefficient is a symmetric matrix per cell (the matrix-valued
+                         a(x) of Section 1): a_dev is [n][n][3] = (a11, a12, a22), each positive definite (else
+                         EINVAL).  0: a scalar per cell (default) */
 } gbl_opts;
 
 typedef struct gbl_solve_info {
@@ -205,7 +208,7 @@ int gbl_version(void);
 /* Fill *opts with defaults: rho 3, MIXED, rtol 1e-8, max_outer 100,
  * Chebyshev inner iterations, inner_iters 16, inner_iters_coarse 2,
  * kappa 200, kappa_coarse 10, max_rhs 1, window_tol 0, exact 0, geometry 0,
- * source 0, w_kind 0, dim 2, autotune 0, autotune_path NULL. */
+ * source 0, w_kind 0, dim 2, autotune 0, autotune_path NULL, tensor 0. */
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with

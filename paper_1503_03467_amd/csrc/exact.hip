@@ -39,8 +39,9 @@ double wrow(int kind, int m, int t, int d) {
 
 }  // namespace
 
-int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs, std::string& msg) {
+int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int tensor, int max_rhs, std::string& msg) {
   if (dim != 2 && dim != 3) { msg = "dim must be 2 or 3"; return GBL_EINVAL; }
+  if (tensor && dim != 2) { msg = "tensor coefficients are built in two dimensions"; return GBL_EINVAL; }
   const int qmax = dim == 2 ? 7 : 4;
   if (q < 2 || q > qmax) {
     msg = dim == 2 ? "the exact hierarchy is built for 2 <= q <= 7" : "the exact hierarchy in 3-D is built for 2 <= q <= 4";
@@ -54,6 +55,7 @@ int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs,
   E.rp = E.cp - 1;
   E.geom = geom;
   E.wkind = wkind;
+  E.tensor = tensor ? 1 : 0;
   E.nc = geom == 0 ? (1 << q) : (1 << q) + 1;
   E.m = E.nc - 1;
   E.nr = std::max(1, std::min(max_rhs, 64));
@@ -105,7 +107,7 @@ int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs,
   E.offSel = b; b = al(b + 4 * 8 + (size_t)kSelHistBins * 4);
   E.offThr = b; b = al(b + 64);
   E.offDot = b; b = al(b + (size_t)E.nr * 8);
-  E.offCoef = b; b = al(b + (size_t)ncd * 8);
+  E.offCoef = b; b = al(b + (size_t)ncd * (E.tensor ? 3 : 1) * 8);
   E.total = b;
   return GBL_OK;
 }
@@ -234,12 +236,14 @@ int exact_build(ExactHier& E, const double* a_dev, hipStream_t st, std::string& 
   if (rc) return rc;
   const int q = E.q;
   double* Aq = E.A(q);
-  if (hipMemcpyAsync(E.at(E.offCoef), a_dev, (size_t)E.ncells * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+  if (hipMemcpyAsync(E.at(E.offCoef), a_dev, (size_t)E.ncells * (E.tensor ? 3 : 1) * 8, hipMemcpyDeviceToDevice,
+                     st) != hipSuccess) {
     msg = "copy failed";
     return GBL_EHIP;
   }
   ex_fill(E.N[q] * E.N[q], 0.0, Aq, st);
-  if (E.dim == 2) launch_ex_assemble(a_dev, E.nc, Aq, status, st);
+  if (E.tensor) launch_ex_assemble_tensor(a_dev, E.nc, Aq, status, st);
+  else if (E.dim == 2) launch_ex_assemble(a_dev, E.nc, Aq, status, st);
   else launch_ex_assemble3(a_dev, E.nc, Aq, status, st);
   for (int k = q; k >= 2; --k) {
     const long N = E.N[k];
@@ -323,7 +327,8 @@ int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u
   for (int r0 = 0; r0 < nrhs; r0 += E.nr) {
     const int nr = std::min(E.nr, nrhs - r0);
     const size_t len = (size_t)Nq * nr;
-    if (E.dim == 2) ex_load(E.nc, source, src + r0 * src_stride, E.at(E.offCoef), u_nodal + r0 * u_stride, nr, b, st);
+    if (E.dim == 2)
+      ex_load(E.nc, source, src + r0 * src_stride, E.at(E.offCoef), u_nodal + r0 * u_stride, nr, b, E.tensor != 0, st);
     else ex_load3(E.nc, source, src + r0 * src_stride, E.at(E.offCoef), u_nodal + r0 * u_stride, nr, b, st);
     subband_solve(E, b, x, nr, st);
     for (int it = 0; it < refine; ++it) {   // r = b - A u;  u += S r

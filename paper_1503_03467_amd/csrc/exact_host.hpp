@@ -14,6 +14,7 @@ namespace gbl {
 struct ExactHier {
   int q = 0, geom = 0;
   int dim = 2;     // 2 or 3
+  int tensor = 0;  // 1: per-cell symmetric tensor (a11, a12, a22) in two dimensions
   int cp = 4;      // child slots per parent, 2^dim
   int rp = 3;      // subband rows per parent, 2^dim - 1
   long ncells = 0; // nc^dim
@@ -32,7 +33,7 @@ struct ExactHier {
   size_t offG[kMaxLevels] = {}, offW[kMaxLevels] = {}, offU[kMaxLevels] = {};
   size_t offBinv[kMaxLevels] = {}, offWt[kMaxLevels] = {};
   size_t offT = 0, offB0 = 0, offX = 0, offRes = 0, offDx = 0, offL1 = 0, offStatus = 0, offSel = 0, offThr = 0;
-  size_t offDot = 0, offCoef = 0;   // offCoef: a copy of the cell coefficient [nc][nc]
+  size_t offDot = 0, offCoef = 0;   // offCoef: a copy of the cell coefficient ([nc]^d, or [nc][nc][3])
   size_t total = 0;
   char* ws = nullptr;
 
@@ -49,7 +50,7 @@ struct ExactHier {
   double* U(int k) const { return at(offU[k]); }    // transform vectors [N_k]
 };
 
-int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int max_rhs, std::string& msg);
+int exact_layout(ExactHier& E, int q, int dim, int geom, int wkind, int tensor, int max_rhs, std::string& msg);
 int exact_build(ExactHier& E, const double* a_dev, hipStream_t st, std::string& msg);
 int exact_solve(ExactHier& E, int nrhs, int source, const double* src, double* u_nodal, int refine, hipStream_t st,
                 std::string& msg);

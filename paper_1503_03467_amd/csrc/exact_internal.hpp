@@ -36,7 +36,7 @@ void ex_identity(long n, double* X, hipStream_t st);
 void ex_level_operators(const double* A, long N, const ExLevelTables& t, double* B, double* C, hipStream_t st);
 void ex_restriction(const double* D, const ExLevelTables& t, long N, double* R, hipStream_t st);
 void ex_load(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
-             hipStream_t st);
+             bool tensor, hipStream_t st);
 void ex_wapply(const ExLevelTables& t, const double* g, int nrhs, double* y, hipStream_t st);
 void ex_wtadd(const ExLevelTables& t, long N, const double* w, int nrhs, double* v, hipStream_t st);
 void ex_to_nodal(int nc, const double* x, int nrhs, double* u, hipStream_t st);
@@ -48,6 +48,7 @@ void ex_diag_scale(const double* M, long n, long ld, const double* in, double* o
 void ex_child_sum(const ExLevelTables& t, const double* in, double* out, hipStream_t st);
 void ex_gram_solve(const ExLevelTables& t, const double* gram_inv, double* w, hipStream_t st);
 void launch_ex_assemble(const double* a, int nc, double* A, int* status, hipStream_t st);
+void launch_ex_assemble_tensor(const double* a3, int nc, double* A, int* status, hipStream_t st);
 void launch_ex_assemble3(const double* a, int nc, double* A, int* status, hipStream_t st);
 void ex_load3(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
               hipStream_t st);

@@ -191,6 +191,8 @@ int validate_opts(const gbl_opts* o, std::string& msg) {
   if (o->dim != 2 && o->dim != 3) { msg = "dim must be 2 or 3"; return GBL_EINVAL; }
   if (o->dim == 3 && !o->exact) { msg = "dim 3 needs the exact hierarchy (exact = 1)"; return GBL_EINVAL; }
   if (o->autotune != 0 && o->autotune != 1) { msg = "autotune must be 0 or 1"; return GBL_EINVAL; }
+  if (o->tensor != 0 && o->tensor != 1) { msg = "tensor must be 0 or 1"; return GBL_EINVAL; }
+  if (o->tensor && !o->exact) { msg = "tensor coefficients need the exact hierarchy (exact = 1)"; return GBL_EINVAL; }
   if (o->w_kind == 1 && !o->exact) {
     msg = "w_kind 1 (Construction 4.11) needs the exact hierarchy: the localized kernels use the orthonormal rows";
     return GBL_EINVAL;
@@ -1250,6 +1252,7 @@ int gbl_default_opts(gbl_opts* o) {
   o->dim = 2;
   o->autotune = 0;
   o->autotune_path = nullptr;
+  o->tensor = 0;
   return GBL_OK;
 }
 
@@ -1259,7 +1262,7 @@ int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes) {
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->tensor, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     *bytes = E.total;
     return GBL_OK;
@@ -1281,7 +1284,7 @@ int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts, v
   if (opts && opts->exact) {
     int st = validate_opts(opts, msg);
     ExactHier E;
-    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->max_rhs, msg);
+    if (!st) st = exact_layout(E, q, opts->dim, opts->geometry, opts->w_kind, opts->tensor, opts->max_rhs, msg);
     if (st) return fail(nullptr, st, msg);
     if (ws_bytes < E.total)
       return fail(nullptr, GBL_ENOMEM, "workspace too small: need " + std::to_string(E.total) + " bytes");

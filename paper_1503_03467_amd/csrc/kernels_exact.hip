@@ -419,6 +419,55 @@ void ex_restriction(const double* D, const ExLevelTables& t, long N, double* R, 
   hipLaunchKernelGGL(k_ex_restriction, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, t, N, R);
 }
 
+// Entry of the bilinear element stiffness of a square cell with the constant
+// symmetric tensor (a11, a12, a22), corners (dxi, dyi) and (dxj, dyj): the
+// gradient components of hat_dx(x) hat_dy(y) split into 1-D factors,
+// stiffness k (1 on, -1 off the diagonal), mass m (2/6 on, 1/6 off) and the
+// mixed c[a][b] = int hat_a' hat_b = (a = 1 ? 1/2 : -1/2); the cell side
+// cancels in two dimensions.
+__device__ __forceinline__ double k_tensor2(const double* t, int dxi, int dyi, int dxj, int dyj) {
+  const double kx = dxi == dxj ? 1.0 : -1.0, ky = dyi == dyj ? 1.0 : -1.0;
+  const double mx = (dxi == dxj ? 2.0 : 1.0) / 6.0, my = (dyi == dyj ? 2.0 : 1.0) / 6.0;
+  const double cxij = dxi == 1 ? 0.5 : -0.5, cxji = dxj == 1 ? 0.5 : -0.5;
+  const double cyji = dyj == 1 ? 0.5 : -0.5, cyij = dyi == 1 ? 0.5 : -0.5;
+  return t[0] * kx * my + t[2] * mx * ky + t[1] * (cxij * cyji + cxji * cyij);
+}
+
+__device__ __forceinline__ bool tensor_ok(const double* t) {
+  const double det = t[0] * t[2] - t[1] * t[1];
+  return t[0] > 0.0 && t[2] > 0.0 && det > 0.0 && isfinite(t[0] + t[1] + t[2]);
+}
+
+// Dense stiffness over the interior nodes of an nc x nc cell grid for a
+// tensor coefficient a3[cell][3] = (a11, a12, a22), one thread per node row:
+// the four cells around the node each add their element entries to the row.
+__global__ void k_ex_assemble_tensor(const double* __restrict__ a3, int nc, double* __restrict__ A,
+                                     int* __restrict__ status) {
+  const int m = nc - 1;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= m * m) return;
+  const int i = id / m + 1, j = id % m + 1;
+  const long N = (long)m * m;
+  double* row = A + (long)id * N;
+  for (int c = 0; c < 4; ++c) {
+    const int cx = i - 1 + (c >> 1), cy = j - 1 + (c & 1);
+    const double* t = a3 + ((long)cx * nc + cy) * 3;
+    if (!tensor_ok(t)) atomicOr(status, kBadCoefficient);
+    const int dxi = i - cx, dyi = j - cy;
+    for (int lj = 0; lj < 4; ++lj) {
+      const int dxj = lj >> 1, dyj = lj & 1;
+      const int ii = cx + dxj, jj = cy + dyj;
+      if (ii < 1 || jj < 1 || ii > m || jj > m) continue;
+      row[(long)(ii - 1) * m + (jj - 1)] += k_tensor2(t, dxi, dyi, dxj, dyj);
+    }
+  }
+}
+
+void launch_ex_assemble_tensor(const double* a3, int nc, double* A, int* status, hipStream_t st) {
+  const int m = nc - 1;
+  hipLaunchKernelGGL(k_ex_assemble_tensor, dim3((m * m + 255) / 256), dim3(256), 0, st, a3, nc, A, status);
+}
+
 // Entry (li, lj) of the trilinear element stiffness of a unit cube, local
 // node index 4 dx + 2 dy + dz: the gradient of a product of 1-D hats splits
 // into three products of 1-D stiffness (k: 1 on, -1 off the diagonal) and
@@ -551,7 +600,7 @@ void ex_to_nodal3(int nc, const double* x, int nrhs, double* u, bool back, hipSt
 // move to the right-hand side: b_i -= sum over boundary nodes j of A_ij u_j,
 // with the Q1 stiffness couplings of the cell coefficient a.
 __global__ void k_ex_load(int nc, int mode, const double* __restrict__ src, const double* __restrict__ a,
-                          const double* __restrict__ u, int nrhs, double* __restrict__ b) {
+                          const double* __restrict__ u, int nrhs, double* __restrict__ b, int tensor) {
   const int m = nc - 1;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long)m * m * nrhs) return;
@@ -573,7 +622,18 @@ __global__ void k_ex_load(int nc, int mode, const double* __restrict__ src, cons
       }
     v *= h * h / 36.0;
   }
-  if (i == 1 || j == 1 || i == m || j == m) {
+  if (tensor && (i == 1 || j == 1 || i == m || j == m)) {
+    const double* uc = u + (long)c * (nc + 1) * (nc + 1);
+    for (int e = 0; e < 4; ++e) {
+      const int cx = i - 1 + (e >> 1), cy = j - 1 + (e & 1);
+      const double* t = a + ((long)cx * nc + cy) * 3;
+      for (int lj = 0; lj < 4; ++lj) {
+        const int ii = cx + (lj >> 1), jj = cy + (lj & 1);
+        if (!(ii == 0 || jj == 0 || ii == nc || jj == nc)) continue;
+        v -= k_tensor2(t, i - cx, j - cy, lj >> 1, lj & 1) * uc[(long)ii * (nc + 1) + jj];
+      }
+    }
+  } else if (i == 1 || j == 1 || i == m || j == m) {
     const double a00 = a[(i - 1) * nc + (j - 1)], a10 = a[i * nc + (j - 1)];
     const double a01 = a[(i - 1) * nc + j], a11 = a[i * nc + j];
     const double* uc = u + (long)c * (nc + 1) * (nc + 1);
@@ -592,10 +652,10 @@ __global__ void k_ex_load(int nc, int mode, const double* __restrict__ src, cons
 }
 
 void ex_load(int nc, int mode, const double* src, const double* a, const double* u, int nrhs, double* b,
-             hipStream_t st) {
+             bool tensor, hipStream_t st) {
   const long tot = (long)(nc - 1) * (nc - 1) * nrhs;
   hipLaunchKernelGGL(k_ex_load, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nc, mode, src, a, u, nrhs,
-                     b);
+                     b, tensor ? 1 : 0);
 }
 
 // y[J][c] = (W g)[J][c] (zero on the rows a parent lacks); g is level-k [N][nrhs]

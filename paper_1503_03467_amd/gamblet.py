@@ -29,7 +29,8 @@ class GblOpts(ctypes.Structure):
                 ("kappa_coarse", ctypes.c_double), ("level_q_mass", ctypes.c_int),
                 ("rho_coarse", ctypes.c_int), ("window_tol", ctypes.c_double), ("exact", ctypes.c_int),
                 ("geometry", ctypes.c_int), ("source", ctypes.c_int), ("w_kind", ctypes.c_int),
-                ("dim", ctypes.c_int), ("autotune", ctypes.c_int), ("autotune_path", ctypes.c_char_p)]
+                ("dim", ctypes.c_int), ("autotune", ctypes.c_int), ("autotune_path", ctypes.c_char_p),
+                ("tensor", ctypes.c_int)]
 
 
 class GblSolveInfo(ctypes.Structure):
@@ -119,7 +120,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
               inner: str | None = None, kappa: float | None = None, kappa_coarse: float | None = None,
               level_q_mass: int = 0, rho_coarse: int = 0, window_tol: float = 0.0, exact: bool = False,
               geometry: int = 0, source: str = "cell", w_kind: int = 0, dim: int = 2, autotune: bool = False,
-              autotune_path: str | None = None) -> GblOpts:
+              autotune_path: str | None = None, tensor: bool = False) -> GblOpts:
     o = GblOpts()
     _check(lib().gbl_default_opts(ctypes.byref(o)))
     if inner is not None:
@@ -147,6 +148,7 @@ def make_opts(rho: int = 3, precision: str = "mixed", rtol: float = 1e-8, max_ou
     o.dim = int(dim)
     o.autotune = 1 if autotune else 0
     o.autotune_path = autotune_path.encode() if autotune_path else None
+    o.tensor = 1 if tensor else 0
     return o
 
 
@@ -188,19 +190,19 @@ class Hierarchy:
                  inner_iters_coarse: int | None = None, inner: str | None = None, kappa: float | None = None,
                  kappa_coarse: float | None = None, level_q_mass: int = 0, rho_coarse: int = 0,
                  window_tol: float = 0.0, exact: bool = False, geometry: int = 0, source: str = "cell",
-                 w_kind: int = 0, autotune: bool = False, autotune_path: str | None = None):
+                 w_kind: int = 0, autotune: bool = False, autotune_path: str | None = None, tensor: bool = False):
         n = a.shape[0]
         q = (n - geometry).bit_length() - 1
-        if n - geometry != (1 << q) or q < 2 or a.dim() not in (2, 3):
+        self.dim = 2 if tensor else a.dim()
+        if n - geometry != (1 << q) or q < 2 or self.dim not in (2, 3):
             raise ValueError("a must be [2^q]^d (geometry 0) or [2^q + 1]^d (geometry 1), d = 2 or 3, q >= 2")
-        self.dim = a.dim()
-        _require(a, (n,) * self.dim, "a")
+        _require(a, (n, n, 3) if tensor else (n,) * self.dim, "a")
         self.q, self.n, self.device = q, n, a.device
         self.exact = bool(exact)
         self.source = source
         self.opts = make_opts(rho, "fp64" if exact else precision, rtol, max_outer, inner_iters, max_rhs,
                               inner_iters_coarse, inner, kappa, kappa_coarse, level_q_mass, rho_coarse, window_tol,
-                              exact, geometry, source, w_kind, self.dim, autotune, autotune_path)
+                              exact, geometry, source, w_kind, self.dim, autotune, autotune_path, tensor)
         self.ws = torch.empty(workspace_bytes(q, self.opts), dtype=torch.uint8, device=a.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(a.device):

@@ -193,3 +193,13 @@ def test_three_dimensional_options_validated():
     assert b"q <= 4" in L.gbl_last_error(None)
     # q = 4: the dense level-4 stiffness alone is 3375^2 doubles
     assert P.workspace_bytes(4, P.make_opts(precision="fp64", exact=True, dim=3)) > 3375 ** 2 * 8
+
+
+def test_tensor_option_validated():
+    P, L = _lib()
+    sz = ctypes.c_size_t()
+    assert L.gbl_workspace_bytes(5, ctypes.byref(P.make_opts(precision="fp64", tensor=True)), ctypes.byref(sz)) == -1
+    assert L.gbl_workspace_bytes(3, ctypes.byref(P.make_opts(precision="fp64", exact=True, tensor=True, dim=3)),
+                                 ctypes.byref(sz)) == -1
+    o = P.make_opts(precision="fp64", exact=True, tensor=True)
+    assert P.workspace_bytes(5, o) > P.workspace_bytes(5, P.make_opts(precision="fp64", exact=True))
