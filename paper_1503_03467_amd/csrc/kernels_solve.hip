@@ -953,7 +953,7 @@ constexpr int kChunkRhs = sizeof(T) == 4 ? 8 : 4;
 template <typename T, int MC>
 __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int blk_begin, int ngroups, int nchunks,
                                                    int m, size_t zs) {
-  __shared__ double sh[16];
+  __shared__ double sh[16 * MC];
   extern __shared__ unsigned char red_raw[];
   T* red = reinterpret_cast<T*>(red_raw);   // [MC][3][nw][64]
   int grp, chunk;
@@ -980,11 +980,16 @@ __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int
 #pragma unroll
     for (int i = 0; i < 3; ++i) red[((r * 3 + i) * nw + wv) * 64 + lane] = acc[r][i];
   __syncthreads();
+  // (p, q) of every right-hand side of the chunk, then one reduction pass for
+  // all of them (one ticket per block instead of one per right-hand side)
+  double v[MC];
+#pragma unroll
+  for (int r = 0; r < MC; ++r) v[r] = 0.0;
   for (int r = 0; r < nr; ++r) {
     const CGLev<T> L = zlev(args.lv[l], (r0 + r) * zs);
-    double v[1] = {0.0};
     if (threadIdx.x < 64 && p < np * np) {
       const T beta = T(L.scal[kCBETA]);
+      double vr = 0.0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         T sum = T(0);
@@ -993,17 +998,26 @@ __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int
         const T pv = L.z[i * np2 + p] + beta * L.p[i * np2 + p];
         L.q[i * np2 + p] = qv;
         L.p[i * np2 + p] = pv;
-        v[0] += (double)(pv * qv);
+        vr += (double)(pv * qv);
       }
+#pragma unroll
+      for (int k = 0; k < MC; ++k)
+        if (k == r) v[k] = vr;
     }
-    block_sum<1>(v, sh);
-    bool last;
-    double res[1];
-    finish_reduction<1>(v, L.part, L.nblks, blk, L.cnt, res, &last, sh);
-    if (last) {
-      const double pq = res[0];
-      L.scal[kCPQ] = pq;
-      L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
+  }
+  block_sum<MC>(v, sh);
+  bool last;
+  double res[MC];
+  finish_reduction_rhs<MC>(v, nr, L0.part, zs, L0.nblks, blk, L0.cnt, res, &last, sh);
+  if (last) {
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      if (k < nr) {
+        const CGLev<T> L = zlev(args.lv[l], (r0 + k) * zs);
+        const double pq = res[k];
+        L.scal[kCPQ] = pq;
+        L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
+      }
     }
   }
 }

@@ -70,4 +70,48 @@ __device__ __forceinline__ void finish_reduction(const double (&v)[NV], double* 
   }
 }
 
+// The same for the right-hand sides of a block solve at once: value k of this
+// block goes to the partial array of right-hand side k (part0 + k * stride
+// bytes), one atomic ticket on cnt elects the last block, and that block
+// reduces every right-hand side's partials exactly as finish_reduction does
+// for one (same loops, same order), so each total is bit-identical to the
+// single-right-hand-side reduction.  Only the first nv values are used.
+template <int NV>
+__device__ __forceinline__ void finish_reduction_rhs(const double (&v)[NV], int nv, double* part0, size_t stride,
+                                                     int nblk, int blk, unsigned* cnt, double (&out)[NV],
+                                                     bool* is_last, double* sh) {
+  __shared__ int last_flag;
+  *is_last = false;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) reinterpret_cast<double*>(reinterpret_cast<char*>(part0) + k * stride)[blk] = v[k];
+    __threadfence();
+    const unsigned ticket = atomicAdd(cnt, 1u);
+    last_flag = (ticket == (unsigned)(nblk - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (last_flag) {
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double x = 0.0;
+      if (k < nv) {
+        const volatile double* vp =
+            reinterpret_cast<const volatile double*>(reinterpret_cast<const char*>(part0) + k * stride);
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) x += vp[b];
+      }
+      acc[k] = x;
+    }
+    block_sum<NV>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) out[k] = acc[k];
+      *cnt = 0u;
+      *is_last = true;
+    }
+  }
+}
+
 }  // namespace gbl
