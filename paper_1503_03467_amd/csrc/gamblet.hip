@@ -121,10 +121,9 @@ struct Layout {
   size_t cgv_off[kMaxLevels] = {};   // T CG vectors per level (5 x 3 np^2)
   size_t cgscal_off = 0;     // doubles
   size_t cgpart_off[kMaxLevels] = {};
-  size_t cgcnt_off = 0;
   size_t fcg_off = 0;        // finest-level CG vectors (9 x 3 np^2, T)
   size_t fcgpart_off = 0;    // tile partials (2 per tile)
-  size_t fcgscal_off = 0;    // kNumFineScalars doubles + ticket
+  size_t fcgscal_off = 0;    // kNumFineScalars doubles
   size_t elog_off = 0;       // per-iteration error estimates of the outer iteration (max_outer + 2 doubles)
   size_t tr_off[kMaxLevels] = {};   // FP64 level vectors of the gamblet transform (nk^2 each)
   size_t sel_off = 0;        // selection state of the compression threshold (4 x 64-bit words + histogram)
@@ -327,8 +326,7 @@ int make_layout(int q, const gbl_opts* o, Layout& L, std::string& msg) {
     }
   }
   L.cgscal_off = b; b = align_up(b + (size_t)kMaxLevels * kNumCGScalars * 8);
-  L.cgcnt_off = b; b = align_up(b + (size_t)kMaxLevels * sizeof(unsigned));
-  L.fcgscal_off = b; b = align_up(b + (kNumFineScalars + 1) * 8);
+  L.fcgscal_off = b; b = align_up(b + kNumFineScalars * 8);
   L.elog_off = b; b = align_up(b + ((size_t)o->max_outer + 2) * 8);
   L.solve_stride = align_up(b - L.solve_off);
   b = L.solve_off + (size_t)L.M * L.solve_stride;
@@ -526,7 +524,6 @@ CGArgs<T> make_cg_args(gbl_ctx* c) {
     v.q = base + 12 * np2;
     v.scal = reinterpret_cast<double*>(c->ws + L.cgscal_off) + l * kNumCGScalars;
     v.part = reinterpret_cast<double*>(c->ws + L.cgpart_off[k]);
-    v.cnt = reinterpret_cast<unsigned*>(c->ws + L.cgcnt_off) + l;
     v.np = g.nk / 2;
     v.t = g.t;
     v.fine = (k == L.q) ? 1 : 0;
@@ -585,7 +582,6 @@ CGArgs<T> make_cgq_args(gbl_ctx* c) {
   // Chebyshev steps use no inner products; the scalar slot is level q - 1's
   v.scal = reinterpret_cast<double*>(c->ws + L.cgscal_off);
   v.part = reinterpret_cast<double*>(c->ws + L.cgpart_off[k]);
-  v.cnt = reinterpret_cast<unsigned*>(c->ws + L.cgcnt_off);
   v.np = g.nk / 2;
   v.t = g.t;
   v.fine = 1;
@@ -618,7 +614,6 @@ FineCG<T> make_fine_cg(gbl_ctx* c) {
   F.s[0] = base + 21 * np2;
   F.s[1] = base + 24 * np2;
   F.scal = reinterpret_cast<double*>(c->ws + L.fcgscal_off);
-  F.cnt = reinterpret_cast<unsigned*>(F.scal + kNumFineScalars);
   F.part = reinterpret_cast<double*>(c->ws + L.fcgpart_off);
   F.np = g.nk / 2;
   const int tp = std::min(16, F.np);

@@ -13,16 +13,6 @@
 
 namespace gbl {
 
-// Partial sums only (no ticket): thread 0 stores this block's sums; a later
-// kernel or the host adds them in block order.
-template <int NV>
-__device__ __forceinline__ void write_partials(const double (&v)[NV], double* part, int nblk, int blk) {
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[k * nblk + blk] = v[k];
-  }
-}
-
 // Every block adds the nblk partials of sum k (fixed order per thread, then
 // a fixed-order block reduction); the total is broadcast through LDS.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int k, double* sh) {
@@ -727,18 +717,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CGArgs<T> args, size_t zs) {
     }
   }
   block_sum<1>(v, sh);
-  bool last;
-  double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last, sh);
-  if (last) {
-    if (L.nwin > 0) {
-      L.scal[kCRZD] = res[0];   // completed by the window correction
-    } else {
-      L.scal[kCRZ] = res[0];
-      L.scal[kCBETA] = 0.0;
-      L.scal[kCALPHA] = 0.0;
-    }
-  }
+  write_partials<1>(v, L.part, L.nblk, blk);
 }
 
 // Coarser levels, stored block stencil.  A workgroup covers 64 consecutive
@@ -834,14 +813,7 @@ __global__ __launch_bounds__(1024) void k_cg_spmv(CGArgs<T> args, int it, int bl
     }
   }
   block_sum<1>(v, sh);
-  bool last;
-  double res[1];
-  finish_reduction<1>(v, L.part, L.nblks, blk, L.cnt, res, &last, sh);
-  if (last) {
-    const double pq = res[0];
-    L.scal[kCPQ] = pq;
-    L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
-  }
+  write_partials<1>(v, L.part, L.nblks, blk);
 }
 
 template <typename T>
@@ -874,17 +846,79 @@ __global__ __launch_bounds__(256) void k_cg_update(CGArgs<T> args, int it, size_
     }
   }
   block_sum<1>(v, sh);
-  bool last;
+  write_partials<1>(v, L.part, L.nblk, blk);
+}
+
+// The scalar steps of the subband CG, one workgroup per (level, right-hand
+// side): the per-block partials that the init, operator, update or window
+// kernel stored are added in a fixed order (no tickets: a release fence per
+// block of those grids costs more than the streaming work itself) and
+//   init:    (r, z) -> rz, beta = alpha = 0
+//   spmv:    (p, q) -> pq, alpha = rz / pq
+//   update:  (r, z) -> beta = rz_new / rz, rz = rz_new
+// On a level with window corrections the (r, D^-1 r) part goes to kCRZD and
+// the window step completes it:
+//   window:  rz_new = kCRZD + (r, sum of window terms), then as update (or
+//            as init for the first one).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_scalars(CGArgs<T> args, int it, int phase, size_t zs) {
+  __shared__ double sh[16];
+  const CGLev<T> L = zlev(args.lv[blockIdx.x], blockIdx.z * zs);
+  int nblk = L.nblk;
+  switch (phase) {
+    case kCGPhaseInit: break;
+    case kCGPhaseSpmv:
+      if (it >= L.iters) return;
+      nblk = L.nblks;
+      break;
+    case kCGPhaseUpdate:
+      if (it >= L.iters) return;
+      break;
+    case kCGPhaseWinInit:
+      if (L.nwin <= 0) return;
+      break;
+    default:   // kCGPhaseWin
+      if (L.nwin <= 0 || it >= L.iters - 1) return;
+      break;
+  }
   double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last, sh);
-  if (last) {
-    const double rz_new = res[0];
-    if (L.nwin > 0 && it < L.iters - 1) {
-      L.scal[kCRZD] = rz_new;   // completed by the window correction
-    } else {
-      const double rz = L.scal[kCRZ];
-      L.scal[kCBETA] = (rz > 0.0) ? rz_new / rz : 0.0;
-      L.scal[kCRZ] = rz_new;
+  total_partials<1>(L.part, nblk, res, sh);
+  if (threadIdx.x != 0) return;
+  const double s = res[0];
+  double* sc = L.scal;
+  switch (phase) {
+    case kCGPhaseInit:
+      if (L.nwin > 0) {
+        sc[kCRZD] = s;
+      } else {
+        sc[kCRZ] = s;
+        sc[kCBETA] = 0.0;
+        sc[kCALPHA] = 0.0;
+      }
+      break;
+    case kCGPhaseSpmv:
+      sc[kCPQ] = s;
+      sc[kCALPHA] = (s > 0.0) ? sc[kCRZ] / s : 0.0;
+      break;
+    case kCGPhaseUpdate:
+      if (L.nwin > 0 && it < L.iters - 1) {
+        sc[kCRZD] = s;
+      } else {
+        const double rz = sc[kCRZ];
+        sc[kCBETA] = (rz > 0.0) ? s / rz : 0.0;
+        sc[kCRZ] = s;
+      }
+      break;
+    case kCGPhaseWinInit:
+      sc[kCRZ] = sc[kCRZD] + s;
+      sc[kCBETA] = 0.0;
+      sc[kCALPHA] = 0.0;
+      break;
+    default: {
+      const double rz = sc[kCRZD] + s, old = sc[kCRZ];
+      sc[kCBETA] = (old > 0.0) ? rz / old : 0.0;
+      sc[kCRZ] = rz;
+      break;
     }
   }
 }
@@ -980,8 +1014,8 @@ __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int
 #pragma unroll
     for (int i = 0; i < 3; ++i) red[((r * 3 + i) * nw + wv) * 64 + lane] = acc[r][i];
   __syncthreads();
-  // (p, q) of every right-hand side of the chunk, then one reduction pass for
-  // all of them (one ticket per block instead of one per right-hand side)
+  // (p, q) of every right-hand side of the chunk, block sums for all of them
+  // in one pass, each stored as that right-hand side's partial
   double v[MC];
 #pragma unroll
   for (int r = 0; r < MC; ++r) v[r] = 0.0;
@@ -1006,19 +1040,10 @@ __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int
     }
   }
   block_sum<MC>(v, sh);
-  bool last;
-  double res[MC];
-  finish_reduction_rhs<MC>(v, nr, L0.part, zs, L0.nblks, blk, L0.cnt, res, &last, sh);
-  if (last) {
+  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < MC; ++k) {
-      if (k < nr) {
-        const CGLev<T> L = zlev(args.lv[l], (r0 + k) * zs);
-        const double pq = res[k];
-        L.scal[kCPQ] = pq;
-        L.scal[kCALPHA] = (pq > 0.0) ? L.scal[kCRZ] / pq : 0.0;
-      }
-    }
+    for (int k = 0; k < MC; ++k)
+      if (k < nr) zsh(L0.part, (size_t)k * zs)[blk] = v[k];
   }
 }
 
@@ -1079,8 +1104,13 @@ __global__ __launch_bounds__(1024) void k_cheb_step_mr(CGArgs<T> args, ChebStep 
 }
 
 template <typename T>
+void launch_cg_scalars(const CGArgs<T>& a, int it, int phase, hipStream_t st, Zb zb) {
+  hipLaunchKernelGGL(k_cg_scalars<T>, dim3(a.nlev, 1, zb.m), dim3(256), 0, st, a, it, phase, zb.zs);
+}
+template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nblocks, 1, zb.m), dim3(256), 0, st, a, zb.zs);
+  launch_cg_scalars<T>(a, 0, kCGPhaseInit, st, zb);
 }
 // The largest coarse level (first in the list) gets its own launch with
 // one wavefront per stencil row; the smaller levels share a second launch.
@@ -1096,6 +1126,7 @@ void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb 
     if (nblocks > n0)
       hipLaunchKernelGGL(k_cg_spmv<T>, dim3(xcd_group_grid(nblocks - n0, 1)), dim3(64 * w1), 0, st, a, it, n0,
                          nblocks - n0, 1, zb.zs);
+    launch_cg_scalars<T>(a, it, kCGPhaseSpmv, st, zb);
     return;
   }
   constexpr int MC = kChunkRhs<T>;
@@ -1105,10 +1136,12 @@ void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb 
   if (nblocks > n0)
     hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(nblocks - n0, nch)), dim3(64 * w1),
                        (size_t)MC * 3 * w1 * 64 * sizeof(T), st, a, it, n0, nblocks - n0, nch, zb.m, zb.zs);
+  launch_cg_scalars<T>(a, it, kCGPhaseSpmv, st, zb);
 }
 template <typename T>
 void launch_cg_update(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
   hipLaunchKernelGGL(k_cg_update<T>, dim3(nblocks, 1, zb.m), dim3(256), 0, st, a, it, zb.zs);
+  launch_cg_scalars<T>(a, it, kCGPhaseUpdate, st, zb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1531,21 +1564,28 @@ __global__ __launch_bounds__(256) void k_fine_cg(FineCG<T> F0, int it, size_t zs
     }
   }
   block_sum<2>(v, sh);
-  bool last;
+  write_partials<2>(v, F.part, F.nblk, blk);
+}
+
+// Scalars of the finest-level CG step from the tile partials of (r, u) and
+// (w, u), added in a fixed order by one workgroup per right-hand side.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fine_cg_scalars(FineCG<T> F0, int it, size_t zs) {
+  __shared__ double sh[2 * 16];
+  const FineCG<T> F = zfine(F0, blockIdx.z * zs);
   double res[2];
-  finish_reduction<2>(v, F.part, F.nblk, blk, F.cnt, res, &last, sh);
-  if (last) {
-    const double gam = res[0], del = res[1];
-    double b = 0.0, eta = del;
-    if (it > 0) {
-      const double gprev = F.scal[kFGamma], aprev = F.scal[kFAlpha];
-      b = (gprev > 0.0) ? gam / gprev : 0.0;
-      eta = (aprev != 0.0) ? del - b * gam / aprev : del;
-    }
-    F.scal[kFGamma] = gam;
-    F.scal[kFBeta] = b;
-    F.scal[kFAlpha] = (eta > 0.0) ? gam / eta : 0.0;
+  total_partials<2>(F.part, F.nblk, res, sh);
+  if (threadIdx.x != 0) return;
+  const double gam = res[0], del = res[1];
+  double b = 0.0, eta = del;
+  if (it > 0) {
+    const double gprev = F.scal[kFGamma], aprev = F.scal[kFAlpha];
+    b = (gprev > 0.0) ? gam / gprev : 0.0;
+    eta = (aprev != 0.0) ? del - b * gam / aprev : del;
   }
+  F.scal[kFGamma] = gam;
+  F.scal[kFBeta] = b;
+  F.scal[kFAlpha] = (eta > 0.0) ? gam / eta : 0.0;
 }
 
 // Last update x += a p after the final iteration (no operator application).
@@ -1564,6 +1604,7 @@ template <typename T>
 void launch_fine_cg(const FineCG<T>& f, int it, hipStream_t st, Zb zb) {
   if (it >= 0) {
     hipLaunchKernelGGL(k_fine_cg<T>, dim3(f.nblk, 1, zb.m), dim3(256), 0, st, f, it, zb.zs);
+    hipLaunchKernelGGL(k_fine_cg_scalars<T>, dim3(1, 1, zb.m), dim3(256), 0, st, f, it, zb.zs);
   } else {
     const size_t n = 3 * (size_t)f.np * f.np;
     hipLaunchKernelGGL(k_fine_cg_finish<T>, dim3((unsigned)((n + 255) / 256), 1, zb.m), dim3(256), 0, st, f, it,
@@ -1750,6 +1791,7 @@ void launch_mass_nodal_dots(int n, int rho, const double* Y, const T* v, double*
   template void launch_prolong<T>(const LevelGeom&, const T*, const T*, const T*, T*, bool, hipStream_t, Zb); \
   template void launch_coarse_solve<T>(const double*, const T*, T*, hipStream_t);                       \
   template void launch_cg_init<T>(const CGArgs<T>&, int, hipStream_t, Zb);                              \
+  template void launch_cg_scalars<T>(const CGArgs<T>&, int, int, hipStream_t, Zb);                      \
   template void launch_cg_spmv<T>(const CGArgs<T>&, int, int, hipStream_t, Zb);                         \
   template void launch_cg_update<T>(const CGArgs<T>&, int, int, hipStream_t, Zb);                       \
   template void launch_zero<T>(size_t, T*, hipStream_t, Zb);                                            \

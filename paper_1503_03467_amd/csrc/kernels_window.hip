@@ -179,8 +179,9 @@ __global__ __launch_bounds__(256) void k_win_apply(CGArgs<T> args, int it, size_
 }
 
 // z += sum over the kept windows containing the parent of their Y entries
-// (a fixed order: origins by dx, then dy), and the (r, z) update of the
-// level: (r, z) = (r, D^-1 r) (left in kCRZD by the CG kernel) + (r, sum).
+// (a fixed order: origins by dx, then dy), and the per-block partials of
+// (r, sum); the scalar step then forms (r, z) = (r, D^-1 r) (left in kCRZD
+// by the CG kernel) + (r, sum).
 template <typename T>
 __global__ __launch_bounds__(256) void k_win_gather(CGLev<T> L0, int it, int init, size_t zs) {
   __shared__ double sh[16];
@@ -215,20 +216,7 @@ __global__ __launch_bounds__(256) void k_win_gather(CGLev<T> L0, int it, int ini
     }
   }
   block_sum<1>(v, sh);
-  bool last;
-  double res[1];
-  finish_reduction<1>(v, L.part, L.nblk, blk, L.cnt, res, &last, sh);
-  if (last) {
-    const double rz = L.scal[kCRZD] + res[0];
-    if (init) {
-      L.scal[kCBETA] = 0.0;
-      L.scal[kCALPHA] = 0.0;
-    } else {
-      const double old = L.scal[kCRZ];
-      L.scal[kCBETA] = (old > 0.0) ? rz / old : 0.0;
-    }
-    L.scal[kCRZ] = rz;
-  }
+  write_partials<1>(v, L.part, L.nblk, blk);
 }
 
 template <typename T>
@@ -242,6 +230,7 @@ void launch_win_correct(const CGArgs<T>& a, int it, bool init, hipStream_t st, Z
     hipLaunchKernelGGL(k_win_gather<T>, dim3(a.lv[l].nblk, 1, zb.m), dim3(256), 0, st, a.lv[l], it, init ? 1 : 0,
                        zb.zs);
   }
+  launch_cg_scalars<T>(a, it, init ? kCGPhaseWinInit : kCGPhaseWin, st, zb);
 }
 
 template void launch_win_build<float>(const LevelGeom&, const float*, double, int, int*, int*, float*, unsigned*,

@@ -6,8 +6,11 @@
 namespace gbl {
 
 // ---------------------------------------------------------------------------
-// Reductions: block sum, then the last block to finish (atomic ticket) adds
-// the per-block partials in a fixed order -- deterministic, no waiting.
+// Reductions: block sum, then the per-block partials are added in a fixed
+// order -- deterministic, no waiting.  Either the last block to finish adds
+// them (atomic ticket; each block then pays an agent-scope release fence,
+// which writes back its XCD's L2, so this is kept for small grids), or the
+// kernel only stores its partials and a one-workgroup step adds them.
 // ---------------------------------------------------------------------------
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
@@ -70,48 +73,32 @@ __device__ __forceinline__ void finish_reduction(const double (&v)[NV], double* 
   }
 }
 
-// The same for the right-hand sides of a block solve at once: value k of this
-// block goes to the partial array of right-hand side k (part0 + k * stride
-// bytes), one atomic ticket on cnt elects the last block, and that block
-// reduces every right-hand side's partials exactly as finish_reduction does
-// for one (same loops, same order), so each total is bit-identical to the
-// single-right-hand-side reduction.  Only the first nv values are used.
+// Partial sums only (no ticket): thread 0 stores this block's sums (after
+// block_sum); a later kernel adds them in block order.
 template <int NV>
-__device__ __forceinline__ void finish_reduction_rhs(const double (&v)[NV], int nv, double* part0, size_t stride,
-                                                     int nblk, int blk, unsigned* cnt, double (&out)[NV],
-                                                     bool* is_last, double* sh) {
-  __shared__ int last_flag;
-  *is_last = false;
+__device__ __forceinline__ void write_partials(const double (&v)[NV], double* part, int nblk, int blk) {
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (k < nv) reinterpret_cast<double*>(reinterpret_cast<char*>(part0) + k * stride)[blk] = v[k];
-    __threadfence();
-    const unsigned ticket = atomicAdd(cnt, 1u);
-    last_flag = (ticket == (unsigned)(nblk - 1)) ? 1 : 0;
+    for (int k = 0; k < NV; ++k) part[k * nblk + blk] = v[k];
   }
-  __syncthreads();
-  if (last_flag) {
-    __threadfence();
-    double acc[NV];
+}
+
+// Total of nblk per-block partial sums by one workgroup, in the order the
+// last block of finish_reduction uses (thread b adds partials b, b +
+// blockDim.x, ... in turn, then the block sum), so for the same block size a
+// reduction split into a partial-writing kernel and this step gives the same
+// bits as the ticketed one.  Thread 0 receives the totals.  Sum k of block b sits at
+// part[k * nblk + b].  Must be called by all threads of the block.
+template <int NV>
+__device__ __forceinline__ void total_partials(const double* __restrict__ part, int nblk, double (&out)[NV],
+                                               double* sh) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double x = 0.0;
-      if (k < nv) {
-        const volatile double* vp =
-            reinterpret_cast<const volatile double*>(reinterpret_cast<const char*>(part0) + k * stride);
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) x += vp[b];
-      }
-      acc[k] = x;
-    }
-    block_sum<NV>(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) out[k] = acc[k];
-      *cnt = 0u;
-      *is_last = true;
-    }
+  for (int k = 0; k < NV; ++k) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) x += part[k * nblk + b];
+    out[k] = x;
   }
+  block_sum<NV>(out, sh);
 }
 
 }  // namespace gbl

@@ -30,6 +30,12 @@ constexpr int kCALPHA = 2;
 constexpr int kCBETA = 3;
 constexpr int kCRZD = 4;   // (r, D^-1 r) of a level with window corrections, before their part
 constexpr int kNumCGScalars = 5;
+// steps of k_cg_scalars (which partial sums it adds and which scalars it sets)
+constexpr int kCGPhaseInit = 0;
+constexpr int kCGPhaseSpmv = 1;
+constexpr int kCGPhaseUpdate = 2;
+constexpr int kCGPhaseWinInit = 3;
+constexpr int kCGPhaseWin = 4;
 
 template <typename T>
 struct CGLev {
@@ -42,8 +48,7 @@ struct CGLev {
   T* p;
   T* q;            // B p
   double* scal;    // kNumCGScalars
-  double* part;    // one partial sum per block
-  unsigned* cnt;   // reduction ticket
+  double* part;    // one partial sum per block (added by k_cg_scalars)
   int np;          // parents per dimension (n_{k-1})
   int t;           // parent-stencil half-width
   int fine;        // k == q
@@ -94,7 +99,6 @@ __device__ __forceinline__ CGLev<T> zlev(CGLev<T> L, size_t off) {
   L.q = zsh(L.q, off);
   L.scal = zsh(L.scal, off);
   L.part = zsh(L.part, off);
-  L.cnt = zsh(L.cnt, off);
   L.Y = zsh(L.Y, off);
   return L;
 }
@@ -125,7 +129,6 @@ struct FineCG {
   T* s[2];
   double* scal;
   double* part;
-  unsigned* cnt;
   int np;
   int nblk;          // tiles
 };
@@ -142,7 +145,6 @@ __device__ __forceinline__ FineCG<T> zfine(FineCG<T> F, size_t off) {
   }
   F.scal = zsh(F.scal, off);
   F.part = zsh(F.part, off);
-  F.cnt = zsh(F.cnt, off);
   return F;
 }
 
@@ -229,6 +231,8 @@ void launch_restrict_chain(const ChainArgs<T>& c, hipStream_t st, Zb zb = Zb());
 template <typename T>
 void launch_prolong_chain(const ChainArgs<T>& c, const double* L1, hipStream_t st, Zb zb = Zb());
 
+template <typename T>
+void launch_cg_scalars(const CGArgs<T>& a, int it, int phase, hipStream_t st, Zb zb = Zb());
 template <typename T>
 void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb = Zb());
 template <typename T>
