@@ -611,43 +611,17 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
   const int ti = parent_type(fine != 0, cx, cy);
   if (tid == 0) sm.bad = 0;
 
-  // scaling and right-hand side
-  for (int r = tid; r < P16; r += 256) {
-    T scale = T(1), rv = T(0);
-    if (r < p) {
-      const int lp = r / 3, tt = r - 3 * lp;
-      const int px = x0 + lp / wy, py = y0 + lp % wy;
-      sm.rowinfo[r] = (px << 20) | (py << 8) | tt;
-      const T d = B[b_index(t * TT + t, tt * 4, px * nc + py, TT)];
-      if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
-      else atomicOr(status, kBadPivot);
-      const int tp = parent_type(fine != 0, px, py);
-      if (abs(px - cx) <= t && abs(py - cy) <= t && !is_pad_row(tp, tt)) {
-        double acc = 0.0;
-        for (int dd = 0; dd < 4; ++dd) {
-          const double wd = wcoef(tp, tt, dd);
-          if (wd == 0.0) continue;
-          const int fx = 2 * px + (dd >> 1), fy = 2 * py + (dd & 1);
-          double inner = 0.0;
-          for (int e = 0; e < 4; ++e) {
-            const double pe = pibar(ti, e);
-            if (pe == 0.0) continue;
-            const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
-            const int ox = gx - fx + s, oy = gy - fy + s;
-            if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
-            inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
-          }
-          acc += wd * inner;
-        }
-        rv = T(-acc);
-      }
-    }
-    sm.sc[r] = scale;
-    sm.rhs[r] = rv * scale;
+  // patch rows: parent and subband index (integer work only)
+  for (int r = tid; r < p; r += 256) {
+    const int lp = r / 3, tt = r - 3 * lp;
+    sm.rowinfo[r] = ((x0 + lp / wy) << 20) | ((y0 + lp % wy) << 8) | tt;
   }
   __syncthreads();
 
-  // this wavefront's tiles, loaded from B^(k)
+  // this wavefront's tiles, gathered from B^(k) unscaled, issued together
+  // with the loads of the scaling and right-hand side below (one round of
+  // global-memory latency instead of two); the scaling is applied after the
+  // barrier, in the same order of products
   acc_t acc[SLOTS];
 #pragma unroll
   for (int m = 0; m < SLOTS; ++m) {
@@ -668,16 +642,65 @@ __device__ __forceinline__ void patch_chol_mfma_body(CholLds<T, NT>& sm, const T
             T bv = T(0);
             if (ox >= 0 && oy >= 0 && ox < TT && oy < TT)
               bv = Bp[(size_t)(rx * nc + ry) * (TT * TT * 9) + (ox * TT + oy) * 9 + trr * 3 + tcc];
-            v = bv * sm.sc[i] * sm.sc[j];
+            v = bv;
           } else {
             v = T(0);
           }
         } else if (i == p && j < p) {
-          v = sm.rhs[j];
+          v = T(0);   // right-hand side, filled in after the barrier
         } else {
           v = (i == j) ? T(1) : T(0);
         }
         acc[m][r] = v;
+      }
+    }
+  }
+
+  // scaling and right-hand side
+  for (int r = tid; r < P16; r += 256) {
+    T scale = T(1), rv = T(0);
+    if (r < p) {
+      const int lp = r / 3, tt = r - 3 * lp;
+      const int px = x0 + lp / wy, py = y0 + lp % wy;
+      const T d = B[b_index(t * TT + t, tt * 4, px * nc + py, TT)];
+      if (d > T(0)) scale = T(1) / my_sqrt<T>(d);
+      else atomicOr(status, kBadPivot);
+      const int tp = parent_type(fine != 0, px, py);
+      if (abs(px - cx) <= t && abs(py - cy) <= t && !is_pad_row(tp, tt)) {
+        double rsum = 0.0;
+        for (int dd = 0; dd < 4; ++dd) {
+          const double wd = wcoef(tp, tt, dd);
+          if (wd == 0.0) continue;
+          const int fx = 2 * px + (dd >> 1), fy = 2 * py + (dd & 1);
+          double inner = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double pe = pibar(ti, e);
+            if (pe == 0.0) continue;
+            const int gx = 2 * cx + (e >> 1), gy = 2 * cy + (e & 1);
+            const int ox = gx - fx + s, oy = gy - fy + s;
+            if (ox < 0 || oy < 0 || ox >= S || oy >= S) continue;
+            inner += pe * (double)A[(size_t)(ox * S + oy) * nk * nk + fx * nk + fy];
+          }
+          rsum += wd * inner;
+        }
+        rv = T(-rsum);
+      }
+    }
+    sm.sc[r] = scale;
+    sm.rhs[r] = rv * scale;
+  }
+  __syncthreads();
+
+  // scaled patch matrix and the right-hand side row
+#pragma unroll
+  for (int m = 0; m < SLOTS; ++m) {
+    const int I = tile_row(4 * m + W, NTILE, NT), J = tile_col(4 * m + W);
+    if (I < nta) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + Mfma<T>::row(l, r), j = 16 * J + lc;
+        if (i < p && j < p && i >= j) acc[m][r] = acc[m][r] * sm.sc[i] * sm.sc[j];
+        else if (i == p && j < p) acc[m][r] = sm.rhs[j];
       }
     }
   }

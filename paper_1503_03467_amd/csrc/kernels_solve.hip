@@ -282,6 +282,21 @@ __global__ void k_convert(size_t len, const TS* __restrict__ s, TD* __restrict__
   if (i < len) d[i] = TD(s[i]);
 }
 
+// Right-hand sides per chunk of the kernels that read a shared operator once
+// for several right-hand sides (registers bound the count).
+template <typename T>
+constexpr int kChunkRhs = sizeof(T) == 4 ? 8 : 4;
+
+// Copy r of a per-solve vector (each copy zs bytes after the previous one).
+template <typename P>
+__device__ __forceinline__ P* rhs_ptr(P* p, int r, size_t zs) {
+  return reinterpret_cast<P*>(reinterpret_cast<char*>(p) + (size_t)r * zs);
+}
+template <typename P>
+__device__ __forceinline__ const P* rhs_ptr(const P* p, int r, size_t zs) {
+  return reinterpret_cast<const P*>(reinterpret_cast<const char*>(p) + (size_t)r * zs);
+}
+
 // ---------------------------------------------------------------------------
 // Restriction g^(k-1)_i = sum_c R_{i,c} g^(k)_c (eq. g^(k) = R g^(k+1),
 // Section 4.7; the right-hand side step of Algorithm 2).  One thread per coarse slot; R is
@@ -334,6 +349,10 @@ __global__ __launch_bounds__(128) void k_restrict(const T* __restrict__ R, const
   if (w == 0 && (int)blockIdx.x * 64 + lane < nc * nc) gc[i] = acc + red[lane];
 }
 
+// One launch per level for every right-hand side of a block (grid z): a
+// variant that applied each R word to a chunk of 8 right-hand sides was 2.5x
+// slower at 2048 x 2048 cells (the gathers of g, reused by about 80 coarse
+// slots each, then come from 8 vectors at once and miss the L2).
 template <typename T>
 void launch_restrict(const LevelGeom& L, const T* R, const T* gf, T* gc, hipStream_t st, Zb zb) {
   const int nc = L.nk / 2;
@@ -384,6 +403,39 @@ __device__ __forceinline__ T prolong_at_r(const T* __restrict__ R, const T* __re
     }
   }
   return acc;
+}
+
+// (R^T v)_c for a chunk of right-hand sides: each R word is loaded once and
+// applied to the nr coarse vectors (copies zs bytes apart), each sum in the
+// order of prolong_at_r.
+template <typename T, int RHO, int MC>
+__device__ __forceinline__ void prolong_at_mr(const T* __restrict__ R, const T* __restrict__ vc0, size_t zs, int nr,
+                                              int nk, int fx, int fy, T (&acc)[MC]) {
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int px = fx >> 1, py = fy >> 1;
+  constexpr int rw = 2 * (2 * RHO + 1);
+#pragma unroll
+  for (int dx = -RHO; dx <= RHO; ++dx) {
+    const int ix = px + dx;
+    const bool okx = ix >= 0 && ix < nc;
+    const int ixc = min(max(ix, 0), nc - 1);
+    const int bx = fx - 2 * (ixc - RHO);
+#pragma unroll
+    for (int dy = -RHO; dy <= RHO; ++dy) {
+      const int iy = py + dy;
+      const bool ok = okx && iy >= 0 && iy < nc;
+      const int iyc = min(max(iy, 0), nc - 1);
+      const int by = fy - 2 * (iyc - RHO);
+      const int bxc = min(max(bx, 0), rw - 1), byc = min(max(by, 0), rw - 1);
+      const int i = ixc * nc + iyc;
+      const T rv = R[(size_t)(bxc * rw + byc) * nc2 + i];
+      const T okv = T(ok ? 1 : 0);
+#pragma unroll
+      for (int r = 0; r < MC; ++r)
+        if (r < nr) acc[r] += rv * (rhs_ptr(vc0, r, zs)[i] * okv);
+    }
+  }
 }
 
 template <typename T>
@@ -438,9 +490,67 @@ __global__ void k_prolong(const T* __restrict__ R, const T* __restrict__ vc, con
   else vf[id] = acc;
 }
 
+// v^(k) = R^T v^(k-1) + W^T w^(k) of a coarser level for a chunk of
+// right-hand sides (R read once per chunk; per right-hand side the sums of
+// k_prolong in the same order).
+template <typename T, int RHO, int MC>
+__global__ __launch_bounds__(256) void k_prolong_mr(const T* __restrict__ R, const T* __restrict__ vc0,
+                                                    const T* __restrict__ w0, T* __restrict__ vf0, int nk, int m,
+                                                    size_t zs) {
+  const int r0 = (int)blockIdx.z * MC;
+  const int nr = min(MC, m - r0);
+  vc0 = rhs_ptr(vc0, r0, zs);
+  w0 = rhs_ptr(w0, r0, zs);
+  vf0 = rhs_ptr(vf0, r0, zs);
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nk * nk) return;
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  const int fx = id / nk, fy = id % nk;
+  T acc[MC];
+#pragma unroll
+  for (int r = 0; r < MC; ++r) acc[r] = T(0);
+  prolong_at_mr<T, RHO, MC>(R, vc0, zs, nr, nk, fx, fy, acc);
+  const int px = fx >> 1, py = fy >> 1;
+  const int d = 2 * (fx & 1) + (fy & 1);
+  const int tp = parent_type(false, px, py);
+  const int p = px * nc + py;
+#pragma unroll
+  for (int r = 0; r < MC; ++r) {
+    if (r < nr) {
+      const T* w = rhs_ptr(w0, r, zs);
+      T a = acc[r];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const T wt = w[t * nc2 + p];
+        a += T(wcoef(tp, t, d)) * wt;
+      }
+      rhs_ptr(vf0, r, zs)[id] = a;
+    }
+  }
+}
+
+template <typename T, int RHO>
+void launch_prolong_mr(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, hipStream_t st, Zb zb) {
+  constexpr int MC = kChunkRhs<T>;
+  const int tot = L.nk * L.nk;
+  hipLaunchKernelGGL((k_prolong_mr<T, RHO, MC>), dim3((tot + 255) / 256, 1, (zb.m + MC - 1) / MC), dim3(256), 0, st,
+                     R, vc, w, vf, L.nk, zb.m, zb.zs);
+}
+
 template <typename T>
 void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
                     hipStream_t st, Zb zb) {
+  if (zb.m > 1 && !fine) {
+    switch (L.rho) {
+      case 1: launch_prolong_mr<T, 1>(L, R, vc, w, vf, st, zb); break;
+      case 2: launch_prolong_mr<T, 2>(L, R, vc, w, vf, st, zb); break;
+      case 3: launch_prolong_mr<T, 3>(L, R, vc, w, vf, st, zb); break;
+      case 4: launch_prolong_mr<T, 4>(L, R, vc, w, vf, st, zb); break;
+      default: launch_prolong_mr<T, 5>(L, R, vc, w, vf, st, zb); break;
+    }
+    return;
+  }
   const int tot = L.nk * L.nk;
   hipLaunchKernelGGL(k_prolong<T>, dim3((tot + 255) / 256, 1, zb.m), dim3(256), 0, st, R, vc, w, vf, L.nk, L.rho,
                      fine ? 1 : 0, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, (double*)nullptr,
@@ -491,9 +601,93 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots(const T* __restrict__
   write_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
 
+// The same for a chunk of right-hand sides (R read once per chunk); per
+// right-hand side the sums, block sums and partials of k_prolong_fine_dots.
+template <typename T, int RHO, int MC>
+__global__ __launch_bounds__(256) void k_prolong_fine_dots_mr(const T* __restrict__ R, const T* __restrict__ vc0,
+                                                              FineCG<T> F0, int nk, double* z0, const double* uo0,
+                                                              const double* wo0, double* part0, int cheb, int m,
+                                                              size_t zs) {
+  __shared__ double sh[3 * MC * 16];
+  const int r0 = (int)blockIdx.z * MC;
+  const int nr = min(MC, m - r0);
+  vc0 = rhs_ptr(vc0, r0, zs);
+  z0 = rhs_ptr(z0, r0, zs);
+  uo0 = rhs_ptr(uo0, r0, zs);
+  wo0 = rhs_ptr(wo0, r0, zs);
+  part0 = rhs_ptr(part0, r0, zs);
+  const int nc = nk / 2;
+  const size_t nc2 = (size_t)nc * nc;
+  double v[3 * MC];
+#pragma unroll
+  for (int k = 0; k < 3 * MC; ++k) v[k] = 0.0;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < nk * nk) {
+    const int fx = id / nk, fy = id % nk;
+    T acc[MC];
+#pragma unroll
+    for (int r = 0; r < MC; ++r) acc[r] = T(0);
+    prolong_at_mr<T, RHO, MC>(R, vc0, zs, nr, nk, fx, fy, acc);
+    const int px = fx >> 1, py = fy >> 1;
+    const int d = 2 * (fx & 1) + (fy & 1);
+    const int tp = parent_type(true, px, py);
+    const int pp = px * nc + py;
+#pragma unroll
+    for (int r = 0; r < MC; ++r) {
+      if (r < nr) {
+        const FineCG<T> F = zfine(F0, (size_t)(r0 + r) * zs);
+        const T alpha = cheb ? T(0) : T(F.scal[kFAlpha]), beta = cheb ? T(0) : T(F.scal[kFBeta]);
+        T a = acc[r];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const T wt =
+              cheb ? F.x[t * nc2 + pp] : F.x[t * nc2 + pp] + alpha * (F.u[t * nc2 + pp] + beta * F.p[t * nc2 + pp]);
+          a += T(wcoef(tp, t, d)) * wt;
+        }
+        const double zv = (double)a;
+        rhs_ptr(z0, r, zs)[id] = zv;
+        const double uv = rhs_ptr(uo0, r, zs)[id];
+        v[3 * r] = zv * zv;
+        v[3 * r + 1] = uv * uv;
+        v[3 * r + 2] = zv * rhs_ptr(wo0, r, zs)[id];
+      }
+    }
+  }
+  block_sum<3 * MC>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < MC; ++r) {
+      if (r < nr) {
+        double* part = rhs_ptr(part0, r, zs);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) part[k * gridDim.x + blockIdx.x] = v[3 * r + k];
+      }
+    }
+  }
+}
+
+template <typename T, int RHO>
+void launch_prolong_fine_dots_mr(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
+                                 const double* uo, const double* wo, double* part, int cheb, hipStream_t st, Zb zb) {
+  constexpr int MC = kChunkRhs<T>;
+  const int tot = L.nk * L.nk;
+  hipLaunchKernelGGL((k_prolong_fine_dots_mr<T, RHO, MC>), dim3((tot + 255) / 256, 1, (zb.m + MC - 1) / MC),
+                     dim3(256), 0, st, R, vc, F, L.nk, z, uo, wo, part, cheb, zb.m, zb.zs);
+}
+
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
                               const double* uo, const double* wo, double* part, int cheb, hipStream_t st, Zb zb) {
+  if (zb.m > 1) {
+    switch (L.rho) {
+      case 1: launch_prolong_fine_dots_mr<T, 1>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
+      case 2: launch_prolong_fine_dots_mr<T, 2>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
+      case 3: launch_prolong_fine_dots_mr<T, 3>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
+      case 4: launch_prolong_fine_dots_mr<T, 4>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
+      default: launch_prolong_fine_dots_mr<T, 5>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
+    }
+    return;
+  }
   const int tot = L.nk * L.nk;
   hipLaunchKernelGGL(k_prolong_fine_dots<T>, dim3((tot + 255) / 256, 1, zb.m), dim3(256), 0, st, R, vc, F, L.nk,
                      L.rho, z, uo, wo, part, cheb, zb.zs);
@@ -981,8 +1175,6 @@ __device__ __forceinline__ void coarse_apply_mr(const CGLev<T>& L, const T* zs0,
 
 // Right-hand sides per chunk of the shared-B kernels (LDS holds 3 x waves x
 // 64 partial sums per right-hand side).
-template <typename T>
-constexpr int kChunkRhs = sizeof(T) == 4 ? 8 : 4;
 
 template <typename T, int MC>
 __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int blk_begin, int ngroups, int nchunks,
