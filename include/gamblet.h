@@ -95,7 +95,7 @@ typedef struct gbl_opts {
   int max_outer;      /* maximum outer (flexible CG) iterations */
   int inner_iters;    /* iterations on the finest subband system per outer iteration (Chebyshev: <= 32) */
   int max_rhs;        /* right-hand sides solved together: a solve or adjoint call takes any number of right-
-                         hand sides and runs them in blocks of min(max_rhs, 16), every kernel of an iteration
+                         hand sides and runs them in blocks of min(max_rhs, 64), every kernel of an iteration
                          launched once for the whole block (each right-hand side with its own copy of the
                          solve vectors, so the workspace grows with it); 1..4096 */
   int inner_iters_coarse; /* iterations on each coarser subband system (k < q) (Chebyshev: <= 32) */
@@ -212,7 +212,7 @@ int gbl_version(void);
 int gbl_default_opts(gbl_opts* opts);
 
 /* Device workspace needed for a hierarchy of depth q (2 <= q <= 12) with
- * these options, including min(opts->max_rhs, 16) copies of the solve buffers.
+ * these options, including min(opts->max_rhs, 64) copies of the solve buffers.
  * Pure host computation.  EINVAL on a bad q or options. */
 int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
 
@@ -228,7 +228,7 @@ int gbl_workspace_bytes(int q, const gbl_opts* opts, size_t* bytes);
 int gbl_build(gbl_ctx** out, int q, const double* a_dev, const gbl_opts* opts,
               void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Solve for nrhs >= 1 right-hand sides (in blocks of min(opts->max_rhs, 16); a block
+/* Solve for nrhs >= 1 right-hand sides (in blocks of min(opts->max_rhs, 64); a block
  * iterates until all its right-hand sides meet rtol).
  * g_dev : [nrhs][n][n] cell source ([nrhs][n-1][n-1] interior nodal values when
  *         opts->source = 1).

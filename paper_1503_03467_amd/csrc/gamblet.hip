@@ -143,7 +143,7 @@ struct Layout {
   size_t total = 0;
 };
 
-constexpr int kMaxBlock = 16;   // right-hand sides per block solve
+constexpr int kMaxBlock = 64;   // right-hand sides per block solve
 
 int validate_opts(const gbl_opts* o, std::string& msg) {
   if (!o) { msg = "opts is NULL"; return GBL_EINVAL; }

@@ -538,10 +538,17 @@ void launch_prolong_mr(const LevelGeom& L, const T* R, const T* vc, const T* w, 
                      R, vc, w, vf, L.nk, zb.m, zb.zs);
 }
 
+// Levels from this many points up take the chunked prolongation in a block
+// solve: there R^(k) is large and its reads dominate; on smaller levels the
+// kernels are latency-bound and a thread per right-hand side is faster (at
+// 64 x 64 to 256 x 256 cells the chunked kernels made a block solve 1.6x
+// slower).
+constexpr size_t kChunkedProlongPoints = size_t(1) << 18;
+
 template <typename T>
 void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
                     hipStream_t st, Zb zb) {
-  if (zb.m > 1 && !fine) {
+  if (zb.m > 1 && !fine && (size_t)L.nk * L.nk >= kChunkedProlongPoints) {
     switch (L.rho) {
       case 1: launch_prolong_mr<T, 1>(L, R, vc, w, vf, st, zb); break;
       case 2: launch_prolong_mr<T, 2>(L, R, vc, w, vf, st, zb); break;
@@ -678,7 +685,7 @@ void launch_prolong_fine_dots_mr(const LevelGeom& L, const T* R, const T* vc, co
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
                               const double* uo, const double* wo, double* part, int cheb, hipStream_t st, Zb zb) {
-  if (zb.m > 1) {
+  if (zb.m > 1 && (size_t)L.nk * L.nk >= kChunkedProlongPoints) {
     switch (L.rho) {
       case 1: launch_prolong_fine_dots_mr<T, 1>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
       case 2: launch_prolong_fine_dots_mr<T, 2>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;

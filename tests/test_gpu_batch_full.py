@@ -1,6 +1,6 @@
 """The full batch workload through gbl_build_batched / gbl_solve_batched: 256
 independent problems with q drawn from {6, 7, 8} (each with its own seeds,
-sigma = 1), 64 N(0,1) right-hand sides each, solved in blocks of 16.
+sigma = 1), 64 N(0,1) right-hand sides each, solved as one block of 64.
 
 Every problem's 64 solutions must equal, bit for bit, the same problem built
 and solved on its own (same options), and a sample of problems and
@@ -29,14 +29,14 @@ def test_full_batch_equals_single_and_matches_direct():
     print("CASE test=batch_full problems=256 rhs=64", flush=True)
     coeffs = [torch.as_tensor(p.a, device="cuda") for p in probs]
     srcs = [torch.as_tensor(p.g, device="cuda") for p in probs]
-    hs = P.build_batched(coeffs, rho=3, precision="mixed", rtol=1e-8, max_rhs=16)
+    hs = P.build_batched(coeffs, rho=3, precision="mixed", rtol=1e-8, max_rhs=64)
     us = P.solve_batched(hs, srcs)
     for h in hs:
         assert h.last_info.status == 0
         h.close()
     print("batched build and solve done", flush=True)
     for i, p in enumerate(probs):
-        H = P.Hierarchy(coeffs[i], rho=3, precision="mixed", rtol=1e-8, max_rhs=16)
+        H = P.Hierarchy(coeffs[i], rho=3, precision="mixed", rtol=1e-8, max_rhs=64)
         u1 = H.solve(srcs[i])
         H.close()
         assert torch.equal(u1, us[i]), (i, p.q)
