@@ -79,12 +79,12 @@ def level_geometry(H):
 # measured on: the entry records the SHA-256 of that source file, and a mismatch reports None.
 MEASURED_TRAFFIC = {
     # matrix-core patch solves, levels 8..2 of the 512x512-cell benchmark (parent-major copy of B^(k),
-    # then the patch kernel): 108,061 KiB fetched and 118,707 KiB written per build over 7 launches
+    # then the patch kernel): 104,893 KiB fetched and 96,059 KiB written per build over 7 launches
     # (FETCH x 2.0 + WRITE x 1.0); profiles/q9_kernels_hbm_fraction_and_mfma.md
     ("patch_solve", 9, "mixed"): {
-        "bytes_per_launch": 48980622,
+        "bytes_per_launch": 44740763,
         "source": "kernels_build.hip",
-        "sha256": "f354d1700ef05376fa7e98cd24d0e535f3ef395fb0e5ed777b249754c82c544f",
+        "sha256": "b28678d5f313c0d07e67c2b30ba4ab038afaa0e9159bff33c6c5f73654f1027c",
     },
 }
 
