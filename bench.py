@@ -347,7 +347,7 @@ def inclusion_workload(P, S, torch, dev, cpu_leg=True):
     """The 2048 x 2048-cell inclusion workload (discs of a = 1e6 on 10% of the
     cells over the product field, 16 N(0,1) right-hand sides, patch radius 4),
     one pass: FP64-built hierarchy with window corrections, the 16 right-hand
-    sides as one block (FP32 subband iterations: 16 Chebyshev steps on the
+    sides as one block (FP32 subband iterations: 8 Chebyshev steps on the
     finest level, 16 CG iterations below; FP64 outer iteration to 1e-8), and
     the adjoint gradient of J = |u_0|^2 / 2 (the first right-hand side's
     solution).  Also the outer iterations of one right-hand side with radius 5
@@ -358,7 +358,7 @@ def inclusion_workload(P, S, torch, dev, cpu_leg=True):
     pr = S.inclusion_problem(q=11, nrhs=16, a_incl=1e6)
     a = torch.as_tensor(pr.a, device=dev)
     g = torch.as_tensor(pr.g, device=dev)
-    kw = dict(precision="mixed-fp64-build", rtol=1e-8, max_outer=6000, inner="cheb-cg", inner_iters=16,
+    kw = dict(precision="mixed-fp64-build", rtol=1e-8, max_outer=6000, inner="cheb-cg", inner_iters=8,
               inner_iters_coarse=16, window_tol=1000.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

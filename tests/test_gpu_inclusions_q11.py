@@ -53,7 +53,7 @@ def test_inclusion_workload_q11(capsys):
     a = torch.as_tensor(pr.a, device=dev)
     g = torch.as_tensor(pr.g[:nrhs], device=dev)
     H = P.Hierarchy(a, rho=4, precision="mixed-fp64-build", rtol=1e-8, max_rhs=4, max_outer=6000,
-                    inner="cheb-cg", inner_iters=16, inner_iters_coarse=16, window_tol=1000.0)
+                    inner="cheb-cg", inner_iters=8, inner_iters_coarse=16, window_tol=1000.0)
     say("built")
     parts = []
     for r0 in range(0, nrhs, 4):   # four calls of one 4-right-hand-side block each
