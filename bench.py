@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and adjoint measurements")
     ap.add_argument("--no-inclusions", action="store_true", help="skip the 2048 x 2048-cell inclusion workload")
+    ap.add_argument("--inclusion-iterations", type=int, default=0,
+                    help="only run K outer iterations of the inclusion workload's 16-right-hand-side block "
+                         "(for kernel profiles) and print their time")
     return ap.parse_args()
 
 
@@ -343,6 +346,31 @@ def cpu_baseline(pr, dof):
     return cpu, u_ref
 
 
+INCLUSION_SETTINGS = dict(precision="mixed-fp64-build", rtol=1e-8, max_outer=6000, inner="cheb-cg", inner_iters=8,
+                          inner_iters_coarse=16, window_tol=1000.0)
+
+
+def inclusion_iterations(P, S, torch, dev, k):
+    """k outer iterations of the inclusion workload's 16-right-hand-side block
+    (the build and the solve settings of the full workload; for profiles)."""
+    pr = S.inclusion_problem(q=11, nrhs=16, a_incl=1e6)
+    a = torch.as_tensor(pr.a, device=dev)
+    g = torch.as_tensor(pr.g, device=dev)
+    kw = dict(INCLUSION_SETTINGS, max_outer=k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = P.Hierarchy(a, rho=4, max_rhs=16, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    H.solve(g, check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    its = H.last_info.outer_iters
+    H.close()
+    print(json.dumps({"workload": "inclusion block, 16 right-hand sides", "build_ms": (t1 - t0) * 1e3,
+                      "outer_iters": its, "ms_per_outer_iter": (t2 - t1) * 1e3 / max(1, its)}), flush=True)
+
+
 def inclusion_workload(P, S, torch, dev, cpu_leg=True):
     """The 2048 x 2048-cell inclusion workload (discs of a = 1e6 on 10% of the
     cells over the product field, 16 N(0,1) right-hand sides, patch radius 4),
@@ -358,8 +386,7 @@ def inclusion_workload(P, S, torch, dev, cpu_leg=True):
     pr = S.inclusion_problem(q=11, nrhs=16, a_incl=1e6)
     a = torch.as_tensor(pr.a, device=dev)
     g = torch.as_tensor(pr.g, device=dev)
-    kw = dict(precision="mixed-fp64-build", rtol=1e-8, max_outer=6000, inner="cheb-cg", inner_iters=8,
-              inner_iters_coarse=16, window_tol=1000.0)
+    kw = dict(INCLUSION_SETTINGS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     H = P.Hierarchy(a, rho=4, max_rhs=16, **kw)
@@ -418,6 +445,9 @@ def main():
     import synthetic as S
 
     dev = torch.device("cuda:0")
+    if args.inclusion_iterations > 0:
+        inclusion_iterations(P, S, torch, dev, args.inclusion_iterations)
+        return
     pr = S.q9_rough_problem()
     q, dof = pr.q, pr.dof
     a = torch.as_tensor(pr.a, device=dev)
