@@ -1,4 +1,4 @@
-"""Several right-hand sides solved together (blocks of up to 16 sharing one
+"""Several right-hand sides solved together (blocks of up to 64 sharing one
 launch per step, each right-hand side in its own copy of the per-solve
 workspace region) against the same right-hand sides solved one at a time.
 
@@ -42,6 +42,32 @@ def test_block_equals_single_bit_for_bit(precision, inner, q):
     Hb.close()
     Hs = P.Hierarchy(a, max_rhs=1, **kw)
     for r in range(6):
+        us = Hs.solve(g[r], check=False)
+        assert torch.equal(us, ub[r]), (r, float((us - ub[r]).abs().max()))
+    Hs.close()
+
+
+@pytest.mark.parametrize("q,nrhs,max_rhs,inner", [(6, 70, 64, "chebyshev"), (6, 70, 64, "cheb-cg"),
+                                                  (9, 10, 10, "chebyshev"), (10, 3, 3, "chebyshev")])
+def test_wide_blocks_equal_single_bit_for_bit(q, nrhs, max_rhs, inner):
+    """Blocks of 64 plus a remainder (the CG scalar steps and window-free
+    operators over 8 chunks), and blocks on levels of 512 x 512 points and more,
+    where the prolongations read R once per chunk of 8 right-hand sides (q = 9:
+    the finest level, chunks of 8 and 2; q = 10: also level 9, one chunk of 3)."""
+    print("CASE test=wide_block_bits", q, nrhs, max_rhs, inner, flush=True)
+    P = _P()
+    pr = S.rough_problem(q, 1.0, 33, nrhs=nrhs)
+    a = _dev(pr.a)
+    g = _dev(pr.g)
+    kw = dict(rho=3, precision="mixed", rtol=1e-15, max_outer=9, inner=inner)
+    if inner != "chebyshev":
+        kw.update(inner_iters=8, inner_iters_coarse=4)
+    Hb = P.Hierarchy(a, max_rhs=max_rhs, **kw)
+    ub = Hb.solve(g, check=False)
+    assert Hb.last_info.outer_iters == 9
+    Hb.close()
+    Hs = P.Hierarchy(a, max_rhs=1, **kw)
+    for r in range(nrhs):
         us = Hs.solve(g[r], check=False)
         assert torch.equal(us, ub[r]), (r, float((us - ub[r]).abs().max()))
     Hs.close()
