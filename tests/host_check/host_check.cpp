@@ -41,7 +41,7 @@ int main() {
     for (int rho = 0; rho <= 6; ++rho)
       for (int rc = 0; rc <= 5; rc += 1)
         for (int prec = 0; prec <= 3; ++prec)
-          for (int rhs : {0, 1, 3, 16, 17, 64})
+          for (int rhs : {0, 1, 3, 16, 17, 64, 65})
             for (int inner = 0; inner <= 3; ++inner)
               for (int mass = 0; mass <= 4; mass += 2)
                 for (double wt : {0.0, 5.0, 1e3}) {
