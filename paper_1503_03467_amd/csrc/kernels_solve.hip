@@ -1315,14 +1315,11 @@ void launch_cg_init(const CGArgs<T>& a, int nblocks, hipStream_t st, Zb zb) {
 // one wavefront per stencil row; the smaller levels share a second launch.
 template <typename T>
 void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb zb) {
-  int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
+  const int n0 = a.lv[0].nblks < nblocks ? a.lv[0].nblks : nblocks;
   const int t0 = 2 * a.lv[0].t + 1;
   int tmax = 1;
   for (int l = 1; l < a.nlev; ++l) tmax = tmax > 2 * a.lv[l].t + 1 ? tmax : 2 * a.lv[l].t + 1;
   const int w0 = t0 < 16 ? t0 : 16, w1 = tmax < 16 ? tmax : 16;
-  // the same wavefront count for every level (wide stencils at radius 4):
-  // one launch, whose workgroups compute exactly what the two would
-  if (w1 == w0) n0 = nblocks;
   if (zb.m == 1) {
     hipLaunchKernelGGL(k_cg_spmv<T>, dim3(xcd_group_grid(n0, 1)), dim3(64 * w0), 0, st, a, it, 0, n0, 1, zb.zs);
     if (nblocks > n0)
