@@ -1164,6 +1164,84 @@ __device__ __forceinline__ void coarse_rows_mr(const CGLev<T>& L, const T* __res
   }
 }
 
+// The same rows for a workgroup whose 64 parents lie in one grid row (np >=
+// 64), with the coarse vectors staged in LDS: for each of its offset rows a
+// wavefront first copies the segment of grid row qx it needs (columns py0 - t
+// .. py0 + 63 + t clamped into the level as in coarse_rows_mr, three
+// components of every right-hand side of the chunk) into its own slice zl,
+// then runs the row from there.  The gathers otherwise re-read every z word
+// through L2 once per stencil offset oy (the kernel was bound by the L2
+// request rate); the products and their order are those of coarse_rows_mr.
+template <typename T, int TT, int MC>
+__device__ __forceinline__ void coarse_rows_mr_staged(const CGLev<T>& L, const T* __restrict__ zs0, size_t zs, int nr,
+                                                      int p, int wv, int nw, T (&acc)[MC][3], T* zl) {
+  constexpr int t = TT / 2;
+  constexpr int ZW = 64 + 2 * t;
+  const int np = L.np;
+  const size_t np2 = (size_t)np * np;
+  const int lane = threadIdx.x & 63;
+  const int px = p / np, py = p - (p / np) * np;
+  const int py0 = py - lane;
+  T* zw = zl + (size_t)wv * MC * 3 * ZW;
+  const int rounds = (TT + nw - 1) / nw;
+  for (int k = 0; k < rounds; ++k) {
+    const int ox = wv + k * nw;
+    const int qx = px + ox - t;
+    const bool row = ox < TT && qx >= 0 && qx < np;
+    if (row) {
+      for (int idx = lane; idx < ZW; idx += 64) {
+        const size_t q = (size_t)qx * np + min(max(py0 - t + idx, 0), np - 1);
+#pragma unroll
+        for (int r = 0; r < MC; ++r) {
+          if (r < nr) {
+            const T* zr = rhs_ptr(zs0, r, zs);
+            zw[(r * 3 + 0) * ZW + idx] = zr[q];
+            zw[(r * 3 + 1) * ZW + idx] = zr[np2 + q];
+            zw[(r * 3 + 2) * ZW + idx] = zr[2 * np2 + q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (row) {
+      const T* Bo = L.B + b_index(ox * TT, 0, p, TT);
+#pragma unroll
+      for (int oy = 0; oy < TT; ++oy) {
+        const T* Bb = Bo + oy * 9 * 64;
+        const T b0 = Bb[0], b1 = Bb[64], b2 = Bb[128], b3 = Bb[192], b4 = Bb[256], b5 = Bb[320];
+        const T b6 = Bb[384], b7 = Bb[448], b8 = Bb[512];
+#pragma unroll
+        for (int r = 0; r < MC; ++r) {
+          if (r < nr) {
+            const T z0 = zw[(r * 3 + 0) * ZW + lane + oy], z1 = zw[(r * 3 + 1) * ZW + lane + oy];
+            const T z2 = zw[(r * 3 + 2) * ZW + lane + oy];
+            acc[r][0] += b0 * z0 + b1 * z1 + b2 * z2;
+            acc[r][1] += b3 * z0 + b4 * z1 + b5 * z2;
+            acc[r][2] += b6 * z0 + b7 * z1 + b8 * z2;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int MC>
+__device__ __forceinline__ void coarse_apply_mr_staged(const CGLev<T>& L, const T* zs0, size_t zs, int nr, int TT,
+                                                       int p, int wv, int nw, T (&acc)[MC][3], T* zl) {
+  switch (TT) {
+    case 1: coarse_rows_mr_staged<T, 1, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 3: coarse_rows_mr_staged<T, 3, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 5: coarse_rows_mr_staged<T, 5, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 7: coarse_rows_mr_staged<T, 7, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 9: coarse_rows_mr_staged<T, 9, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 11: coarse_rows_mr_staged<T, 11, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 13: coarse_rows_mr_staged<T, 13, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    case 15: coarse_rows_mr_staged<T, 15, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+    default: coarse_rows_mr_staged<T, 17, MC>(L, zs0, zs, nr, p, wv, nw, acc, zl); break;
+  }
+}
+
 template <typename T, int MC>
 __device__ __forceinline__ void coarse_apply_mr(const CGLev<T>& L, const T* zs0, size_t zs, int nr, int TT, int p,
                                                 int wv, int nw, T (&acc)[MC][3]) {
@@ -1207,7 +1285,13 @@ __global__ __launch_bounds__(1024) void k_cg_spmv_mr(CGArgs<T> args, int it, int
   T acc[MC][3];
 #pragma unroll
   for (int r = 0; r < MC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = T(0);
-  if (p < np * np) coarse_apply_mr<T, MC>(L0, L0.z, zs, nr, TT, p, wv, nw, acc);
+  if (np >= 64) {
+    // the staging buffer shares the dynamic LDS with the wavefront sums below;
+    // the staged rows end with a barrier
+    coarse_apply_mr_staged<T, MC>(L0, L0.z, zs, nr, TT, p, wv, nw, acc, red);
+  } else if (p < np * np) {
+    coarse_apply_mr<T, MC>(L0, L0.z, zs, nr, TT, p, wv, nw, acc);
+  }
 #pragma unroll
   for (int r = 0; r < MC; ++r)
 #pragma unroll
@@ -1330,11 +1414,15 @@ void launch_cg_spmv(const CGArgs<T>& a, int nblocks, int it, hipStream_t st, Zb 
   }
   constexpr int MC = kChunkRhs<T>;
   const int nch = (zb.m + MC - 1) / MC;
-  hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(n0, nch)), dim3(64 * w0),
-                     (size_t)MC * 3 * w0 * 64 * sizeof(T), st, a, it, 0, n0, nch, zb.m, zb.zs);
+  // dynamic LDS: the wavefront sums [MC][3][w][64], or the staged z rows
+  // [w][MC][3][64 + 2t] of the widest stencil in the launch (the larger)
+  const size_t lds0 = (size_t)MC * 3 * w0 * (64 + 2 * a.lv[0].t) * sizeof(T);
+  const size_t lds1 = (size_t)MC * 3 * w1 * (64 + 2 * ((tmax - 1) / 2)) * sizeof(T);
+  hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(n0, nch)), dim3(64 * w0), lds0, st, a, it, 0, n0,
+                     nch, zb.m, zb.zs);
   if (nblocks > n0)
-    hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(nblocks - n0, nch)), dim3(64 * w1),
-                       (size_t)MC * 3 * w1 * 64 * sizeof(T), st, a, it, n0, nblocks - n0, nch, zb.m, zb.zs);
+    hipLaunchKernelGGL((k_cg_spmv_mr<T, MC>), dim3(xcd_group_grid(nblocks - n0, nch)), dim3(64 * w1), lds1, st, a,
+                       it, n0, nblocks - n0, nch, zb.m, zb.zs);
   launch_cg_scalars<T>(a, it, kCGPhaseSpmv, st, zb);
 }
 template <typename T>

@@ -48,12 +48,15 @@ def test_block_equals_single_bit_for_bit(precision, inner, q):
 
 
 @pytest.mark.parametrize("q,nrhs,max_rhs,inner", [(6, 70, 64, "chebyshev"), (6, 70, 64, "cheb-cg"),
-                                                  (9, 10, 10, "chebyshev"), (10, 3, 3, "chebyshev")])
+                                                  (9, 10, 10, "chebyshev"), (10, 3, 3, "chebyshev"),
+                                                  (8, 10, 10, "cheb-cg"), (9, 9, 9, "cheb-cg")])
 def test_wide_blocks_equal_single_bit_for_bit(q, nrhs, max_rhs, inner):
     """Blocks of 64 plus a remainder (the CG scalar steps and window-free
     operators over 8 chunks), and blocks on levels of 512 x 512 points and more,
     where the prolongations read R once per chunk of 8 right-hand sides (q = 9:
-    the finest level, chunks of 8 and 2; q = 10: also level 9, one chunk of 3)."""
+    the finest level, chunks of 8 and 2; q = 10: also level 9, one chunk of 3),
+    and the block CG operator stages the coarse vectors of levels with 64 or
+    more parents per side in LDS (q = 8 and 9 with CG below the finest level)."""
     print("CASE test=wide_block_bits", q, nrhs, max_rhs, inner, flush=True)
     P = _P()
     pr = S.rough_problem(q, 1.0, 33, nrhs=nrhs)
