@@ -405,16 +405,42 @@ __device__ __forceinline__ T prolong_at_r(const T* __restrict__ R, const T* __re
   return acc;
 }
 
-// (R^T v)_c for a chunk of right-hand sides: each R word is loaded once and
-// applied to the nr coarse vectors (copies zs bytes apart), each sum in the
-// order of prolong_at_r.
+// The coarse values a workgroup of 256 consecutive level-k slots in one row
+// (fine row fx, columns fy0 .. fy0 + 255; nk a multiple of 256) gathers in
+// the chunked prolongation: coarse rows px - RHO .. px + RHO and columns py0 -
+// RHO .. py0 + 127 + RHO of every right-hand side's coarse vector, clamped
+// into the level as prolong_at_r clamps them (the zero weight of the terms
+// outside the level is applied at the gather), copied once into LDS: the
+// gather otherwise fetched each of them through L2 for every one of the
+// (2 RHO + 1)^2 terms.  Must be called by all threads of the workgroup.
 template <typename T, int RHO, int MC>
-__device__ __forceinline__ void prolong_at_mr(const T* __restrict__ R, const T* __restrict__ vc0, size_t zs, int nr,
-                                              int nk, int fx, int fy, T (&acc)[MC]) {
+__device__ __forceinline__ void stage_coarse_rows(const T* __restrict__ vc0, size_t zs, int nr, int nc, int px,
+                                                  int py0, T* zl) {
+  constexpr int RW = 2 * RHO + 1, CW = 128 + 2 * RHO;
+  for (int e = threadIdx.x; e < MC * RW * CW; e += blockDim.x) {
+    const int r = e / (RW * CW);
+    const int rem = e - r * (RW * CW);
+    const int dx = rem / CW, col = rem - (rem / CW) * CW;
+    if (r < nr) {
+      const int ixc = min(max(px - RHO + dx, 0), nc - 1);
+      const int iyc = min(max(py0 - RHO + col, 0), nc - 1);
+      zl[e] = rhs_ptr(vc0, r, zs)[ixc * nc + iyc];
+    }
+  }
+  __syncthreads();
+}
+
+// (R^T v)_c for a chunk of right-hand sides, with the coarse values from
+// stage_coarse_rows: each R word is loaded once and applied to the nr coarse
+// vectors, each sum in the terms and order of prolong_at_r.
+template <typename T, int RHO, int MC>
+__device__ __forceinline__ void prolong_at_mr_staged(const T* __restrict__ R, const T* __restrict__ zl, int nr, int nk,
+                                                     int fx, int fy, int py0, T (&acc)[MC]) {
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
   const int px = fx >> 1, py = fy >> 1;
   constexpr int rw = 2 * (2 * RHO + 1);
+  constexpr int RW = 2 * RHO + 1, CW = 128 + 2 * RHO;
 #pragma unroll
   for (int dx = -RHO; dx <= RHO; ++dx) {
     const int ix = px + dx;
@@ -431,9 +457,10 @@ __device__ __forceinline__ void prolong_at_mr(const T* __restrict__ R, const T* 
       const int i = ixc * nc + iyc;
       const T rv = R[(size_t)(bxc * rw + byc) * nc2 + i];
       const T okv = T(ok ? 1 : 0);
+      const int col = py - py0 + dy + RHO;
 #pragma unroll
       for (int r = 0; r < MC; ++r)
-        if (r < nr) acc[r] += rv * (rhs_ptr(vc0, r, zs)[i] * okv);
+        if (r < nr) acc[r] += rv * (zl[(r * RW + dx + RHO) * CW + col] * okv);
     }
   }
 }
@@ -497,20 +524,24 @@ template <typename T, int RHO, int MC>
 __global__ __launch_bounds__(256) void k_prolong_mr(const T* __restrict__ R, const T* __restrict__ vc0,
                                                     const T* __restrict__ w0, T* __restrict__ vf0, int nk, int m,
                                                     size_t zs) {
+  __shared__ T zl[MC * (2 * RHO + 1) * (128 + 2 * RHO)];
   const int r0 = (int)blockIdx.z * MC;
   const int nr = min(MC, m - r0);
   vc0 = rhs_ptr(vc0, r0, zs);
   w0 = rhs_ptr(w0, r0, zs);
   vf0 = rhs_ptr(vf0, r0, zs);
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nk * nk) return;
   const int nc = nk / 2;
+  const int first = (int)blockIdx.x * (int)blockDim.x;
+  const int py0 = (first % nk) >> 1;
+  stage_coarse_rows<T, RHO, MC>(vc0, zs, nr, nc, (first / nk) >> 1, py0, zl);
+  const int id = first + (int)threadIdx.x;
+  if (id >= nk * nk) return;
   const size_t nc2 = (size_t)nc * nc;
   const int fx = id / nk, fy = id % nk;
   T acc[MC];
 #pragma unroll
   for (int r = 0; r < MC; ++r) acc[r] = T(0);
-  prolong_at_mr<T, RHO, MC>(R, vc0, zs, nr, nk, fx, fy, acc);
+  prolong_at_mr_staged<T, RHO, MC>(R, zl, nr, nk, fx, fy, py0, acc);
   const int px = fx >> 1, py = fy >> 1;
   const int d = 2 * (fx & 1) + (fy & 1);
   const int tp = parent_type(false, px, py);
@@ -548,7 +579,7 @@ constexpr size_t kChunkedProlongPoints = size_t(1) << 18;
 template <typename T>
 void launch_prolong(const LevelGeom& L, const T* R, const T* vc, const T* w, T* vf, bool fine,
                     hipStream_t st, Zb zb) {
-  if (zb.m > 1 && !fine && (size_t)L.nk * L.nk >= kChunkedProlongPoints) {
+  if (zb.m > 1 && !fine && (size_t)L.nk * L.nk >= kChunkedProlongPoints && L.nk % 256 == 0) {
     switch (L.rho) {
       case 1: launch_prolong_mr<T, 1>(L, R, vc, w, vf, st, zb); break;
       case 2: launch_prolong_mr<T, 2>(L, R, vc, w, vf, st, zb); break;
@@ -616,6 +647,7 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots_mr(const T* __restric
                                                               const double* wo0, double* part0, int cheb, int m,
                                                               size_t zs) {
   __shared__ double sh[3 * MC * 16];
+  __shared__ T zl[MC * (2 * RHO + 1) * (128 + 2 * RHO)];
   const int r0 = (int)blockIdx.z * MC;
   const int nr = min(MC, m - r0);
   vc0 = rhs_ptr(vc0, r0, zs);
@@ -625,16 +657,19 @@ __global__ __launch_bounds__(256) void k_prolong_fine_dots_mr(const T* __restric
   part0 = rhs_ptr(part0, r0, zs);
   const int nc = nk / 2;
   const size_t nc2 = (size_t)nc * nc;
+  const int first = (int)blockIdx.x * (int)blockDim.x;
+  const int py0 = (first % nk) >> 1;
+  stage_coarse_rows<T, RHO, MC>(vc0, zs, nr, nc, (first / nk) >> 1, py0, zl);
   double v[3 * MC];
 #pragma unroll
   for (int k = 0; k < 3 * MC; ++k) v[k] = 0.0;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  const int id = first + (int)threadIdx.x;
   if (id < nk * nk) {
     const int fx = id / nk, fy = id % nk;
     T acc[MC];
 #pragma unroll
     for (int r = 0; r < MC; ++r) acc[r] = T(0);
-    prolong_at_mr<T, RHO, MC>(R, vc0, zs, nr, nk, fx, fy, acc);
+    prolong_at_mr_staged<T, RHO, MC>(R, zl, nr, nk, fx, fy, py0, acc);
     const int px = fx >> 1, py = fy >> 1;
     const int d = 2 * (fx & 1) + (fy & 1);
     const int tp = parent_type(true, px, py);
@@ -685,7 +720,7 @@ void launch_prolong_fine_dots_mr(const LevelGeom& L, const T* R, const T* vc, co
 template <typename T>
 void launch_prolong_fine_dots(const LevelGeom& L, const T* R, const T* vc, const FineCG<T>& F, double* z,
                               const double* uo, const double* wo, double* part, int cheb, hipStream_t st, Zb zb) {
-  if (zb.m > 1 && (size_t)L.nk * L.nk >= kChunkedProlongPoints) {
+  if (zb.m > 1 && (size_t)L.nk * L.nk >= kChunkedProlongPoints && L.nk % 256 == 0) {
     switch (L.rho) {
       case 1: launch_prolong_fine_dots_mr<T, 1>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
       case 2: launch_prolong_fine_dots_mr<T, 2>(L, R, vc, F, z, uo, wo, part, cheb, st, zb); break;
